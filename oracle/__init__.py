@@ -1,0 +1,245 @@
+"""ctypes binding of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` import this
+package.  It loads ``oracle/liboracle.so`` (building it with gcc when it is absent) and exposes the
+oracle's C functions on numpy arrays.  It shares no code with the GPU library.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+
+
+class OrcParams(C.Structure):
+    """Mirror of ``orc_params`` in bss_oracle.h (field order matters)."""
+    _fields_ = [
+        ("m", C.c_double), ("Iz", C.c_double), ("lf", C.c_double), ("lr", C.c_double),
+        ("Cf", C.c_double), ("Cr", C.c_double), ("mu", C.c_double), ("g", C.c_double),
+        ("v_min", C.c_double), ("dt", C.c_double),
+        ("steer_max", C.c_double), ("accel_max", C.c_double),
+        ("sigma_eps", C.c_double * 2), ("sigma_w", C.c_double * 3),
+        ("K", C.c_int32), ("M", C.c_int32), ("T", C.c_int32),
+        ("delta", C.c_double), ("gamma", C.c_double),
+        ("backoff", C.c_int32),
+        ("lambda_", C.c_double), ("gamma_u", C.c_double), ("v_goal", C.c_double),
+        ("q_vx", C.c_double), ("q_vy", C.c_double), ("q_r", C.c_double), ("q_ey", C.c_double),
+        ("q_epsi", C.c_double), ("C_cbf", C.c_double), ("C_obs", C.c_double),
+        ("phi_scale", C.c_double),
+        ("ell_a", C.c_double), ("ell_b", C.c_double), ("half_width", C.c_double),
+        ("shield_iters", C.c_int32), ("shield_gmin", C.c_double), ("shield_fd", C.c_double),
+        ("seed", C.c_uint64),
+        ("model", C.c_int32),
+        ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
+    ]
+
+
+def make_params(cfg: dict) -> OrcParams:
+    """Build an ``OrcParams`` from a problem dict (keys as in ``workloads.default_problem``)."""
+    p = OrcParams()
+    for name, _ in OrcParams._fields_:
+        key = "lambda" if name == "lambda_" else name
+        if key not in cfg:
+            continue
+        val = cfg[key]
+        if name in ("sigma_eps", "sigma_w", "lin_A", "lin_B"):
+            arr = getattr(p, name)
+            flat = np.asarray(val, dtype=np.float64).ravel()
+            for i, x in enumerate(flat):
+                arr[i] = float(x)
+        else:
+            setattr(p, name, type(getattr(p, name))(val))
+    return p
+
+
+def _load():
+    path = os.path.join(_HERE, "liboracle.so")
+    if not os.path.exists(path):
+        _build.build()
+    lib = C.CDLL(path)
+    P = C.POINTER(OrcParams)
+    lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.orc_philox4x32_10.restype = None
+    lib.orc_uniform.argtypes = [C.c_uint32]
+    lib.orc_uniform.restype = C.c_double
+    lib.orc_normals.argtypes = [C.c_uint64, _u32p, _f64p]
+    lib.orc_normals.restype = None
+    lib.orc_backoff.argtypes = [C.c_double, C.c_int32]
+    lib.orc_backoff.restype = C.c_double
+    lib.orc_car_deriv.argtypes = [P, _f64p, _f64p, _f64p]
+    lib.orc_car_deriv.restype = None
+    lib.orc_model_step.argtypes = [P, _f64p, _f64p, _f64p]
+    lib.orc_model_step.restype = None
+    lib.orc_ellipse_sdf.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.POINTER(C.c_double), _f64p]
+    lib.orc_ellipse_sdf.restype = None
+    lib.orc_barrier.argtypes = [P, C.c_double, _f64p]
+    lib.orc_barrier.restype = C.c_double
+    lib.orc_stage_cost.argtypes = [P, _f64p]
+    lib.orc_stage_cost.restype = C.c_double
+    lib.orc_moments.argtypes = [_f64p, C.c_int32, _f64p]
+    lib.orc_moments.restype = None
+    lib.orc_repair.argtypes = [P, C.c_double, _f64p, _f64p]
+    lib.orc_repair.restype = None
+    lib.orc_score.argtypes = [P, C.c_double, _f64p, _f64p, _f64p]
+    lib.orc_score.restype = C.c_double
+    lib.orc_rollout.argtypes = [P, C.c_double, C.c_uint32, C.c_int32, _f64p, C.c_void_p,
+                                C.c_void_p, _f64p, _f64p, _f64p]
+    lib.orc_rollout.restype = C.c_double
+    lib.orc_update.argtypes = [P, _f64p, _f64p, _f64p, _f64p]
+    lib.orc_update.restype = C.c_int32
+    lib.orc_solve.argtypes = [P, C.c_uint32, _f64p, C.c_void_p, _f64p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, _f64p, C.c_int32]
+    lib.orc_solve.restype = C.c_int32
+    lib.orc_step_shift.argtypes = [C.c_int32, _f64p]
+    lib.orc_step_shift.restype = None
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr, key):
+    """Philox4x32-10 of one counter (4 uint32) under one key (2 uint32)."""
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(np.ascontiguousarray(ctr, dtype=np.uint32),
+                            np.ascontiguousarray(key, dtype=np.uint32), out)
+    return out
+
+
+def normals(seed, ctr):
+    z = np.zeros(4)
+    lib().orc_normals(int(seed), np.ascontiguousarray(ctr, dtype=np.uint32), z)
+    return z
+
+
+def uniform(r):
+    return lib().orc_uniform(int(r))
+
+
+def backoff(delta, kind=0):
+    return lib().orc_backoff(float(delta), int(kind))
+
+
+def car_deriv(cfg, x, u):
+    p = make_params(cfg)
+    dx = np.zeros(6)
+    lib().orc_car_deriv(C.byref(p), np.ascontiguousarray(x, dtype=np.float64),
+                        np.ascontiguousarray(u, dtype=np.float64), dx)
+    return dx
+
+
+def model_step(cfg, x, u):
+    p = make_params(cfg)
+    xn = np.zeros(6)
+    lib().orc_model_step(C.byref(p), np.ascontiguousarray(x, dtype=np.float64),
+                         np.ascontiguousarray(u, dtype=np.float64), xn)
+    return xn
+
+
+def ellipse_sdf(a, b, X, Y):
+    sd = C.c_double()
+    n = np.zeros(2)
+    lib().orc_ellipse_sdf(float(a), float(b), float(X), float(Y), C.byref(sd), n)
+    return sd.value, n
+
+
+def barrier(cfg, nu, mom):
+    p = make_params(cfg)
+    return lib().orc_barrier(C.byref(p), float(nu), np.ascontiguousarray(mom, dtype=np.float64))
+
+
+def stage_cost(cfg, mom):
+    p = make_params(cfg)
+    return lib().orc_stage_cost(C.byref(p), np.ascontiguousarray(mom, dtype=np.float64))
+
+
+def moments(particles):
+    particles = np.ascontiguousarray(particles, dtype=np.float64)
+    out = np.zeros(9)
+    lib().orc_moments(particles, int(particles.shape[0]), out)
+    return out
+
+
+def repair(cfg, nu, mom_t, u):
+    p = make_params(cfg)
+    uu = np.array(u, dtype=np.float64)
+    lib().orc_repair(C.byref(p), float(nu), np.ascontiguousarray(mom_t, dtype=np.float64), uu)
+    return uu
+
+
+def score(cfg, nu, mom, u, v):
+    """Trajectory cost of one sample from injected moments [T+1][9], controls [T][2], v [T][2]."""
+    p = make_params(cfg)
+    return lib().orc_score(C.byref(p), float(nu), np.ascontiguousarray(mom, dtype=np.float64),
+                           np.ascontiguousarray(u, dtype=np.float64),
+                           np.ascontiguousarray(v, dtype=np.float64))
+
+
+def rollout(cfg, s, k, x0, v, Sigma0=None):
+    """One sample's rollout: returns (S_k, u [T][2], moments [T+1][9])."""
+    p = make_params(cfg)
+    T = cfg["T"]
+    nu = backoff(cfg["delta"], cfg.get("backoff", 0))
+    u = np.zeros((T, 2))
+    mom = np.zeros((T + 1, 9))
+    L0 = None
+    S0 = None
+    if Sigma0 is not None:
+        S0 = np.ascontiguousarray(Sigma0, dtype=np.float64)
+        L0 = np.linalg.cholesky(S0 + 0.0) if np.any(S0 != 0) else None
+    Sk = lib().orc_rollout(C.byref(p), nu, int(s), int(k),
+                           np.ascontiguousarray(x0, dtype=np.float64), _ptr(S0),
+                           _ptr(None if L0 is None else np.ascontiguousarray(L0)),
+                           np.ascontiguousarray(v, dtype=np.float64), u, mom)
+    return Sk, u, mom
+
+
+def update(cfg, S, u, v):
+    """MPPI update from injected costs [K] and controls [K][T][2]; returns (rc, v+, stats)."""
+    p = make_params(cfg)
+    vv = np.array(v, dtype=np.float64)
+    stats = np.zeros(4)
+    rc = lib().orc_update(C.byref(p), np.ascontiguousarray(S, dtype=np.float64),
+                          np.ascontiguousarray(u, dtype=np.float64), vv, stats)
+    return rc, vv, stats
+
+
+def solve(cfg, s, x0, v, Sigma0=None, want_traces=True, nthreads=None):
+    """One full solve.  Returns dict(rc, v (updated), u, mom, S, stats)."""
+    p = make_params(cfg)
+    K, T = cfg["K"], cfg["T"]
+    vv = np.array(v, dtype=np.float64).reshape(T, 2).copy()
+    stats = np.zeros(4)
+    u = np.zeros((K, T, 2)) if want_traces else None
+    mom = np.zeros((K, T + 1, 9)) if want_traces else None
+    S = np.zeros(K)
+    S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
+    if nthreads is None:
+        nthreads = min(8, os.cpu_count() or 1)
+    rc = lib().orc_solve(C.byref(p), int(s), np.ascontiguousarray(x0, dtype=np.float64),
+                         _ptr(S0), vv, _ptr(u), _ptr(mom), _ptr(S), stats, int(nthreads))
+    return {"rc": rc, "v": vv, "u": u, "mom": mom, "S": S, "stats": stats}
+
+
+def step_shift(v):
+    vv = np.array(v, dtype=np.float64)
+    lib().orc_step_shift(int(vv.shape[0]), vv)
+    return vv

@@ -1,0 +1,106 @@
+/*
+ * bss_oracle.h -- plain FP64 CPU oracle for belief-space stochastic MPPI (BSS-MPPI).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct reference that the
+ * GPU path is checked against.  Only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it; the product path never calls it and shares no code with it.
+ *
+ * Everything is double precision.  Paper references are to "Chance-Constrained
+ * Information-Theoretic Stochastic MPC with Safety Shielding" (Yin, Tsiotras, Berntorp,
+ * arXiv 2408.00494): eq. numbers follow the order of the paper's displayed equations,
+ * Alg. 1 is the BSS-MPPI algorithm and Alg. 2 the Monte-Carlo mean/covariance propagation.
+ */
+#ifndef BSS_ORACLE_H
+#define BSS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Problem description.  Field meanings:
+ *  car (6 states X, Y, psi, vx, vy, r; 2 controls steer [rad], accel [m/s^2]):
+ *    m [kg], Iz [kg m^2], lf, lr [m], Cf, Cr [N/rad], mu, g, v_min [m/s] (slip-angle floor), dt [s]
+ *  steer_max, accel_max: symmetric control box
+ *  sigma_eps: control-noise std (u ~ N(v, Sigma_eps), Sigma_eps diagonal)
+ *  sigma_w:   per-step disturbance std on (vx, vy, r)
+ *  K control samples, M disturbance particles per sample, T horizon steps
+ *  delta: per-wall violation probability; gamma: linear class-kappa rate (beta in the paper's
+ *    linear DCBF condition); backoff: 0 Gaussian nu = sqrt(2) erfinv(1-2 delta), 1 Cantelli
+ *  lambda: MPPI temperature; gamma_u: control-cost weight of the trajectory cost
+ *  v_goal, q_*: tracking weights; C_cbf: safety-violation weight C; C_obs: collision penalty;
+ *  phi_scale: terminal cost = phi_scale * running cost
+ *  ell_a, ell_b: centerline ellipse semi-axes [m]; half_width: w_T [m]
+ *  shield_iters, shield_gmin, shield_fd: shield repair (0 iterations = no repair)
+ *  seed: Philox key
+ *  model: 0 = car with explicit-midpoint RK2, 1 = linear test model x+ = A x + B u (+ noise)
+ */
+typedef struct orc_params {
+    double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
+    double steer_max, accel_max;
+    double sigma_eps[2];
+    double sigma_w[3];
+    int32_t K, M, T;
+    double delta, gamma;
+    int32_t backoff;
+    double lambda, gamma_u, v_goal, q_vx, q_vy, q_r, q_ey, q_epsi, C_cbf, C_obs, phi_scale;
+    double ell_a, ell_b, half_width;
+    int32_t shield_iters;
+    double shield_gmin, shield_fd;
+    uint64_t seed;
+    int32_t model;
+    double lin_A[36];
+    double lin_B[12];
+} orc_params;
+
+/* Layout of one moment record (9 doubles): mean X, Y, psi, vx, vy, r, then the position
+ * covariance Sxx, Sxy, Syy.  Only the position block of the covariance enters the belief
+ * heuristic, so only it is kept (the paper notes a reduced covariance may suffice). */
+#define ORC_NMOM 9
+
+/* ---- random numbers: Philox4x32-10 (Salmon et al., SC'11) and Box-Muller --------------- */
+void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_uniform(uint32_t r);
+void   orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
+
+/* ---- back-off coefficient (Remark 1) ---------------------------------------------------- */
+double orc_backoff(double delta, int32_t backoff);
+
+/* ---- dynamics ----------------------------------------------------------------------------- */
+void orc_car_deriv(const orc_params* p, const double x[6], const double u[2], double dx[6]);
+void orc_model_step(const orc_params* p, const double x[6], const double u[2], double xn[6]);
+
+/* ---- track geometry and belief heuristic ------------------------------------------------ */
+void   orc_ellipse_sdf(double a, double b, double X, double Y, double* sd, double n[2]);
+double orc_barrier(const orc_params* p, double nu, const double mom[9]);
+double orc_stage_cost(const orc_params* p, const double mom[9]);
+
+/* ---- Monte-Carlo moments (Alg. 2) --------------------------------------------------------- */
+void orc_moments(const double* particles, int32_t M, double out[9]);
+
+/* ---- shield repair of one control ------------------------------------------------------- */
+void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[2]);
+
+/* ---- one sample's rollout and its cost ---------------------------------------------------- */
+double orc_score(const orc_params* p, double nu, const double* mom, const double* u,
+                 const double* v);
+double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const double x0[6],
+                   const double* Sigma0, const double* L0, const double* v, double* u_out,
+                   double* mom_out);
+
+/* ---- MPPI update (eqs. 6-7) ---------------------------------------------------------------- */
+int32_t orc_update(const orc_params* p, const double* S, const double* u, double* v,
+                   double stats[4]);
+
+/* ---- one full solve -------------------------------------------------------------------------- */
+int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
+                  double* v, double* u_out, double* mom_out, double* S_out, double stats[4],
+                  int32_t nthreads);
+
+void orc_step_shift(int32_t T, double* v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,149 @@
+"""Seeded synthetic workloads (problem descriptions and start states).
+
+This module only generates inputs: parameter sets, start poses on the synthetic elliptical track,
+warm-start sequences and the per-instance draws of the batched and serving workloads.  It holds
+none of the method's arithmetic, and both the GPU path and the oracle take their inputs from it.
+
+The paper's experiments use the AutoRally track and simulator, which are not available; a
+synthetic ellipse track (centerline semi-axes a x b, constant half-width w_T) stands in for them,
+with the paper's goal speed (6 m/s), lateral-deviation weight (0.1) and half-width (2 m).
+"""
+import math
+
+import numpy as np
+
+# Problem description shared by both implementations.  Car data beyond the mass and the tire
+# stiffness are not given anywhere, so the remaining values are stated choices.
+_DEFAULTS = dict(
+    # single-track car with linear tires
+    m=1500.0, Iz=2500.0, lf=1.2, lr=1.6, Cf=5.0e4, Cr=5.0e4, mu=1.0, g=9.81, v_min=3.0,
+    dt=0.05,
+    # control box and noise
+    steer_max=0.4, accel_max=4.0,
+    sigma_eps=[0.1, 1.0],
+    sigma_w=[0.1, 0.1, 0.05],
+    # sizes
+    K=256, M=16, T=30,
+    # chance constraint and DCBF
+    delta=0.05, gamma=0.2, backoff=0,
+    # MPPI and costs
+    **{"lambda": 1.0},
+    gamma_u=1.0, v_goal=6.0, q_vx=1.0, q_vy=0.0, q_r=0.0, q_ey=0.1, q_epsi=1.0,
+    C_cbf=100.0, C_obs=1000.0, phi_scale=1.0,
+    # track
+    ell_a=30.0, ell_b=20.0, half_width=2.0,
+    # shield repair (0 iterations = off)
+    shield_iters=0, shield_gmin=1.0e-6, shield_fd=1.0e-4,
+    # random numbers and model selector (0 = car)
+    seed=1, model=0,
+)
+
+
+def default_problem(**overrides) -> dict:
+    """The small single-solve problem (K=256, M=16, T=30) with optional overrides."""
+    p = {k: (list(v) if isinstance(v, list) else v) for k, v in _DEFAULTS.items()}
+    for k, v in overrides.items():
+        if k not in p:
+            raise KeyError(f"unknown problem key {k!r}")
+        p[k] = v
+    return p
+
+
+# ------------------------------------------------------------------------------------------------
+# start poses on the ellipse track
+# ------------------------------------------------------------------------------------------------
+def _arclength_table(a: float, b: float, n: int = 4096):
+    """Cumulative arc length of (a cos th, b sin th) at n+1 equally spaced th in [0, 2 pi]."""
+    th = np.linspace(0.0, 2.0 * math.pi, n + 1)
+    speed = np.hypot(a * np.sin(th), b * np.cos(th))
+    seg = 0.5 * (speed[1:] + speed[:-1]) * (th[1] - th[0])
+    return th, np.concatenate([[0.0], np.cumsum(seg)])
+
+
+def pose_on_centerline(a: float, b: float, theta: float, vx: float = 5.0) -> np.ndarray:
+    """State [X, Y, psi, vx, vy, r] on the centerline at parameter theta, heading along the
+    counter-clockwise tangent."""
+    X, Y = a * math.cos(theta), b * math.sin(theta)
+    psi = math.atan2(b * math.cos(theta), -a * math.sin(theta))
+    return np.array([X, Y, psi, vx, 0.0, 0.0])
+
+
+def random_start(a: float, b: float, rng: np.random.Generator, vx: float = 5.0) -> np.ndarray:
+    """Start pose with arc length uniform on [0, perimeter) (4096-point arc-length table)."""
+    th, cum = _arclength_table(a, b)
+    s = rng.uniform(0.0, cum[-1])
+    theta = float(np.interp(s, cum, th))
+    return pose_on_centerline(a, b, theta, vx)
+
+
+# ------------------------------------------------------------------------------------------------
+# the five workloads
+# ------------------------------------------------------------------------------------------------
+def config_small():
+    """Plain solve, K=256, M=16, T=30, seed 1; start at (30, 0) heading +Y at 5 m/s, v = 0."""
+    prob = default_problem(K=256, M=16, T=30, seed=1)
+    x0 = pose_on_centerline(prob["ell_a"], prob["ell_b"], 0.0, 5.0)
+    v = np.zeros((prob["T"], 2))
+    return prob, x0, v
+
+
+def config_paper_scale(seed: int = 2):
+    """Paper-scale solve: K=4096, M=64, T=50, disturbance std x2, start uniform along the track."""
+    base = default_problem()
+    prob = default_problem(K=4096, M=64, T=50, seed=seed,
+                           sigma_w=[2.0 * s for s in base["sigma_w"]])
+    rng = np.random.default_rng(seed)
+    x0 = random_start(prob["ell_a"], prob["ell_b"], rng)
+    v = np.zeros((prob["T"], 2))
+    return prob, x0, v
+
+
+def config_shielded(delta: float = 0.05, gamma: float = 0.1, seed: int = 3000):
+    """Shielded solve: the paper-scale problem with K=8192, M=128, T=60 and the repair on."""
+    base = default_problem()
+    prob = default_problem(K=8192, M=128, T=60, seed=seed, delta=delta, gamma=gamma,
+                           sigma_w=[2.0 * s for s in base["sigma_w"]], shield_iters=2)
+    rng = np.random.default_rng(seed)
+    x0 = random_start(prob["ell_a"], prob["ell_b"], rng)
+    v = np.zeros((prob["T"], 2))
+    return prob, x0, v
+
+
+def config_batch(n: int = 64, seed: int = 4):
+    """64 independent instances with K in {512..8192}, M in {16..256}, T uniform in [20, 80],
+    ellipse semi-axes uniform 15-50 m, half-width 1.5-3 m, disturbance std x U[0.5, 3]."""
+    rng = np.random.default_rng(seed)
+    base = default_problem()
+    out = []
+    for i in range(n):
+        K = int(rng.choice([512, 1024, 2048, 4096, 8192]))
+        M = int(rng.choice([16, 32, 64, 128, 256]))
+        T = int(rng.integers(20, 81))
+        a = float(rng.uniform(15.0, 50.0))
+        b = float(rng.uniform(15.0, 50.0))
+        wT = float(rng.uniform(1.5, 3.0))
+        mult = float(rng.uniform(0.5, 3.0))
+        prob = default_problem(K=K, M=M, T=T, seed=seed * 1000 + i, ell_a=a, ell_b=b,
+                               half_width=wT, sigma_w=[mult * s for s in base["sigma_w"]])
+        x0 = random_start(a, b, rng)
+        out.append((prob, x0, np.zeros((T, 2))))
+    return out
+
+
+def serving_requests(n_vehicles: int = 256, duration_s: float = 60.0, rate_hz: float = 20.0,
+                     seed: int = 5):
+    """Poisson request trace: per vehicle exponential inter-arrival times with mean 1/rate_hz.
+    Each request draws K ~ U[1024, 8192], M ~ U[32, 128], delta ~ U[0.01, 0.1]; T = 50.
+    Returns a list of (arrival_s, vehicle, K, M, delta) sorted by arrival time."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for veh in range(n_vehicles):
+        t = rng.exponential(1.0 / rate_hz)
+        while t < duration_s:
+            K = int(rng.integers(1024, 8193))
+            M = int(rng.integers(32, 129))
+            delta = float(rng.uniform(0.01, 0.1))
+            reqs.append((t, veh, K, M, delta))
+            t += rng.exponential(1.0 / rate_hz)
+    reqs.sort(key=lambda r: r[0])
+    return reqs
