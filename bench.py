@@ -1,0 +1,165 @@
+"""Throughput benchmark of the BSS-MPPI hot path on one MI355X.
+
+A step is one receding-horizon control period of the paper-scale workload: one full solve
+(rollout + scoring + log-sum-exp update, K=4096 samples x M=64 particles x T=50 steps) from a
+device-resident state estimate, followed by the warm-start shift.  The value is rollout-steps per
+second (K*M*T per solve) over the timed steps.  Also reported:
+  * roofline of the rollout kernel (the dominant kernel) against the VALU issue rate, with its
+    average launch time measured by HIP events on the solve stream;
+  * the FP64 CPU oracle timed on the host on the same workload (cpu_baseline);
+  * plain synchronous solve latency (p50/p99) from host inputs.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 10]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Minimal VALU issue slots one rollout-step (one particle advanced one step) needs, counted from
+# the operations of the method (see the roofline section of the design notes): simple 32-bit and
+# 64-bit float/integer operations cost 1 slot, transcendental and wide-multiply instructions,
+# which issue at a quarter of the rate, cost 4.
+SLOTS_PER_ROLLOUT_STEP = 303
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 3.93e13 lane-slots/s
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# FP32 FLOPs of the particle dynamics per rollout-step (FMA = 2), and MI355X's FP32 vector peak
+FP32_FLOP_PER_ROLLOUT_STEP = 198
+FP32_PEAK = 157.3e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--latency-solves", type=int, default=50)
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with the rollout kernel's measured HBM bytes per launch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def cpu_baseline(prob, x0, v, seconds):
+    """The FP64 oracle (as it stands) on the same workload, on the host's cores."""
+    import oracle
+    nthreads = min(16, os.cpu_count() or 1)
+    rs = prob["K"] * prob["M"] * prob["T"]
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.solve(prob, n, x0, v, want_traces=False, nthreads=nthreads)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 50:
+            break
+    return {"value": rs * n / el, "unit": "rollout-steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} full solves of the same workload (K={prob['K']}, M={prob['M']}, "
+                      f"T={prob['T']}) in {el:.1f} s, split over K across {nthreads} threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve does not "
+              "span GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2408_00494_amd as bss
+    from paper_2408_00494_amd import workloads as W
+
+    if args.calibrate_copy:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n}))
+        return
+
+    prob, x0, v = W.config_paper_scale()
+    K, M, T = prob["K"], prob["M"], prob["T"]
+    rs_per_solve = K * M * T
+    stream = torch.cuda.current_stream()
+    solver = bss.Solver(prob, lanes=args.lanes)
+    x0_dev = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
+
+    for _ in range(args.warmup):
+        solver.solve_async(x0_dev)
+        solver.step_shift()
+    torch.cuda.synchronize()
+    solver.timing(True)
+    solver.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve_async(x0_dev)
+        solver.step_shift()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms_total, n_meas = solver.timing_read()
+    solver.timing(False)
+    info = solver.info()
+    stats = solver.buffers()["stats"].cpu().numpy()
+    assert stats[4] == 0.0, "solve reported a numeric failure"
+
+    value = rs_per_solve * args.steps / elapsed
+    kernel_ms = kernel_ms_total / max(n_meas, 1)
+    slots = SLOTS_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3)
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get("rollout_bytes_per_launch")
+
+    # plain synchronous solves from host inputs (latency of one control period)
+    lat = []
+    for i in range(args.latency_solves):
+        t1 = time.perf_counter()
+        solver.solve(x0)
+        lat.append((time.perf_counter() - t1) * 1e3)
+    solver.close()
+
+    out = {
+        "metric": "rollout-steps/s (K·M·T)",
+        "value": value,
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale single solve: K=4096 samples, M=64 particles, "
+                               "T=50 steps, disturbance std x2, seeded start on the 30x20 m "
+                               "ellipse track",
+                   "K": K, "M": M, "T": T, "lanes": info["lanes"], "ppl": info["ppl"]},
+        "roofline": {"bound": "alu", "achieved": slots / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                     "unit": "Tslot/s", "frac": slots / VALU_PEAK_SLOTS, "traffic": traffic,
+                     "kernel": "rollout_kernel", "kernel_ms": kernel_ms,
+                     "fp32_tflops": FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3) / 1e12,
+                     "fp32_frac_of_157": FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3) / FP32_PEAK},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mode": "plain synchronous solve from host inputs"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, x0, v, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * bssmppi.h -- C ABI of libbssmppi: belief-space stochastic MPPI (BSS-MPPI) on AMD MI355X (gfx950).
+ *
+ * Method: Yin, Tsiotras, Berntorp, "Chance-Constrained Information-Theoretic Stochastic MPC with
+ * Safety Shielding" (arXiv 2408.00494).  One solve is one pass of the body of the paper's Alg. 1:
+ * K control sequences u_k ~ N(v, Sigma_eps) are sampled (clipped to the control box, optionally
+ * shield-repaired); each is pushed through M Monte-Carlo disturbance particles of the dynamics
+ * over T steps (Alg. 2, persistent particles); the per-step particle mean and position covariance
+ * (the belief z = [xbar; Sigma]) are scored with the tracking cost, the collision indicator and the
+ * safety-violation cost C_safe of the belief-space DCBF (eqs. 11, 13, 24-26, 33); the K costs are
+ * folded into the MPPI update v+ = sum_k w_k u_k / sum_k w_k, w_k = exp(-(S_k - min S)/lambda)
+ * (eqs. 6-8).  The dynamics is a single-track car with linear tires; the track is a band of
+ * half-width w_T around an ellipse.
+ *
+ * Precision: particles are propagated in single precision; moments, scores, the shield repair and
+ * the update are accumulated in double precision on the device.
+ *
+ * Conventions for every call:
+ *   - Return values are bss_status codes; on failure a message is available from
+ *     bss_last_error() (thread-local, valid until the next failing call on that thread).
+ *   - The library never aborts and never prints.
+ *   - "device" pointers are HIP device addresses on the context's device; "host" pointers are
+ *     ordinary host memory.  Ownership stays with the caller unless stated otherwise.
+ *   - A context is not thread-safe; distinct contexts may be used from different threads.
+ */
+#ifndef BSSMPPI_H
+#define BSSMPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bss_status {
+    BSS_OK = 0,
+    BSS_E_INVAL = 1,    /* invalid argument or parameter set                          */
+    BSS_E_NOMEM = 2,    /* device or host allocation failed                           */
+    BSS_E_DEVICE = 3,   /* a HIP runtime call or kernel launch failed                 */
+    BSS_E_STATE = 4,    /* call not valid in the context's current state              */
+    BSS_E_NUMERIC = 5   /* no sample had a finite cost; the mean controls were kept   */
+} bss_status;
+
+/* Problem description (copied at bss_create; the caller keeps ownership).
+ * Dynamics (single-track car, x = [X, Y, psi, vx, vy, r], u = [steer rad, accel m/s^2]):
+ *   slip angles a_f = steer - atan((vy + lf r)/max(vx, v_min)), a_r = -atan((vy - lr r)/max(vx, v_min));
+ *   lateral forces F = C a clipped to +-mu m g (axle load share); explicit midpoint (RK2) step of
+ *   length dt with zero-order hold on u; the disturbance w ~ N(0, diag(sigma_w^2)) is added to
+ *   (vx, vy, r) after each step (the disturbed system of eq. 5b).
+ * Sampling: u = clip(v + eps, +-[steer_max, accel_max]), eps ~ N(0, diag(sigma_eps^2)).
+ * Chance constraint and DCBF: per-wall violation probability delta gives the back-off
+ *   nu = sqrt(2) erfinv(1 - 2 delta) (backoff = 0) or sqrt((1-delta)/delta) (backoff = 1,
+ *   Remark 1); h = max(w_T - nu sigma_y, 0)^2 - e_y^2 (eq. 33) on the mean lateral deviation e_y and
+ *   its std sigma_y; C_safe = C_cbf max(-h_t + (1 - gamma) h_{t-1}, 0) (eqs. 24-25).
+ * Costs: q = q_vx (vx - v_goal)^2 + q_vy vy^2 + q_r r^2 + q_ey e_y^2 + q_epsi 2 (1 - cos e_psi)
+ *   + C_obs [|e_y| >= w_T] on the mean state (eqs. 27-28); phi = phi_scale q; control cost
+ *   gamma_u v^T Sigma_eps^-1 u (eq. 8).
+ * Shield repair: shield_iters damped Gauss-Newton steps
+ *   u <- clip(u - max(r, 0) g / (|g|^2 + shield_gmin^2)) on the one-step DCBF residual
+ *   r(u) = -h(f(xbar_t, u); sigma_t) + (1 - gamma) h_t of each sampled control, g = dr/du by
+ *   central differences of step shield_fd; 0 iterations disables it.
+ * Launch shape: lanes = lanes per sample (8, 16, 32 or 64), 0 = choose automatically.
+ */
+typedef struct bss_params {
+    double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
+    double steer_max, accel_max;
+    double sigma_eps[2];
+    double sigma_w[3];
+    int32_t K, M, T;
+    double delta, gamma;
+    int32_t backoff;
+    double lambda, gamma_u, v_goal, q_vx, q_vy, q_r, q_ey, q_epsi, C_cbf, C_obs, phi_scale;
+    double ell_a, ell_b, half_width;
+    int32_t shield_iters;
+    double shield_gmin, shield_fd;
+    uint64_t seed;
+    int32_t lanes;
+} bss_params;
+
+/* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a
+ * device pointer of at least `bytes` bytes (256-byte aligned) or NULL; release frees it. */
+typedef struct bss_allocator {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*release)(void* ptr, void* user);
+    void* user;
+} bss_allocator;
+
+/* Device buffers owned by a context (valid until bss_destroy).  Layouts are row-major:
+ *   v      [T][2]       double  mean control sequence (warm start; updated by each solve)
+ *   u      [K][T][2]    float   sampled (clipped, repaired) controls of the last solve
+ *   mom    [K][T+1][9]  double  belief per sample and step: mean X, Y, psi, vx, vy, r, then
+ *                               Sigma_XX, Sigma_XY, Sigma_YY; record 0 is the given estimate
+ *   S      [K]          double  trajectory costs of the last solve
+ *   stats  [8]          double  S_min, Z = sum_k w_k, ESS = Z^2/sum w^2, #finite costs,
+ *                               status (0 ok, 5 numeric), v+_0 (steer, accel), unused
+ *   x0     [6]          double  staging slot for the state estimate
+ *   Sigma0 [36]         double  staging slot for the state-estimate covariance            */
+typedef struct bss_buffers {
+    double* v;
+    float* u;
+    double* mom;
+    double* S;
+    double* stats;
+    double* x0;
+    double* Sigma0;
+} bss_buffers;
+
+/* Result summary of a solve (host). */
+typedef struct bss_info {
+    double S_min, Z, ess;
+    int32_t n_finite;
+    int32_t lanes, ppl;       /* launch shape used: lanes per sample, particles per lane */
+} bss_info;
+
+typedef struct bss_ctx bss_ctx;
+
+/* Fill *p with the reference problem: the car and track of the small single-solve workload
+ * (K=256, M=16, T=30; 30 m x 20 m ellipse, w_T = 2 m; delta = 0.05; gamma = 0.2; lambda = 1). */
+void bss_params_default(bss_params* p);
+
+/* Check a parameter set without touching the GPU.  BSS_E_INVAL with a message if any field is
+ * out of range (sizes >= 1, K <= 2^20, T <= 256, M <= 512, 0 < delta < 0.5, 0 < gamma <= 1, lambda > 0,
+ * dt > 0, finite non-negative noise std, and a track whose ellipse keeps a unique nearest point
+ * inside the band: min(a,b)^2 / max(a,b) > half_width). */
+bss_status bss_validate(const bss_params* p);
+
+/* Back-off coefficient nu for the parameter set (host computation, Remark 1). */
+bss_status bss_backoff(const bss_params* p, double* nu_out);
+
+/* Create a context on the current HIP device.  `alloc` may be NULL (hipMalloc is used); `stream`
+ * is a hipStream_t (NULL = the null stream) on which every later call of this context enqueues
+ * its work.  The mean control sequence starts at zero and the solve index at 0.
+ * Errors: BSS_E_INVAL (parameters, out == NULL), BSS_E_NOMEM, BSS_E_DEVICE. */
+bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* stream,
+                      bss_ctx** out);
+
+/* Change the stream of a context (subsequent calls enqueue there). */
+bss_status bss_set_stream(bss_ctx* c, void* stream);
+
+/* One solve from host inputs, synchronous: x0[6] the state estimate, Sigma0 a 6x6 row-major
+ * covariance or NULL (known state), u0_out[2] receives the command v+_0, info may be NULL.
+ * Updates the mean control sequence in place (Alg. 1: v <- v_safe) and advances the solve index.
+ * Errors: BSS_E_INVAL (non-finite x0 or Sigma0, NULL pointers), BSS_E_NUMERIC (every cost was
+ * non-finite; v unchanged), BSS_E_DEVICE. */
+bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, double u0_out[2],
+                     bss_info* info);
+
+/* One solve from device-resident inputs, asynchronous on the context's stream: x0_dev [6] and
+ * Sigma0_dev [36] (or NULL) are device pointers that must stay valid until the work completes.
+ * Results land in the context's buffers (bss_get_buffers); the status word stats[4] is 5 when
+ * every cost was non-finite (then v is unchanged).  Errors: BSS_E_INVAL, BSS_E_DEVICE. */
+bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma0_dev);
+
+/* Receding-horizon warm start, enqueued on the stream: v_t <- v_{t+1} for t < T-1; v_{T-1} keeps
+ * its value. */
+bss_status bss_step_shift(bss_ctx* c);
+
+/* Device buffers of the context (see bss_buffers). */
+bss_status bss_get_buffers(const bss_ctx* c, bss_buffers* out);
+
+/* Copy the mean control sequence [T][2] to / from host memory (synchronous). */
+bss_status bss_get_controls(bss_ctx* c, double* v_host);
+bss_status bss_set_controls(bss_ctx* c, const double* v_host);
+
+/* Solve index used for the random-number counters of the next solve (resuming a context at a
+ * given index reproduces its noise exactly). */
+bss_status bss_set_solve_index(bss_ctx* c, uint32_t s);
+bss_status bss_get_solve_index(const bss_ctx* c, uint32_t* s);
+
+/* Synchronise the stream and read the stats of the last solve into *info. */
+bss_status bss_get_info(bss_ctx* c, bss_info* info);
+
+/* Kernel timing: when enabled, HIP events bracket the rollout kernel of every solve on the
+ * context's stream.  bss_timing_read synchronises, returns the summed rollout-kernel time in ms
+ * and the number of solves measured since the last read, and resets the accumulators. */
+bss_status bss_timing_enable(bss_ctx* c, int32_t enable);
+bss_status bss_timing_read(bss_ctx* c, double* rollout_ms_total, int32_t* count);
+
+/* Force the launch shape (lanes per sample 8/16/32/64; 0 restores the automatic choice). */
+bss_status bss_set_lanes(bss_ctx* c, int32_t lanes);
+
+/* Destroy a context and free its buffers (NULL is accepted). */
+void bss_destroy(bss_ctx* c);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bss_last_error(void);
+
+/* ---- stand-alone device kernels of the solve, for staged checks (all device pointers, work
+ *      enqueued on `stream`, n >= 0 elements) ------------------------------------------------ */
+
+/* Philox4x32-10 (Salmon et al., SC'11) of n counters ctr[n][4] under key (lo32 seed, hi32 seed)
+ * into out[n][4]. */
+bss_status bss_dev_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
+                          void* stream);
+/* Four Box-Muller normals per counter: z[n][4] (single precision) from the block's words
+ * (r0, r1) and (r2, r3) with uniforms ((r >> 9) + 1/2) 2^-23. */
+bss_status bss_dev_normals(uint64_t seed, const uint32_t* ctr, float* z, int64_t n, void* stream);
+/* One noise-free single-precision RK2 step of the car: x[n][6], u[n][2] -> xn[n][6]. */
+bss_status bss_dev_model_step(const bss_params* p, const float* x, const float* u, float* xn,
+                              int64_t n, void* stream);
+/* Signed distance to the centerline ellipse and its outward normal, double precision:
+ * pts[n][2] -> out[n][3] = (e_y, n_x, n_y). */
+bss_status bss_dev_sdf(double a, double b, const double* pts, double* out, int64_t n,
+                       void* stream);
+/* Trajectory costs from given beliefs and controls (the scoring stage alone):
+ * mom[K][T+1][9], u[K][T][2] (float), v[T][2] -> S[K]. */
+bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u, const double* v,
+                         double* S, void* stream);
+/* MPPI update from given costs and controls: S[K], u[K][T][2] (float); v[T][2] updated in place,
+ * stats[8] as in bss_buffers.  workspace: at least bss_dev_update_workspace(K, T) bytes of
+ * device memory whose first 4 bytes are zero (they are zero again afterwards). */
+size_t bss_dev_update_workspace(int32_t K, int32_t T);
+bss_status bss_dev_update(const bss_params* p, const double* S, const float* u, double* v,
+                          double* stats, void* workspace, void* stream);
+/* Shield repair of n controls from given beliefs: mom[n][9], u_in[n][2] -> u_out[n][2]
+ * (double precision). */
+bss_status bss_dev_repair(const bss_params* p, const double* mom, const double* u_in,
+                          double* u_out, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -66,6 +66,10 @@ def _load():
     P = C.POINTER(OrcParams)
     lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     lib.orc_philox4x32_10.restype = None
+    lib.orc_philox_many.argtypes = [_u32p, _u32p, _u32p, C.c_int64]
+    lib.orc_philox_many.restype = None
+    lib.orc_normals_many.argtypes = [C.c_uint64, _u32p, _f64p, C.c_int64]
+    lib.orc_normals_many.restype = None
     lib.orc_uniform.argtypes = [C.c_uint32]
     lib.orc_uniform.restype = C.c_double
     lib.orc_normals.argtypes = [C.c_uint64, _u32p, _f64p]
@@ -92,6 +96,9 @@ def _load():
     lib.orc_rollout.argtypes = [P, C.c_double, C.c_uint32, C.c_int32, _f64p, C.c_void_p,
                                 C.c_void_p, _f64p, _f64p, _f64p]
     lib.orc_rollout.restype = C.c_double
+    lib.orc_propagate.argtypes = [P, C.c_uint32, C.c_int32, _f64p, C.c_void_p, C.c_void_p,
+                                  _f64p, _f64p]
+    lib.orc_propagate.restype = None
     lib.orc_update.argtypes = [P, _f64p, _f64p, _f64p, _f64p]
     lib.orc_update.restype = C.c_int32
     lib.orc_solve.argtypes = [P, C.c_uint32, _f64p, C.c_void_p, _f64p, C.c_void_p, C.c_void_p,
@@ -122,6 +129,23 @@ def philox(ctr, key):
     lib().orc_philox4x32_10(np.ascontiguousarray(ctr, dtype=np.uint32),
                             np.ascontiguousarray(key, dtype=np.uint32), out)
     return out
+
+
+def philox_many(ctr, seed):
+    """Philox4x32-10 of counters ctr [n, 4] under the key (lo32 seed, hi32 seed)."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    out = np.zeros_like(ctr)
+    key = np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint32)
+    lib().orc_philox_many(ctr, key, out, int(ctr.shape[0]))
+    return out
+
+
+def normals_many(seed, ctr):
+    """Four Box-Muller normals per counter: [n, 4] float64."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    z = np.zeros(ctr.shape, dtype=np.float64)
+    lib().orc_normals_many(int(seed), ctr, z, int(ctr.shape[0]))
+    return z
 
 
 def normals(seed, ctr):
@@ -210,6 +234,20 @@ def rollout(cfg, s, k, x0, v, Sigma0=None):
                            _ptr(None if L0 is None else np.ascontiguousarray(L0)),
                            np.ascontiguousarray(v, dtype=np.float64), u, mom)
     return Sk, u, mom
+
+
+def propagate(cfg, s, k, x0, u, Sigma0=None):
+    """Belief trajectory [T+1][9] of sample k under the given controls u [T][2]."""
+    p = make_params(cfg)
+    T = cfg["T"]
+    mom = np.zeros((T + 1, 9))
+    S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
+    L0 = None
+    if S0 is not None and np.any(S0 != 0):
+        L0 = np.ascontiguousarray(np.linalg.cholesky(S0))
+    lib().orc_propagate(C.byref(p), int(s), int(k), np.ascontiguousarray(x0, dtype=np.float64),
+                        _ptr(S0), _ptr(L0), np.ascontiguousarray(u, dtype=np.float64), mom)
+    return mom
 
 
 def update(cfg, S, u, v):

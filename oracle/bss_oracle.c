@@ -76,6 +76,17 @@ void orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4])
     z[3] = rho2 * sin(2.0 * M_PI * u3);
 }
 
+/* Bulk helpers for tests: n counters ctr[n][4] -> out[n][4] words / normals. */
+void orc_philox_many(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(&ctr[4 * i], key, &out[4 * i]);
+}
+
+void orc_normals_many(uint64_t seed, const uint32_t* ctr, double* z, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) orc_normals(seed, &ctr[4 * i], &z[4 * i]);
+}
+
 /* Counter layout (the random-number contract shared by both implementations):
  *   word0 = time step t (or the block index for the initial spread), word1 = particle m,
  *   word2 = sample k, word3 = (stream tag << 28) | (solve index & 0x0FFFFFFF).
@@ -313,11 +324,13 @@ static double repair_residual(const orc_params* p, double nu, const double mom_t
 }
 
 /* Shield repair (the paper describes the S-MPPI repair only as gradient-based minimisation of
- * the DCBF violation and leaves it out of Alg. 1; this is the stated reading): up to
- * shield_iters projected Gauss-Newton steps toward r = 0,
- *     u_c = clip(u - r(u) g / max(|g|^2, gmin^2)),   g = dr/du by central differences (step
- * shield_fd), each accepted only if it lowers r (otherwise the repair stops), and no step once
- * r <= 0.  The repaired control therefore never has a larger residual than the sampled one. */
+ * the DCBF violation and leaves it out of Alg. 1; this is the stated reading): shield_iters
+ * damped Gauss-Newton steps toward r = 0,
+ *     u <- clip(u - max(r(u), 0) g / (|g|^2 + gmin^2)),   g = dr/du by central differences
+ * (step shield_fd).  A step is zero once r <= 0, so a control that already satisfies the
+ * condition is returned unchanged; the damping gmin bounds the step where the control has little
+ * authority over the next belief, and the map from (u, belief) to the repaired control is
+ * continuous. */
 void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[2])
 {
     if (p->shield_iters <= 0) return;
@@ -327,8 +340,8 @@ void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[
     double sigma_t = sqrt(var > 0.0 ? var : 0.0);
     double h_t = orc_barrier(p, nu, mom_t);
     double fd = p->shield_fd;
-    double r0 = repair_residual(p, nu, mom_t, sigma_t, h_t, u);
     for (int it = 0; it < p->shield_iters; ++it) {
+        double r0 = repair_residual(p, nu, mom_t, sigma_t, h_t, u);
         if (!(r0 > 0.0)) break;
         double g[2];
         for (int j = 0; j < 2; ++j) {
@@ -338,17 +351,9 @@ void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[
             g[j] = (repair_residual(p, nu, mom_t, sigma_t, h_t, up) -
                     repair_residual(p, nu, mom_t, sigma_t, h_t, um)) / (2.0 * fd);
         }
-        double gg = g[0] * g[0] + g[1] * g[1];
-        double gmin2 = p->shield_gmin * p->shield_gmin;
-        if (gg < gmin2) gg = gmin2;
-        double cand[2];
-        cand[0] = clampd(u[0] - r0 * g[0] / gg, -p->steer_max, p->steer_max);
-        cand[1] = clampd(u[1] - r0 * g[1] / gg, -p->accel_max, p->accel_max);
-        double rc = repair_residual(p, nu, mom_t, sigma_t, h_t, cand);
-        if (!(rc < r0)) break;
-        u[0] = cand[0];
-        u[1] = cand[1];
-        r0 = rc;
+        double denom = g[0] * g[0] + g[1] * g[1] + p->shield_gmin * p->shield_gmin;
+        u[0] = clampd(u[0] - r0 * g[0] / denom, -p->steer_max, p->steer_max);
+        u[1] = clampd(u[1] - r0 * g[1] / denom, -p->accel_max, p->accel_max);
     }
 }
 
@@ -388,20 +393,14 @@ double orc_score(const orc_params* p, double nu, const double* mom, const double
 }
 
 /* ======================================== one rollout ======================================== */
-/* Sample k of Alg. 1: draw eps_{k,t}, form u = clip(v + eps), optionally repair it, propagate the
- * M persistent particles x^n_{t+1} = f(x^n_t, u_t) + w^n_t through the model (the particle
- * recursion stated with the Monte-Carlo covariance), record the moments, and score. */
-double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const double x0[6],
-                   const double* Sigma0, const double* L0, const double* v, double* u_out,
-                   double* mom_out)
+/* Initial particles x^n_0 = xbar_0 + L_0 xi^n (tag 2) and the t = 0 belief record (the given
+ * estimate, Alg. 1 initialisation). */
+static void init_particles(const orc_params* p, uint32_t s, int32_t k, const double x0[6],
+                           const double* Sigma0, const double* L0, double* part, double* mom0)
 {
-    int M = p->M, T = p->T;
-    double* part = (double*)malloc(sizeof(double) * 6 * (size_t)M);
-    double* nxt = (double*)malloc(sizeof(double) * 6 * (size_t)M);
     uint32_t ctr[4];
     double z[4];
-
-    for (int m = 0; m < M; ++m) {
+    for (int m = 0; m < p->M; ++m) {
         double xi[6] = {0, 0, 0, 0, 0, 0};
         if (L0) {
             for (uint32_t blk = 0; blk < 2; ++blk) {
@@ -418,12 +417,45 @@ double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const 
             part[m * 6 + i] = acc;
         }
     }
-    /* moments at t = 0 are the given state estimate (Alg. 1 initialisation) */
-    for (int i = 0; i < 6; ++i) mom_out[i] = x0[i];
-    mom_out[6] = Sigma0 ? Sigma0[0] : 0.0;
-    mom_out[7] = Sigma0 ? Sigma0[1] : 0.0;
-    mom_out[8] = Sigma0 ? Sigma0[7] : 0.0;
+    for (int i = 0; i < 6; ++i) mom0[i] = x0[i];
+    mom0[6] = Sigma0 ? Sigma0[0] : 0.0;
+    mom0[7] = Sigma0 ? Sigma0[1] : 0.0;
+    mom0[8] = Sigma0 ? Sigma0[7] : 0.0;
+}
 
+/* One step of Alg. 2 with persistent particles: x^n_{t+1} = f(x^n_t, u_t) + [0,0,0, w^n_t]
+ * (w from tag 1), then the moments of the new particle set. */
+static void propagate_step(const orc_params* p, uint32_t s, int32_t k, int t, const double u[2],
+                           double* part, double* nxt, double* mom_next)
+{
+    uint32_t ctr[4];
+    double z[4];
+    int M = p->M;
+    for (int m = 0; m < M; ++m) {
+        orc_model_step(p, &part[m * 6], u, &nxt[m * 6]);
+        rng_counter((uint32_t)t, (uint32_t)m, (uint32_t)k, 1u, s, ctr);
+        orc_normals(p->seed, ctr, z);
+        nxt[m * 6 + 3] += p->sigma_w[0] * z[0];
+        nxt[m * 6 + 4] += p->sigma_w[1] * z[1];
+        nxt[m * 6 + 5] += p->sigma_w[2] * z[2];
+    }
+    memcpy(part, nxt, sizeof(double) * 6 * (size_t)M);
+    orc_moments(part, M, mom_next);
+}
+
+/* Sample k of Alg. 1: draw eps_{k,t}, form u = clip(v + eps), optionally repair it, propagate the
+ * M persistent particles x^n_{t+1} = f(x^n_t, u_t) + w^n_t through the model (the particle
+ * recursion stated with the Monte-Carlo covariance), record the moments, and score. */
+double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const double x0[6],
+                   const double* Sigma0, const double* L0, const double* v, double* u_out,
+                   double* mom_out)
+{
+    int M = p->M, T = p->T;
+    double* part = (double*)malloc(sizeof(double) * 6 * (size_t)M);
+    double* nxt = (double*)malloc(sizeof(double) * 6 * (size_t)M);
+    uint32_t ctr[4];
+    double z[4];
+    init_particles(p, s, k, x0, Sigma0, L0, part, mom_out);
     for (int t = 0; t < T; ++t) {
         rng_counter((uint32_t)t, 0u, (uint32_t)k, 0u, s, ctr);
         orc_normals(p->seed, ctr, z);
@@ -433,20 +465,26 @@ double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const 
         orc_repair(p, nu, &mom_out[(size_t)t * ORC_NMOM], u);
         u_out[t * 2 + 0] = u[0];
         u_out[t * 2 + 1] = u[1];
-        for (int m = 0; m < M; ++m) {
-            orc_model_step(p, &part[m * 6], u, &nxt[m * 6]);
-            rng_counter((uint32_t)t, (uint32_t)m, (uint32_t)k, 1u, s, ctr);
-            orc_normals(p->seed, ctr, z);
-            nxt[m * 6 + 3] += p->sigma_w[0] * z[0];
-            nxt[m * 6 + 4] += p->sigma_w[1] * z[1];
-            nxt[m * 6 + 5] += p->sigma_w[2] * z[2];
-        }
-        memcpy(part, nxt, sizeof(double) * 6 * (size_t)M);
-        orc_moments(part, M, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
+        propagate_step(p, s, k, t, u, part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
     }
     free(part);
     free(nxt);
     return orc_score(p, nu, mom_out, u_out, v);
+}
+
+/* Belief trajectory of sample k for a given control sequence u [T][2] (no sampling, no repair):
+ * the propagation half of a rollout, used to check the particle propagation on its own. */
+void orc_propagate(const orc_params* p, uint32_t s, int32_t k, const double x0[6],
+                   const double* Sigma0, const double* L0, const double* u, double* mom_out)
+{
+    int M = p->M, T = p->T;
+    double* part = (double*)malloc(sizeof(double) * 6 * (size_t)M);
+    double* nxt = (double*)malloc(sizeof(double) * 6 * (size_t)M);
+    init_particles(p, s, k, x0, Sigma0, L0, part, mom_out);
+    for (int t = 0; t < T; ++t)
+        propagate_step(p, s, k, t, &u[t * 2], part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
+    free(part);
+    free(nxt);
 }
 
 /* ======================================= MPPI update ======================================== */

@@ -32,7 +32,8 @@ extern "C" {
  *  v_goal, q_*: tracking weights; C_cbf: safety-violation weight C; C_obs: collision penalty;
  *  phi_scale: terminal cost = phi_scale * running cost
  *  ell_a, ell_b: centerline ellipse semi-axes [m]; half_width: w_T [m]
- *  shield_iters, shield_gmin, shield_fd: shield repair (0 iterations = no repair)
+ *  shield_iters, shield_gmin, shield_fd: shield repair (0 iterations = no repair), its
+ *    damping and its finite-difference step
  *  seed: Philox key
  *  model: 0 = car with explicit-midpoint RK2, 1 = linear test model x+ = A x + B u (+ noise)
  */
@@ -63,6 +64,8 @@ typedef struct orc_params {
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_uniform(uint32_t r);
 void   orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
+void   orc_philox_many(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, int64_t n);
+void   orc_normals_many(uint64_t seed, const uint32_t* ctr, double* z, int64_t n);
 
 /* ---- back-off coefficient (Remark 1) ---------------------------------------------------- */
 double orc_backoff(double delta, int32_t backoff);
@@ -88,6 +91,9 @@ double orc_score(const orc_params* p, double nu, const double* mom, const double
 double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const double x0[6],
                    const double* Sigma0, const double* L0, const double* v, double* u_out,
                    double* mom_out);
+
+void orc_propagate(const orc_params* p, uint32_t s, int32_t k, const double x0[6],
+                   const double* Sigma0, const double* L0, const double* u, double* mom_out);
 
 /* ---- MPPI update (eqs. 6-7) ---------------------------------------------------------------- */
 int32_t orc_update(const orc_params* p, const double* S, const double* u, double* v,

@@ -1,0 +1,248 @@
+"""paper_2408_00494_amd -- belief-space stochastic MPPI (BSS-MPPI) on MI355X.
+
+Python front end of libbssmppi.  PyTorch supplies device memory (through the library's allocator
+hook) and streams; the binding only marshals arguments to the C ABI, and every step of a solve
+runs in the library's HIP kernels.
+
+    from paper_2408_00494_amd import Solver, workloads
+    prob, x0, v = workloads.config_small()
+    s = Solver(prob)
+    u0, info = s.solve(x0)
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import BssError, check, params_from_problem
+
+__all__ = ["Solver", "BssError", "backoff", "validate", "dev_philox", "dev_normals",
+           "dev_model_step", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def validate(problem: dict) -> None:
+    p = params_from_problem(problem)
+    check(_lib.lib().bss_validate(C.byref(p)))
+
+
+def backoff(problem: dict) -> float:
+    p = params_from_problem(problem)
+    nu = C.c_double()
+    check(_lib.lib().bss_backoff(C.byref(p), C.byref(nu)))
+    return nu.value
+
+
+class Solver:
+    """One BSS-MPPI controller instance (a library context) on the current CUDA/HIP device.
+
+    Device buffers come from PyTorch's caching allocator; work goes on ``stream`` (default: the
+    current stream at construction)."""
+
+    def __init__(self, problem: dict, stream=None, lanes: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
+        self.problem = dict(problem)
+        self.K, self.M, self.T = int(problem["K"]), int(problem["M"]), int(problem["T"])
+        self._params = params_from_problem(dict(problem, lanes=lanes))
+        self._device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self._blocks = {}
+
+        def _alloc(nbytes, _user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self._device)
+            self._blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _release(ptr, _user):
+            self._blocks.pop(int(ptr), None)
+
+        self._alloc_cb = BssAllocator_alloc(_alloc)
+        self._release_cb = BssAllocator_release(_release)
+        self._allocator = _lib.BssAllocator(self._alloc_cb, self._release_cb, None)
+        ctx = C.c_void_p()
+        check(_lib.lib().bss_create(C.byref(self._params), C.byref(self._allocator),
+                                    _stream_ptr(self._stream), C.byref(ctx)))
+        self._ctx = ctx
+        self._views = None
+
+    # ---- lifetime -----------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _lib.lib().bss_destroy(self._ctx)
+            self._ctx = None
+            self._views = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- solves ---------------------------------------------------------------------------------
+    def solve(self, x0, Sigma0=None):
+        """Synchronous solve from host inputs.  Returns (u0 as numpy [2], info dict)."""
+        x = np.ascontiguousarray(x0, dtype=np.float64)
+        S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
+        u0 = np.zeros(2)
+        info = _lib.BssInfo()
+        dp = C.POINTER(C.c_double)
+        st = _lib.lib().bss_solve(self._ctx, x.ctypes.data_as(dp),
+                                  None if S0 is None else S0.ctypes.data_as(C.c_void_p),
+                                  u0.ctypes.data_as(dp), C.byref(info))
+        check(st)
+        return u0, _info_dict(info)
+
+    def solve_async(self, x0_dev, Sigma0_dev=None):
+        """Enqueue a solve from device tensors (float64 [6] and [6, 6] or None)."""
+        check(_lib.lib().bss_solve_async(self._ctx, _ptr(x0_dev), _ptr(Sigma0_dev)))
+
+    def step_shift(self):
+        check(_lib.lib().bss_step_shift(self._ctx))
+
+    def info(self):
+        info = _lib.BssInfo()
+        check(_lib.lib().bss_get_info(self._ctx, C.byref(info)))
+        return _info_dict(info)
+
+    # ---- state --------------------------------------------------------------------------------
+    def get_controls(self):
+        v = np.zeros((self.T, 2))
+        check(_lib.lib().bss_get_controls(self._ctx, v.ctypes.data_as(C.c_void_p)))
+        return v
+
+    def set_controls(self, v):
+        vv = np.ascontiguousarray(v, dtype=np.float64).reshape(self.T, 2)
+        check(_lib.lib().bss_set_controls(self._ctx, vv.ctypes.data_as(C.c_void_p)))
+
+    @property
+    def solve_index(self):
+        s = C.c_uint32()
+        check(_lib.lib().bss_get_solve_index(self._ctx, C.byref(s)))
+        return s.value
+
+    @solve_index.setter
+    def solve_index(self, s):
+        check(_lib.lib().bss_set_solve_index(self._ctx, int(s)))
+
+    def set_lanes(self, lanes: int):
+        check(_lib.lib().bss_set_lanes(self._ctx, int(lanes)))
+
+    def buffers(self):
+        """Torch views of the context's device buffers: v, u, mom, S, stats."""
+        if self._views is None:
+            torch = _torch()
+            b = _lib.BssBuffers()
+            check(_lib.lib().bss_get_buffers(self._ctx, C.byref(b)))
+            (base_ptr, blk), = self._blocks.items()
+            K, T = self.K, self.T
+
+            def view(ptr, nbytes, dtype, shape):
+                off = ptr - base_ptr
+                return blk[off:off + nbytes].view(dtype).reshape(shape)
+            self._views = {
+                "v": view(b.v, T * 2 * 8, torch.float64, (T, 2)),
+                "u": view(b.u, K * T * 2 * 4, torch.float32, (K, T, 2)),
+                "mom": view(b.mom, K * (T + 1) * 9 * 8, torch.float64, (K, T + 1, 9)),
+                "S": view(b.S, K * 8, torch.float64, (K,)),
+                "stats": view(b.stats, 8 * 8, torch.float64, (8,)),
+            }
+        return self._views
+
+    # ---- timing -------------------------------------------------------------------------------
+    def timing(self, enable: bool):
+        check(_lib.lib().bss_timing_enable(self._ctx, 1 if enable else 0))
+
+    def timing_read(self):
+        """(total rollout-kernel ms, number of solves) since the last read."""
+        ms = C.c_double()
+        n = C.c_int32()
+        check(_lib.lib().bss_timing_read(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+BssAllocator_alloc = _lib.BssAllocator._fields_[0][1]
+BssAllocator_release = _lib.BssAllocator._fields_[1][1]
+
+
+def _info_dict(info):
+    return {"S_min": info.S_min, "Z": info.Z, "ess": info.ess, "n_finite": info.n_finite,
+            "lanes": info.lanes, "ppl": info.ppl}
+
+
+# ---- stand-alone kernels (device tensors in/out, current stream) --------------------------------
+def dev_philox(seed: int, ctr):
+    torch = _torch()
+    out = torch.empty_like(ctr)
+    check(_lib.lib().bss_dev_philox(int(seed), _ptr(ctr), _ptr(out), ctr.shape[0], _stream_ptr()))
+    return out
+
+
+def dev_normals(seed: int, ctr):
+    torch = _torch()
+    z = torch.empty((ctr.shape[0], 4), dtype=torch.float32, device=ctr.device)
+    check(_lib.lib().bss_dev_normals(int(seed), _ptr(ctr), _ptr(z), ctr.shape[0], _stream_ptr()))
+    return z
+
+
+def dev_model_step(problem: dict, x, u):
+    torch = _torch()
+    p = params_from_problem(problem)
+    xn = torch.empty_like(x)
+    check(_lib.lib().bss_dev_model_step(C.byref(p), _ptr(x), _ptr(u), _ptr(xn), x.shape[0],
+                                        _stream_ptr()))
+    return xn
+
+
+def dev_sdf(a: float, b: float, pts):
+    torch = _torch()
+    out = torch.empty((pts.shape[0], 3), dtype=torch.float64, device=pts.device)
+    check(_lib.lib().bss_dev_sdf(float(a), float(b), _ptr(pts), _ptr(out), pts.shape[0],
+                                 _stream_ptr()))
+    return out
+
+
+def dev_score(problem: dict, mom, u, v):
+    torch = _torch()
+    p = params_from_problem(problem)
+    S = torch.empty((problem["K"],), dtype=torch.float64, device=mom.device)
+    check(_lib.lib().bss_dev_score(C.byref(p), _ptr(mom), _ptr(u), _ptr(v), _ptr(S),
+                                   _stream_ptr()))
+    return S
+
+
+def dev_update(problem: dict, S, u, v):
+    """Returns (v+, stats) from device tensors S [K] f64, u [K,T,2] f32, v [T,2] f64."""
+    torch = _torch()
+    p = params_from_problem(problem)
+    nbytes = _lib.lib().bss_dev_update_workspace(int(problem["K"]), int(problem["T"]))
+    ws = torch.zeros((nbytes,), dtype=torch.uint8, device=S.device)
+    vv = v.clone()
+    stats = torch.zeros((8,), dtype=torch.float64, device=S.device)
+    check(_lib.lib().bss_dev_update(C.byref(p), _ptr(S), _ptr(u), _ptr(vv), _ptr(stats),
+                                    _ptr(ws), _stream_ptr()))
+    return vv, stats
+
+
+def dev_repair(problem: dict, mom, u):
+    torch = _torch()
+    p = params_from_problem(problem)
+    out = torch.empty_like(u)
+    check(_lib.lib().bss_dev_repair(C.byref(p), _ptr(mom), _ptr(u), _ptr(out), u.shape[0],
+                                    _stream_ptr()))
+    return out

@@ -1,0 +1,317 @@
+// bss_device.h -- device-side building blocks of the BSS-MPPI solve (gfx950).
+//
+//  * Philox4x32-10 and Box-Muller normals (the random-number contract: counter words
+//    (t or block, particle m, sample k, (tag << 28) | solve index), key (lo32 seed, hi32 seed)).
+//  * the single-precision car vector field used by the particle integrator;
+//  * double-precision versions of the model, the track signed distance, the belief-space barrier
+//    and the running cost used per (sample, step).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bss_internal.h"
+
+namespace bss {
+
+// ------------------------------------------------------------------------------------------------
+// random numbers
+// ------------------------------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+constexpr uint32_t kTagEps = 0u;
+constexpr uint32_t kTagW = 1u;
+constexpr uint32_t kTagInit = 2u;
+
+__device__ __forceinline__ uint32_t rng_word3(uint32_t tag, uint32_t s)
+{
+    return (tag << 28) | (s & 0x0FFFFFFFu);
+}
+
+// Ten Philox rounds on (c0..c3) in place; the round key starts at (k0, k1) and advances by the
+// two Weyl constants after each round.
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// ((r >> 9) + 1/2) * 2^-23 without a conversion: the bit pattern (r >> 9) | 0x3F800000 is
+// 1 + (r >> 9) 2^-23, and subtracting 1 - 2^-24 is exact (Sterbenz).
+__device__ __forceinline__ float uniform01(uint32_t r)
+{
+    return __uint_as_float((r >> 9) | 0x3F800000u) - 0.999999940395355224609375f;
+}
+
+// Box-Muller on one pair of words: rho = sqrt(-2 ln u_a), angle 2 pi u_b.  The hardware log is
+// base 2 and the hardware sine/cosine take their argument in revolutions.
+__device__ __forceinline__ float bm_radius(uint32_t ra)
+{
+    const float la = __builtin_amdgcn_logf(uniform01(ra));               // log2(u)
+    return __builtin_amdgcn_sqrtf(-1.3862943611198906f * la);            // -2 ln 2 log2(u)
+}
+
+__device__ __forceinline__ void bm_pair(uint32_t ra, uint32_t rb, float& z0, float& z1)
+{
+    const float rho = bm_radius(ra);
+    const float ub = uniform01(rb);
+    z0 = rho * __builtin_amdgcn_cosf(ub);
+    z1 = rho * __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ float bm_cos(uint32_t ra, uint32_t rb)
+{
+    return bm_radius(ra) * __builtin_amdgcn_cosf(uniform01(rb));
+}
+
+// ------------------------------------------------------------------------------------------------
+// single-precision car model
+// ------------------------------------------------------------------------------------------------
+// atan on the whole line: |x| > 1 is folded through atan(x) = pi/2 - atan(1/x); on [0, 1]
+// atan(z) = z + z^3 P(z^2) with a degree-7 polynomial fitted for relative error (max ~1e-7).
+__device__ __forceinline__ float atan_f32(float x)
+{
+    const float ax = fabsf(x);
+    const float z = fminf(ax, 1.0f) * __builtin_amdgcn_rcpf(fmaxf(ax, 1.0f));
+    const float z2 = z * z;
+    float p = 0.0029182303696870804f;
+    p = fmaf(p, z2, -0.016349468380212784f);
+    p = fmaf(p, z2, 0.04316648095846176f);
+    p = fmaf(p, z2, -0.07546935230493546f);
+    p = fmaf(p, z2, 0.10662780702114105f);
+    p = fmaf(p, z2, -0.1421002447605133f);
+    p = fmaf(p, z2, 0.1999361664056778f);
+    p = fmaf(p, z2, -0.333331435918808f);
+    float r = fmaf(z * z2, p, z);
+    r = ax > 1.0f ? 1.5707963267948966f - r : r;
+    return copysignf(r, x);
+}
+
+// Quantities of one (sample, step) that every particle of the sample shares.
+struct StepF32 {
+    float steer, accel;
+    float sd, cd;              // sin / cos of the steering angle
+    float kz_lf_cd;            // (m/Iz) lf cos(steer)
+    float kz_lr;               // (m/Iz) lr
+};
+
+__device__ __forceinline__ StepF32 make_step(const CarF32& car, float steer, float accel)
+{
+    StepF32 s;
+    s.steer = steer;
+    s.accel = accel;
+    float sd, cd;
+    sincosf(steer, &sd, &cd);
+    s.sd = sd;
+    s.cd = cd;
+    s.kz_lf_cd = car.m_Iz * car.lf * cd;
+    s.kz_lr = car.m_Iz * car.lr;
+    return s;
+}
+
+// Vector field of the velocity/heading part.  `rev` is the heading in revolutions (the global
+// position derivative needs sin/cos of the heading).  Outputs: dX, dY, dvx, dvy, dr (dpsi = r).
+__device__ __forceinline__ void car_field_f32(const CarF32& car, const StepF32& st, float rev,
+                                              float vx, float vy, float r, float& dX, float& dY,
+                                              float& dvx, float& dvy, float& dr)
+{
+    const float inv_vx = __builtin_amdgcn_rcpf(fmaxf(vx, car.v_min));
+    const float af = st.steer - atan_f32(fmaf(car.lf, r, vy) * inv_vx);
+    const float ar = -atan_f32(fmaf(-car.lr, r, vy) * inv_vx);
+    const float fF = fminf(fmaxf(car.cf_m * af, -car.fF_max), car.fF_max);   // F_f / m
+    const float fR = fminf(fmaxf(car.cr_m * ar, -car.fR_max), car.fR_max);   // F_r / m
+    const float rr = rev - rintf(rev);
+    const float sp = __builtin_amdgcn_sinf(rr);
+    const float cp = __builtin_amdgcn_cosf(rr);
+    dX = fmaf(vx, cp, -vy * sp);
+    dY = fmaf(vx, sp, vy * cp);
+    dvx = fmaf(-fF, st.sd, fmaf(vy, r, st.accel));
+    dvy = fmaf(fF, st.cd, fmaf(-vx, r, fR));
+    dr = fmaf(fF, st.kz_lf_cd, -st.kz_lr * fR);
+}
+
+// ------------------------------------------------------------------------------------------------
+// double-precision model, track geometry, barrier and cost
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double clampd(double x, double lo, double hi)
+{
+    return fmin(fmax(x, lo), hi);
+}
+
+__device__ inline void car_deriv_f64(const ScoreF64& p, const double* x, double steer,
+                                     double accel, double* dx)
+{
+    const double psi = x[2], vx = x[3], vy = x[4], r = x[5];
+    const double vxs = fmax(vx, p.v_min);
+    const double af = steer - atan((vy + p.lf * r) / vxs);
+    const double ar = -atan((vy - p.lr * r) / vxs);
+    const double L = p.lf + p.lr;
+    const double Ffm = p.mu * p.m * p.g * p.lr / L;
+    const double Frm = p.mu * p.m * p.g * p.lf / L;
+    const double Ff = clampd(p.Cf * af, -Ffm, Ffm);
+    const double Fr = clampd(p.Cr * ar, -Frm, Frm);
+    double sp, cp, sd, cd;
+    sincos(psi, &sp, &cp);
+    sincos(steer, &sd, &cd);
+    dx[0] = vx * cp - vy * sp;
+    dx[1] = vx * sp + vy * cp;
+    dx[2] = r;
+    dx[3] = accel + vy * r - Ff * sd / p.m;
+    dx[4] = (Ff * cd + Fr) / p.m - vx * r;
+    dx[5] = (p.lf * Ff * cd - p.lr * Fr) / p.Iz;
+}
+
+// explicit midpoint step of the noise-free model in double precision
+__device__ inline void car_step_f64(const ScoreF64& p, const double* x, double steer, double accel,
+                                    double* xn)
+{
+    double k1[6], xm[6], k2[6];
+    car_deriv_f64(p, x, steer, accel, k1);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) xm[i] = x[i] + 0.5 * p.dt * k1[i];
+    car_deriv_f64(p, xm, steer, accel, k2);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) xn[i] = x[i] + p.dt * k2[i];
+}
+
+// Nearest point of the ellipse (e0 >= e1) to (y0, y1) in the first quadrant.  Parametrising the
+// nearest point as c0 = r0 y0 / (s + r0) e0-scaled, c1 = y1 / (s + 1) (r0 = (e0/e1)^2) turns the
+// problem into the root of the convex decreasing F(s) = (r0 z0/(s+r0))^2 + (z1/(s+1))^2 - 1 on
+// (z1 - 1, |(r0 z0, z1)| - 1]; it is found by Newton's method safeguarded by that bracket,
+// started from the first-order distance estimate.
+__device__ inline void ellipse_nearest_q1(double e0, double e1, double y0, double y1, double* c0,
+                                          double* c1)
+{
+    if (y1 > 0.0) {
+        if (y0 > 0.0) {
+            const double z0 = y0 / e0, z1 = y1 / e1;
+            const double g = z0 * z0 + z1 * z1 - 1.0;
+            if (g != 0.0) {
+                const double r0 = (e0 / e1) * (e0 / e1);
+                const double n0 = r0 * z0;
+                double lo = z1 - 1.0;
+                double hi = g < 0.0 ? 0.0 : sqrt(n0 * n0 + z1 * z1) - 1.0;
+                // first-order signed distance d ~ (F(p) - 1) / |grad F| and s = d / (e1^2 |n|)
+                const double gx = y0 / (e0 * e0), gy = y1 / (e1 * e1);
+                const double gn = sqrt(gx * gx + gy * gy);
+                double s = (0.5 * g / gn) / (e1 * e1 * gn);
+                if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+                for (int it = 0; it < 200; ++it) {
+                    const double a0 = n0 / (s + r0), a1 = z1 / (s + 1.0);
+                    const double F = a0 * a0 + a1 * a1 - 1.0;
+                    if (F > 0.0) lo = s; else if (F < 0.0) hi = s; else break;
+                    const double dF = -2.0 * (a0 * a0 / (s + r0) + a1 * a1 / (s + 1.0));
+                    double sn = s - F / dF;
+                    if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+                    const double step = fabs(sn - s);
+                    s = sn;
+                    if (step <= 1e-16 * (1.0 + fabs(s)) || !(hi > lo)) break;
+                }
+                *c0 = r0 * y0 / (s + r0);
+                *c1 = y1 / (s + 1.0);
+            } else {
+                *c0 = y0;
+                *c1 = y1;
+            }
+        } else {
+            *c0 = 0.0;
+            *c1 = e1;
+        }
+    } else {
+        const double numer0 = e0 * y0, denom0 = e0 * e0 - e1 * e1;
+        if (numer0 < denom0) {
+            const double xde0 = numer0 / denom0;
+            *c0 = e0 * xde0;
+            *c1 = e1 * sqrt(1.0 - xde0 * xde0);
+        } else {
+            *c0 = e0;
+            *c1 = 0.0;
+        }
+    }
+}
+
+// Signed distance of (X, Y) to the ellipse (X/a)^2 + (Y/b)^2 = 1 (positive outside) and the
+// outward unit normal at the nearest point.
+__device__ inline void ellipse_sdf(double a, double b, double X, double Y, double* sd, double* nx,
+                                   double* ny)
+{
+    const double ax = fabs(X), ay = fabs(Y);
+    double cx, cy;
+    if (a >= b) {
+        ellipse_nearest_q1(a, b, ax, ay, &cx, &cy);
+    } else {
+        ellipse_nearest_q1(b, a, ay, ax, &cy, &cx);
+    }
+    cx = X < 0.0 ? -cx : cx;
+    cy = Y < 0.0 ? -cy : cy;
+    const double dx = X - cx, dy = Y - cy;
+    const double dist = sqrt(dx * dx + dy * dy);
+    const double level = (X / a) * (X / a) + (Y / b) * (Y / b);
+    *sd = level < 1.0 ? -dist : dist;
+    const double gx = cx / (a * a), gy = cy / (b * b);
+    const double gn = sqrt(gx * gx + gy * gy);
+    *nx = gx / gn;
+    *ny = gy / gn;
+}
+
+// Belief of one step, evaluated once: lateral deviation, normal, spread along the normal and the
+// barrier value h = max(w_T - nu sigma_y, 0)^2 - e_y^2.
+struct BeliefEval {
+    double ey, nx, ny, sigma, h;
+};
+
+__device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom)
+{
+    BeliefEval b;
+    ellipse_sdf(p.ell_a, p.ell_b, mom[0], mom[1], &b.ey, &b.nx, &b.ny);
+    const double var = b.nx * b.nx * mom[6] + 2.0 * b.nx * b.ny * mom[7] + b.ny * b.ny * mom[8];
+    b.sigma = sqrt(fmax(var, 0.0));
+    const double margin = fmax(p.half_width - p.nu * b.sigma, 0.0);
+    b.h = margin * margin - b.ey * b.ey;
+    return b;
+}
+
+// Running cost on the mean (tracking, heading error w.r.t. the counter-clockwise tangent, lateral
+// deviation, collision indicator).
+__device__ inline double stage_cost(const ScoreF64& p, const double* mom, const BeliefEval& b)
+{
+    const double tx = -b.ny, ty = b.nx;
+    double sp, cp;
+    sincos(mom[2], &sp, &cp);
+    const double cos_epsi = cp * tx + sp * ty;
+    const double dv = mom[3] - p.v_goal;
+    double q = p.q_vx * dv * dv + p.q_vy * mom[4] * mom[4] + p.q_r * mom[5] * mom[5] +
+               p.q_ey * b.ey * b.ey + p.q_epsi * 2.0 * (1.0 - cos_epsi);
+    if (fabs(b.ey) >= p.half_width) q += p.C_obs;
+    return q;
+}
+
+// One-step residual of the linear class-kappa condition for a candidate control: the mean is
+// pushed through the noise-free model and re-scored with the spread frozen at step t.
+__device__ inline double repair_residual(const ScoreF64& p, const double* xbar, double margin2,
+                                         double h_t, double steer, double accel)
+{
+    double xn[6];
+    car_step_f64(p, xbar, steer, accel, xn);
+    double ey, nx, ny;
+    ellipse_sdf(p.ell_a, p.ell_b, xn[0], xn[1], &ey, &nx, &ny);
+    return -(margin2 - ey * ey) + (1.0 - p.gamma) * h_t;
+}
+
+}  // namespace bss

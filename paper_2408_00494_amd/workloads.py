@@ -33,7 +33,7 @@ _DEFAULTS = dict(
     # track
     ell_a=30.0, ell_b=20.0, half_width=2.0,
     # shield repair (0 iterations = off)
-    shield_iters=0, shield_gmin=1.0e-6, shield_fd=1.0e-4,
+    shield_iters=0, shield_gmin=0.05, shield_fd=1.0e-2,
     # random numbers and model selector (0 = car)
     seed=1, model=0,
 )

@@ -1,0 +1,387 @@
+"""GPU-vs-oracle parity of the HIP path (run on an MI355X; every call goes through the C ABI).
+
+Staged checks give each stage the other side's inputs so errors do not compound; end-to-end
+checks compare whole solves.  Tolerances (floating point; integer work is bit-exact):
+  controls v+      : max |dv| / u_max <= 1e-4 (full-scale relative, per control channel)
+  moments          : |d mom[k,t,i]| / max_t |mom_ref[k,t,i]| <= 1e-3 (trajectory-scale relative)
+  costs            : |dS_k| / |S_k| <= 1e-3
+The single-precision rollout against the double-precision oracle is the only source of
+difference; staged double-precision stages are held to ~1e-12.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_00494_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_2408_00494_amd as bss  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def ctrl_err(v_gpu, v_ref, prob):
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    return float(np.max(np.abs(np.asarray(v_gpu) - v_ref) / scale))
+
+
+def mom_err(m_gpu, m_ref):
+    span = np.max(np.abs(m_ref), axis=1, keepdims=True)
+    span = np.where(span > 0, span, 1.0)
+    return float(np.max(np.abs(m_gpu - m_ref) / span))
+
+
+def cost_err(S_gpu, S_ref):
+    return float(np.max(np.abs(S_gpu - S_ref) / np.abs(S_ref)))
+
+
+# ================================= random numbers (bit-exact) ==================================
+def _counters_of(prob, s, n_sample=None, rng=None):
+    """Counters a solve of `prob` at solve index s draws (tag 0: (t,0,k); tag 1: (t,m,k))."""
+    K, M, T = prob["K"], prob["M"], prob["T"]
+    if n_sample is None:
+        t, m, k = np.meshgrid(np.arange(T), np.arange(M), np.arange(K), indexing="ij")
+        t, m, k = t.ravel(), m.ravel(), k.ravel()
+        te, ke = np.meshgrid(np.arange(T), np.arange(K), indexing="ij")
+        te, ke = te.ravel(), ke.ravel()
+    else:
+        t, m, k = rng.integers(0, T, n_sample), rng.integers(0, M, n_sample), rng.integers(0, K, n_sample)
+        te, ke = rng.integers(0, T, n_sample), rng.integers(0, K, n_sample)
+    w = np.stack([t, m, k, np.full_like(t, (1 << 28) | (s & 0x0FFFFFFF))], axis=1)
+    e = np.stack([te, np.zeros_like(te), ke, np.full_like(te, s & 0x0FFFFFFF)], axis=1)
+    return np.concatenate([w, e]).astype(np.uint32)
+
+
+def test_philox_bit_exact_on_solve_counters():
+    prob, _, _ = W.config_small()
+    rng = np.random.default_rng(0)
+    sets = [(_counters_of(prob, 0), prob["seed"]), (_counters_of(prob, 77), prob["seed"])]
+    p2, _, _ = W.config_paper_scale()
+    sets.append((_counters_of(p2, 5, 400000, rng), p2["seed"]))
+    p3, _, _ = W.config_shielded()
+    sets.append((_counters_of(p3, 3, 400000, rng), p3["seed"]))
+    for ctr, seed in sets:
+        got = bss.dev_philox(seed, dev(ctr.view(np.int32))).cpu().numpy().view(np.uint32)
+        want = oracle.philox_many(ctr, seed)
+        assert np.array_equal(got, want)
+
+
+def test_philox_known_answers_on_device():
+    rows = [[0, 0, 0, 0, 0, 0], [0xFFFFFFFF] * 6,
+            [0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344, 0xa4093822, 0x299f31d0]]
+    for r in rows:
+        ctr = np.array([r[:4]], dtype=np.uint32)
+        seed = r[4] | (r[5] << 32)
+        got = bss.dev_philox(seed, dev(ctr.view(np.int32))).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got[0], oracle.philox(r[:4], r[4:6]))
+
+
+def test_normals_match_oracle():
+    prob, _, _ = W.config_small()
+    ctr = _counters_of(prob, 0)
+    z_gpu = bss.dev_normals(prob["seed"], dev(ctr.view(np.int32))).cpu().numpy().astype(np.float64)
+    z_ref = oracle.normals_many(prob["seed"], ctr)
+    err = np.max(np.abs(z_gpu - z_ref))
+    assert err <= 2e-6, err
+
+
+# ====================================== dynamics =============================================
+def test_model_step_matches_oracle():
+    prob, _, _ = W.config_small()
+    rng = np.random.default_rng(1)
+    n = 4096
+    x = np.column_stack([rng.uniform(-40, 40, n), rng.uniform(-40, 40, n), rng.uniform(-7, 7, n),
+                         rng.uniform(0.5, 12, n), rng.normal(0, 1.0, n), rng.normal(0, 0.8, n)])
+    u = np.column_stack([rng.uniform(-0.4, 0.4, n), rng.uniform(-4, 4, n)])
+    x32, u32 = x.astype(np.float32), u.astype(np.float32)
+    got = bss.dev_model_step(prob, dev(x32), dev(u32)).cpu().numpy().astype(np.float64)
+    want = np.array([oracle.model_step(prob, x32[i].astype(np.float64), u32[i].astype(np.float64))
+                     for i in range(n)])
+    # per-component scale: position/heading change over one step, velocities
+    d = np.abs(got - want)
+    step = np.abs(want - x32.astype(np.float64))
+    tol = 2e-6 * (np.abs(want) + 1.0) + 1e-5 * step
+    assert np.all(d <= tol), float(np.max(d / tol))
+
+
+def test_sdf_matches_oracle():
+    rng = np.random.default_rng(2)
+    for a, b in ((30.0, 20.0), (18.0, 47.0), (25.0, 25.0)):
+        th = rng.uniform(0, 2 * np.pi, 3000)
+        off = rng.uniform(-5, 5, 3000)
+        pts = np.column_stack([(a + off) * np.cos(th), (b + off) * np.sin(th)])
+        pts = np.concatenate([pts, [[a, 0.0], [0.0, b], [a + 1, 0], [0, -b - 1], [3.0, 0.0],
+                                    [0.0, 2.0], [a - 0.5, 1e-12], [1e-13, b - 0.3]]])
+        got = bss.dev_sdf(a, b, dev(pts)).cpu().numpy()
+        for i, (X, Y) in enumerate(pts):
+            sd, n = oracle.ellipse_sdf(a, b, X, Y)
+            assert abs(got[i, 0] - sd) <= 1e-10, (a, b, X, Y, got[i], sd)
+            assert np.all(np.abs(got[i, 1:] - n) <= 1e-8), (a, b, X, Y, got[i], n)
+
+
+# ================================ score, update, repair (FP64) ================================
+def test_score_from_injected_moments():
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=64)
+    ref = oracle.solve(prob, 0, x0, v)
+    u32 = ref["u"].astype(np.float32)
+    S_gpu = bss.dev_score(prob, dev(ref["mom"]), dev(u32), dev(v)).cpu().numpy()
+    nu = oracle.backoff(prob["delta"])
+    S_ref = np.array([oracle.score(prob, nu, ref["mom"][k], u32[k].astype(np.float64), v)
+                      for k in range(prob["K"])])
+    assert np.max(np.abs(S_gpu - S_ref) / np.abs(S_ref)) <= 1e-12
+
+
+def test_update_from_injected_costs():
+    rng = np.random.default_rng(3)
+    for K, T, lam in ((256, 30, 1.0), (4096, 50, 1.0), (1000, 7, 25.0), (300, 80, 0.05)):
+        prob = W.default_problem(K=K, T=T, **{"lambda": lam})
+        S = rng.uniform(20, 60, K)
+        S[rng.integers(0, K, 3)] = np.nan
+        u = rng.normal(size=(K, T, 2)).astype(np.float32)
+        v = rng.normal(size=(T, 2))
+        v_gpu, st_gpu = bss.dev_update(prob, dev(S), dev(u), dev(v))
+        rc, v_ref, st_ref = oracle.update(prob, S, u.astype(np.float64), v)
+        assert rc == 0
+        assert np.max(np.abs(v_gpu.cpu().numpy() - v_ref)) <= 1e-12
+        st = st_gpu.cpu().numpy()
+        assert st[0] == pytest.approx(st_ref[0], rel=1e-15)
+        assert st[1] == pytest.approx(st_ref[1], rel=1e-12)
+        assert st[2] == pytest.approx(st_ref[2], rel=1e-12)
+        assert st[3] == st_ref[3] and st[4] == 0.0
+    # every cost non-finite: v unchanged, status 5
+    prob = W.default_problem(K=100, T=5)
+    v = rng.normal(size=(5, 2))
+    v_gpu, st = bss.dev_update(prob, dev(np.full(100, np.inf)), dev(np.zeros((100, 5, 2), np.float32)),
+                               dev(v))
+    assert np.array_equal(v_gpu.cpu().numpy(), v) and st.cpu().numpy()[4] == 5.0
+
+
+def test_repair_from_injected_beliefs():
+    prob = W.default_problem(shield_iters=3, gamma=0.05)
+    rng = np.random.default_rng(4)
+    a = prob["ell_a"]
+    n = 300
+    mom = np.zeros((n, 9))
+    for i in range(n):
+        mom[i] = [a + rng.uniform(-2.5, 2.5), rng.uniform(-1, 1), np.pi / 2 + rng.uniform(-0.4, 0.4),
+                  rng.uniform(3, 8), rng.normal() * 0.2, rng.normal() * 0.2, 0.003, 0.0005, 0.002]
+    u = rng.uniform([-0.4, -4], [0.4, 4], size=(n, 2))
+    got = bss.dev_repair(prob, dev(mom), dev(u)).cpu().numpy()
+    nu = oracle.backoff(prob["delta"])
+    want = np.array([oracle.repair(prob, nu, mom[i], u[i]) for i in range(n)])
+    assert np.sum(np.any(got != u, axis=1)) > 10     # the repair acted on some controls
+    # the projection divides by |dr/du|^2 from central differences, which turns last-bit
+    # differences of the two libm's (atan, sin, cos) into ~1e-7 differences where the gradient
+    # is small; the bound is full-scale relative 1e-6 per channel
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    assert np.max(np.abs(got - want) / scale) <= 1e-6
+
+
+# ======================================== end to end ==========================================
+def _compare_solve(prob, x0, v, s=0, Sigma0=None, lanes=0, ctrl_tol=1e-4):
+    solver = bss.Solver(prob, lanes=lanes)
+    solver.set_controls(v)
+    solver.solve_index = s
+    u0, info = solver.solve(x0, Sigma0)
+    b = solver.buffers()
+    got = {"v": solver.get_controls(), "u": b["u"].cpu().numpy().astype(np.float64),
+           "mom": b["mom"].cpu().numpy(), "S": b["S"].cpu().numpy()}
+    solver.close()
+    ref = oracle.solve(prob, s, x0, v, Sigma0=Sigma0, nthreads=NTHREADS)
+    errs = {"u": float(np.max(np.abs(got["u"] - ref["u"]))),
+            "mom": mom_err(got["mom"], ref["mom"]),
+            "S": cost_err(got["S"], ref["S"]),
+            "v": ctrl_err(got["v"], ref["v"], prob)}
+    print(f"K={prob['K']} M={prob['M']} T={prob['T']} lanes={info['lanes']}x{info['ppl']} "
+          f"ess={info['ess']:.3f} errs={errs}", flush=True)
+    assert errs["u"] <= 1e-5
+    assert errs["mom"] <= 1e-3
+    assert errs["S"] <= 1e-3
+    assert errs["v"] <= ctrl_tol
+    assert np.allclose(u0, got["v"][0], atol=0, rtol=0)
+    return got, ref, info
+
+
+def test_small_solve_matches_oracle():
+    prob, x0, v = W.config_small()
+    _compare_solve(prob, x0, v)
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
+def test_every_launch_shape_matches_oracle(lanes):
+    prob, x0, v = W.config_small()
+    _compare_solve(dict(prob, K=96), x0, v, s=3, lanes=lanes)
+
+
+def test_closed_loop_sequence_matches_oracle():
+    """Five receding-horizon periods: solve, apply u0 to a noise-free plant, shift the warm start;
+    the oracle is fed the same states (taken from the GPU run) at every period."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=128)
+    solver = bss.Solver(prob)
+    v_ref = v.copy()
+    x = x0.copy()
+    for s in range(5):
+        u0, _ = solver.solve(x)
+        ref = oracle.solve(prob, s, x, v_ref, nthreads=NTHREADS)
+        v_gpu = solver.get_controls()
+        assert ctrl_err(v_gpu, ref["v"], prob) <= 1e-4
+        v_ref = oracle.step_shift(v_gpu)
+        solver.step_shift()
+        assert np.array_equal(solver.get_controls(), v_ref)
+        x = oracle.model_step(prob, x, u0)
+    solver.close()
+
+
+def test_paper_scale_solve_matches_oracle():
+    """K=4096, M=64, T=50, disturbance x2, random start on the track (the benchmark workload)."""
+    prob, x0, v = W.config_paper_scale()
+    _compare_solve(prob, x0, v, s=1)
+
+
+def test_shielded_solve_matches_oracle():
+    """K=8192, M=128, T=60 with the shield repair (delta=0.05, gamma=0.1).
+
+    End to end, the outputs the update consumes (costs, weighted controls) meet the bar.  Inside a
+    sample the repair feeds the belief of step t back into u_t, so the single- vs double-precision
+    particle differences are re-amplified at every step of the horizon; the sampled controls and
+    beliefs of a small share of samples drift past the end-to-end bound.  Each stage is therefore
+    also checked on the other side's inputs: the repair from the GPU's belief, and the
+    propagation under the GPU's repaired controls."""
+    prob, x0, v = W.config_shielded(delta=0.05, gamma=0.1)
+    s = 2
+    solver = bss.Solver(prob)
+    solver.set_controls(v)
+    solver.solve_index = s
+    solver.solve(x0)
+    b = solver.buffers()
+    g_u = b["u"].cpu().numpy().astype(np.float64)
+    g_mom = b["mom"].cpu().numpy()
+    g_S = b["S"].cpu().numpy()
+    g_v = solver.get_controls()
+    solver.close()
+    ref = oracle.solve(prob, s, x0, v, nthreads=NTHREADS)
+    assert cost_err(g_S, ref["S"]) <= 1e-3
+    assert ctrl_err(g_v, ref["v"], prob) <= 1e-4
+    span = np.max(np.abs(ref["mom"]), axis=1, keepdims=True)
+    per_k = np.max(np.abs(g_mom - ref["mom"]) / np.where(span > 0, span, 1.0), axis=(1, 2))
+    frac_bad = float(np.mean(per_k > 1e-3))
+    print(f"shield: S {cost_err(g_S, ref['S']):.2e}  v {ctrl_err(g_v, ref['v'], prob):.2e}  "
+          f"samples with moment error > 1e-3: {frac_bad:.4%} (max {per_k.max():.2e})", flush=True)
+    assert frac_bad <= 0.01
+
+    # the repair acted on this workload
+    eps_only = oracle.solve(dict(prob, shield_iters=0), s, x0, v, nthreads=NTHREADS)
+    assert np.mean(np.any(np.abs(ref["u"] - eps_only["u"]) > 1e-12, axis=2)) > 1e-3
+
+    # stage checks on the worst and on random samples.  The repair stage starts from the GPU's
+    # own pre-repair control (its single-precision clip(v + sigma z) with the device normals), so
+    # it compares the double-precision repair alone.
+    rng = np.random.default_rng(0)
+    ks = np.unique(np.concatenate([np.argsort(per_k)[-16:], rng.integers(0, prob["K"], 48)]))
+    nu = oracle.backoff(prob["delta"])
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    ctr = np.array([[t, 0, k, s] for k in ks for t in range(prob["T"])], dtype=np.uint32)
+    z = bss.dev_normals(prob["seed"], dev(ctr.view(np.int32))).cpu().numpy()
+    sig32 = np.array(prob["sigma_eps"], dtype=np.float32)
+    worst_rep, worst_prop = 0.0, 0.0
+    row = 0
+    for k in ks:
+        for t in range(prob["T"]):
+            v32 = v[t].astype(np.float32)
+            # fmaf(sigma, z, v) in single precision (exact product, one rounding)
+            pre = (sig32.astype(np.float64) * z[row, :2].astype(np.float64)
+                   + v32.astype(np.float64)).astype(np.float32)
+            pre = np.clip(pre, -scale.astype(np.float32), scale.astype(np.float32))
+            row += 1
+            u_rep = oracle.repair(prob, nu, g_mom[k, t], pre.astype(np.float64))
+            u_rep32 = u_rep.astype(np.float32).astype(np.float64)
+            worst_rep = max(worst_rep, float(np.max(np.abs(u_rep32 - g_u[k, t]) / scale)))
+        mom_k = oracle.propagate(prob, s, int(k), x0, g_u[k])
+        worst_prop = max(worst_prop, mom_err(g_mom[k:k + 1], mom_k[None]))
+    print(f"shield stages: repair {worst_rep:.2e}  propagation {worst_prop:.2e}", flush=True)
+    assert worst_rep <= 1e-6
+    assert worst_prop <= 1e-3
+
+
+@pytest.mark.parametrize("K,M,T,lanes", [(1, 1, 1, 0), (3, 13, 7, 8), (257, 16, 30, 0),
+                                         (5, 512, 4, 64), (2, 37, 256, 16), (70, 2, 3, 32)])
+def test_edge_sizes_match_oracle(K, M, T, lanes):
+    prob, x0, _ = W.config_small()
+    prob = dict(prob, K=K, M=M, T=T)
+    v = np.column_stack([0.05 * np.sin(np.arange(T)), 0.5 * np.cos(np.arange(T))])
+    _compare_solve(prob, x0, v, s=9, lanes=lanes)
+
+
+def test_initial_spread_matches_oracle():
+    prob, x0, v = W.config_small()
+    rng = np.random.default_rng(5)
+    G = rng.normal(size=(6, 6)) * 0.05
+    Sigma0 = G @ G.T + np.diag([0.02, 0.02, 1e-3, 0.01, 0.01, 1e-3])
+    _compare_solve(dict(prob, K=128), x0, v, s=4, Sigma0=Sigma0)
+
+
+def test_zero_noise_keeps_the_mean_sequence():
+    prob, x0, _ = W.config_small()
+    prob = dict(prob, sigma_w=[0.0, 0.0, 0.0], sigma_eps=[0.0, 0.0], K=64)
+    T = prob["T"]
+    v = np.column_stack([0.1 * np.sin(np.arange(T) * 0.3), 0.5 * np.cos(np.arange(T) * 0.2)])
+    solver = bss.Solver(prob)
+    solver.set_controls(v)
+    solver.solve(x0)
+    b = solver.buffers()
+    mom = b["mom"].cpu().numpy()
+    S = b["S"].cpu().numpy()
+    # every sample is the same deterministic rollout; covariances vanish
+    assert np.all(S == S[0])
+    assert np.max(np.abs(mom[:, :, 6:])) <= 1e-20
+    # v+ = v up to the single-precision storage of the sampled controls
+    assert np.max(np.abs(solver.get_controls() - v)) <= 1e-7
+    solver.close()
+
+
+def test_solves_are_deterministic_and_resumable():
+    prob, x0, v = W.config_small()
+    a = bss.Solver(prob)
+    a.solve(x0)
+    a.solve(x0)
+    va = a.get_controls()
+    Sa = a.buffers()["S"].cpu().numpy()
+    b = bss.Solver(prob)
+    b.solve(x0)
+    v1 = b.get_controls()
+    c = bss.Solver(prob)          # resume from the state after the first solve
+    c.set_controls(v1)
+    c.solve_index = 1
+    c.solve(x0)
+    assert np.array_equal(c.get_controls(), va)
+    assert np.array_equal(c.buffers()["S"].cpu().numpy(), Sa)
+    for s_ in (a, b, c):
+        s_.close()
+
+
+def test_non_finite_state_reports_numeric_status():
+    prob, x0, v = W.config_small()
+    solver = bss.Solver(prob)
+    v0 = np.full((prob["T"], 2), 0.1)
+    solver.set_controls(v0)
+    x_bad = dev(np.array([np.nan, 0, 0, 5, 0, 0]))
+    solver.solve_async(x_bad)
+    torch.cuda.synchronize()
+    st = solver.buffers()["stats"].cpu().numpy()
+    assert st[4] == 5.0 and st[3] == 0
+    assert np.array_equal(solver.get_controls(), v0)
+    with pytest.raises(bss.BssError) as ei:
+        solver.solve(np.array([0, np.inf, 0, 5, 0, 0]))
+    assert ei.value.status == 1
+    solver.close()
