@@ -87,8 +87,11 @@ typedef struct bss_allocator {
 } bss_allocator;
 
 /* Device buffers owned by a context (valid until bss_destroy).  Layouts are row-major:
- *   v      [T][2]       double  mean control sequence (warm start; updated by each solve)
- *   u      [K][T][2]    float   sampled (clipped, repaired) controls of the last solve
+ *   v      [T][2]       double  mean control sequence (warm start).  Each solve writes the
+ *                               updated sequence into the other buffer of a ping-pong pair, so
+ *                               this pointer changes after every solve: query it again.
+ *   u      [K][T][2]    float   sampled (clipped, repaired) controls of the last solve (written
+ *                               only when BSS_OUT_CONTROLS is set)
  *   mom    [K][T+1][9]  double  belief per sample and step: mean X, Y, psi, vx, vy, r, then
  *                               Sigma_XX, Sigma_XY, Sigma_YY; record 0 is the given estimate
  *   S      [K]          double  trajectory costs of the last solve
@@ -104,7 +107,12 @@ typedef struct bss_buffers {
     double* stats;
     double* x0;
     double* Sigma0;
+    int32_t v_shift;   /* warm-start shifts pending on v: the mean sequence is
+                          v[min(t + v_shift, T - 1)] */
 } bss_buffers;
+
+/* Optional per-solve copy to device memory (bss_set_outputs); the solve itself does not need it. */
+#define BSS_OUT_CONTROLS 1   /* sampled controls u [K][T][2] */
 
 /* Result summary of a solve (host). */
 typedef struct bss_info {
@@ -152,9 +160,14 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
  * every cost was non-finite (then v is unchanged).  Errors: BSS_E_INVAL, BSS_E_DEVICE. */
 bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma0_dev);
 
-/* Receding-horizon warm start, enqueued on the stream: v_t <- v_{t+1} for t < T-1; v_{T-1} keeps
- * its value. */
+/* Receding-horizon warm start: v_t <- v_{t+1} for t < T-1; v_{T-1} keeps its value.  The shift is
+ * recorded in the context and applied when the next solve reads v (no kernel is launched);
+ * bss_get_controls returns the shifted sequence. */
 bss_status bss_step_shift(bss_ctx* c);
+
+/* Select the optional per-solve copy of the sampled controls (BSS_OUT_CONTROLS, on after
+ * bss_create; 0 turns it off). */
+bss_status bss_set_outputs(bss_ctx* c, int32_t flags);
 
 /* Device buffers of the context (see bss_buffers). */
 bss_status bss_get_buffers(const bss_ctx* c, bss_buffers* out);
@@ -209,7 +222,7 @@ bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u,
                          double* S, void* stream);
 /* MPPI update from given costs and controls: S[K], u[K][T][2] (float); v[T][2] updated in place,
  * stats[8] as in bss_buffers.  workspace: at least bss_dev_update_workspace(K, T) bytes of
- * device memory whose first 4 bytes are zero (they are zero again afterwards). */
+ * device memory (scratch, caller-owned). */
 size_t bss_dev_update_workspace(int32_t K, int32_t T);
 bss_status bss_dev_update(const bss_params* p, const double* S, const float* u, double* v,
                           double* stats, void* workspace, void* stream);

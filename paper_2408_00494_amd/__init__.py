@@ -79,14 +79,12 @@ class Solver:
         check(_lib.lib().bss_create(C.byref(self._params), C.byref(self._allocator),
                                     _stream_ptr(self._stream), C.byref(ctx)))
         self._ctx = ctx
-        self._views = None
 
     # ---- lifetime -----------------------------------------------------------------------------
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             _lib.lib().bss_destroy(self._ctx)
             self._ctx = None
-            self._views = None
 
     def __del__(self):
         try:
@@ -143,26 +141,31 @@ class Solver:
     def set_lanes(self, lanes: int):
         check(_lib.lib().bss_set_lanes(self._ctx, int(lanes)))
 
-    def buffers(self):
-        """Torch views of the context's device buffers: v, u, mom, S, stats."""
-        if self._views is None:
-            torch = _torch()
-            b = _lib.BssBuffers()
-            check(_lib.lib().bss_get_buffers(self._ctx, C.byref(b)))
-            (base_ptr, blk), = self._blocks.items()
-            K, T = self.K, self.T
+    def set_outputs(self, controls: bool = True):
+        """Turn the optional per-solve copy of the sampled controls on or off."""
+        check(_lib.lib().bss_set_outputs(self._ctx, _lib.BSS_OUT_CONTROLS if controls else 0))
 
-            def view(ptr, nbytes, dtype, shape):
-                off = ptr - base_ptr
-                return blk[off:off + nbytes].view(dtype).reshape(shape)
-            self._views = {
-                "v": view(b.v, T * 2 * 8, torch.float64, (T, 2)),
-                "u": view(b.u, K * T * 2 * 4, torch.float32, (K, T, 2)),
-                "mom": view(b.mom, K * (T + 1) * 9 * 8, torch.float64, (K, T + 1, 9)),
-                "S": view(b.S, K * 8, torch.float64, (K,)),
-                "stats": view(b.stats, 8 * 8, torch.float64, (8,)),
-            }
-        return self._views
+    def buffers(self):
+        """Torch views of the context's device buffers: v (current mean sequence, before any
+        pending warm-start shift), u, mom, S, stats.  Query again after each solve (the mean
+        sequence alternates between two buffers)."""
+        torch = _torch()
+        b = _lib.BssBuffers()
+        check(_lib.lib().bss_get_buffers(self._ctx, C.byref(b)))
+        (base_ptr, blk), = self._blocks.items()
+        K, T = self.K, self.T
+
+        def view(ptr, nbytes, dtype, shape):
+            off = ptr - base_ptr
+            return blk[off:off + nbytes].view(dtype).reshape(shape)
+        return {
+            "v": view(b.v, T * 2 * 8, torch.float64, (T, 2)),
+            "u": view(b.u, K * T * 2 * 4, torch.float32, (K, T, 2)),
+            "mom": view(b.mom, K * (T + 1) * 9 * 8, torch.float64, (K, T + 1, 9)),
+            "S": view(b.S, K * 8, torch.float64, (K,)),
+            "stats": view(b.stats, 8 * 8, torch.float64, (8,)),
+            "v_shift": b.v_shift,
+        }
 
     # ---- timing -------------------------------------------------------------------------------
     def timing(self, enable: bool):

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbssmppi.so")
 
 BSS_OK, BSS_E_INVAL, BSS_E_NOMEM, BSS_E_DEVICE, BSS_E_STATE, BSS_E_NUMERIC = range(6)
+BSS_OUT_CONTROLS = 1
 STATUS_NAMES = {0: "BSS_OK", 1: "BSS_E_INVAL", 2: "BSS_E_NOMEM", 3: "BSS_E_DEVICE",
                 4: "BSS_E_STATE", 5: "BSS_E_NUMERIC"}
 
@@ -51,7 +52,8 @@ class BssAllocator(C.Structure):
 
 class BssBuffers(C.Structure):
     _fields_ = [("v", C.c_void_p), ("u", C.c_void_p), ("mom", C.c_void_p), ("S", C.c_void_p),
-                ("stats", C.c_void_p), ("x0", C.c_void_p), ("Sigma0", C.c_void_p)]
+                ("stats", C.c_void_p), ("x0", C.c_void_p), ("Sigma0", C.c_void_p),
+                ("v_shift", C.c_int32)]
 
 
 class BssInfo(C.Structure):
@@ -62,7 +64,8 @@ class BssInfo(C.Structure):
 # every exported symbol of include/bssmppi.h
 EXPORTS = [
     "bss_params_default", "bss_validate", "bss_backoff", "bss_create", "bss_set_stream",
-    "bss_solve", "bss_solve_async", "bss_step_shift", "bss_get_buffers", "bss_get_controls",
+    "bss_solve", "bss_solve_async", "bss_step_shift", "bss_set_outputs", "bss_get_buffers",
+    "bss_get_controls",
     "bss_set_controls", "bss_set_solve_index", "bss_get_solve_index", "bss_get_info",
     "bss_timing_enable", "bss_timing_read", "bss_set_lanes", "bss_destroy", "bss_last_error",
     "bss_dev_philox", "bss_dev_normals", "bss_dev_model_step", "bss_dev_sdf", "bss_dev_score",
@@ -84,6 +87,7 @@ def _declare(lib):
         "bss_solve": (i32, [vp, C.POINTER(d), vp, C.POINTER(d), C.POINTER(BssInfo)]),
         "bss_solve_async": (i32, [vp, vp, vp]),
         "bss_step_shift": (i32, [vp]),
+        "bss_set_outputs": (i32, [vp, i32]),
         "bss_get_buffers": (i32, [vp, C.POINTER(BssBuffers)]),
         "bss_get_controls": (i32, [vp, vp]),
         "bss_set_controls": (i32, [vp, vp]),

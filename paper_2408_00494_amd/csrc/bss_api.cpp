@@ -130,18 +130,19 @@ struct bss_ctx {
     bool has_alloc;
     hipStream_t stream;
     void* block;
-    double* v;
+    double* vbuf[2];         // ping-pong pair of mean sequences [T][2]
+    int cur;                 // index of the current mean sequence
+    int pending_shift;       // warm-start shifts not yet applied to vbuf[cur]
     float* u;
     double* mom;
     double* S;
     double* stats;
     double* partial;
-    uint32_t* counter;
     double* x0;
     double* Sigma0;
     double* host;            // pinned [16]
     uint32_t solve_index;
-    int lanes_req;
+    int32_t outputs;         // BSS_OUT_* flags
     LaunchShape shape;
     bool timing;
     std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -272,24 +273,22 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->has_alloc = alloc != nullptr;
     if (alloc) c->alloc = *alloc;
     c->stream = (hipStream_t)stream;
-    c->lanes_req = p->lanes;
     c->shape = choose_shape(p->K, p->M, p->T, p->lanes);
     c->timing = false;
     c->ev_used = 0;
     c->solve_index = 0;
 
     const size_t K = (size_t)p->K, T = (size_t)p->T;
-    const size_t G = (size_t)update_groups(p->K);
+    const size_t G = (size_t)solve_blocks(p->K, 8);   // most blocks any launch shape uses
     const size_t sz_v = align256(T * 2 * sizeof(double));
     const size_t sz_u = align256(K * T * 2 * sizeof(float));
     const size_t sz_mom = align256(K * (T + 1) * 9 * sizeof(double));
     const size_t sz_S = align256(K * sizeof(double));
     const size_t sz_stats = align256(8 * sizeof(double));
     const size_t sz_part = align256(G * (2 * T + 4) * sizeof(double));
-    const size_t sz_cnt = 256;
     const size_t sz_x0 = 256;
     const size_t sz_sig = align256(36 * sizeof(double));
-    const size_t total = sz_v + sz_u + sz_mom + sz_S + sz_stats + sz_part + sz_cnt + sz_x0 + sz_sig;
+    const size_t total = 2 * sz_v + sz_u + sz_mom + sz_S + sz_stats + sz_part + sz_x0 + sz_sig;
 
     void* block = nullptr;
     if (c->has_alloc) {
@@ -307,7 +306,9 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     }
     c->block = block;
     char* b = (char*)block;
-    c->v = (double*)b;
+    c->vbuf[0] = (double*)b;
+    b += sz_v;
+    c->vbuf[1] = (double*)b;
     b += sz_v;
     c->u = (float*)b;
     b += sz_u;
@@ -319,11 +320,12 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     b += sz_stats;
     c->partial = (double*)b;
     b += sz_part;
-    c->counter = (uint32_t*)b;
-    b += sz_cnt;
     c->x0 = (double*)b;
     b += sz_x0;
     c->Sigma0 = (double*)b;
+    c->cur = 0;
+    c->pending_shift = 0;
+    c->outputs = BSS_OUT_CONTROLS;
 
     hipError_t e = hipHostMalloc((void**)&c->host, 16 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -332,7 +334,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         delete c;
         return fail(BSS_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
-    // zero the warm start, counters and stats (whole block: also makes unused slots defined)
+    // zero the warm start and stats (whole block: also makes unused slots defined)
     e = hipMemsetAsync(block, 0, total, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -357,6 +359,7 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
     a.K = p.K;
     a.M = p.M;
     a.T = p.T;
+    a.vshift = c->pending_shift;
     a.solve_index = c->solve_index;
     a.key0 = (uint32_t)p.seed;
     a.key1 = (uint32_t)(p.seed >> 32);
@@ -371,10 +374,11 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
     a.sc = make_score(p);
     a.x0 = x0_dev;
     a.Sigma0 = Sigma0_dev;
-    a.v = c->v;
-    a.u = c->u;
+    a.v = c->vbuf[c->cur];
+    a.u = (c->outputs & BSS_OUT_CONTROLS) ? c->u : nullptr;
     a.mom = c->mom;
     a.S = c->S;
+    a.partial = c->partial;
 
     hipError_t e;
     if (c->timing) {
@@ -389,28 +393,26 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         e = hipEventRecord(c->ev[c->ev_used], c->stream);
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
-    e = launch_rollout(a, c->shape, c->stream);
-    if (e != hipSuccess) return device_fail(e, "rollout launch");
+    e = launch_solve(a, c->shape, c->stream);
+    if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
         e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
         c->ev_used += 2;
     }
-    e = launch_score(a, c->stream);
-    if (e != hipSuccess) return device_fail(e, "score launch");
-    UpdateArgs ua;
-    ua.K = p.K;
-    ua.T = p.T;
-    ua.lambda = p.lambda;
-    ua.S = c->S;
-    ua.u = c->u;
-    ua.v = c->v;
-    ua.partial = c->partial;
-    ua.counter = c->counter;
-    ua.stats = c->stats;
-    ua.groups = update_groups(p.K);
-    e = launch_update(ua, c->stream);
-    if (e != hipSuccess) return device_fail(e, "update launch");
+    MergeArgs ma;
+    ma.T = p.T;
+    ma.G = solve_blocks(p.K, c->shape.lanes);
+    ma.vshift = c->pending_shift;
+    ma.lambda = p.lambda;
+    ma.partial = c->partial;
+    ma.v_in = c->vbuf[c->cur];
+    ma.v_out = c->vbuf[1 - c->cur];
+    ma.stats = c->stats;
+    e = launch_merge(ma, c->stream);
+    if (e != hipSuccess) return device_fail(e, "merge launch");
+    c->cur = 1 - c->cur;
+    c->pending_shift = 0;
     c->solve_index += 1;
     return BSS_OK;
 }
@@ -466,31 +468,46 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
 bss_status bss_step_shift(bss_ctx* c)
 {
     if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
-    hipError_t e = launch_shift(c->v, c->p.T, c->stream);
-    if (e != hipSuccess) return device_fail(e, "shift launch");
+    if (c->pending_shift < c->p.T - 1) c->pending_shift += 1;
+    return BSS_OK;
+}
+
+bss_status bss_set_outputs(bss_ctx* c, int32_t flags)
+{
+    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    if (flags & ~BSS_OUT_CONTROLS) return fail(BSS_E_INVAL, "unknown flags");
+    c->outputs = flags;
     return BSS_OK;
 }
 
 bss_status bss_get_buffers(const bss_ctx* c, bss_buffers* out)
 {
     if (!c || !out) return fail(BSS_E_INVAL, "NULL argument");
-    out->v = c->v;
+    out->v = c->vbuf[c->cur];
     out->u = c->u;
     out->mom = c->mom;
     out->S = c->S;
     out->stats = c->stats;
     out->x0 = c->x0;
     out->Sigma0 = c->Sigma0;
+    out->v_shift = c->pending_shift;
     return BSS_OK;
 }
 
 bss_status bss_get_controls(bss_ctx* c, double* v_host)
 {
     if (!c || !v_host) return fail(BSS_E_INVAL, "NULL argument");
-    hipError_t e = hipMemcpyAsync(v_host, c->v, (size_t)c->p.T * 2 * sizeof(double),
+    const int T = c->p.T;
+    std::vector<double> tmp((size_t)T * 2);
+    hipError_t e = hipMemcpyAsync(tmp.data(), c->vbuf[c->cur], (size_t)T * 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(e, "reading controls");
+    for (int t = 0; t < T; ++t) {
+        const int r = t + c->pending_shift < T ? t + c->pending_shift : T - 1;
+        v_host[2 * t] = tmp[2 * r];
+        v_host[2 * t + 1] = tmp[2 * r + 1];
+    }
     return BSS_OK;
 }
 
@@ -499,10 +516,11 @@ bss_status bss_set_controls(bss_ctx* c, const double* v_host)
     if (!c || !v_host) return fail(BSS_E_INVAL, "NULL argument");
     for (int i = 0; i < 2 * c->p.T; ++i)
         if (!std::isfinite(v_host[i])) return fail(BSS_E_INVAL, "controls must be finite");
-    hipError_t e = hipMemcpyAsync(c->v, v_host, (size_t)c->p.T * 2 * sizeof(double),
+    hipError_t e = hipMemcpyAsync(c->vbuf[c->cur], v_host, (size_t)c->p.T * 2 * sizeof(double),
                                   hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(e, "writing controls");
+    c->pending_shift = 0;
     return BSS_OK;
 }
 
@@ -563,7 +581,6 @@ bss_status bss_set_lanes(bss_ctx* c, int32_t lanes)
     q.lanes = lanes;
     bss_status st = bss_validate(&q);
     if (st != BSS_OK) return st;
-    c->lanes_req = lanes;
     c->shape = choose_shape(q.K, q.M, q.T, lanes);
     return BSS_OK;
 }
@@ -635,6 +652,7 @@ bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u,
     a.K = p->K;
     a.M = p->M;
     a.T = p->T;
+    a.vshift = 0;
     a.sc = make_score(*p);
     a.mom = const_cast<double*>(mom);
     a.u = const_cast<float*>(u);
@@ -648,7 +666,8 @@ bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u,
 size_t bss_dev_update_workspace(int32_t K, int32_t T)
 {
     if (K < 1 || T < 1) return 0;
-    return 256 + (size_t)update_groups(K) * (2 * (size_t)T + 4) * sizeof(double);
+    return align256((size_t)T * 2 * sizeof(double)) +
+           (size_t)partial_blocks(K) * (2 * (size_t)T + 4) * sizeof(double);
 }
 
 bss_status bss_dev_update(const bss_params* p, const double* S, const float* u, double* v,
@@ -657,19 +676,24 @@ bss_status bss_dev_update(const bss_params* p, const double* S, const float* u, 
     bss_status st = bss_validate(p);
     if (st != BSS_OK) return st;
     if (!S || !u || !v || !stats || !workspace) return fail(BSS_E_INVAL, "NULL buffer");
-    UpdateArgs ua;
-    ua.K = p->K;
-    ua.T = p->T;
-    ua.lambda = p->lambda;
-    ua.S = S;
-    ua.u = u;
-    ua.v = v;
-    ua.counter = (uint32_t*)workspace;
-    ua.partial = (double*)((char*)workspace + 256);
-    ua.stats = stats;
-    ua.groups = update_groups(p->K);
-    hipError_t e = launch_update(ua, (hipStream_t)stream);
-    if (e != hipSuccess) return device_fail(e, "update launch");
+    hipStream_t s = (hipStream_t)stream;
+    double* v_out = (double*)workspace;
+    double* partial = (double*)((char*)workspace + align256((size_t)p->T * 2 * sizeof(double)));
+    hipError_t e = launch_partials(p->K, p->T, p->lambda, S, u, v, partial, s);
+    if (e != hipSuccess) return device_fail(e, "partial launch");
+    MergeArgs ma;
+    ma.T = p->T;
+    ma.G = partial_blocks(p->K);
+    ma.vshift = 0;
+    ma.lambda = p->lambda;
+    ma.partial = partial;
+    ma.v_in = v;
+    ma.v_out = v_out;
+    ma.stats = stats;
+    e = launch_merge(ma, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(v, v_out, (size_t)p->T * 2 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return device_fail(e, "merge launch");
     return BSS_OK;
 }
 

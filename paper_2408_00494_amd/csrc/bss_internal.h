@@ -38,6 +38,7 @@ struct ScoreF64 {
 // One solve's launch description.
 struct SolveArgs {
     int32_t K, M, T;
+    int32_t vshift;                // the mean sequence is read as v[min(t + vshift, T - 1)]
     uint32_t solve_index;
     uint32_t key0, key1;           // Philox key = (lo32 seed, hi32 seed)
     float steer_max, accel_max;
@@ -47,23 +48,27 @@ struct SolveArgs {
     ScoreF64 sc;
     const double* x0;              // device [6]
     const double* Sigma0;          // device [36] row-major, or nullptr
-    const double* v;               // device [T][2]
-    float* u;                      // device [K][T][2]
-    double* mom;                   // device [K][T+1][9]
-    double* S;                     // device [K]
+    const double* v;               // device [T][2] mean sequence read by this solve
+    float* u;                      // device [K][T][2] copy of the sampled controls, or nullptr
+    double* mom;                   // device [K][T+1][9] beliefs (always written; scoring reads them)
+    double* S;                     // device [K] trajectory costs
+    double* partial;               // device [G][2T + 4] per-block log-sum-exp partials
 };
 
-struct UpdateArgs {
-    int32_t K, T;
+// Per-block partial of the K-reduction (weights relative to the block's own minimum cost m_b):
+//   [0, 2T)  N_i = sum_k w_k (u_{k,i} - v_i),   [2T] Z_b = sum w_k,   [2T+1] sum w_k^2,
+//   [2T+2]   number of finite costs,            [2T+3] m_b (+inf if none is finite).
+struct MergeArgs {
+    int32_t T, G, vshift;
     double lambda;
-    const double* S;               // [K]
-    const float* u;                // [K][T][2]
-    double* v;                     // [T][2] in/out
-    double* partial;               // [G][2T + 4]: numerators, Z, sum w^2, #finite, slice min
-    uint32_t* counter;             // one word, zero between launches
-    double* stats;                 // [8]: S_min, Z, ESS, n_finite, status, u0_0, u0_1, spare
-    int32_t groups;                // G
+    const double* partial;         // [G][2T + 4]
+    const double* v_in;            // [T][2] mean sequence the solve read (with vshift)
+    double* v_out;                 // [T][2] updated mean sequence (a different buffer)
+    double* stats;                 // [8]: S_min, Z, ESS, #finite, status, v+_0 (2), unused
 };
+
+// samples per block of the partial kernel used for stand-alone K-reductions
+constexpr int kPartialSlice = 16;
 
 // lanes per sample (L) and particles per lane (P) of one rollout launch
 struct LaunchShape {
@@ -71,18 +76,22 @@ struct LaunchShape {
     int ppl;
 };
 
-constexpr int kUpdateGroupsMax = 64;
-constexpr int kMaxT = 256;   // u staging in LDS: (256/L) * T * 8 bytes <= 64 KiB
+constexpr int kMaxT = 256;
+constexpr size_t kMaxLds = 65536;
 
+// dynamic LDS of one solve block with L lanes per sample
+size_t solve_lds_bytes(int lanes, int T);
 LaunchShape choose_shape(int K, int M, int T, int requested_lanes);
+int solve_blocks(int K, int lanes);
 
-hipError_t launch_rollout(const SolveArgs& a, LaunchShape shape, hipStream_t stream);
-hipError_t launch_score(const SolveArgs& a, hipStream_t stream);
-hipError_t launch_update(const UpdateArgs& a, hipStream_t stream);
-hipError_t launch_shift(double* v, int T, hipStream_t stream);
-int update_groups(int K);
+hipError_t launch_solve(const SolveArgs& a, LaunchShape shape, hipStream_t stream);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t stream);
 
 // stand-alone kernels for staged checks
+hipError_t launch_score(const SolveArgs& a, hipStream_t stream);
+hipError_t launch_partials(int K, int T, double lambda, const double* S, const float* u,
+                           const double* v, double* partial, hipStream_t stream);
+int partial_blocks(int K);
 hipError_t launch_philox(uint32_t key0, uint32_t key1, const uint32_t* ctr, uint32_t* out,
                          int64_t n, hipStream_t stream);
 hipError_t launch_normals(uint32_t key0, uint32_t key1, const uint32_t* ctr, float* z, int64_t n,

@@ -1,17 +1,20 @@
 // bss_kernels.hip -- HIP kernels of the BSS-MPPI solve for gfx950 (MI355X).
 //
-// One solve = three launches on one stream:
-//   rollout  : L lanes per control sample k (256/L samples per 256-thread block), P particles per
-//              lane in registers.  Draws eps_{k,t} (Philox tag 0) lane-parallel over t, optionally
-//              shield-repairs u_{k,t} per step, propagates the M particles with the single-
-//              precision midpoint rule plus the disturbance (tag 1), and reduces the particle
-//              mean and position covariance across the L lanes in double precision every step.
-//   score    : one wave per sample, lanes parallel over t: signed distance, sigma_y, barrier h,
-//              running/terminal cost, control cost, C_safe on the transitions; S_k in double.
-//   update   : log-sum-exp K-reduction in double precision: each block takes a slice of the
-//              samples, forms weights relative to its own minimum cost, and the last block to
-//              finish merges the slices with the rescaling exp(-(m_b - m)/lambda), then writes
-//              v+ = v + N/Z in place.
+// One solve = two launches on one stream:
+//   solve  : L lanes per control sample k (256/L samples per 256-thread block), P particles per
+//            lane in registers.  Draws eps_{k,t} (Philox tag 0) lane-parallel over t, optionally
+//            shield-repairs u_{k,t} per step, propagates the M particles with the single-
+//            precision midpoint rule plus the disturbance (tag 1), reduces the particle mean and
+//            position covariance across the L lanes in double precision every step (the belief
+//            record of each step goes to a [K][T+1][9] buffer), then scores the belief
+//            trajectory L records at a time (one per lane: signed distance, sigma_y, barrier h,
+//            running cost, control cost, C_safe), and folds the block's samples into a
+//            log-sum-exp partial (weights relative to the block's own minimum cost).  Scoring
+//            after the particle loop keeps its double-precision temporaries out of the loop's
+//            register budget.
+//   merge  : one block per control entry (t, j): rescales the block partials to the global
+//            minimum, exp(-(m_b - m)/lambda), and writes v+ = v + N/Z into the other buffer of the
+//            ping-pong pair (so no block reads what another writes).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -59,20 +62,106 @@ __device__ __forceinline__ double group_sum(double x)
     return x;
 }
 
+__device__ __forceinline__ int vrow(int t, int vshift, int T)
+{
+    const int r = t + vshift;
+    return r < T ? r : T - 1;
+}
+
+// Score one chunk of belief records, one record per lane of a W-lane group: running cost (times
+// phi_scale on the terminal record), control cost on records < T, and C_safe on the transition
+// into the record (record 0 has none).  `h_carry` holds h of the record before the chunk and is
+// advanced to the chunk's last record.  Returns this lane's contribution.
+template <int W>
+__device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int rec_idx, int count,
+                                     int lane, int T, const float2* u_row, const double* v,
+                                     int vshift, double& h_carry)
+{
+    const bool valid = lane < count;
+    double part = 0.0;
+    double h = 0.0;
+    if (valid) {
+        const BeliefEval be = eval_belief(sc, rec);
+        double q = stage_cost(sc, rec, be);
+        if (rec_idx == T) {
+            q *= sc.phi_scale;
+        } else {
+            const float2 ut = u_row[rec_idx];
+            const int r = vrow(rec_idx, vshift, T);
+            q += sc.gamma_u * (v[2 * r] * sc.inv_var0 * (double)ut.x +
+                               v[2 * r + 1] * sc.inv_var1 * (double)ut.y);
+        }
+        h = be.h;
+        part = q;
+    }
+    const double h_left = __shfl(h, lane > 0 ? lane - 1 : 0, W);
+    const double h_prev = lane == 0 ? h_carry : h_left;
+    if (valid && rec_idx >= 1) part += sc.C_cbf * fmax(-h + (1.0 - sc.gamma) * h_prev, 0.0);
+    h_carry = __shfl(h, count - 1, W);
+    return part;
+}
+
+// Fold n samples (costs S_sh[0..n), controls u_sh[g][T]) into one log-sum-exp partial.
+// Must be called by all 256 threads of the block after the inputs are visible in LDS.
+__device__ inline void block_partial(int T, int n, const double* S_sh, double* w_sh,
+                                     const float2* u_sh, const double* v, int vshift,
+                                     double lambda, double* out)
+{
+    const int tid = threadIdx.x;
+    double mb = INFINITY;
+    for (int g = 0; g < n; ++g) {
+        const double s = S_sh[g];
+        if (isfinite(s)) mb = fmin(mb, s);
+    }
+    if (tid < n) {
+        const double s = S_sh[tid];
+        w_sh[tid] = (isfinite(s) && isfinite(mb)) ? exp(-(s - mb) / lambda) : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * T; i += 256) {
+        const int t = i >> 1;
+        const int r = vrow(t, vshift, T);
+        const double vi = v[2 * r + (i & 1)];
+        double acc = 0.0;
+        for (int g = 0; g < n; ++g) {
+            const float2 ut = u_sh[g * T + t];
+            const double ui = (i & 1) ? (double)ut.y : (double)ut.x;
+            acc += w_sh[g] * (ui - vi);
+        }
+        out[i] = acc;
+    }
+    if (tid == 0) {
+        double Z = 0.0, W2 = 0.0, nf = 0.0;
+        for (int g = 0; g < n; ++g) {
+            Z += w_sh[g];
+            W2 += w_sh[g] * w_sh[g];
+            nf += isfinite(S_sh[g]) ? 1.0 : 0.0;
+        }
+        out[2 * T] = Z;
+        out[2 * T + 1] = W2;
+        out[2 * T + 2] = nf;
+        out[2 * T + 3] = mb;
+    }
+}
+
 // ----------------------------------------------------------------------------------------------
-// rollout
+// solve: rollout + scoring + block partial of the K-reduction
 // ----------------------------------------------------------------------------------------------
 template <int L, int P, bool SHIELD>
-__global__ __launch_bounds__(256) void rollout_kernel(SolveArgs a)
+__global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
 {
     constexpr int kGroups = 256 / L;
-    extern __shared__ float2 u_sh[];
+    extern __shared__ double smem[];
     const int T = a.T, M = a.M;
+    double* S_sh = smem;                                     // [kGroups]
+    double* w_sh = S_sh + kGroups;                           // [kGroups]
+    float2* u_sh = reinterpret_cast<float2*>(w_sh + kGroups);  // [kGroups][T]
     const int g = threadIdx.x / L;
     const int j = threadIdx.x % L;
     const int k = blockIdx.x * kGroups + g;
     const bool active = k < a.K;
     float2* us = u_sh + g * T;
+    double* mom_k = a.mom + (size_t)(active ? k : 0) * (T + 1) * 9;
     const uint32_t s = a.solve_index;
 
     // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
@@ -82,379 +171,317 @@ __global__ __launch_bounds__(256) void rollout_kernel(SolveArgs a)
             philox10(c0, c1, c2, c3, a.key0, a.key1);
             float z0, z1;
             bm_pair(c0, c1, z0, z1);
-            const float v0 = (float)a.v[2 * t], v1 = (float)a.v[2 * t + 1];
+            const int r = vrow(t, a.vshift, T);
+            const float v0 = (float)a.v[2 * r], v1 = (float)a.v[2 * r + 1];
             const float u0 = fminf(fmaxf(fmaf(a.sig_eps0, z0, v0), -a.steer_max), a.steer_max);
             const float u1 = fminf(fmaxf(fmaf(a.sig_eps1, z1, v1), -a.accel_max), a.accel_max);
             us[t] = make_float2(u0, u1);
-            if (!SHIELD) {
-                float2* uo = reinterpret_cast<float2*>(a.u) + (size_t)k * T + t;
-                *uo = make_float2(u0, u1);
-            }
+            if (!SHIELD && a.u) reinterpret_cast<float2*>(a.u)[(size_t)k * T + t] = us[t];
         }
     }
     __syncthreads();
-    if (!active) return;
 
-    // ---- phase 2: particles ----
-    double x0[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) x0[i] = a.x0[i];
-    const bool spread = a.Sigma0 != nullptr;
-    double L0[36];
-    if (spread) chol6(a.Sigma0, L0);
-
-    // state relative to the estimate: position and heading as compensated (sum, correction)
-    float Xs[P], Xc[P], Ys[P], Yc[P], Ps[P], Pc[P], vx[P], vy[P], vr[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int m = j + p * L;
-        double dev[6] = {0, 0, 0, 0, 0, 0};
-        if (spread) {
-            double xi[6];
-#pragma unroll
-            for (int blk = 0; blk < 2; ++blk) {
-                uint32_t c0 = (uint32_t)blk, c1 = (uint32_t)m, c2 = (uint32_t)k,
-                         c3 = rng_word3(kTagInit, s);
-                philox10(c0, c1, c2, c3, a.key0, a.key1);
-                float z0, z1;
-                bm_pair(c0, c1, z0, z1);
-                xi[blk * 3 + 0] = z0;
-                xi[blk * 3 + 1] = z1;
-                xi[blk * 3 + 2] = bm_cos(c2, c3);
-            }
-            for (int i = 0; i < 6; ++i) {
-                double acc = 0.0;
-                for (int q = 0; q <= i; ++q) acc += L0[i * 6 + q] * xi[q];
-                dev[i] = acc;
-            }
-        }
-        Xs[p] = (float)dev[0];
-        Xc[p] = (float)((double)Xs[p] - dev[0]);
-        Ys[p] = (float)dev[1];
-        Yc[p] = (float)((double)Ys[p] - dev[1]);
-        Ps[p] = (float)dev[2];
-        Pc[p] = (float)((double)Ps[p] - dev[2]);
-        vx[p] = (float)(x0[3] + dev[3]);
-        vy[p] = (float)(x0[4] + dev[4]);
-        vr[p] = (float)(x0[5] + dev[5]);
-    }
-    const double rev0d = x0[2] * 0.15915494309189535;
-    const float rev0 = (float)(rev0d - rint(rev0d));
-    const CarF32 car = a.car;
-
-    double* mom_k = a.mom + (size_t)k * (T + 1) * 9;
-    // belief at t = 0 is the given estimate
-    double bel[9];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) bel[i] = x0[i];
-    bel[6] = spread ? a.Sigma0[0] : 0.0;
-    bel[7] = spread ? a.Sigma0[1] : 0.0;
-    bel[8] = spread ? a.Sigma0[7] : 0.0;
-    if (j == 0) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
-    }
-    const uint32_t c3w = rng_word3(kTagW, s);
-    const double invM = 1.0 / (double)M;
-    const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
-
-    for (int t = 0; t < T; ++t) {
-        float2 uu = us[t];
-        if (SHIELD) {
-            const ScoreF64& sc = a.sc;
-            if (sc.shield_iters > 0) {
-                const BeliefEval be = eval_belief(sc, bel);
-                const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
-                const double margin2 = margin * margin;
-                const double fd = sc.shield_fd;
-                const int role = j < 5 ? j : 0;
-                const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
-                const double o1 = role == 3 ? fd : (role == 4 ? -fd : 0.0);
-                double us0 = uu.x, us1 = uu.y;
-                for (int it = 0; it < sc.shield_iters; ++it) {
-                    // lanes 0-4 of the group evaluate r at u and at the four difference points
-                    const double rv = repair_residual(sc, bel, margin2, be.h, us0 + o0, us1 + o1);
-                    const double r0 = __shfl(rv, 0, L);
-                    const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
-                    const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
-                    if (!(r0 > 0.0)) break;
-                    const double g0 = (rp0 - rm0) / (2.0 * fd);
-                    const double g1 = (rp1 - rm1) / (2.0 * fd);
-                    const double den = g0 * g0 + g1 * g1 + sc.shield_gmin * sc.shield_gmin;
-                    us0 = clampd(us0 - r0 * g0 / den, -sc.steer_max, sc.steer_max);
-                    us1 = clampd(us1 - r0 * g1 / den, -sc.accel_max, sc.accel_max);
-                }
-                uu = make_float2((float)us0, (float)us1);
-            }
-            if (j == 0) {
-                float2* uo = reinterpret_cast<float2*>(a.u) + (size_t)k * T + t;
-                *uo = uu;
-            }
-        }
-        const StepF32 st = make_step(car, uu.x, uu.y);
-        double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0, sYY = 0;
-        double refX = 0.0, refY = 0.0;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int m = j + p * L;
-            uint32_t c0 = (uint32_t)t, c1 = (uint32_t)m, c2 = (uint32_t)k, c3 = c3w;
-            philox10(c0, c1, c2, c3, a.key0, a.key1);
-            float w0, w1;
-            bm_pair(c0, c1, w0, w1);
-            const float w2 = bm_cos(c2, c3);
-
-            float dX1, dY1, dvx1, dvy1, dr1;
-            car_field_f32(car, st, fmaf(Ps[p], kInv2Pi, rev0), vx[p], vy[p], vr[p], dX1, dY1,
-                          dvx1, dvy1, dr1);
-            const float pm = fmaf(car.half_dt, vr[p], Ps[p]);
-            const float vxm = fmaf(car.half_dt, dvx1, vx[p]);
-            const float vym = fmaf(car.half_dt, dvy1, vy[p]);
-            const float vrm = fmaf(car.half_dt, dr1, vr[p]);
-            float dX2, dY2, dvx2, dvy2, dr2;
-            car_field_f32(car, st, fmaf(pm, kInv2Pi, rev0), vxm, vym, vrm, dX2, dY2, dvx2, dvy2,
-                          dr2);
-            kahan_add(Xs[p], Xc[p], car.dt * dX2);
-            kahan_add(Ys[p], Yc[p], car.dt * dY2);
-            kahan_add(Ps[p], Pc[p], car.dt * vrm);
-            vx[p] = fmaf(a.sig_w0, w0, fmaf(car.dt, dvx2, vx[p]));
-            vy[p] = fmaf(a.sig_w1, w1, fmaf(car.dt, dvy2, vy[p]));
-            vr[p] = fmaf(a.sig_w2, w2, fmaf(car.dt, dr2, vr[p]));
-
-            if (p == 0) {
-                // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
-                refX = (double)__shfl(Xs[0], 0, L) - (double)__shfl(Xc[0], 0, L);
-                refY = (double)__shfl(Ys[0], 0, L) - (double)__shfl(Yc[0], 0, L);
-            }
-            if (m < M) {   // masked particles beyond M contribute nothing
-                const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
-                const double Y = ((double)Ys[p] - (double)Yc[p]) - refY;
-                sX += X;
-                sY += Y;
-                sP += (double)Ps[p] - (double)Pc[p];
-                svx += (double)vx[p];
-                svy += (double)vy[p];
-                svr += (double)vr[p];
-                sXX = fma(X, X, sXX);
-                sXY = fma(X, Y, sXY);
-                sYY = fma(Y, Y, sYY);
-            }
-        }
-        sX = group_sum<L>(sX);
-        sY = group_sum<L>(sY);
-        sP = group_sum<L>(sP);
-        svx = group_sum<L>(svx);
-        svy = group_sum<L>(svy);
-        svr = group_sum<L>(svr);
-        sXX = group_sum<L>(sXX);
-        sXY = group_sum<L>(sXY);
-        sYY = group_sum<L>(sYY);
-        // moments: sums of positions shifted by particle 0, heading relative to the estimate
-        const double mX = sX * invM, mY = sY * invM;
-        bel[0] = x0[0] + (refX + mX);
-        bel[1] = x0[1] + (refY + mY);
-        bel[2] = x0[2] + sP * invM;
-        bel[3] = svx * invM;
-        bel[4] = svy * invM;
-        bel[5] = svr * invM;
-        bel[6] = (sXX - sX * mX) * invM1;
-        bel[7] = (sXY - sX * mY) * invM1;
-        bel[8] = (sYY - sY * mY) * invM1;
-        if (j == 0) {
-            double* rec = mom_k + (size_t)(t + 1) * 9;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) rec[i] = bel[i];
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------------------------
-// score: one wave per sample
-// ----------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void score_kernel(int K, int T, ScoreF64 sc, const double* mom,
-                                                    const float* u, const double* v, double* S)
-{
-    extern __shared__ double h_sh[];   // [4][T+1]
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int k = blockIdx.x * 4 + w;
-    const bool active = k < K;
-    double* hs = h_sh + w * (T + 1);
-    double part = 0.0;
     if (active) {
-        const double* mk = mom + (size_t)k * (T + 1) * 9;
-        for (int t = lane; t <= T; t += 64) {
-            const double* rec = mk + (size_t)t * 9;
-            const BeliefEval be = eval_belief(sc, rec);
-            double q = stage_cost(sc, rec, be);
-            if (t == T) {
-                q *= sc.phi_scale;
-            } else {
-                const float2 ut = reinterpret_cast<const float2*>(u)[(size_t)k * T + t];
-                q += sc.gamma_u * (v[2 * t] * sc.inv_var0 * (double)ut.x +
-                                   v[2 * t + 1] * sc.inv_var1 * (double)ut.y);
-            }
-            hs[t] = be.h;
-            part += q;
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    for (int t = lane; t <= T; t += 64) {
-        if (t >= 1) {
-            const double viol = -hs[t] + (1.0 - sc.gamma) * hs[t - 1];
-            part += sc.C_cbf * fmax(viol, 0.0);
-        }
-    }
+        double x0[6];
 #pragma unroll
-    for (int mask = 1; mask < 64; mask <<= 1) part += __shfl_xor(part, mask, 64);
-    if (lane == 0) S[k] = part;
-}
+        for (int i = 0; i < 6; ++i) x0[i] = a.x0[i];
+        const bool spread = a.Sigma0 != nullptr;
 
-// ----------------------------------------------------------------------------------------------
-// update: log-sum-exp K-reduction with the weighted perturbation average
-// ----------------------------------------------------------------------------------------------
-constexpr int kUpdateSlice = 256;   // samples per block
-
-__device__ __forceinline__ double block_min_256(double x, double* red)
-{
-    const int tid = threadIdx.x;
-    red[tid] = x;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) red[tid] = fmin(red[tid], red[tid + off]);
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ double block_sum_256(double x, double* red)
-{
-    const int tid = threadIdx.x;
-    red[tid] = x;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a)
-{
-    __shared__ double w_sh[kUpdateSlice];
-    __shared__ double red[256];
-    __shared__ bool is_last;
-    const int tid = threadIdx.x;
-    const int K = a.K, T = a.T;
-    const int k_begin = blockIdx.x * kUpdateSlice;
-    const int k_end = min(K, k_begin + kUpdateSlice);
-    const int nk = k_end - k_begin;
-    const int width = 2 * T + 3;   // numerators, Z, sum w^2, finite count
-    double* part = a.partial + (size_t)blockIdx.x * (width + 1);
-
-    // block-local minimum over finite costs
-    double Sk = INFINITY;
-    bool fin = false;
-    if (tid < nk) {
-        Sk = a.S[k_begin + tid];
-        fin = isfinite(Sk);
-    }
-    const double mb = block_min_256(fin ? Sk : INFINITY, red);
-    const double wk = (fin && isfinite(mb)) ? exp(-(Sk - mb) / a.lambda) : 0.0;
-    if (tid < nk) w_sh[tid] = wk;
-    const double Zb = block_sum_256(wk, red);
-    const double W2b = block_sum_256(wk * wk, red);
-    const double nf = block_sum_256(fin ? 1.0 : 0.0, red);
-    for (int i = tid; i < 2 * T; i += 256) {
-        const double vi = a.v[i];
-        double acc = 0.0;
-        for (int q = 0; q < nk; ++q) {
-            const double w = w_sh[q];
-            const double ui = (double)a.u[(size_t)(k_begin + q) * 2 * T + i];
-            acc += w * (ui - vi);
+        // state relative to the estimate: position and heading as compensated (sum, correction)
+        float Xs[P], Xc[P], Ys[P], Yc[P], Ps[P], Pc[P], vx[P], vy[P], vr[P];
+        {
+            double L0[36];
+            if (spread) chol6(a.Sigma0, L0);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int m = j + p * L;
+                double dev[6] = {0, 0, 0, 0, 0, 0};
+                if (spread) {
+                    double xi[6];
+#pragma unroll
+                    for (int blk = 0; blk < 2; ++blk) {
+                        uint32_t c0 = (uint32_t)blk, c1 = (uint32_t)m, c2 = (uint32_t)k,
+                                 c3 = rng_word3(kTagInit, s);
+                        philox10(c0, c1, c2, c3, a.key0, a.key1);
+                        float z0, z1;
+                        bm_pair(c0, c1, z0, z1);
+                        xi[blk * 3 + 0] = z0;
+                        xi[blk * 3 + 1] = z1;
+                        xi[blk * 3 + 2] = bm_cos(c2, c3);
+                    }
+                    for (int i = 0; i < 6; ++i) {
+                        double acc = 0.0;
+                        for (int q = 0; q <= i; ++q) acc += L0[i * 6 + q] * xi[q];
+                        dev[i] = acc;
+                    }
+                }
+                Xs[p] = (float)dev[0];
+                Xc[p] = (float)((double)Xs[p] - dev[0]);
+                Ys[p] = (float)dev[1];
+                Yc[p] = (float)((double)Ys[p] - dev[1]);
+                Ps[p] = (float)dev[2];
+                Pc[p] = (float)((double)Ps[p] - dev[2]);
+                vx[p] = (float)(x0[3] + dev[3]);
+                vy[p] = (float)(x0[4] + dev[4]);
+                vr[p] = (float)(x0[5] + dev[5]);
+            }
         }
-        part[i] = acc;
-    }
-    if (tid == 0) {
-        part[2 * T] = Zb;
-        part[2 * T + 1] = W2b;
-        part[2 * T + 2] = nf;
-        part[2 * T + 3] = mb;
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const uint32_t done = atomicAdd(a.counter, 1u);
-        is_last = (done == (uint32_t)(gridDim.x - 1));
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+        const double rev0d = x0[2] * 0.15915494309189535;
+        const float rev0 = (float)(rev0d - rint(rev0d));
+        const CarF32 car = a.car;
 
-    // last block: merge the slices in a fixed order
-    const int G = gridDim.x;
+        // belief at t = 0 is the given estimate (record 0)
+        double bel[9];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) bel[i] = x0[i];
+        bel[6] = spread ? a.Sigma0[0] : 0.0;
+        bel[7] = spread ? a.Sigma0[1] : 0.0;
+        bel[8] = spread ? a.Sigma0[7] : 0.0;
+        if (j == 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
+        }
+        const uint32_t c3w = rng_word3(kTagW, s);
+        const double invM = 1.0 / (double)M;
+        const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
+
+        for (int t = 0; t < T; ++t) {
+            float2 uu = us[t];
+            if (SHIELD) {
+                const ScoreF64& sc = a.sc;
+                if (sc.shield_iters > 0) {
+                    const BeliefEval be = eval_belief(sc, bel);
+                    const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
+                    const double margin2 = margin * margin;
+                    const double fd = sc.shield_fd;
+                    const int role = j < 5 ? j : 0;
+                    const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
+                    const double o1 = role == 3 ? fd : (role == 4 ? -fd : 0.0);
+                    double us0 = uu.x, us1 = uu.y;
+                    for (int it = 0; it < sc.shield_iters; ++it) {
+                        // lanes 0-4 of the group evaluate r at u and at the four difference points
+                        const double rv =
+                            repair_residual(sc, bel, margin2, be.h, us0 + o0, us1 + o1);
+                        const double r0 = __shfl(rv, 0, L);
+                        const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
+                        const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
+                        if (!(r0 > 0.0)) break;
+                        const double g0 = (rp0 - rm0) / (2.0 * fd);
+                        const double g1 = (rp1 - rm1) / (2.0 * fd);
+                        const double den = g0 * g0 + g1 * g1 + sc.shield_gmin * sc.shield_gmin;
+                        us0 = clampd(us0 - r0 * g0 / den, -sc.steer_max, sc.steer_max);
+                        us1 = clampd(us1 - r0 * g1 / den, -sc.accel_max, sc.accel_max);
+                    }
+                    uu = make_float2((float)us0, (float)us1);
+                }
+                if (j == 0) {
+                    us[t] = uu;
+                    if (a.u) reinterpret_cast<float2*>(a.u)[(size_t)k * T + t] = uu;
+                }
+            }
+            const StepF32 st = make_step(car, uu.x, uu.y);
+            double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0, sYY = 0;
+            double refX = 0.0, refY = 0.0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int m = j + p * L;
+                uint32_t c0 = (uint32_t)t, c1 = (uint32_t)m, c2 = (uint32_t)k, c3 = c3w;
+                philox10(c0, c1, c2, c3, a.key0, a.key1);
+                float w0, w1;
+                bm_pair(c0, c1, w0, w1);
+                const float w2 = bm_cos(c2, c3);
+
+                float dX1, dY1, dvx1, dvy1, dr1;
+                car_field_f32(car, st, fmaf(Ps[p], kInv2Pi, rev0), vx[p], vy[p], vr[p], dX1, dY1,
+                              dvx1, dvy1, dr1);
+                const float pm = fmaf(car.half_dt, vr[p], Ps[p]);
+                const float vxm = fmaf(car.half_dt, dvx1, vx[p]);
+                const float vym = fmaf(car.half_dt, dvy1, vy[p]);
+                const float vrm = fmaf(car.half_dt, dr1, vr[p]);
+                float dX2, dY2, dvx2, dvy2, dr2;
+                car_field_f32(car, st, fmaf(pm, kInv2Pi, rev0), vxm, vym, vrm, dX2, dY2, dvx2,
+                              dvy2, dr2);
+                kahan_add(Xs[p], Xc[p], car.dt * dX2);
+                kahan_add(Ys[p], Yc[p], car.dt * dY2);
+                kahan_add(Ps[p], Pc[p], car.dt * vrm);
+                vx[p] = fmaf(a.sig_w0, w0, fmaf(car.dt, dvx2, vx[p]));
+                vy[p] = fmaf(a.sig_w1, w1, fmaf(car.dt, dvy2, vy[p]));
+                vr[p] = fmaf(a.sig_w2, w2, fmaf(car.dt, dr2, vr[p]));
+
+                if (p == 0) {
+                    // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
+                    refX = (double)__shfl(Xs[0], 0, L) - (double)__shfl(Xc[0], 0, L);
+                    refY = (double)__shfl(Ys[0], 0, L) - (double)__shfl(Yc[0], 0, L);
+                }
+                if (m < M) {   // masked particles beyond M contribute nothing
+                    const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
+                    const double Y = ((double)Ys[p] - (double)Yc[p]) - refY;
+                    sX += X;
+                    sY += Y;
+                    sP += (double)Ps[p] - (double)Pc[p];
+                    svx += (double)vx[p];
+                    svy += (double)vy[p];
+                    svr += (double)vr[p];
+                    sXX = fma(X, X, sXX);
+                    sXY = fma(X, Y, sXY);
+                    sYY = fma(Y, Y, sYY);
+                }
+            }
+            sX = group_sum<L>(sX);
+            sY = group_sum<L>(sY);
+            sP = group_sum<L>(sP);
+            svx = group_sum<L>(svx);
+            svy = group_sum<L>(svy);
+            svr = group_sum<L>(svr);
+            sXX = group_sum<L>(sXX);
+            sXY = group_sum<L>(sXY);
+            sYY = group_sum<L>(sYY);
+            // moments: sums of positions shifted by particle 0, heading relative to the estimate
+            const double mX = sX * invM, mY = sY * invM;
+            bel[0] = x0[0] + (refX + mX);
+            bel[1] = x0[1] + (refY + mY);
+            bel[2] = x0[2] + sP * invM;
+            bel[3] = svx * invM;
+            bel[4] = svy * invM;
+            bel[5] = svr * invM;
+            bel[6] = (sXX - sX * mX) * invM1;
+            bel[7] = (sXY - sX * mY) * invM1;
+            bel[8] = (sYY - sY * mY) * invM1;
+
+            // record t+1, written by lane (t+1) % L of the group (spreads the stores)
+            if (j == (t + 1) % L) {
+                double* rec = mom_k + (size_t)(t + 1) * 9;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+            }
+        }
+    }
+    // ---- phase 3: score the belief trajectory, L records at a time (one per lane) ----
+    __threadfence_block();
+    __syncthreads();
+    double S_part = 0.0;
+    if (active) {
+        double h_carry = 0.0;
+        for (int base = 0; base <= T; base += L) {
+            const int count = min(L, T + 1 - base);
+            const int rec = base + min(j, count - 1);
+            S_part += score_chunk<L>(a.sc, mom_k + (size_t)rec * 9, base + j, count, j, T, us,
+                                     a.v, a.vshift, h_carry);
+        }
+    }
+    const double S_k = group_sum<L>(S_part);
+    if (j == 0) {
+        S_sh[g] = active ? S_k : INFINITY;
+        if (active) a.S[k] = S_k;
+    }
+    __syncthreads();
+    const int n = min(kGroups, a.K - (int)blockIdx.x * kGroups);
+    block_partial(T, n, S_sh, w_sh, u_sh, a.v, a.vshift, a.sc.lambda,
+                  a.partial + (size_t)blockIdx.x * (2 * T + 4));
+}
+
+// ----------------------------------------------------------------------------------------------
+// merge: one block per control entry
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_reduce_256(double x, double* red, bool is_min)
+{
+    const int tid = threadIdx.x;
+    red[tid] = x;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) red[tid] = is_min ? fmin(red[tid], red[tid + off]) : red[tid] + red[tid + off];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(MergeArgs a)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int T = a.T, G = a.G;
+    const int col = blockIdx.x;          // control entry 2t + j
+    const int stride = 2 * T + 4;
     double m = INFINITY;
-    for (int b = 0; b < G; ++b) m = fmin(m, a.partial[(size_t)b * (width + 1) + 2 * T + 3]);
-    double Z = 0.0, W2 = 0.0, n_fin = 0.0;
-    for (int b = 0; b < G; ++b) {
-        const double* pb = a.partial + (size_t)b * (width + 1);
-        const double sc = isfinite(pb[2 * T + 3]) ? exp(-(pb[2 * T + 3] - m) / a.lambda) : 0.0;
+    for (int b = tid; b < G; b += 256) m = fmin(m, a.partial[(size_t)b * stride + 2 * T + 3]);
+    m = block_reduce_256(m, red, true);
+    double Z = 0.0, W2 = 0.0, nf = 0.0, N = 0.0;
+    for (int b = tid; b < G; b += 256) {
+        const double* pb = a.partial + (size_t)b * stride;
+        const double mb = pb[2 * T + 3];
+        const double sc = isfinite(mb) ? exp(-(mb - m) / a.lambda) : 0.0;
         Z += sc * pb[2 * T];
         W2 += sc * sc * pb[2 * T + 1];
-        n_fin += pb[2 * T + 2];
+        nf += pb[2 * T + 2];
+        N += sc * pb[col];
     }
-    const bool ok = n_fin > 0.0 && Z > 0.0;
-    for (int i = tid; i < 2 * T; i += 256) {
-        double num = 0.0;
-        for (int b = 0; b < G; ++b) {
-            const double* pb = a.partial + (size_t)b * (width + 1);
-            const double sc = isfinite(pb[2 * T + 3]) ? exp(-(pb[2 * T + 3] - m) / a.lambda) : 0.0;
-            num += sc * pb[i];
-        }
-        if (ok) a.v[i] = a.v[i] + num / Z;
-    }
-    __syncthreads();
+    Z = block_reduce_256(Z, red, false);
+    W2 = block_reduce_256(W2, red, false);
+    nf = block_reduce_256(nf, red, false);
+    N = block_reduce_256(N, red, false);
     if (tid == 0) {
-        a.stats[0] = m;
-        a.stats[1] = Z;
-        a.stats[2] = ok ? Z * Z / W2 : 0.0;
-        a.stats[3] = n_fin;
-        a.stats[4] = ok ? 0.0 : 5.0;
-        a.stats[5] = a.v[0];
-        a.stats[6] = a.v[1];
-        a.stats[7] = 0.0;
-        *a.counter = 0u;
-    }
-}
-
-__global__ void shift_kernel(double* v, int T)
-{
-    // one block: read everything, then write shifted
-    const int tid = threadIdx.x;
-    double a0 = 0.0, a1 = 0.0;
-    for (int base = 0; base < T; base += 256) {
-        const int t = base + tid;
-        const bool ok = t < T;
-        const int src = (t + 1 < T) ? t + 1 : T - 1;
-        if (ok) {
-            a0 = v[2 * src];
-            a1 = v[2 * src + 1];
+        const bool ok = nf > 0.0 && Z > 0.0;
+        const int t = col >> 1;
+        const int r = vrow(t, a.vshift, T);
+        const double vi = a.v_in[2 * r + (col & 1)];
+        const double vo = ok ? vi + N / Z : vi;
+        a.v_out[col] = vo;
+        if (col < 2) a.stats[5 + col] = vo;
+        if (col == 0) {
+            a.stats[0] = m;
+            a.stats[1] = Z;
+            a.stats[2] = ok ? Z * Z / W2 : 0.0;
+            a.stats[3] = nf;
+            a.stats[4] = ok ? 0.0 : 5.0;
+            a.stats[7] = 0.0;
         }
-        __syncthreads();
-        if (ok) {
-            v[2 * t] = a0;
-            v[2 * t + 1] = a1;
-        }
-        __syncthreads();
     }
 }
 
 // ----------------------------------------------------------------------------------------------
 // stand-alone kernels for staged checks
 // ----------------------------------------------------------------------------------------------
+// scoring from given beliefs: one wave per sample, records in chunks of 64 lanes
+__global__ __launch_bounds__(256) void score_kernel(int K, int T, int vshift, ScoreF64 sc,
+                                                    const double* mom, const float* u,
+                                                    const double* v, double* S)
+{
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int k = blockIdx.x * 4 + w;
+    if (k >= K) return;
+    const double* mk = mom + (size_t)k * (T + 1) * 9;
+    const float2* uk = reinterpret_cast<const float2*>(u) + (size_t)k * T;
+    double part = 0.0, h_carry = 0.0;
+    for (int base = 0; base <= T; base += 64) {
+        const int count = min(64, T + 1 - base);
+        const int rec = base + min(lane, count - 1);
+        part += score_chunk<64>(sc, mk + (size_t)rec * 9, base + lane, count, lane, T, uk, v,
+                                vshift, h_carry);
+    }
+    part = group_sum<64>(part);
+    if (lane == 0) S[k] = part;
+}
+
+// K-reduction partials from given costs and controls (kPartialSlice samples per block)
+__global__ __launch_bounds__(256) void partial_kernel(int K, int T, double lambda, const double* S,
+                                                      const float* u, const double* v,
+                                                      double* partial)
+{
+    extern __shared__ double psm[];
+    double* S_sh = psm;
+    double* w_sh = psm + kPartialSlice;
+    float2* u_sh = reinterpret_cast<float2*>(psm + 2 * kPartialSlice);
+    const int k0 = blockIdx.x * kPartialSlice;
+    const int n = min(kPartialSlice, K - k0);
+    if (threadIdx.x < n) S_sh[threadIdx.x] = S[k0 + threadIdx.x];
+    const float2* uu = reinterpret_cast<const float2*>(u) + (size_t)k0 * T;
+    for (int i = threadIdx.x; i < n * T; i += 256) u_sh[i] = uu[i];
+    __syncthreads();
+    block_partial(T, n, S_sh, w_sh, u_sh, v, 0, lambda, partial + (size_t)blockIdx.x * (2 * T + 4));
+}
+
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out,
                               int64_t n)
 {
@@ -551,26 +578,26 @@ __global__ void repair_kernel(ScoreF64 sc, const double* mom, const double* u_in
 }
 
 template <int L, int P>
-hipError_t launch_rollout_lp(const SolveArgs& a, bool shield, hipStream_t stream)
+hipError_t launch_solve_lp(const SolveArgs& a, bool shield, hipStream_t stream)
 {
     constexpr int kGroups = 256 / L;
     const unsigned blocks = (unsigned)((a.K + kGroups - 1) / kGroups);
-    const size_t lds = (size_t)kGroups * a.T * sizeof(float2);
+    const size_t lds = solve_lds_bytes(L, a.T);
     if (shield)
-        hipLaunchKernelGGL((rollout_kernel<L, P, true>), dim3(blocks), dim3(256), lds, stream, a);
+        hipLaunchKernelGGL((solve_kernel<L, P, true>), dim3(blocks), dim3(256), lds, stream, a);
     else
-        hipLaunchKernelGGL((rollout_kernel<L, P, false>), dim3(blocks), dim3(256), lds, stream, a);
+        hipLaunchKernelGGL((solve_kernel<L, P, false>), dim3(blocks), dim3(256), lds, stream, a);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t launch_rollout_l(const SolveArgs& a, int ppl, bool shield, hipStream_t stream)
+hipError_t launch_solve_l(const SolveArgs& a, int ppl, bool shield, hipStream_t stream)
 {
     switch (ppl) {
-    case 1: return launch_rollout_lp<L, 1>(a, shield, stream);
-    case 2: return launch_rollout_lp<L, 2>(a, shield, stream);
-    case 4: return launch_rollout_lp<L, 4>(a, shield, stream);
-    case 8: return launch_rollout_lp<L, 8>(a, shield, stream);
+    case 1: return launch_solve_lp<L, 1>(a, shield, stream);
+    case 2: return launch_solve_lp<L, 2>(a, shield, stream);
+    case 4: return launch_solve_lp<L, 4>(a, shield, stream);
+    case 8: return launch_solve_lp<L, 8>(a, shield, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -588,60 +615,73 @@ static int ppl_for(int M, int lanes)
     return p;
 }
 
+size_t solve_lds_bytes(int lanes, int T)
+{
+    const int groups = 256 / lanes;
+    return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2);
+}
+
 LaunchShape choose_shape(int K, int M, int T, int requested_lanes)
 {
     (void)K;
-    (void)T;
     LaunchShape s;
     if (requested_lanes == 8 || requested_lanes == 16 || requested_lanes == 32 ||
         requested_lanes == 64) {
         s.lanes = requested_lanes;
     } else {
-        // default: about four particles per lane, 8..64 lanes per sample
-        int lanes = 8;
+        // default: about four particles per lane, 16..64 lanes per sample
+        int lanes = 16;
         while (lanes < 64 && lanes * 4 < M) lanes <<= 1;
         s.lanes = lanes;
     }
     s.ppl = ppl_for(M, s.lanes);
-    while (s.ppl > 8 && s.lanes < 64) {
+    while ((s.ppl > 8 || solve_lds_bytes(s.lanes, T) > kMaxLds) && s.lanes < 64) {
         s.lanes <<= 1;
         s.ppl = ppl_for(M, s.lanes);
     }
     return s;
 }
 
-hipError_t launch_rollout(const SolveArgs& a, LaunchShape shape, hipStream_t stream)
+int solve_blocks(int K, int lanes)
+{
+    const int groups = 256 / lanes;
+    return (K + groups - 1) / groups;
+}
+
+hipError_t launch_solve(const SolveArgs& a, LaunchShape shape, hipStream_t stream)
 {
     const bool shield = a.sc.shield_iters > 0;
     switch (shape.lanes) {
-    case 8: return launch_rollout_l<8>(a, shape.ppl, shield, stream);
-    case 16: return launch_rollout_l<16>(a, shape.ppl, shield, stream);
-    case 32: return launch_rollout_l<32>(a, shape.ppl, shield, stream);
-    case 64: return launch_rollout_l<64>(a, shape.ppl, shield, stream);
+    case 8: return launch_solve_l<8>(a, shape.ppl, shield, stream);
+    case 16: return launch_solve_l<16>(a, shape.ppl, shield, stream);
+    case 32: return launch_solve_l<32>(a, shape.ppl, shield, stream);
+    case 64: return launch_solve_l<64>(a, shape.ppl, shield, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
+hipError_t launch_merge(const MergeArgs& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(merge_kernel, dim3(2 * a.T), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_score(const SolveArgs& a, hipStream_t stream)
 {
-    const unsigned blocks = blocks_for(a.K, 4);
-    const size_t lds = (size_t)4 * (a.T + 1) * sizeof(double);
-    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), lds, stream, a.K, a.T, a.sc, a.mom,
-                       a.u, a.v, a.S);
+    hipLaunchKernelGGL(score_kernel, dim3(blocks_for(a.K, 4)), dim3(256), 0, stream, a.K, a.T,
+                       a.vshift, a.sc, a.mom, a.u, a.v, a.S);
     return hipGetLastError();
 }
 
-int update_groups(int K) { return (K + kUpdateSlice - 1) / kUpdateSlice; }
+int partial_blocks(int K) { return (K + kPartialSlice - 1) / kPartialSlice; }
 
-hipError_t launch_update(const UpdateArgs& a, hipStream_t stream)
+hipError_t launch_partials(int K, int T, double lambda, const double* S, const float* u,
+                           const double* v, double* partial, hipStream_t stream)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(a.groups), dim3(256), 0, stream, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_shift(double* v, int T, hipStream_t stream)
-{
-    hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(256), 0, stream, v, T);
+    const size_t lds = (size_t)2 * kPartialSlice * sizeof(double) +
+                       (size_t)kPartialSlice * T * sizeof(float2);
+    hipLaunchKernelGGL(partial_kernel, dim3(partial_blocks(K)), dim3(256), lds, stream, K, T,
+                       lambda, S, u, v, partial);
     return hipGetLastError();
 }
 
