@@ -32,6 +32,25 @@ __device__ __forceinline__ uint32_t rng_word3(uint32_t tag, uint32_t s)
     return (tag << 28) | (s & 0x0FFFFFFFu);
 }
 
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);   // a ^ b ^ c in one instruction
+}
+
+// One Philox round on (c0..c3) with round key (k0, k1).
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                             uint32_t k0, uint32_t k1)
+{
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+}
+
 // Ten Philox rounds on (c0..c3) in place; the round key starts at (k0, k1) and advances by the
 // two Weyl constants after each round.
 __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
@@ -39,14 +58,66 @@ __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c
 {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
+        philox_round(c0, c1, c2, c3, k0, k1);
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// The disturbance stream uses counters (t, m, k, w3): over a sample's horizon only t changes.
+// The first round's products M0 t and M1 k, and the second round's product of word 0, are
+// therefore shared: per particle (m, k) two words are fixed for the whole horizon, per step t
+// three words are common to all particles of the sample.  philox10_tail finishes the remaining
+// eight rounds; the result equals philox10 on (t, m, k, w3) bit for bit.
+struct PhiloxParticle {
+    uint32_t ph;   // hi(M0 a0) ^ (k1 + W1), with a0 = hi(M1 k) ^ m ^ k0
+    uint32_t pl;   // lo(M0 a0)
+};
+
+struct PhiloxStep {
+    uint32_t b0;   // hi(M1 a2) ^ lo(M1 k) ^ (k0 + W0), with a2 = hi(M0 t) ^ w3 ^ k1
+    uint32_t b1;   // lo(M1 a2)
+    uint32_t a3;   // lo(M0 t)
+};
+
+__device__ __forceinline__ PhiloxParticle philox_particle(uint32_t m, uint32_t hk, uint32_t k0,
+                                                          uint32_t k1)
+{
+    const uint32_t a0 = xor3(hk, m, k0);
+    const uint64_t p = (uint64_t)kPhiloxM0 * a0;
+    PhiloxParticle r;
+    r.ph = (uint32_t)(p >> 32) ^ (k1 + kPhiloxW1);
+    r.pl = (uint32_t)p;
+    return r;
+}
+
+__device__ __forceinline__ PhiloxStep philox_step(uint32_t t, uint32_t w3, uint32_t lk,
+                                                  uint32_t k0, uint32_t k1)
+{
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * t;
+    const uint32_t a2 = xor3((uint32_t)(p0 >> 32), w3, k1);
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * a2;
+    PhiloxStep r;
+    r.b0 = xor3((uint32_t)(p1 >> 32), lk, k0 + kPhiloxW0);
+    r.b1 = (uint32_t)p1;
+    r.a3 = (uint32_t)p0;
+    return r;
+}
+
+// rounds 3..10 from the shared first two rounds; outputs the four words in (c0..c3)
+__device__ __forceinline__ void philox10_tail(const PhiloxStep& st, const PhiloxParticle& pp,
+                                              uint32_t k0, uint32_t k1, uint32_t& c0,
+                                              uint32_t& c1, uint32_t& c2, uint32_t& c3)
+{
+    c0 = st.b0;
+    c1 = st.b1;
+    c2 = pp.ph ^ st.a3;
+    c3 = pp.pl;
+    k0 += 2u * kPhiloxW0;
+    k1 += 2u * kPhiloxW1;
+#pragma unroll
+    for (int i = 2; i < 10; ++i) {
+        philox_round(c0, c1, c2, c3, k0, k1);
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }
@@ -83,12 +154,10 @@ __device__ __forceinline__ float bm_cos(uint32_t ra, uint32_t rb)
 // ------------------------------------------------------------------------------------------------
 // single-precision car model
 // ------------------------------------------------------------------------------------------------
-// atan on the whole line: |x| > 1 is folded through atan(x) = pi/2 - atan(1/x); on [0, 1]
-// atan(z) = z + z^3 P(z^2) with a degree-7 polynomial fitted for relative error (max ~1e-7).
-__device__ __forceinline__ float atan_f32(float x)
+// atan on [-1, 1]: atan(z) = z + z^3 P(z^2) with a degree-7 polynomial P fitted for relative
+// error (max ~1e-7).
+__device__ __forceinline__ float atan_poly(float z)
 {
-    const float ax = fabsf(x);
-    const float z = fminf(ax, 1.0f) * __builtin_amdgcn_rcpf(fmaxf(ax, 1.0f));
     const float z2 = z * z;
     float p = 0.0029182303696870804f;
     p = fmaf(p, z2, -0.016349468380212784f);
@@ -98,9 +167,31 @@ __device__ __forceinline__ float atan_f32(float x)
     p = fmaf(p, z2, -0.1421002447605133f);
     p = fmaf(p, z2, 0.1999361664056778f);
     p = fmaf(p, z2, -0.333331435918808f);
-    float r = fmaf(z * z2, p, z);
+    return fmaf(z * z2, p, z);
+}
+
+// atan on the whole line: |x| > 1 is folded through atan(x) = sign(x) pi/2 - atan(1/x).
+__device__ __forceinline__ float atan_f32(float x)
+{
+    const float ax = fabsf(x);
+    const float z = fminf(ax, 1.0f) * __builtin_amdgcn_rcpf(fmaxf(ax, 1.0f));
+    float r = atan_poly(z);
     r = ax > 1.0f ? 1.5707963267948966f - r : r;
     return copysignf(r, x);
+}
+
+// Both slip-angle arctangents of one field evaluation.  When no lane of the wave has an argument
+// outside [-1, 1] (the usual case: the body-frame lateral speeds are small against
+// max(vx, v_min)), the folding is skipped; the result is the same function either way.
+__device__ __forceinline__ void atan_pair(float xa, float xb, float& ra, float& rb)
+{
+    if (__all(fmaxf(fabsf(xa), fabsf(xb)) <= 1.0f)) {
+        ra = atan_poly(xa);
+        rb = atan_poly(xb);
+    } else {
+        ra = atan_f32(xa);
+        rb = atan_f32(xb);
+    }
 }
 
 // Quantities of one (sample, step) that every particle of the sample shares.
@@ -116,11 +207,11 @@ __device__ __forceinline__ StepF32 make_step(const CarF32& car, float steer, flo
     StepF32 s;
     s.steer = steer;
     s.accel = accel;
-    float sd, cd;
-    sincosf(steer, &sd, &cd);
-    s.sd = sd;
-    s.cd = cd;
-    s.kz_lf_cd = car.m_Iz * car.lf * cd;
+    // |steer| <= steer_max < pi, so the hardware sine/cosine (argument in revolutions) is used
+    const float rev = steer * 0.15915494309189535f;
+    s.sd = __builtin_amdgcn_sinf(rev);
+    s.cd = __builtin_amdgcn_cosf(rev);
+    s.kz_lf_cd = car.m_Iz * car.lf * s.cd;
     s.kz_lr = car.m_Iz * car.lr;
     return s;
 }
@@ -132,8 +223,10 @@ __device__ __forceinline__ void car_field_f32(const CarF32& car, const StepF32& 
                                               float& dvx, float& dvy, float& dr)
 {
     const float inv_vx = __builtin_amdgcn_rcpf(fmaxf(vx, car.v_min));
-    const float af = st.steer - atan_f32(fmaf(car.lf, r, vy) * inv_vx);
-    const float ar = -atan_f32(fmaf(-car.lr, r, vy) * inv_vx);
+    float atf, atr;
+    atan_pair(fmaf(car.lf, r, vy) * inv_vx, fmaf(-car.lr, r, vy) * inv_vx, atf, atr);
+    const float af = st.steer - atf;
+    const float ar = -atr;
     const float fF = fminf(fmaxf(car.cf_m * af, -car.fF_max), car.fF_max);   // F_f / m
     const float fR = fminf(fmaxf(car.cr_m * ar, -car.fR_max), car.fR_max);   // F_r / m
     const float rr = rev - rintf(rev);

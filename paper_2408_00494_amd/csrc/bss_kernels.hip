@@ -54,12 +54,53 @@ __device__ inline void chol6(const double* A, double* L)
     }
 }
 
+// Cross-lane moves inside a row of 16 lanes (DPP): no LDS traffic, one VALU move per dword.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppHalfRowMirror = 0x141; // lane i <- lane 7-i within each 8
+constexpr int kDppRowMirror = 0x140;     // lane i <- lane 15-i within each 16
+constexpr int kDppRowBcast0 = 0x150;     // every lane of a row <- lane 0 of the row
+constexpr int kDppRowBcast8 = 0x158;     // every lane of a row <- lane 8 of the row
+
+// Sum over the L lanes of a group (L = 1..64, groups aligned in the wave), result in every lane
+// of the group and bitwise identical across them (each stage adds the same two partial sums in
+// either order).  Within a row of 16 the partners come from DPP; across rows from a shuffle.
 template <int L>
 __device__ __forceinline__ double group_sum(double x)
 {
-#pragma unroll
-    for (int mask = 1; mask < L; mask <<= 1) x += __shfl_xor(x, mask, L);
+    if (L > 1) x += dpp_f64<kDppQuadSwap1>(x);
+    if (L > 2) x += dpp_f64<kDppQuadSwap2>(x);
+    if (L > 4) x += dpp_f64<kDppHalfRowMirror>(x);
+    if (L > 8) x += dpp_f64<kDppRowMirror>(x);
+    if (L > 16) x += __shfl_xor(x, 16, 64);
+    if (L > 32) x += __shfl_xor(x, 32, 64);
     return x;
+}
+
+// Value of lane 0 of the group in every lane of the group.
+template <int L>
+__device__ __forceinline__ float group_first(float x)
+{
+    if (L == 16) return dpp_f32<kDppRowBcast0>(x);
+    if (L == 8) {
+        const float a = dpp_f32<kDppRowBcast0>(x), b = dpp_f32<kDppRowBcast8>(x);
+        return (threadIdx.x & 8) ? b : a;
+    }
+    return __shfl(x, 0, L);
 }
 
 __device__ __forceinline__ int vrow(int t, int vshift, int T)
@@ -147,8 +188,11 @@ __device__ inline void block_partial(int T, int n, const double* S_sh, double* w
 // ----------------------------------------------------------------------------------------------
 // solve: rollout + scoring + block partial of the K-reduction
 // ----------------------------------------------------------------------------------------------
+// Up to four particles per lane the loop fits 128 registers, which keeps four waves per SIMD;
+// larger P (and the shield's double-precision repair) get the register budget of two.
 template <int L, int P, bool SHIELD>
-__global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_kernel(SolveArgs a)
 {
     constexpr int kGroups = 256 / L;
     extern __shared__ double smem[];
@@ -242,6 +286,12 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
             for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
         }
         const uint32_t c3w = rng_word3(kTagW, s);
+        // shared parts of the disturbance stream's first two Philox rounds
+        const uint64_t pk = (uint64_t)kPhiloxM1 * (uint32_t)k;
+        const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
+        PhiloxParticle pp[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) pp[p] = philox_particle((uint32_t)(j + p * L), hk, a.key0, a.key1);
         const double invM = 1.0 / (double)M;
         const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
 
@@ -280,13 +330,14 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
                 }
             }
             const StepF32 st = make_step(car, uu.x, uu.y);
+            const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, a.key0, a.key1);
             double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0, sYY = 0;
             double refX = 0.0, refY = 0.0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int m = j + p * L;
-                uint32_t c0 = (uint32_t)t, c1 = (uint32_t)m, c2 = (uint32_t)k, c3 = c3w;
-                philox10(c0, c1, c2, c3, a.key0, a.key1);
+                uint32_t c0, c1, c2, c3;
+                philox10_tail(ps, pp[p], a.key0, a.key1, c0, c1, c2, c3);
                 float w0, w1;
                 bm_pair(c0, c1, w0, w1);
                 const float w2 = bm_cos(c2, c3);
@@ -310,8 +361,8 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a)
 
                 if (p == 0) {
                     // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
-                    refX = (double)__shfl(Xs[0], 0, L) - (double)__shfl(Xc[0], 0, L);
-                    refY = (double)__shfl(Ys[0], 0, L) - (double)__shfl(Yc[0], 0, L);
+                    refX = (double)group_first<L>(Xs[0]) - (double)group_first<L>(Xc[0]);
+                    refY = (double)group_first<L>(Ys[0]) - (double)group_first<L>(Yc[0]);
                 }
                 if (m < M) {   // masked particles beyond M contribute nothing
                     const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
