@@ -24,15 +24,48 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Minimal VALU issue slots one rollout-step (one particle advanced one step) needs, counted from
-# the operations of the method (see the roofline section of the design notes): simple 32-bit and
-# 64-bit float/integer operations cost 1 slot, transcendental and wide-multiply instructions,
-# which issue at a quarter of the rate, cost 4.
-SLOTS_PER_ROLLOUT_STEP = 303
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 3.93e13 lane-slots/s
-VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# the operations of the method: a 32-bit float or integer operation is 1 slot, a double-precision
+# operation 2, a transcendental (log, sqrt, sin, cos, rcp) or a 32x32->64-bit multiply 4 (they
+# issue at a quarter of the full rate).  Breakdown: Philox4x32-10 100, uniforms 8, Box-Muller 33,
+# two vector-field evaluations 116, midpoint combination and noise 13, double-precision moment
+# accumulation 34.
+SLOTS_PER_ROLLOUT_STEP = 304
+# MI355X: 256 CUs x 128 lane-slots per clock (4 SIMDs x 32 lanes, the rate behind the published
+# 157.3 TFLOP/s FP32 vector peak with FMA = 2 FLOP) x 2.4 GHz = 78.6e12 lane-slots/s
+VALU_PEAK_SLOTS = 256 * 128 * 2.4e9
 # FP32 FLOPs of the particle dynamics per rollout-step (FMA = 2), and MI355X's FP32 vector peak
-FP32_FLOP_PER_ROLLOUT_STEP = 198
+FP32_FLOP_PER_ROLLOUT_STEP = 206
 FP32_PEAK = 157.3e12
+
+# HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a 1 GiB device copy
+# (FETCH_SIZE x2.0, WRITE_SIZE x1.0); valid only for the kernel sources they were taken on.
+MEASURED_TRAFFIC = {"sources_sha256_16": "fbcb53a70a81b2af", "lanes": 16,
+                    "fetch_bytes": 7545.125 * 1024 * 2.0, "write_bytes": 15035.9125 * 1024 * 1.0}
+KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_kernels.hip",
+                  "paper_2408_00494_amd/csrc/bss_device.h",
+                  "paper_2408_00494_amd/csrc/bss_internal.h"]
+
+
+def ALG_BYTES_PER_SOLVE(K, M, T, lanes):
+    """Bytes the solve kernel must move: belief records written and read back by the scoring
+    phase (K (T+1) 9 doubles each way), costs, block partials, and the mean sequence read."""
+    groups = 256 // lanes
+    blocks = (K + groups - 1) // groups
+    return 2 * K * (T + 1) * 9 * 8 + K * 8 + blocks * (2 * T + 4) * 8 + T * 2 * 8
+
+
+def measured_traffic(lanes):
+    """Counter-measured HBM bytes per solve-kernel launch, or None if the kernel changed since."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != MEASURED_TRAFFIC["sources_sha256_16"] or \
+            lanes != MEASURED_TRAFFIC["lanes"]:
+        return None
+    return MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
 
 
 def parse():
@@ -44,8 +77,6 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--latency-solves", type=int, default=50)
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with the rollout kernel's measured HBM bytes per launch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -119,10 +150,7 @@ def main():
     value = rs_per_solve * args.steps / elapsed
     kernel_ms = kernel_ms_total / max(n_meas, 1)
     slots = SLOTS_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3)
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get("rollout_bytes_per_launch")
+    traffic = measured_traffic(info["lanes"])
 
     # plain synchronous solves from host inputs (latency of one control period)
     lat = []
@@ -151,7 +179,8 @@ def main():
                    "K": K, "M": M, "T": T, "lanes": info["lanes"], "ppl": info["ppl"]},
         "roofline": {"bound": "alu", "achieved": slots / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": slots / VALU_PEAK_SLOTS, "traffic": traffic,
-                     "kernel": "rollout_kernel", "kernel_ms": kernel_ms,
+                     "kernel": "solve_kernel", "kernel_ms": kernel_ms,
+                     "algorithmic_bytes": ALG_BYTES_PER_SOLVE(K, M, T, info["lanes"]),
                      "fp32_tflops": FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3) / 1e12,
                      "fp32_frac_of_157": FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3) / FP32_PEAK},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
