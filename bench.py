@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--latency-solves", type=int, default=50)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -97,6 +98,74 @@ def cpu_baseline(prob, x0, v, seconds):
     return {"value": rs * n / el, "unit": "rollout-steps/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{n} full solves of the same workload (K={prob['K']}, M={prob['M']}, "
                       f"T={prob['T']}) in {el:.1f} s, split over K across {nthreads} threads"}
+
+
+def bench_batched(bss, W, torch, rounds=20, warmup=3):
+    """The 64-instance mixed workload (K 512..8192, M 16..256, T 20..80, own track and disturbance
+    per instance): one batched solve of every instance per round, replayed from a captured graph
+    with the autotuned particles-per-lane, against the plain path (each instance's own solve
+    launches, one after another on the same stream)."""
+    members = W.config_batch()
+    rs = sum(p["K"] * p["M"] * p["T"] for p, _, _ in members)
+    stream = torch.cuda.Stream()
+    solvers = []
+    for p, _, v in members:
+        s = bss.Solver(p, stream=stream)
+        s.set_outputs(controls=False)
+        s.set_controls(v)
+        solvers.append(s)
+    x0s = np.stack([x0 for _, x0, _ in members])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    batch = bss.Batch(solvers, ppl=0, shift_after=True)
+    ppl = batch.tune()
+    layout = batch.layout()
+    batch.set_states(x0s)
+    batch.capture()
+    for _ in range(warmup):
+        batch.solve()
+    stream.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        batch.solve()
+    ev1.record(stream)
+    ev1.synchronize()
+    wall_b = (time.perf_counter() - t0) / rounds
+    gpu_b = ev0.elapsed_time(ev1) * 1e-3 / rounds
+    st = [s.info() for s in solvers]
+    assert all(i["n_finite"] > 0 for i in st)
+    batch.close()
+
+    x0_dev = torch.as_tensor(x0s, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            for i, s in enumerate(solvers):
+                s.solve_async(x0_dev[i])
+                s.step_shift()
+        stream.synchronize()
+        ev0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            for i, s in enumerate(solvers):
+                s.solve_async(x0_dev[i])
+                s.step_shift()
+        ev1.record(stream)
+        ev1.synchronize()
+    wall_p = (time.perf_counter() - t0) / rounds
+    gpu_p = ev0.elapsed_time(ev1) * 1e-3 / rounds
+    for s in solvers:
+        s.close()
+    return {"workload": "64 uneven instances, K 512..8192, M 16..256, T 20..80 (mixed-size "
+                        "batch, seed 4)",
+            "rollout_steps_per_round": rs,
+            "batched": {"value": rs / wall_b, "unit": "rollout-steps/s", "ms_per_round":
+                        wall_b * 1e3, "gpu_ms_per_round": gpu_b * 1e3, "ppl": ppl,
+                        "solve_blocks": layout["nblocks"], "launch": "captured HIP graph"},
+            "plain": {"value": rs / wall_p, "unit": "rollout-steps/s", "ms_per_round":
+                      wall_p * 1e3, "gpu_ms_per_round": gpu_p * 1e3,
+                      "launch": "two launches per instance, one stream"},
+            "speedup": wall_p / wall_b}
 
 
 def main():
@@ -186,6 +255,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mode": "plain synchronous solve from host inputs"},
     }
+    if not args.no_batched:
+        out["batched"] = bench_batched(bss, W, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, x0, v, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -193,8 +193,68 @@ bss_status bss_timing_read(bss_ctx* c, double* rollout_ms_total, int32_t* count)
 /* Force the launch shape (lanes per sample 8/16/32/64; 0 restores the automatic choice). */
 bss_status bss_set_lanes(bss_ctx* c, int32_t lanes);
 
-/* Destroy a context and free its buffers (NULL is accepted). */
+/* Force lanes per sample (0, 8, 16, 32, 64) and particles per lane (0, 1, 2, 4, 8; 0 = automatic)
+ * together.  The M particles of a sample are spread over L lanes with P = ceil(M / L) per lane.
+ * Results depend on the shape only through the summation order of the per-step moments.
+ * Errors: BSS_E_INVAL (values, or M > 64 P), BSS_E_STATE (context in a batch). */
+bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl);
+
+/* Destroy a context and free its buffers (NULL is accepted; a context that belongs to a batch is
+ * left alone: destroy the batch first). */
 void bss_destroy(bss_ctx* c);
+
+/* ---- batches: many controllers, one solve launch and one merge launch ---------------------------
+ *
+ * A batch runs one solve of each of n contexts (each with its own K, M, T, costs, seed and warm
+ * start, Alg. 1 per context) in two kernel launches: the rollout/scoring grid is the union of the
+ * contexts' blocks (ordered longest horizon first) and the merge grid the union of their control
+ * entries.  All per-solve state (mean-sequence buffer, pending shift, solve index) advances on the
+ * device, so the two launches can be captured once in a HIP graph and replayed.  Each context of a
+ * batch computes exactly what it computes alone with the same launch shape.  While a context
+ * belongs to a batch, its own solve and state calls return BSS_E_STATE. */
+typedef struct bss_batch bss_batch;
+
+/* Group n contexts (distinct, not in another batch, all on the current device) into a batch whose
+ * work is enqueued on the stream of ctxs[0].  ppl: particles per lane used by every member (1, 2,
+ * 4 or 8; 0 = automatic; bss_batch_tune measures the candidates).  shift_after = 1 leaves one
+ * warm-start shift pending after each solve (the receding-horizon loop of a controller), 0 none.
+ * The batch takes over each context's mean sequence, shift and solve index, and hands them back
+ * in bss_batch_destroy.  Errors: BSS_E_INVAL, BSS_E_STATE, BSS_E_NOMEM, BSS_E_DEVICE. */
+bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_t shift_after,
+                            bss_batch** out);
+
+/* Device array x0[n][6] (double) read by each batched solve: member i's state estimate is row i.
+ * The caller may write it with its own kernels or copies, ordered before bss_batch_solve on the
+ * batch's stream.  The batched solve uses a known state (Sigma0 = 0). */
+bss_status bss_batch_states(bss_batch* b, double** x0_dev);
+
+/* Copy x0_host[n][6] into the state array (synchronous).  Errors: BSS_E_INVAL (non-finite). */
+bss_status bss_batch_set_states(bss_batch* b, const double* x0_host);
+
+/* Enqueue a device-to-device copy of x0_dev[n][6] (double, device memory that stays valid until
+ * the copy completes) into the state array on the batch's stream. */
+bss_status bss_batch_copy_states(bss_batch* b, const double* x0_dev);
+
+/* Enqueue one solve of every member (asynchronous; replays the captured graph if there is one).
+ * Results land in each member's buffers; bss_get_buffers, bss_get_controls and bss_get_info
+ * work on members (they synchronise the batch's stream). */
+bss_status bss_batch_solve(bss_batch* b);
+
+/* Capture the batch's two launches into a HIP graph used by later bss_batch_solve calls.  The
+ * batch's stream must be a created stream (BSS_E_STATE on the null stream). */
+bss_status bss_batch_capture(bss_batch* b);
+
+/* Time each particles-per-lane candidate on the batch (trial solves whose state changes are undone)
+ * and keep the fastest; *ppl_out (may be NULL) receives it.  Call before bss_batch_capture. */
+bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out);
+
+/* Number of solve blocks and particles per lane of the batch's current layout (either may be
+ * NULL). */
+bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl);
+
+/* Synchronise the batch's stream, hand each member its state back and free the batch (NULL is
+ * accepted). */
+void bss_batch_destroy(bss_batch* b);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* bss_last_error(void);

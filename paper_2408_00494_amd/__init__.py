@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import BssError, check, params_from_problem
 
-__all__ = ["Solver", "BssError", "backoff", "validate", "dev_philox", "dev_normals",
+__all__ = ["Solver", "Batch", "BssError", "backoff", "validate", "dev_philox", "dev_normals",
            "dev_model_step", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
 
 
@@ -141,6 +141,10 @@ class Solver:
     def set_lanes(self, lanes: int):
         check(_lib.lib().bss_set_lanes(self._ctx, int(lanes)))
 
+    def set_shape(self, lanes: int = 0, ppl: int = 0):
+        """Force lanes per sample and/or particles per lane (0 = automatic; ppl wins)."""
+        check(_lib.lib().bss_set_shape(self._ctx, int(lanes), int(ppl)))
+
     def set_outputs(self, controls: bool = True):
         """Turn the optional per-solve copy of the sampled controls on or off."""
         check(_lib.lib().bss_set_outputs(self._ctx, _lib.BSS_OUT_CONTROLS if controls else 0))
@@ -177,6 +181,61 @@ class Solver:
         n = C.c_int32()
         check(_lib.lib().bss_timing_read(self._ctx, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Many Solvers solved together: one rollout launch and one merge launch per batched solve
+    (optionally replayed from a captured HIP graph).  Member i reads its state estimate from row i
+    of the batch's state array (``set_states`` / ``copy_states_from``); results land in each
+    member's buffers.  The members get their advanced state back in ``close``."""
+
+    def __init__(self, solvers, ppl: int = 0, shift_after: bool = True):
+        self.solvers = list(solvers)
+        self.n = len(self.solvers)
+        arr = (C.c_void_p * self.n)(*[s._ctx.value for s in self.solvers])
+        b = C.c_void_p()
+        check(_lib.lib().bss_batch_create(arr, self.n, int(ppl), 1 if shift_after else 0,
+                                          C.byref(b)))
+        self._b = b
+        ptr = C.c_void_p()
+        check(_lib.lib().bss_batch_states(self._b, C.byref(ptr)))
+        self.states_ptr = ptr.value
+
+    def set_states(self, x0):
+        x = np.ascontiguousarray(x0, dtype=np.float64).reshape(self.n, 6)
+        check(_lib.lib().bss_batch_set_states(self._b, x.ctypes.data_as(C.c_void_p)))
+
+    def copy_states_from(self, x0_dev):
+        """Enqueue a device-to-device copy of x0_dev (float64 [n, 6], contiguous) into the state
+        array on the batch's stream."""
+        check(_lib.lib().bss_batch_copy_states(self._b, _ptr(x0_dev.contiguous())))
+
+    def solve(self):
+        check(_lib.lib().bss_batch_solve(self._b))
+
+    def capture(self):
+        check(_lib.lib().bss_batch_capture(self._b))
+
+    def tune(self):
+        p = C.c_int32()
+        check(_lib.lib().bss_batch_tune(self._b, C.byref(p)))
+        return p.value
+
+    def layout(self):
+        nb, p = C.c_int32(), C.c_int32()
+        check(_lib.lib().bss_batch_info(self._b, C.byref(nb), C.byref(p)))
+        return {"nblocks": nb.value, "ppl": p.value}
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            _lib.lib().bss_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 BssAllocator_alloc = _lib.BssAllocator._fields_[0][1]

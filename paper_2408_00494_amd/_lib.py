@@ -69,7 +69,9 @@ EXPORTS = [
     "bss_set_controls", "bss_set_solve_index", "bss_get_solve_index", "bss_get_info",
     "bss_timing_enable", "bss_timing_read", "bss_set_lanes", "bss_destroy", "bss_last_error",
     "bss_dev_philox", "bss_dev_normals", "bss_dev_model_step", "bss_dev_sdf", "bss_dev_score",
-    "bss_dev_update_workspace", "bss_dev_update", "bss_dev_repair",
+    "bss_dev_update_workspace", "bss_dev_update", "bss_dev_repair", "bss_set_shape",
+    "bss_batch_create", "bss_batch_states", "bss_batch_set_states", "bss_batch_copy_states", "bss_batch_solve",
+    "bss_batch_capture", "bss_batch_tune", "bss_batch_info", "bss_batch_destroy",
 ]
 
 
@@ -107,6 +109,16 @@ def _declare(lib):
         "bss_dev_update_workspace": (C.c_size_t, [i32, i32]),
         "bss_dev_update": (i32, [P, vp, vp, vp, vp, vp, vp]),
         "bss_dev_repair": (i32, [P, vp, vp, vp, i64, vp]),
+        "bss_set_shape": (i32, [vp, i32, i32]),
+        "bss_batch_create": (i32, [C.POINTER(vp), i32, i32, i32, C.POINTER(vp)]),
+        "bss_batch_states": (i32, [vp, C.POINTER(vp)]),
+        "bss_batch_set_states": (i32, [vp, vp]),
+        "bss_batch_copy_states": (i32, [vp, vp]),
+        "bss_batch_solve": (i32, [vp]),
+        "bss_batch_capture": (i32, [vp]),
+        "bss_batch_tune": (i32, [vp, C.POINTER(i32)]),
+        "bss_batch_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "bss_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <cstddef>
 #include <new>
 #include <string>
 #include <vector>
@@ -129,25 +131,129 @@ struct bss_ctx {
     bss_allocator alloc;
     bool has_alloc;
     hipStream_t stream;
-    void* block;
-    double* vbuf[2];         // ping-pong pair of mean sequences [T][2]
-    int cur;                 // index of the current mean sequence
-    int pending_shift;       // warm-start shifts not yet applied to vbuf[cur]
-    float* u;
-    double* mom;
-    double* S;
-    double* stats;
-    double* partial;
-    double* x0;
-    double* Sigma0;
-    double* host;            // pinned [16]
-    uint32_t solve_index;
-    int32_t outputs;         // BSS_OUT_* flags
+    void* block;              // one device allocation holding every buffer below
+    InstanceDesc desc;        // host copy of the static descriptor fields
+    InstanceDesc* d_desc;     // device descriptor (state fields advanced on the device)
+    BlockDesc* d_blocks;      // solve grid of this context
+    MergeDesc* d_cols;        // merge grid of this context
+    double* x0;               // staging [6]
+    double* Sigma0;           // staging [36]
+    double* host;             // pinned [64]
     LaunchShape shape;
+    size_t lds;
+    int pending_shift;        // warm-start shifts requested on the host since the last solve
+    int32_t outputs;
     bool timing;
     std::vector<hipEvent_t> ev;   // pairs (start, stop)
     size_t ev_used;
+    bss_batch* batch;         // batch that currently owns the context, or nullptr
+    int batch_index;          // index of the context in that batch
 };
+
+struct bss_batch {
+    std::vector<bss_ctx*> ctxs;
+    int n;
+    hipStream_t stream;
+    void* block;
+    InstanceDesc* d_desc;     // [n]
+    InstanceDesc* d_backup;   // [n] (autotuning)
+    BlockDesc* d_blocks;
+    MergeDesc* d_cols;
+    double* d_x0;             // [n][6]
+    int nblocks, ncols, ppl, shift_after;
+    std::vector<int> lanes;   // lanes per sample of each member in the current layout
+    size_t lds;
+    bool shield;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool captured;
+};
+
+namespace {
+
+constexpr size_t kStateOffset = offsetof(InstanceDesc, cur);
+constexpr size_t kStateBytes = offsetof(InstanceDesc, shift_after) - offsetof(InstanceDesc, cur);
+
+size_t max_blocks(int K) { return (size_t)solve_blocks(K, 64); }
+
+// sizes, params and buffer pointers of a context's descriptor (state fields zero)
+void fill_desc(bss_ctx* c)
+{
+    const bss_params& p = c->p;
+    InstanceDesc& d = c->desc;
+    d.K = p.K;
+    d.M = p.M;
+    d.T = p.T;
+    d.lanes = c->shape.lanes;
+    d.nblocks = solve_blocks(p.K, c->shape.lanes);
+    d.x0_index = 0;
+    d.cur = 0;
+    d.vshift = 0;
+    d.solve_index = 0;
+    d.done = 0;
+    d.shift_after = 0;
+    d.status = 0;
+    d.key0 = (uint32_t)p.seed;
+    d.key1 = (uint32_t)(p.seed >> 32);
+    d.steer_max = (float)p.steer_max;
+    d.accel_max = (float)p.accel_max;
+    d.sig_eps0 = (float)p.sigma_eps[0];
+    d.sig_eps1 = (float)p.sigma_eps[1];
+    d.sig_w0 = (float)p.sigma_w[0];
+    d.sig_w1 = (float)p.sigma_w[1];
+    d.sig_w2 = (float)p.sigma_w[2];
+    d.car = make_car(p);
+    d.sc = make_score(p);
+}
+
+std::vector<BlockDesc> block_table(int inst, int K, int lanes)
+{
+    const int groups = 256 / lanes;
+    std::vector<BlockDesc> out;
+    for (int k0 = 0; k0 < K; k0 += groups) out.push_back(BlockDesc{inst, k0});
+    return out;
+}
+
+hipError_t upload_shape(bss_ctx* c)
+{
+    c->desc.lanes = c->shape.lanes;
+    c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
+    c->lds = solve_lds_bytes(c->shape.lanes, c->p.T);
+    // static leading fields only: the device state is left as it is
+    hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    const std::vector<BlockDesc> tab = block_table(0, c->p.K, c->shape.lanes);
+    return hipMemcpy(c->d_blocks, tab.data(), tab.size() * sizeof(BlockDesc),
+                     hipMemcpyHostToDevice);
+}
+
+// stream the context's work is on (the batch's while it belongs to one)
+hipStream_t work_stream(const bss_ctx* c) { return c->batch ? c->batch->stream : c->stream; }
+
+// device state fields (cur, vshift, solve_index, done) of a context; while the context belongs to
+// a batch they live in the batch's descriptor array
+hipError_t read_state(bss_ctx* c, int32_t* st)
+{
+    const char* src = c->batch ? (const char*)(c->batch->d_desc + c->batch_index)
+                               : (const char*)c->d_desc;
+    const hipStream_t s = work_stream(c);
+    hipError_t e = hipMemcpyAsync(c->host, src + kStateOffset, kStateBytes,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) std::memcpy(st, c->host, kStateBytes);
+    return e;
+}
+
+hipError_t write_state(bss_ctx* c, const int32_t* st)
+{
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)c->d_desc + kStateOffset, st, kStateBytes, hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -273,13 +379,17 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->has_alloc = alloc != nullptr;
     if (alloc) c->alloc = *alloc;
     c->stream = (hipStream_t)stream;
-    c->shape = choose_shape(p->K, p->M, p->T, p->lanes);
+    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0);
     c->timing = false;
     c->ev_used = 0;
-    c->solve_index = 0;
+    c->pending_shift = 0;
+    c->outputs = BSS_OUT_CONTROLS;
+    c->batch = nullptr;
+    c->batch_index = 0;
+    c->host = nullptr;
 
     const size_t K = (size_t)p->K, T = (size_t)p->T;
-    const size_t G = (size_t)solve_blocks(p->K, 8);   // most blocks any launch shape uses
+    const size_t G = max_blocks(p->K);
     const size_t sz_v = align256(T * 2 * sizeof(double));
     const size_t sz_u = align256(K * T * 2 * sizeof(float));
     const size_t sz_mom = align256(K * (T + 1) * 9 * sizeof(double));
@@ -288,7 +398,11 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     const size_t sz_part = align256(G * (2 * T + 4) * sizeof(double));
     const size_t sz_x0 = 256;
     const size_t sz_sig = align256(36 * sizeof(double));
-    const size_t total = 2 * sz_v + sz_u + sz_mom + sz_S + sz_stats + sz_part + sz_x0 + sz_sig;
+    const size_t sz_desc = align256(sizeof(InstanceDesc));
+    const size_t sz_blk = align256(G * sizeof(BlockDesc));
+    const size_t sz_col = align256(2 * T * sizeof(MergeDesc));
+    const size_t total = 2 * sz_v + sz_u + sz_mom + sz_S + sz_stats + sz_part + sz_x0 + sz_sig +
+                         sz_desc + sz_blk + sz_col;
 
     void* block = nullptr;
     if (c->has_alloc) {
@@ -306,37 +420,49 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     }
     c->block = block;
     char* b = (char*)block;
-    c->vbuf[0] = (double*)b;
+    fill_desc(c);
+    c->desc.v[0] = (double*)b;
     b += sz_v;
-    c->vbuf[1] = (double*)b;
+    c->desc.v[1] = (double*)b;
     b += sz_v;
-    c->u = (float*)b;
+    c->desc.u = (float*)b;
     b += sz_u;
-    c->mom = (double*)b;
+    c->desc.mom = (double*)b;
     b += sz_mom;
-    c->S = (double*)b;
+    c->desc.S = (double*)b;
     b += sz_S;
-    c->stats = (double*)b;
+    c->desc.stats = (double*)b;
     b += sz_stats;
-    c->partial = (double*)b;
+    c->desc.partial = (double*)b;
     b += sz_part;
     c->x0 = (double*)b;
     b += sz_x0;
     c->Sigma0 = (double*)b;
-    c->cur = 0;
-    c->pending_shift = 0;
-    c->outputs = BSS_OUT_CONTROLS;
+    b += sz_sig;
+    c->d_desc = (InstanceDesc*)b;
+    b += sz_desc;
+    c->d_blocks = (BlockDesc*)b;
+    b += sz_blk;
+    c->d_cols = (MergeDesc*)b;
 
-    hipError_t e = hipHostMalloc((void**)&c->host, 16 * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
-        if (c->has_alloc) c->alloc.release(block, c->alloc.user);
-        else (void)hipFree(block);
-        delete c;
+        c->host = nullptr;
+        bss_destroy(c);
         return fail(BSS_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
-    // zero the warm start and stats (whole block: also makes unused slots defined)
+    // zero every buffer (warm start, stats), then the descriptors and grids
     e = hipMemsetAsync(block, 0, total, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_desc, &c->desc, sizeof(InstanceDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = upload_shape(c);
+    if (e == hipSuccess) {
+        std::vector<MergeDesc> cols;
+        for (int col = 0; col < 2 * p->T; ++col) cols.push_back(MergeDesc{0, col});
+        e = hipMemcpy(c->d_cols, cols.data(), cols.size() * sizeof(MergeDesc),
+                      hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         bss_destroy(c);
         return device_fail(e, "initialising context buffers");
@@ -352,34 +478,15 @@ bss_status bss_set_stream(bss_ctx* c, void* stream)
     return BSS_OK;
 }
 
+static bss_status check_free(const bss_ctx* c)
+{
+    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    if (c->batch) return fail(BSS_E_STATE, "context belongs to a batch (bss_batch_destroy first)");
+    return BSS_OK;
+}
+
 static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* Sigma0_dev)
 {
-    const bss_params& p = c->p;
-    SolveArgs a;
-    a.K = p.K;
-    a.M = p.M;
-    a.T = p.T;
-    a.vshift = c->pending_shift;
-    a.solve_index = c->solve_index;
-    a.key0 = (uint32_t)p.seed;
-    a.key1 = (uint32_t)(p.seed >> 32);
-    a.steer_max = (float)p.steer_max;
-    a.accel_max = (float)p.accel_max;
-    a.sig_eps0 = (float)p.sigma_eps[0];
-    a.sig_eps1 = (float)p.sigma_eps[1];
-    a.sig_w0 = (float)p.sigma_w[0];
-    a.sig_w1 = (float)p.sigma_w[1];
-    a.sig_w2 = (float)p.sigma_w[2];
-    a.car = make_car(p);
-    a.sc = make_score(p);
-    a.x0 = x0_dev;
-    a.Sigma0 = Sigma0_dev;
-    a.v = c->vbuf[c->cur];
-    a.u = (c->outputs & BSS_OUT_CONTROLS) ? c->u : nullptr;
-    a.mom = c->mom;
-    a.S = c->S;
-    a.partial = c->partial;
-
     hipError_t e;
     if (c->timing) {
         if (c->ev_used + 2 > c->ev.size()) {
@@ -393,34 +500,29 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         e = hipEventRecord(c->ev[c->ev_used], c->stream);
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
-    e = launch_solve(a, c->shape, c->stream);
+    e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
+                     c->p.shield_iters > 0, c->lds, x0_dev, Sigma0_dev, c->pending_shift,
+                     c->stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
         e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
         c->ev_used += 2;
     }
-    MergeArgs ma;
-    ma.T = p.T;
-    ma.G = solve_blocks(p.K, c->shape.lanes);
-    ma.vshift = c->pending_shift;
-    ma.lambda = p.lambda;
-    ma.partial = c->partial;
-    ma.v_in = c->vbuf[c->cur];
-    ma.v_out = c->vbuf[1 - c->cur];
-    ma.stats = c->stats;
-    e = launch_merge(ma, c->stream);
+    e = launch_merge(c->d_desc, c->d_cols, 2 * c->p.T, c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "merge launch");
-    c->cur = 1 - c->cur;
     c->pending_shift = 0;
-    c->solve_index += 1;
     return BSS_OK;
 }
 
 bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma0_dev)
 {
-    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
     if (!x0_dev) return fail(BSS_E_INVAL, "x0 is NULL");
+    if (c->outputs & BSS_OUT_CONTROLS) {
+        // the copy pointer lives in the descriptor; keep it in sync with the flag
+    }
     return enqueue_solve(c, x0_dev, Sigma0_dev);
 }
 
@@ -431,14 +533,20 @@ static void fill_info(const bss_ctx* c, const double* stats, bss_info* info)
     info->Z = stats[1];
     info->ess = stats[2];
     info->n_finite = (int32_t)stats[3];
-    info->lanes = c->shape.lanes;
-    info->ppl = c->shape.ppl;
+    if (c->batch) {
+        info->lanes = c->batch->lanes[c->batch_index];
+        info->ppl = c->batch->ppl;
+    } else {
+        info->lanes = c->shape.lanes;
+        info->ppl = c->shape.ppl;
+    }
 }
 
 bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, double u0_out[2],
                      bss_info* info)
 {
-    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
     if (!x0 || !u0_out) return fail(BSS_E_INVAL, "x0 and u0_out must not be NULL");
     for (int i = 0; i < 6; ++i)
         if (!std::isfinite(x0[i])) return fail(BSS_E_INVAL, "x0[%d] is not finite", i);
@@ -448,14 +556,19 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
         for (int i = 0; i < 6; ++i)
             if (Sigma0[i * 6 + i] < 0.0) return fail(BSS_E_INVAL, "Sigma0 has a negative variance");
     }
-    hipError_t e = hipMemcpyAsync(c->x0, x0, 6 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    // stage through pinned memory so the copies are truly asynchronous
+    std::memcpy(c->host + 16, x0, 6 * sizeof(double));
+    if (Sigma0) std::memcpy(c->host + 24, Sigma0, 36 * sizeof(double));
+    hipError_t e = hipMemcpyAsync(c->x0, c->host + 16, 6 * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream);
     if (e == hipSuccess && Sigma0)
-        e = hipMemcpyAsync(c->Sigma0, Sigma0, 36 * sizeof(double), hipMemcpyHostToDevice,
+        e = hipMemcpyAsync(c->Sigma0, c->host + 24, 36 * sizeof(double), hipMemcpyHostToDevice,
                            c->stream);
     if (e != hipSuccess) return device_fail(e, "staging x0");
-    bss_status st = enqueue_solve(c, c->x0, Sigma0 ? c->Sigma0 : nullptr);
+    st = enqueue_solve(c, c->x0, Sigma0 ? c->Sigma0 : nullptr);
     if (st != BSS_OK) return st;
-    e = hipMemcpyAsync(c->host, c->stats, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(c->host, c->desc.stats, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                       c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(e, "solve");
     fill_info(c, c->host, info);
@@ -467,44 +580,63 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
 
 bss_status bss_step_shift(bss_ctx* c)
 {
-    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
     if (c->pending_shift < c->p.T - 1) c->pending_shift += 1;
     return BSS_OK;
 }
 
 bss_status bss_set_outputs(bss_ctx* c, int32_t flags)
 {
-    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
     if (flags & ~BSS_OUT_CONTROLS) return fail(BSS_E_INVAL, "unknown flags");
     c->outputs = flags;
+    float* u = (flags & BSS_OUT_CONTROLS) ? (float*)((char*)c->desc.v[1] +
+                                                     align256((size_t)c->p.T * 2 * sizeof(double)))
+                                          : nullptr;
+    c->desc.u = u;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)c->d_desc + offsetof(InstanceDesc, u), &u, sizeof(u),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(e, "setting outputs");
     return BSS_OK;
 }
 
-bss_status bss_get_buffers(const bss_ctx* c, bss_buffers* out)
+bss_status bss_get_buffers(const bss_ctx* cc, bss_buffers* out)
 {
+    bss_ctx* c = const_cast<bss_ctx*>(cc);
     if (!c || !out) return fail(BSS_E_INVAL, "NULL argument");
-    out->v = c->vbuf[c->cur];
-    out->u = c->u;
-    out->mom = c->mom;
-    out->S = c->S;
-    out->stats = c->stats;
+    int32_t stv[4];
+    hipError_t e = read_state(c, stv);
+    if (e != hipSuccess) return device_fail(e, "reading state");
+    const int cur = stv[0];
+    out->v = c->desc.v[cur];
+    out->u = (float*)((char*)c->desc.v[1] + align256((size_t)c->p.T * 2 * sizeof(double)));
+    out->mom = c->desc.mom;
+    out->S = c->desc.S;
+    out->stats = c->desc.stats;
     out->x0 = c->x0;
     out->Sigma0 = c->Sigma0;
-    out->v_shift = c->pending_shift;
+    out->v_shift = stv[1] + c->pending_shift;
     return BSS_OK;
 }
 
 bss_status bss_get_controls(bss_ctx* c, double* v_host)
 {
     if (!c || !v_host) return fail(BSS_E_INVAL, "NULL argument");
+    int32_t stv[4];
+    hipError_t e = read_state(c, stv);
+    if (e != hipSuccess) return device_fail(e, "reading state");
     const int T = c->p.T;
+    const int shift = stv[1] + c->pending_shift;
     std::vector<double> tmp((size_t)T * 2);
-    hipError_t e = hipMemcpyAsync(tmp.data(), c->vbuf[c->cur], (size_t)T * 2 * sizeof(double),
-                                  hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    e = hipMemcpy(tmp.data(), c->desc.v[stv[0]], (size_t)T * 2 * sizeof(double),
+                  hipMemcpyDeviceToHost);
     if (e != hipSuccess) return device_fail(e, "reading controls");
     for (int t = 0; t < T; ++t) {
-        const int r = t + c->pending_shift < T ? t + c->pending_shift : T - 1;
+        const int r = t + shift < T ? t + shift : T - 1;
         v_host[2 * t] = tmp[2 * r];
         v_host[2 * t + 1] = tmp[2 * r + 1];
     }
@@ -513,12 +645,20 @@ bss_status bss_get_controls(bss_ctx* c, double* v_host)
 
 bss_status bss_set_controls(bss_ctx* c, const double* v_host)
 {
-    if (!c || !v_host) return fail(BSS_E_INVAL, "NULL argument");
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
+    if (!v_host) return fail(BSS_E_INVAL, "NULL argument");
     for (int i = 0; i < 2 * c->p.T; ++i)
         if (!std::isfinite(v_host[i])) return fail(BSS_E_INVAL, "controls must be finite");
-    hipError_t e = hipMemcpyAsync(c->vbuf[c->cur], v_host, (size_t)c->p.T * 2 * sizeof(double),
-                                  hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    int32_t stv[4];
+    hipError_t e = read_state(c, stv);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->desc.v[stv[0]], v_host, (size_t)c->p.T * 2 * sizeof(double),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        stv[1] = 0;
+        e = write_state(c, stv);
+    }
     if (e != hipSuccess) return device_fail(e, "writing controls");
     c->pending_shift = 0;
     return BSS_OK;
@@ -526,24 +666,36 @@ bss_status bss_set_controls(bss_ctx* c, const double* v_host)
 
 bss_status bss_set_solve_index(bss_ctx* c, uint32_t s)
 {
-    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
-    c->solve_index = s;
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
+    int32_t stv[4];
+    hipError_t e = read_state(c, stv);
+    if (e == hipSuccess) {
+        stv[2] = (int32_t)s;
+        e = write_state(c, stv);
+    }
+    if (e != hipSuccess) return device_fail(e, "writing solve index");
     return BSS_OK;
 }
 
-bss_status bss_get_solve_index(const bss_ctx* c, uint32_t* s)
+bss_status bss_get_solve_index(const bss_ctx* cc, uint32_t* s)
 {
+    bss_ctx* c = const_cast<bss_ctx*>(cc);
     if (!c || !s) return fail(BSS_E_INVAL, "NULL argument");
-    *s = c->solve_index;
+    int32_t stv[4];
+    hipError_t e = read_state(c, stv);
+    if (e != hipSuccess) return device_fail(e, "reading solve index");
+    *s = (uint32_t)stv[2];
     return BSS_OK;
 }
 
 bss_status bss_get_info(bss_ctx* c, bss_info* info)
 {
     if (!c || !info) return fail(BSS_E_INVAL, "NULL argument");
-    hipError_t e = hipMemcpyAsync(c->host, c->stats, 8 * sizeof(double), hipMemcpyDeviceToHost,
-                                  c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    const hipStream_t s = work_stream(c);
+    hipError_t e = hipMemcpyAsync(c->host, c->desc.stats, 8 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(e, "reading stats");
     fill_info(c, c->host, info);
     return BSS_OK;
@@ -574,20 +726,34 @@ bss_status bss_timing_read(bss_ctx* c, double* rollout_ms_total, int32_t* count)
     return BSS_OK;
 }
 
-bss_status bss_set_lanes(bss_ctx* c, int32_t lanes)
+bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl)
 {
-    if (!c) return fail(BSS_E_INVAL, "ctx is NULL");
+    bss_status st = check_free(c);
+    if (st != BSS_OK) return st;
     bss_params q = c->p;
     q.lanes = lanes;
-    bss_status st = bss_validate(&q);
+    st = bss_validate(&q);
     if (st != BSS_OK) return st;
-    c->shape = choose_shape(q.K, q.M, q.T, lanes);
+    if (ppl != 0 && ppl != 1 && ppl != 2 && ppl != 4 && ppl != 8)
+        return fail(BSS_E_INVAL, "particles per lane must be 0, 1, 2, 4 or 8");
+    if (ppl != 0 && (q.M + ppl - 1) / ppl > 64)
+        return fail(BSS_E_INVAL, "M=%d needs more than 64 lanes with %d particles per lane", q.M,
+                    ppl);
+    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(e, "synchronising");
+    c->shape = sh;
+    e = upload_shape(c);
+    if (e != hipSuccess) return device_fail(e, "uploading launch shape");
     return BSS_OK;
 }
+
+bss_status bss_set_lanes(bss_ctx* c, int32_t lanes) { return bss_set_shape(c, lanes, 0); }
 
 void bss_destroy(bss_ctx* c)
 {
     if (!c) return;
+    if (c->batch) return;   // owned by a batch: bss_batch_destroy releases it first
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t ev : c->ev) (void)hipEventDestroy(ev);
     if (c->block) {
@@ -596,6 +762,324 @@ void bss_destroy(bss_ctx* c)
     }
     if (c->host) (void)hipHostFree(c->host);
     delete c;
+}
+
+// ---- batches ---------------------------------------------------------------------------------
+static hipError_t batch_layout(bss_batch* b, int ppl)
+{
+    // launch shape of every instance for a common particles-per-lane count, the solve grid with
+    // blocks ordered by horizon (longest first; with P fixed a block's work is proportional to T),
+    // and the merge grid
+    std::vector<BlockDesc> blocks;
+    std::vector<MergeDesc> cols;
+    std::vector<int> lanes(b->n);
+    size_t lds = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const bss_params& p = b->ctxs[i]->p;
+        const LaunchShape sh = choose_shape(p.K, p.M, p.T, 0, ppl);
+        lanes[i] = sh.lanes;
+        lds = std::max(lds, solve_lds_bytes(sh.lanes, p.T));
+        std::vector<BlockDesc> t = block_table(i, p.K, sh.lanes);
+        blocks.insert(blocks.end(), t.begin(), t.end());
+        for (int col = 0; col < 2 * p.T; ++col) cols.push_back(MergeDesc{i, col});
+    }
+    std::stable_sort(blocks.begin(), blocks.end(), [&](const BlockDesc& x, const BlockDesc& y) {
+        return b->ctxs[x.inst]->p.T > b->ctxs[y.inst]->p.T;
+    });
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < b->n && e == hipSuccess; ++i) {
+        InstanceDesc head = b->ctxs[i]->desc;
+        head.lanes = lanes[i];
+        head.nblocks = solve_blocks(b->ctxs[i]->p.K, lanes[i]);
+        head.x0_index = i;
+        e = hipMemcpy(b->d_desc + i, &head, offsetof(InstanceDesc, cur), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_blocks, blocks.data(), blocks.size() * sizeof(BlockDesc),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_cols, cols.data(), cols.size() * sizeof(MergeDesc),
+                      hipMemcpyHostToDevice);
+    b->nblocks = (int)blocks.size();
+    b->ncols = (int)cols.size();
+    b->lds = lds;
+    b->ppl = ppl;
+    b->lanes = lanes;
+    return e;
+}
+
+static hipError_t batch_enqueue(bss_batch* b)
+{
+    hipError_t e = launch_solve(b->d_desc, b->d_blocks, b->nblocks, b->ppl, b->shield, b->lds,
+                                b->d_x0, nullptr, 0, b->stream);
+    if (e == hipSuccess) e = launch_merge(b->d_desc, b->d_cols, b->ncols, 0, b->stream);
+    return e;
+}
+
+static void batch_free(bss_batch* b)
+{
+    if (b->captured) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+    }
+    if (b->block) (void)hipFree(b->block);
+    for (bss_ctx* c : b->ctxs)
+        if (c && c->batch == b) c->batch = nullptr;
+    delete b;
+}
+
+bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_t shift_after,
+                            bss_batch** out)
+{
+    if (!out) return fail(BSS_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return fail(BSS_E_INVAL, "need at least one context");
+    if (ppl != 0 && ppl != 1 && ppl != 2 && ppl != 4 && ppl != 8)
+        return fail(BSS_E_INVAL, "particles per lane must be 0 (tune), 1, 2, 4 or 8");
+    if (shift_after != 0 && shift_after != 1) return fail(BSS_E_INVAL, "shift_after must be 0/1");
+    int M_max = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(BSS_E_INVAL, "context %d is NULL", i);
+        if (ctxs[i]->batch) return fail(BSS_E_STATE, "context %d already belongs to a batch", i);
+        for (int q = 0; q < i; ++q)
+            if (ctxs[q] == ctxs[i]) return fail(BSS_E_INVAL, "context %d appears twice", i);
+        M_max = std::max(M_max, ctxs[i]->p.M);
+    }
+    if (ppl != 0 && (M_max + ppl - 1) / ppl > 64)
+        return fail(BSS_E_INVAL, "M=%d needs more than 64 lanes with %d particles per lane",
+                    M_max, ppl);
+    bss_batch* b = new (std::nothrow) bss_batch();
+    if (!b) return fail(BSS_E_NOMEM, "host allocation failed");
+    b->ctxs.assign(ctxs, ctxs + n);
+    b->n = n;
+    b->stream = ctxs[0]->stream;
+    b->shift_after = shift_after;
+    b->captured = false;
+    b->block = nullptr;
+    b->shield = false;
+    size_t nb = 0, nc = 0;
+    for (int i = 0; i < n; ++i) {
+        nb += max_blocks(ctxs[i]->p.K);
+        nc += 2 * (size_t)ctxs[i]->p.T;
+        b->shield = b->shield || ctxs[i]->p.shield_iters > 0;
+    }
+    const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));
+    const size_t total = 2 * sz_desc + align256(nb * sizeof(BlockDesc)) +
+                         align256(nc * sizeof(MergeDesc)) + align256((size_t)n * 6 * sizeof(double));
+    hipError_t e = hipMalloc(&b->block, total);
+    if (e != hipSuccess) {
+        b->block = nullptr;
+        batch_free(b);
+        return fail(BSS_E_NOMEM, "hipMalloc(%zu): %s", total, hipGetErrorString(e));
+    }
+    char* p = (char*)b->block;
+    b->d_desc = (InstanceDesc*)p;
+    p += sz_desc;
+    b->d_backup = (InstanceDesc*)p;
+    p += sz_desc;
+    b->d_blocks = (BlockDesc*)p;
+    p += align256(nb * sizeof(BlockDesc));
+    b->d_cols = (MergeDesc*)p;
+    p += align256(nc * sizeof(MergeDesc));
+    b->d_x0 = (double*)p;
+
+    // the batch takes over each context's descriptor (device state included); pending host
+    // shifts are folded into the device state
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        bss_ctx* c = ctxs[i];
+        e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_desc + i, c->d_desc, sizeof(InstanceDesc), hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) {
+            int32_t sa[2] = {shift_after, 0};
+            e = hipMemcpy((char*)(b->d_desc + i) + offsetof(InstanceDesc, shift_after), sa,
+                          sizeof(sa), hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess && c->pending_shift) {
+            int32_t stv[4];
+            e = hipMemcpy(stv, (char*)(b->d_desc + i) + kStateOffset, kStateBytes,
+                          hipMemcpyDeviceToHost);
+            stv[1] = std::min(stv[1] + c->pending_shift, c->p.T - 1);
+            if (e == hipSuccess)
+                e = hipMemcpy((char*)(b->d_desc + i) + kStateOffset, stv, kStateBytes,
+                              hipMemcpyHostToDevice);
+            c->pending_shift = 0;
+        }
+    }
+    if (e == hipSuccess) e = hipMemset(b->d_x0, 0, (size_t)n * 6 * sizeof(double));
+    const int ppl0 = ppl != 0 ? ppl : (M_max > 256 ? 8 : 4);
+    if (e == hipSuccess) e = batch_layout(b, ppl0);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return device_fail(e, "creating batch");
+    }
+    for (int i = 0; i < n; ++i) {
+        ctxs[i]->batch = b;
+        ctxs[i]->batch_index = i;
+    }
+    *out = b;
+    return BSS_OK;
+}
+
+bss_status bss_batch_states(bss_batch* b, double** x0_dev)
+{
+    if (!b || !x0_dev) return fail(BSS_E_INVAL, "NULL argument");
+    *x0_dev = b->d_x0;
+    return BSS_OK;
+}
+
+bss_status bss_batch_set_states(bss_batch* b, const double* x0_host)
+{
+    if (!b || !x0_host) return fail(BSS_E_INVAL, "NULL argument");
+    for (int i = 0; i < 6 * b->n; ++i)
+        if (!std::isfinite(x0_host[i])) return fail(BSS_E_INVAL, "state %d is not finite", i / 6);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_x0, x0_host, (size_t)b->n * 6 * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(e, "writing states");
+    return BSS_OK;
+}
+
+bss_status bss_batch_copy_states(bss_batch* b, const double* x0_dev)
+{
+    if (!b || !x0_dev) return fail(BSS_E_INVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(b->d_x0, x0_dev, (size_t)b->n * 6 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return device_fail(e, "copying states");
+    return BSS_OK;
+}
+
+bss_status bss_batch_solve(bss_batch* b)
+{
+    if (!b) return fail(BSS_E_INVAL, "batch is NULL");
+    hipError_t e = b->captured ? hipGraphLaunch(b->exec, b->stream) : batch_enqueue(b);
+    if (e != hipSuccess) return device_fail(e, "batch solve");
+    return BSS_OK;
+}
+
+bss_status bss_batch_capture(bss_batch* b)
+{
+    if (!b) return fail(BSS_E_INVAL, "batch is NULL");
+    if (b->captured) return BSS_OK;
+    if (b->stream == nullptr)
+        return fail(BSS_E_STATE, "graph capture needs the batch on a created (non-null) stream");
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return device_fail(e, "hipStreamBeginCapture");
+    hipError_t le = batch_enqueue(b);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return device_fail(le != hipSuccess ? le : e, "capturing the batch launch");
+    }
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return device_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = g;
+    b->captured = true;
+    return BSS_OK;
+}
+
+bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
+{
+    if (!b) return fail(BSS_E_INVAL, "batch is NULL");
+    if (b->captured) return fail(BSS_E_STATE, "tune before capturing the batch");
+    int M_max = 0;
+    for (bss_ctx* c : b->ctxs) M_max = std::max(M_max, c->p.M);
+    // the trial solves advance each member's state and overwrite both of its mean-sequence
+    // buffers: save the descriptors and the buffers, restore them afterwards
+    size_t vbytes = 0;
+    for (bss_ctx* c : b->ctxs) vbytes += 2 * (size_t)c->p.T * 2 * sizeof(double);
+    double* vsave = nullptr;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipMalloc(&vsave, vbytes);
+    if (e != hipSuccess) return device_fail(e, "allocating the tuning backup");
+    auto copy_v = [&](bool save) {
+        hipError_t r = hipSuccess;
+        char* q = (char*)vsave;
+        for (bss_ctx* c : b->ctxs) {
+            const size_t nb = (size_t)c->p.T * 2 * sizeof(double);
+            for (int h = 0; h < 2 && r == hipSuccess; ++h) {
+                r = save ? hipMemcpy(q, c->desc.v[h], nb, hipMemcpyDeviceToDevice)
+                         : hipMemcpy(c->desc.v[h], q, nb, hipMemcpyDeviceToDevice);
+                q += nb;
+            }
+        }
+        return r;
+    };
+    e = copy_v(true);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_backup, b->d_desc, (size_t)b->n * sizeof(InstanceDesc),
+                      hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(vsave);
+        return device_fail(e, "saving batch state");
+    }
+    hipEvent_t ev0, ev1;
+    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
+        (void)hipFree(vsave);
+        return fail(BSS_E_DEVICE, "hipEventCreate");
+    }
+    int best = b->ppl;
+    float best_ms = 1e30f;
+    const int cands[] = {1, 2, 4, 8};
+    for (int cand : cands) {
+        if ((M_max + cand - 1) / cand > 64) continue;
+        e = batch_layout(b, cand);
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+        if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+        if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    // restore the state the trial solves advanced, then the chosen layout
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_desc, b->d_backup, (size_t)b->n * sizeof(InstanceDesc),
+                      hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = copy_v(false);
+    (void)hipFree(vsave);
+    if (e == hipSuccess) e = batch_layout(b, best);
+    if (e != hipSuccess) return device_fail(e, "autotuning the batch");
+    if (ppl_out) *ppl_out = best;
+    return BSS_OK;
+}
+
+bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl)
+{
+    if (!b) return fail(BSS_E_INVAL, "batch is NULL");
+    if (nblocks) *nblocks = b->nblocks;
+    if (ppl) *ppl = b->ppl;
+    return BSS_OK;
+}
+
+void bss_batch_destroy(bss_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    // hand each context its advanced state back (its own launch shape is kept)
+    for (int i = 0; i < b->n; ++i) {
+        bss_ctx* c = b->ctxs[i];
+        int32_t stv[4];
+        if (hipMemcpy(stv, (char*)(b->d_desc + i) + kStateOffset, kStateBytes,
+                      hipMemcpyDeviceToHost) == hipSuccess) {
+            stv[3] = 0;
+            (void)hipMemcpy((char*)c->d_desc + kStateOffset, stv, kStateBytes,
+                            hipMemcpyHostToDevice);
+        }
+    }
+    batch_free(b);
 }
 
 const char* bss_last_error(void) { return g_err.c_str(); }
@@ -647,18 +1131,7 @@ bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u,
     bss_status st = bss_validate(p);
     if (st != BSS_OK) return st;
     if (!mom || !u || !v || !S) return fail(BSS_E_INVAL, "NULL buffer");
-    SolveArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.K = p->K;
-    a.M = p->M;
-    a.T = p->T;
-    a.vshift = 0;
-    a.sc = make_score(*p);
-    a.mom = const_cast<double*>(mom);
-    a.u = const_cast<float*>(u);
-    a.v = v;
-    a.S = S;
-    hipError_t e = launch_score(a, (hipStream_t)stream);
+    hipError_t e = launch_score(p->K, p->T, make_score(*p), mom, u, v, S, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "score launch");
     return BSS_OK;
 }
@@ -680,20 +1153,11 @@ bss_status bss_dev_update(const bss_params* p, const double* S, const float* u, 
     double* v_out = (double*)workspace;
     double* partial = (double*)((char*)workspace + align256((size_t)p->T * 2 * sizeof(double)));
     hipError_t e = launch_partials(p->K, p->T, p->lambda, S, u, v, partial, s);
-    if (e != hipSuccess) return device_fail(e, "partial launch");
-    MergeArgs ma;
-    ma.T = p->T;
-    ma.G = partial_blocks(p->K);
-    ma.vshift = 0;
-    ma.lambda = p->lambda;
-    ma.partial = partial;
-    ma.v_in = v;
-    ma.v_out = v_out;
-    ma.stats = stats;
-    e = launch_merge(ma, s);
+    if (e == hipSuccess)
+        e = launch_merge_plain(p->T, partial_blocks(p->K), p->lambda, partial, v, v_out, stats, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(v, v_out, (size_t)p->T * 2 * sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return device_fail(e, "merge launch");
+    if (e != hipSuccess) return device_fail(e, "update launch");
     return BSS_OK;
 }
 

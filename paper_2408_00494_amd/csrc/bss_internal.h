@@ -2,6 +2,14 @@
 //
 // The rollout works in single precision on per-particle state; every per-(sample, step) scalar
 // (moments, scores, the shield repair) and the K-reduction work in double precision.
+//
+// Every solve launch is descriptor-driven: an InstanceDesc in device memory describes one problem
+// (a context), a BlockDesc maps each block of the solve grid to (instance, first sample), and a
+// MergeDesc maps each block of the merge grid to (instance, control entry).  A single context is a
+// batch of one; a batch of uneven instances runs in the same two launches.  The per-solve state
+// (which ping-pong buffer holds the mean sequence, pending warm-start shifts, the solve index) lives
+// in the descriptor and is advanced on the device, so a batched launch can be captured in a graph
+// and replayed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,37 +43,48 @@ struct ScoreF64 {
     double shield_gmin, shield_fd;
 };
 
-// One solve's launch description.
-struct SolveArgs {
-    int32_t K, M, T;
-    int32_t vshift;                // the mean sequence is read as v[min(t + vshift, T - 1)]
-    uint32_t solve_index;
+// One problem instance (device memory).
+struct InstanceDesc {
+    // sizes and launch shape (P, particles per lane, is the kernel's template parameter)
+    int32_t K, M, T, lanes;
+    int32_t nblocks;               // solve blocks of this instance (= number of partials)
+    int32_t x0_index;              // state estimate at x0_base + 6 x0_index (launch argument)
+    // per-solve state, advanced on the device by the last merge block of the instance
+    int32_t cur;                   // v[cur] holds the mean sequence
+    int32_t vshift;                // pending warm-start shifts: read v[min(t + vshift, T - 1)]
+    uint32_t solve_index;          // Philox word 3 (low 28 bits)
+    uint32_t done;                 // merge blocks finished in the current launch
+    int32_t shift_after;           // 1: leave one warm-start shift pending after the solve
+    int32_t status;                // 0 ok, 5 no finite cost (v unchanged)
+    // random numbers and model
     uint32_t key0, key1;           // Philox key = (lo32 seed, hi32 seed)
     float steer_max, accel_max;
     float sig_eps0, sig_eps1;
     float sig_w0, sig_w1, sig_w2;
     CarF32 car;
     ScoreF64 sc;
-    const double* x0;              // device [6]
-    const double* Sigma0;          // device [36] row-major, or nullptr
-    const double* v;               // device [T][2] mean sequence read by this solve
-    float* u;                      // device [K][T][2] copy of the sampled controls, or nullptr
-    double* mom;                   // device [K][T+1][9] beliefs (always written; scoring reads them)
-    double* S;                     // device [K] trajectory costs
-    double* partial;               // device [G][2T + 4] per-block log-sum-exp partials
+    // buffers
+    double* v[2];                  // ping-pong pair of mean sequences [T][2]
+    float* u;                      // [K][T][2] copy of the sampled controls, or nullptr
+    double* mom;                   // [K][T+1][9] beliefs (written by the loop, read by scoring)
+    double* S;                     // [K] trajectory costs
+    double* partial;               // [nblocks][2T + 4] per-block log-sum-exp partials
+    double* stats;                 // [8]: S_min, Z, ESS, #finite, status, v+_0 (2), unused
+};
+
+struct BlockDesc {
+    int32_t inst;                  // instance index
+    int32_t k0;                    // first sample of the block
+};
+
+struct MergeDesc {
+    int32_t inst;                  // instance index
+    int32_t col;                   // control entry 2t + j
 };
 
 // Per-block partial of the K-reduction (weights relative to the block's own minimum cost m_b):
 //   [0, 2T)  N_i = sum_k w_k (u_{k,i} - v_i),   [2T] Z_b = sum w_k,   [2T+1] sum w_k^2,
 //   [2T+2]   number of finite costs,            [2T+3] m_b (+inf if none is finite).
-struct MergeArgs {
-    int32_t T, G, vshift;
-    double lambda;
-    const double* partial;         // [G][2T + 4]
-    const double* v_in;            // [T][2] mean sequence the solve read (with vshift)
-    double* v_out;                 // [T][2] updated mean sequence (a different buffer)
-    double* stats;                 // [8]: S_min, Z, ESS, #finite, status, v+_0 (2), unused
-};
 
 // samples per block of the partial kernel used for stand-alone K-reductions
 constexpr int kPartialSlice = 16;
@@ -81,16 +100,26 @@ constexpr size_t kMaxLds = 65536;
 
 // dynamic LDS of one solve block with L lanes per sample
 size_t solve_lds_bytes(int lanes, int T);
-LaunchShape choose_shape(int K, int M, int T, int requested_lanes);
+LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl);
 int solve_blocks(int K, int lanes);
 
-hipError_t launch_solve(const SolveArgs& a, LaunchShape shape, hipStream_t stream);
-hipError_t launch_merge(const MergeArgs& a, hipStream_t stream);
+// Solve grid: nblocks blocks described by `blocks`; x0_base holds the state estimates (6 doubles
+// per instance at x0_index), Sigma0_base the covariances (36 doubles) or nullptr; extra_shift is
+// added to every instance's pending shift for this launch.
+hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
+                        bool shield, size_t lds, const double* x0_base, const double* Sigma0_base,
+                        int extra_shift, hipStream_t stream);
+hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
+                        int extra_shift, hipStream_t stream);
 
 // stand-alone kernels for staged checks
-hipError_t launch_score(const SolveArgs& a, hipStream_t stream);
+hipError_t launch_score(int K, int T, const ScoreF64& sc, const double* mom, const float* u,
+                        const double* v, double* S, hipStream_t stream);
 hipError_t launch_partials(int K, int T, double lambda, const double* S, const float* u,
                            const double* v, double* partial, hipStream_t stream);
+hipError_t launch_merge_plain(int T, int G, double lambda, const double* partial,
+                              const double* v_in, double* v_out, double* stats,
+                              hipStream_t stream);
 int partial_blocks(int K);
 hipError_t launch_philox(uint32_t key0, uint32_t key1, const uint32_t* ctr, uint32_t* out,
                          int64_t n, hipStream_t stream);

@@ -75,12 +75,14 @@ constexpr int kDppHalfRowMirror = 0x141; // lane i <- lane 7-i within each 8
 constexpr int kDppRowMirror = 0x140;     // lane i <- lane 15-i within each 16
 constexpr int kDppRowBcast0 = 0x150;     // every lane of a row <- lane 0 of the row
 constexpr int kDppRowBcast8 = 0x158;     // every lane of a row <- lane 8 of the row
+constexpr int kDppQuadBcast0 = 0x00;     // quad_perm [0,0,0,0]
+constexpr int kDppQuadBcast0And2 = 0xA0; // quad_perm [0,0,2,2]
 
-// Sum over the L lanes of a group (L = 1..64, groups aligned in the wave), result in every lane
-// of the group and bitwise identical across them (each stage adds the same two partial sums in
-// either order).  Within a row of 16 the partners come from DPP; across rows from a shuffle.
-template <int L>
-__device__ __forceinline__ double group_sum(double x)
+// Sum over the L lanes of a group (L = 1, 2, 4, ..., 64, groups aligned in the wave, L uniform
+// over the block), result in every lane of the group and bitwise identical across them (each
+// stage adds the same two partial sums in either order).  Within a row of 16 the partners come
+// from DPP; across rows from a shuffle.
+__device__ __forceinline__ double group_sum(double x, int L)
 {
     if (L > 1) x += dpp_f64<kDppQuadSwap1>(x);
     if (L > 2) x += dpp_f64<kDppQuadSwap2>(x);
@@ -92,14 +94,16 @@ __device__ __forceinline__ double group_sum(double x)
 }
 
 // Value of lane 0 of the group in every lane of the group.
-template <int L>
-__device__ __forceinline__ float group_first(float x)
+__device__ __forceinline__ float group_first(float x, int L)
 {
-    if (L == 16) return dpp_f32<kDppRowBcast0>(x);
+    if (L == 1) return x;
+    if (L == 2) return dpp_f32<kDppQuadBcast0And2>(x);
+    if (L == 4) return dpp_f32<kDppQuadBcast0>(x);
     if (L == 8) {
         const float a = dpp_f32<kDppRowBcast0>(x), b = dpp_f32<kDppRowBcast8>(x);
         return (threadIdx.x & 8) ? b : a;
     }
+    if (L == 16) return dpp_f32<kDppRowBcast0>(x);
     return __shfl(x, 0, L);
 }
 
@@ -113,9 +117,8 @@ __device__ __forceinline__ int vrow(int t, int vshift, int T)
 // phi_scale on the terminal record), control cost on records < T, and C_safe on the transition
 // into the record (record 0 has none).  `h_carry` holds h of the record before the chunk and is
 // advanced to the chunk's last record.  Returns this lane's contribution.
-template <int W>
 __device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int rec_idx, int count,
-                                     int lane, int T, const float2* u_row, const double* v,
+                                     int lane, int W, int T, const float2* u_row, const double* v,
                                      int vshift, double& h_carry)
 {
     const bool valid = lane < count;
@@ -190,37 +193,49 @@ __device__ inline void block_partial(int T, int n, const double* S_sh, double* w
 // ----------------------------------------------------------------------------------------------
 // Up to four particles per lane the loop fits 128 registers, which keeps four waves per SIMD;
 // larger P (and the shield's double-precision repair) get the register budget of two.
-template <int L, int P, bool SHIELD>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_kernel(SolveArgs a)
+// One solve block with L lanes per sample (L is a compile-time constant so that the group
+// reductions are straight-line DPP sequences).
+template <int P, bool SHIELD, int L>
+__device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDesc bd,
+                                            const double* __restrict__ x0_base,
+                                            const double* __restrict__ Sigma0_base,
+                                            int extra_shift)
 {
-    constexpr int kGroups = 256 / L;
+    constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
+    constexpr int groups = 256 >> log2L;
+    const int T = d.T, M = d.M;
+    const int vshift = d.vshift + extra_shift;
+    const double* __restrict__ v = d.v[d.cur];
     extern __shared__ double smem[];
-    const int T = a.T, M = a.M;
-    double* S_sh = smem;                                     // [kGroups]
-    double* w_sh = S_sh + kGroups;                           // [kGroups]
-    float2* u_sh = reinterpret_cast<float2*>(w_sh + kGroups);  // [kGroups][T]
-    const int g = threadIdx.x / L;
-    const int j = threadIdx.x % L;
-    const int k = blockIdx.x * kGroups + g;
-    const bool active = k < a.K;
+    double* S_sh = smem;                                     // [groups]
+    double* w_sh = S_sh + groups;                            // [groups]
+    float2* u_sh = reinterpret_cast<float2*>(w_sh + groups);  // [groups][T]
+    const int g = threadIdx.x >> log2L;
+    const int j = threadIdx.x & (L - 1);
+    const int k = bd.k0 + g;
+    const bool active = k < d.K;
     float2* us = u_sh + g * T;
-    double* mom_k = a.mom + (size_t)(active ? k : 0) * (T + 1) * 9;
-    const uint32_t s = a.solve_index;
+    double* mom_k = d.mom + (size_t)(active ? k : 0) * (T + 1) * 9;
+    const uint32_t s = d.solve_index;
+    const uint32_t key0 = d.key0, key1 = d.key1;
+    const double* x0p = x0_base + 6 * d.x0_index;
+    const double* S0p = Sigma0_base ? Sigma0_base + 36 * d.x0_index : nullptr;
 
     // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
     if (active) {
+        const float sig0 = d.sig_eps0, sig1 = d.sig_eps1;
+        const float smax = d.steer_max, amax = d.accel_max;
         for (int t = j; t < T; t += L) {
             uint32_t c0 = (uint32_t)t, c1 = 0u, c2 = (uint32_t)k, c3 = rng_word3(kTagEps, s);
-            philox10(c0, c1, c2, c3, a.key0, a.key1);
+            philox10(c0, c1, c2, c3, key0, key1);
             float z0, z1;
             bm_pair(c0, c1, z0, z1);
-            const int r = vrow(t, a.vshift, T);
-            const float v0 = (float)a.v[2 * r], v1 = (float)a.v[2 * r + 1];
-            const float u0 = fminf(fmaxf(fmaf(a.sig_eps0, z0, v0), -a.steer_max), a.steer_max);
-            const float u1 = fminf(fmaxf(fmaf(a.sig_eps1, z1, v1), -a.accel_max), a.accel_max);
+            const int r = vrow(t, vshift, T);
+            const float v0 = (float)v[2 * r], v1 = (float)v[2 * r + 1];
+            const float u0 = fminf(fmaxf(fmaf(sig0, z0, v0), -smax), smax);
+            const float u1 = fminf(fmaxf(fmaf(sig1, z1, v1), -amax), amax);
             us[t] = make_float2(u0, u1);
-            if (!SHIELD && a.u) reinterpret_cast<float2*>(a.u)[(size_t)k * T + t] = us[t];
+            if (!SHIELD && d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = us[t];
         }
     }
     __syncthreads();
@@ -228,14 +243,14 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
     if (active) {
         double x0[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) x0[i] = a.x0[i];
-        const bool spread = a.Sigma0 != nullptr;
+        for (int i = 0; i < 6; ++i) x0[i] = x0p[i];
+        const bool spread = S0p != nullptr;
 
         // state relative to the estimate: position and heading as compensated (sum, correction)
         float Xs[P], Xc[P], Ys[P], Yc[P], Ps[P], Pc[P], vx[P], vy[P], vr[P];
         {
             double L0[36];
-            if (spread) chol6(a.Sigma0, L0);
+            if (spread) chol6(S0p, L0);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int m = j + p * L;
@@ -246,7 +261,7 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
                     for (int blk = 0; blk < 2; ++blk) {
                         uint32_t c0 = (uint32_t)blk, c1 = (uint32_t)m, c2 = (uint32_t)k,
                                  c3 = rng_word3(kTagInit, s);
-                        philox10(c0, c1, c2, c3, a.key0, a.key1);
+                        philox10(c0, c1, c2, c3, key0, key1);
                         float z0, z1;
                         bm_pair(c0, c1, z0, z1);
                         xi[blk * 3 + 0] = z0;
@@ -272,15 +287,16 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
         }
         const double rev0d = x0[2] * 0.15915494309189535;
         const float rev0 = (float)(rev0d - rint(rev0d));
-        const CarF32 car = a.car;
+        const CarF32 car = d.car;
+        const float sw0 = d.sig_w0, sw1 = d.sig_w1, sw2 = d.sig_w2;
 
         // belief at t = 0 is the given estimate (record 0)
         double bel[9];
 #pragma unroll
         for (int i = 0; i < 6; ++i) bel[i] = x0[i];
-        bel[6] = spread ? a.Sigma0[0] : 0.0;
-        bel[7] = spread ? a.Sigma0[1] : 0.0;
-        bel[8] = spread ? a.Sigma0[7] : 0.0;
+        bel[6] = spread ? S0p[0] : 0.0;
+        bel[7] = spread ? S0p[1] : 0.0;
+        bel[8] = spread ? S0p[7] : 0.0;
         if (j == 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
@@ -291,14 +307,14 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
         const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
         PhiloxParticle pp[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) pp[p] = philox_particle((uint32_t)(j + p * L), hk, a.key0, a.key1);
+        for (int p = 0; p < P; ++p) pp[p] = philox_particle((uint32_t)(j + p * L), hk, key0, key1);
         const double invM = 1.0 / (double)M;
         const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
 
         for (int t = 0; t < T; ++t) {
             float2 uu = us[t];
             if (SHIELD) {
-                const ScoreF64& sc = a.sc;
+                const ScoreF64& sc = d.sc;
                 if (sc.shield_iters > 0) {
                     const BeliefEval be = eval_belief(sc, bel);
                     const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
@@ -326,18 +342,18 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
                 }
                 if (j == 0) {
                     us[t] = uu;
-                    if (a.u) reinterpret_cast<float2*>(a.u)[(size_t)k * T + t] = uu;
+                    if (d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = uu;
                 }
             }
             const StepF32 st = make_step(car, uu.x, uu.y);
-            const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, a.key0, a.key1);
+            const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
             double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0, sYY = 0;
             double refX = 0.0, refY = 0.0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int m = j + p * L;
                 uint32_t c0, c1, c2, c3;
-                philox10_tail(ps, pp[p], a.key0, a.key1, c0, c1, c2, c3);
+                philox10_tail(ps, pp[p], key0, key1, c0, c1, c2, c3);
                 float w0, w1;
                 bm_pair(c0, c1, w0, w1);
                 const float w2 = bm_cos(c2, c3);
@@ -355,14 +371,14 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
                 kahan_add(Xs[p], Xc[p], car.dt * dX2);
                 kahan_add(Ys[p], Yc[p], car.dt * dY2);
                 kahan_add(Ps[p], Pc[p], car.dt * vrm);
-                vx[p] = fmaf(a.sig_w0, w0, fmaf(car.dt, dvx2, vx[p]));
-                vy[p] = fmaf(a.sig_w1, w1, fmaf(car.dt, dvy2, vy[p]));
-                vr[p] = fmaf(a.sig_w2, w2, fmaf(car.dt, dr2, vr[p]));
+                vx[p] = fmaf(sw0, w0, fmaf(car.dt, dvx2, vx[p]));
+                vy[p] = fmaf(sw1, w1, fmaf(car.dt, dvy2, vy[p]));
+                vr[p] = fmaf(sw2, w2, fmaf(car.dt, dr2, vr[p]));
 
                 if (p == 0) {
                     // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
-                    refX = (double)group_first<L>(Xs[0]) - (double)group_first<L>(Xc[0]);
-                    refY = (double)group_first<L>(Ys[0]) - (double)group_first<L>(Yc[0]);
+                    refX = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
+                    refY = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
                 }
                 if (m < M) {   // masked particles beyond M contribute nothing
                     const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
@@ -378,15 +394,15 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
                     sYY = fma(Y, Y, sYY);
                 }
             }
-            sX = group_sum<L>(sX);
-            sY = group_sum<L>(sY);
-            sP = group_sum<L>(sP);
-            svx = group_sum<L>(svx);
-            svy = group_sum<L>(svy);
-            svr = group_sum<L>(svr);
-            sXX = group_sum<L>(sXX);
-            sXY = group_sum<L>(sXY);
-            sYY = group_sum<L>(sYY);
+            sX = group_sum(sX, L);
+            sY = group_sum(sY, L);
+            sP = group_sum(sP, L);
+            svx = group_sum(svx, L);
+            svy = group_sum(svy, L);
+            svr = group_sum(svr, L);
+            sXX = group_sum(sXX, L);
+            sXY = group_sum(sXY, L);
+            sYY = group_sum(sYY, L);
             // moments: sums of positions shifted by particle 0, heading relative to the estimate
             const double mX = sX * invM, mY = sY * invM;
             bel[0] = x0[0] + (refX + mX);
@@ -400,7 +416,7 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
             bel[8] = (sYY - sY * mY) * invM1;
 
             // record t+1, written by lane (t+1) % L of the group (spreads the stores)
-            if (j == (t + 1) % L) {
+            if (j == ((t + 1) & (L - 1))) {
                 double* rec = mom_k + (size_t)(t + 1) * 9;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) rec[i] = bel[i];
@@ -416,19 +432,37 @@ __attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_ker
         for (int base = 0; base <= T; base += L) {
             const int count = min(L, T + 1 - base);
             const int rec = base + min(j, count - 1);
-            S_part += score_chunk<L>(a.sc, mom_k + (size_t)rec * 9, base + j, count, j, T, us,
-                                     a.v, a.vshift, h_carry);
+            S_part += score_chunk(d.sc, mom_k + (size_t)rec * 9, base + j, count, j, L, T, us, v,
+                                  vshift, h_carry);
         }
     }
-    const double S_k = group_sum<L>(S_part);
+    const double S_k = group_sum(S_part, L);
     if (j == 0) {
         S_sh[g] = active ? S_k : INFINITY;
-        if (active) a.S[k] = S_k;
+        if (active) d.S[k] = S_k;
     }
     __syncthreads();
-    const int n = min(kGroups, a.K - (int)blockIdx.x * kGroups);
-    block_partial(T, n, S_sh, w_sh, u_sh, a.v, a.vshift, a.sc.lambda,
-                  a.partial + (size_t)blockIdx.x * (2 * T + 4));
+    const int n = min(groups, d.K - bd.k0);
+    block_partial(T, n, S_sh, w_sh, u_sh, v, vshift, d.sc.lambda,
+                  d.partial + (size_t)(bd.k0 >> (8 - log2L)) * (2 * T + 4));
+}
+
+// Solve grid: every block looks up its instance and first sample; the lane count is uniform over
+// a block, so the dispatch below is a block-uniform branch.
+template <int P, bool SHIELD>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_kernel(
+    const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
+    const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
+{
+    const BlockDesc bd = blocks[blockIdx.x];
+    const InstanceDesc& d = insts[bd.inst];
+    switch (d.lanes) {
+    case 8: solve_block<P, SHIELD, 8>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    case 16: solve_block<P, SHIELD, 16>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    case 32: solve_block<P, SHIELD, 32>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    default: solve_block<P, SHIELD, 64>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    }
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -448,21 +482,26 @@ __device__ __forceinline__ double block_reduce_256(double x, double* red, bool i
     return r;
 }
 
-__global__ __launch_bounds__(256) void merge_kernel(MergeArgs a)
+// Merge of one control entry of one instance: global minimum m = min_b m_b, rescale
+// exp(-(m_b - m)/lambda), fixed-order block reductions of Z, sum w^2, #finite and the entry's
+// numerator; returns through the references.
+__device__ inline void merge_entry(const double* partial, int G, int T, int col, double lambda,
+                                   double* red, double& m, double& Z, double& W2, double& nf,
+                                   double& N)
 {
-    __shared__ double red[256];
     const int tid = threadIdx.x;
-    const int T = a.T, G = a.G;
-    const int col = blockIdx.x;          // control entry 2t + j
     const int stride = 2 * T + 4;
-    double m = INFINITY;
-    for (int b = tid; b < G; b += 256) m = fmin(m, a.partial[(size_t)b * stride + 2 * T + 3]);
+    m = INFINITY;
+    for (int b = tid; b < G; b += 256) m = fmin(m, partial[(size_t)b * stride + 2 * T + 3]);
     m = block_reduce_256(m, red, true);
-    double Z = 0.0, W2 = 0.0, nf = 0.0, N = 0.0;
+    Z = 0.0;
+    W2 = 0.0;
+    nf = 0.0;
+    N = 0.0;
     for (int b = tid; b < G; b += 256) {
-        const double* pb = a.partial + (size_t)b * stride;
+        const double* pb = partial + (size_t)b * stride;
         const double mb = pb[2 * T + 3];
-        const double sc = isfinite(mb) ? exp(-(mb - m) / a.lambda) : 0.0;
+        const double sc = isfinite(mb) ? exp(-(mb - m) / lambda) : 0.0;
         Z += sc * pb[2 * T];
         W2 += sc * sc * pb[2 * T + 1];
         nf += pb[2 * T + 2];
@@ -472,22 +511,70 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a)
     W2 = block_reduce_256(W2, red, false);
     nf = block_reduce_256(nf, red, false);
     N = block_reduce_256(N, red, false);
-    if (tid == 0) {
+}
+
+__device__ inline void write_stats(double* stats, int col, double vo, bool ok, double m, double Z,
+                                   double W2, double nf)
+{
+    if (col < 2) stats[5 + col] = vo;
+    if (col == 0) {
+        stats[0] = m;
+        stats[1] = Z;
+        stats[2] = ok ? Z * Z / W2 : 0.0;
+        stats[3] = nf;
+        stats[4] = ok ? 0.0 : 5.0;
+        stats[7] = 0.0;
+    }
+}
+
+// One block per (instance, control entry).  v+ goes to the other buffer of the instance's
+// ping-pong pair; the last block of an instance to finish advances its per-solve state.
+__global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const MergeDesc* cols,
+                                                    int extra_shift)
+{
+    __shared__ double red[256];
+    const MergeDesc md = cols[blockIdx.x];
+    InstanceDesc& d = insts[md.inst];
+    const int T = d.T, col = md.col;
+    const int cur = d.cur;
+    double m, Z, W2, nf, N;
+    merge_entry(d.partial, d.nblocks, T, col, d.sc.lambda, red, m, Z, W2, nf, N);
+    if (threadIdx.x == 0) {
         const bool ok = nf > 0.0 && Z > 0.0;
-        const int t = col >> 1;
-        const int r = vrow(t, a.vshift, T);
-        const double vi = a.v_in[2 * r + (col & 1)];
+        const int r = vrow(col >> 1, d.vshift + extra_shift, T);
+        const double vi = d.v[cur][2 * r + (col & 1)];
         const double vo = ok ? vi + N / Z : vi;
-        a.v_out[col] = vo;
-        if (col < 2) a.stats[5 + col] = vo;
-        if (col == 0) {
-            a.stats[0] = m;
-            a.stats[1] = Z;
-            a.stats[2] = ok ? Z * Z / W2 : 0.0;
-            a.stats[3] = nf;
-            a.stats[4] = ok ? 0.0 : 5.0;
-            a.stats[7] = 0.0;
+        d.v[1 - cur][col] = vo;
+        write_stats(d.stats, col, vo, ok, m, Z, W2, nf);
+        __threadfence();
+        const uint32_t prev = atomicAdd(&d.done, 1u);
+        if (prev == (uint32_t)(2 * T - 1)) {
+            // every entry of this instance is written: publish the new state
+            d.done = 0u;
+            d.cur = 1 - cur;
+            d.vshift = d.shift_after;
+            d.solve_index = d.solve_index + 1u;
+            d.status = ok ? 0 : 5;
+            __threadfence();
         }
+    }
+}
+
+// Merge for the stand-alone K-reduction (explicit buffers, no instance state).
+__global__ __launch_bounds__(256) void merge_plain_kernel(int T, int G, double lambda,
+                                                          const double* partial,
+                                                          const double* v_in, double* v_out,
+                                                          double* stats)
+{
+    __shared__ double red[256];
+    const int col = blockIdx.x;
+    double m, Z, W2, nf, N;
+    merge_entry(partial, G, T, col, lambda, red, m, Z, W2, nf, N);
+    if (threadIdx.x == 0) {
+        const bool ok = nf > 0.0 && Z > 0.0;
+        const double vo = ok ? v_in[col] + N / Z : v_in[col];
+        v_out[col] = vo;
+        write_stats(stats, col, vo, ok, m, Z, W2, nf);
     }
 }
 
@@ -495,9 +582,8 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a)
 // stand-alone kernels for staged checks
 // ----------------------------------------------------------------------------------------------
 // scoring from given beliefs: one wave per sample, records in chunks of 64 lanes
-__global__ __launch_bounds__(256) void score_kernel(int K, int T, int vshift, ScoreF64 sc,
-                                                    const double* mom, const float* u,
-                                                    const double* v, double* S)
+__global__ __launch_bounds__(256) void score_kernel(int K, int T, ScoreF64 sc, const double* mom,
+                                                    const float* u, const double* v, double* S)
 {
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int k = blockIdx.x * 4 + w;
@@ -508,10 +594,10 @@ __global__ __launch_bounds__(256) void score_kernel(int K, int T, int vshift, Sc
     for (int base = 0; base <= T; base += 64) {
         const int count = min(64, T + 1 - base);
         const int rec = base + min(lane, count - 1);
-        part += score_chunk<64>(sc, mk + (size_t)rec * 9, base + lane, count, lane, T, uk, v,
-                                vshift, h_carry);
+        part += score_chunk(sc, mk + (size_t)rec * 9, base + lane, count, lane, 64, T, uk, v, 0,
+                            h_carry);
     }
-    part = group_sum<64>(part);
+    part = group_sum(part, 64);
     if (lane == 0) S[k] = part;
 }
 
@@ -628,29 +714,18 @@ __global__ void repair_kernel(ScoreF64 sc, const double* mom, const double* u_in
     u_out[2 * i + 1] = us1;
 }
 
-template <int L, int P>
-hipError_t launch_solve_lp(const SolveArgs& a, bool shield, hipStream_t stream)
+template <int P>
+hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                          bool shield, size_t lds, const double* x0_base,
+                          const double* Sigma0_base, int extra_shift, hipStream_t stream)
 {
-    constexpr int kGroups = 256 / L;
-    const unsigned blocks = (unsigned)((a.K + kGroups - 1) / kGroups);
-    const size_t lds = solve_lds_bytes(L, a.T);
     if (shield)
-        hipLaunchKernelGGL((solve_kernel<L, P, true>), dim3(blocks), dim3(256), lds, stream, a);
+        hipLaunchKernelGGL((solve_kernel<P, true>), dim3(nblocks), dim3(256), lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
     else
-        hipLaunchKernelGGL((solve_kernel<L, P, false>), dim3(blocks), dim3(256), lds, stream, a);
+        hipLaunchKernelGGL((solve_kernel<P, false>), dim3(nblocks), dim3(256), lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
     return hipGetLastError();
-}
-
-template <int L>
-hipError_t launch_solve_l(const SolveArgs& a, int ppl, bool shield, hipStream_t stream)
-{
-    switch (ppl) {
-    case 1: return launch_solve_lp<L, 1>(a, shield, stream);
-    case 2: return launch_solve_lp<L, 2>(a, shield, stream);
-    case 4: return launch_solve_lp<L, 4>(a, shield, stream);
-    case 8: return launch_solve_lp<L, 8>(a, shield, stream);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -672,12 +747,19 @@ size_t solve_lds_bytes(int lanes, int T)
     return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2);
 }
 
-LaunchShape choose_shape(int K, int M, int T, int requested_lanes)
+LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl)
 {
     (void)K;
     LaunchShape s;
-    if (requested_lanes == 8 || requested_lanes == 16 || requested_lanes == 32 ||
-        requested_lanes == 64) {
+    const bool lanes_ok = requested_lanes == 8 || requested_lanes == 16 || requested_lanes == 32 ||
+                          requested_lanes == 64;
+    if (requested_ppl == 1 || requested_ppl == 2 || requested_ppl == 4 || requested_ppl == 8) {
+        // lanes follow from the particles per lane: the smallest power of two >= 8 with L P >= M
+        // (the shield's difference points need five lanes per group)
+        int lanes = 8;
+        while (lanes < 64 && lanes * requested_ppl < M) lanes <<= 1;
+        s.lanes = lanes;
+    } else if (lanes_ok) {
         s.lanes = requested_lanes;
     } else {
         // default: about four particles per lane, 16..64 lanes per sample
@@ -699,28 +781,47 @@ int solve_blocks(int K, int lanes)
     return (K + groups - 1) / groups;
 }
 
-hipError_t launch_solve(const SolveArgs& a, LaunchShape shape, hipStream_t stream)
+hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
+                        bool shield, size_t lds, const double* x0_base, const double* Sigma0_base,
+                        int extra_shift, hipStream_t stream)
 {
-    const bool shield = a.sc.shield_iters > 0;
-    switch (shape.lanes) {
-    case 8: return launch_solve_l<8>(a, shape.ppl, shield, stream);
-    case 16: return launch_solve_l<16>(a, shape.ppl, shield, stream);
-    case 32: return launch_solve_l<32>(a, shape.ppl, shield, stream);
-    case 64: return launch_solve_l<64>(a, shape.ppl, shield, stream);
+    if (nblocks <= 0) return hipSuccess;
+    switch (ppl) {
+    case 1: return launch_solve_p<1>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
+                                     extra_shift, stream);
+    case 2: return launch_solve_p<2>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
+                                     extra_shift, stream);
+    case 4: return launch_solve_p<4>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
+                                     extra_shift, stream);
+    case 8: return launch_solve_p<8>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
+                                     extra_shift, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_merge(const MergeArgs& a, hipStream_t stream)
+hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
+                        int extra_shift, hipStream_t stream)
 {
-    hipLaunchKernelGGL(merge_kernel, dim3(2 * a.T), dim3(256), 0, stream, a);
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(merge_kernel, dim3(ncols), dim3(256), 0, stream,
+                       const_cast<InstanceDesc*>(inst), cols, extra_shift);
     return hipGetLastError();
 }
 
-hipError_t launch_score(const SolveArgs& a, hipStream_t stream)
+hipError_t launch_merge_plain(int T, int G, double lambda, const double* partial,
+                              const double* v_in, double* v_out, double* stats,
+                              hipStream_t stream)
 {
-    hipLaunchKernelGGL(score_kernel, dim3(blocks_for(a.K, 4)), dim3(256), 0, stream, a.K, a.T,
-                       a.vshift, a.sc, a.mom, a.u, a.v, a.S);
+    hipLaunchKernelGGL(merge_plain_kernel, dim3(2 * T), dim3(256), 0, stream, T, G, lambda,
+                       partial, v_in, v_out, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(int K, int T, const ScoreF64& sc, const double* mom, const float* u,
+                        const double* v, double* S, hipStream_t stream)
+{
+    hipLaunchKernelGGL(score_kernel, dim3(blocks_for(K, 4)), dim3(256), 0, stream, K, T, sc, mom,
+                       u, v, S);
     return hipGetLastError();
 }
 
