@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--ppl", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -194,6 +195,8 @@ def main():
     rs_per_solve = K * M * T
     stream = torch.cuda.current_stream()
     solver = bss.Solver(prob, lanes=args.lanes)
+    if args.ppl:
+        solver.set_shape(lanes=args.lanes, ppl=args.ppl)
     solver.set_outputs(controls=False)   # the solve does not need the copy
     x0_dev = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
 

@@ -54,19 +54,21 @@ __device__ inline void chol6(const double* A, double* L)
     }
 }
 
-// Cross-lane moves inside a row of 16 lanes (DPP): no LDS traffic, one VALU move per dword.
+// Cross-lane moves inside a row of 16 lanes (DPP): no LDS traffic, one VALU move per dword.  Every
+// control used here reads a valid lane of the same row, so no "old" value is needed (bound_ctrl
+// set): the destination register is not initialised first.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
 }
 
 constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
@@ -78,18 +80,54 @@ constexpr int kDppRowBcast8 = 0x158;     // every lane of a row <- lane 8 of the
 constexpr int kDppQuadBcast0 = 0x00;     // quad_perm [0,0,0,0]
 constexpr int kDppQuadBcast0And2 = 0xA0; // quad_perm [0,0,2,2]
 
+// Cross-row exchanges with the gfx950 swap instructions (plain VALU ops, no LDS round trip).
+// With both operands equal to x, v_permlane16_swap leaves in its first result, in every lane of
+// a row pair (0,1) or (2,3), the even row's value of x and in its second result the odd row's;
+// v_permlane32_swap does the same for the lower and upper halves of the wave.
+__device__ __forceinline__ void pair_rows16(float x, float& even, float& odd)
+{
+    const uint32_t u = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    even = __uint_as_float(r[0]);
+    odd = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void pair_halves32(float x, float& lower, float& upper)
+{
+    const uint32_t u = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    lower = __uint_as_float(r[0]);
+    upper = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ double xor16_sum(double x)
+{
+    const uint32_t lo = (uint32_t)__double2loint(x), hi = (uint32_t)__double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+__device__ __forceinline__ double xor32_sum(double x)
+{
+    const uint32_t lo = (uint32_t)__double2loint(x), hi = (uint32_t)__double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
 // Sum over the L lanes of a group (L = 1, 2, 4, ..., 64, groups aligned in the wave, L uniform
 // over the block), result in every lane of the group and bitwise identical across them (each
 // stage adds the same two partial sums in either order).  Within a row of 16 the partners come
-// from DPP; across rows from a shuffle.
+// from DPP; across rows from the swap instructions.
 __device__ __forceinline__ double group_sum(double x, int L)
 {
     if (L > 1) x += dpp_f64<kDppQuadSwap1>(x);
     if (L > 2) x += dpp_f64<kDppQuadSwap2>(x);
     if (L > 4) x += dpp_f64<kDppHalfRowMirror>(x);
     if (L > 8) x += dpp_f64<kDppRowMirror>(x);
-    if (L > 16) x += __shfl_xor(x, 16, 64);
-    if (L > 32) x += __shfl_xor(x, 32, 64);
+    if (L > 16) x = xor16_sum(x);
+    if (L > 32) x = xor32_sum(x);
     return x;
 }
 
@@ -103,8 +141,14 @@ __device__ __forceinline__ float group_first(float x, int L)
         const float a = dpp_f32<kDppRowBcast0>(x), b = dpp_f32<kDppRowBcast8>(x);
         return (threadIdx.x & 8) ? b : a;
     }
-    if (L == 16) return dpp_f32<kDppRowBcast0>(x);
-    return __shfl(x, 0, L);
+    float y = dpp_f32<kDppRowBcast0>(x);
+    if (L == 16) return y;
+    float even, odd;
+    pair_rows16(y, even, odd);
+    if (L == 32) return even;
+    float lower, upper;
+    pair_halves32(even, lower, upper);
+    return lower;
 }
 
 __device__ __forceinline__ int vrow(int t, int vshift, int T)
