@@ -68,6 +68,10 @@ def measured_traffic(lanes):
     return MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +81,10 @@ def parse():
     ap.add_argument("--ppl", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the serving trace replayed with batching (0 skips serving)")
+    ap.add_argument("--plain-seconds", type=float, default=15.0,
+                    help="length of the trace prefix replayed with plain per-request launches")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--latency-solves", type=int, default=50)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -169,6 +177,46 @@ def bench_batched(bss, W, torch, rounds=20, warmup=3):
             "speedup": wall_p / wall_b}
 
 
+def bench_serving(bss, W, seconds, plain_seconds, skip=5.0):
+    """256 vehicles issuing solves as Poisson processes at 20 Hz each (K U[1024, 8192], M U[32,
+    128], delta U[0.01, 0.1], T = 50), replayed in real time: continuous batching over two
+    streams with a 32 GiB scratch budget, against plain per-request launches (one request per
+    launch, FIFO, one stream) on the first plain_seconds of the same trace.  Latency = completion
+    - arrival, percentiles over requests arriving after `skip` seconds."""
+    fleet = W.serving_fleet()
+    tr = W.serving_trace(fleet, duration_s=seconds)
+
+    def run(n_streams, max_batch, horizon):
+        sel = tr["t"] < horizon
+        args = [tr[k][sel] for k in ("t", "vehicle", "K", "M", "delta", "x0")]
+        srv = bss.Server(fleet[0], T=50, K_max=8192, M_max=128, ppl=4, n_streams=n_streams,
+                         max_batch=max_batch, hbm_budget=32 << 30)
+        t0 = time.perf_counter()
+        lat, u0, st = srv.replay(*args)
+        wall = time.perf_counter() - t0
+        srv.close()
+        rs = float(np.sum(args[2].astype(np.float64) * args[3] * 50))
+        keep = args[0] >= min(skip, horizon / 3)
+        return {"requests": int(sel.sum()), "trace_s": horizon, "wall_s": wall,
+                "rollout_steps_per_s": rs / wall,
+                "offered_rollout_steps_per_s": rs / horizon,
+                "p50_ms": float(np.percentile(lat[keep], 50) * 1e3),
+                "p99_ms": float(np.percentile(lat[keep], 99) * 1e3),
+                "max_ms": float(np.max(lat[keep]) * 1e3),
+                "failed": int(np.sum(st != 0)),
+                "launch": (f"continuous batching, {n_streams} streams, up to {max_batch} "
+                           "requests per launch" if max_batch > 1 else
+                           "one request per launch, FIFO, one stream")}
+
+    batched = run(2, 256, seconds)
+    progress(f"serving, batched: {batched['requests']} requests, p99 {batched['p99_ms']:.2f} ms")
+    plain = run(1, 1, min(plain_seconds, seconds))
+    progress(f"serving, plain: {plain['requests']} requests, p99 {plain['p99_ms']:.2f} ms")
+    return {"workload": "256 vehicles, Poisson 20 Hz each, K U[1024,8192], M U[32,128], "
+                        "delta U[0.01,0.1], T=50, 32 GiB scratch budget (seed 5)",
+            "batched": batched, "plain": plain}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,8 +306,12 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mode": "plain synchronous solve from host inputs"},
     }
+    progress(f"single solve: {value:.3e} rollout-steps/s, kernel {kernel_ms:.4f} ms")
     if not args.no_batched:
         out["batched"] = bench_batched(bss, W, torch)
+        progress(f"mixed batch: {out['batched']['batched']['value']:.3e} rollout-steps/s")
+    if args.serve_seconds > 0:
+        out["serving"] = bench_serving(bss, W, args.serve_seconds, args.plain_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, x0, v, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -256,6 +256,90 @@ bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl);
  * accepted). */
 void bss_batch_destroy(bss_batch* b);
 
+/* ---- serving: many vehicles, solves batched as their requests arrive ------------------------
+ *
+ * Each vehicle runs the receding-horizon loop of Alg. 1 on its own problem (track, car, noise,
+ * seed: a bss_params); every request asks for one solve of that vehicle from a state estimate, with
+ * its own sample count K, particle count M and risk level delta.  The vehicle's mean control
+ * sequence stays in device memory between requests and is warm-started (shifted by one step)
+ * after every solve; its solve index advances by one per solve, so a vehicle's results depend only
+ * on its own request sequence, never on which other requests shared a launch.
+ *
+ * Device memory: the resident mean sequences (2 x T x 2 doubles per vehicle) plus hbm_budget bytes
+ * of scratch split evenly over n_streams slots.  A request is admitted into a batch while its
+ * scratch (belief records, costs and block partials: about 3.7 KB x K at T = 50) fits in the slot.
+ * Whenever a slot is free, bss_server_pump launches every admissible pending request (oldest first,
+ * at most one per vehicle, at most max_batch) as one solve launch and one merge launch on the slot's
+ * stream; slots run concurrently.  Not thread-safe: one thread drives a server. */
+typedef struct bss_server bss_server;
+
+typedef struct bss_server_config {
+    int32_t n_vehicles;
+    int32_t T;            /* horizon shared by every vehicle */
+    int32_t K_max, M_max; /* per-request limits */
+    int32_t ppl;          /* particles per lane of the batched launches (0 = 4) */
+    int32_t n_streams;    /* batches in flight at once, 1..16 */
+    int32_t max_batch;    /* requests per launch, 1..4096 */
+    uint64_t hbm_budget;  /* bytes of device scratch for in-flight solves */
+} bss_server_config;
+
+/* A finished request: its command v+_0, BSS_OK or BSS_E_NUMERIC (no finite cost; the warm start
+ * was kept), and the host steady-clock time (seconds) at which the server saw it complete. */
+typedef struct bss_completion {
+    int64_t req;
+    int32_t vehicle;
+    int32_t status;
+    double u0[2];
+    double t_done;
+} bss_completion;
+
+/* 256 vehicles, T = 50, K <= 8192, M <= 128, 4 particles per lane, 2 streams, batches of up to
+ * 256, 32 GiB of scratch. */
+void bss_server_config_default(bss_server_config* c);
+
+/* Create a server on the current device.  vehicles[n_vehicles] are copied; their K, M and T fields
+ * are ignored (validated as K_max, M_max, T), delta is replaced per request.  Mean sequences start
+ * at zero, solve indices at 0.  Errors: BSS_E_INVAL (a budget below one K_max request per stream,
+ * M_max above 64 x ppl, invalid vehicle parameters), BSS_E_NOMEM, BSS_E_DEVICE. */
+bss_status bss_server_create(const bss_server_config* cfg, const bss_params* vehicles,
+                             bss_server** out);
+
+/* Queue one solve of `vehicle` from the state estimate x0[6] (copied).  *req_id (may be NULL)
+ * receives the request's id (consecutive from 0).  Nothing is launched until bss_server_pump. */
+bss_status bss_server_submit(bss_server* s, int32_t vehicle, int32_t K, int32_t M, double delta,
+                             const double x0[6], int64_t* req_id);
+
+/* Retire completed batches (their requests become pollable) and launch new batches on free slots.
+ * Never blocks.  *n_launched (may be NULL) receives the number of requests launched. */
+bss_status bss_server_pump(bss_server* s, int32_t* n_launched);
+
+/* Move up to max completions into out[]; returns how many. */
+int32_t bss_server_poll(bss_server* s, bss_completion* out, int32_t max);
+
+/* Pump until nothing is pending or in flight (completions stay pollable). */
+bss_status bss_server_drain(bss_server* s);
+
+/* Mean control sequence [T][2] of an idle vehicle (no request pending or in flight; BSS_E_STATE
+ * otherwise), with its pending warm-start shift applied; and setting it (clears the shift). */
+bss_status bss_server_get_controls(bss_server* s, int32_t vehicle, double* v_host);
+bss_status bss_server_set_controls(bss_server* s, int32_t vehicle, const double* v_host);
+
+/* Solve index of the vehicle's next solve and its number of unfinished requests. */
+bss_status bss_server_vehicle_state(const bss_server* s, int32_t vehicle, uint32_t* solve_index,
+                                    int64_t* pending);
+
+/* Replay a request trace in real time: request i is submitted once t_arrival[i] seconds have
+ * passed since the call started (non-decreasing times), the server is pumped continuously, and
+ * latency_s[i] = completion time - scheduled arrival.  x0 is [n][6]; u0_out [n][2] and status_out
+ * [n] may be NULL.  Drains the server first; returns when every request has completed. */
+bss_status bss_server_replay(bss_server* s, int64_t n, const double* t_arrival,
+                             const int32_t* vehicle, const int32_t* K, const int32_t* M,
+                             const double* delta, const double* x0, double* latency_s,
+                             double* u0_out, int32_t* status_out);
+
+/* Wait for the work in flight and free the server (NULL is accepted). */
+void bss_server_destroy(bss_server* s);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* bss_last_error(void);
 

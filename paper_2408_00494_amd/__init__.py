@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import BssError, check, params_from_problem
 
-__all__ = ["Solver", "Batch", "BssError", "backoff", "validate", "dev_philox", "dev_normals",
+__all__ = ["Solver", "Batch", "Server", "BssError", "backoff", "validate", "dev_philox", "dev_normals",
            "dev_model_step", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
 
 
@@ -230,6 +230,92 @@ class Batch:
         if getattr(self, "_b", None) is not None and self._b.value:
             _lib.lib().bss_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving runtime: vehicles with device-resident warm starts whose solve requests (own K, M
+    and delta each) are batched as they arrive over ``n_streams`` concurrent slots, admitted by an
+    HBM scratch budget.  ``vehicles`` is a list of problem dicts (their K, M are ignored)."""
+
+    def __init__(self, vehicles, T, K_max, M_max, ppl=4, n_streams=2, max_batch=256,
+                 hbm_budget=32 << 30):
+        self.n = len(vehicles)
+        self.T = int(T)
+        cfg = _lib.BssServerConfig(self.n, self.T, int(K_max), int(M_max), int(ppl),
+                                   int(n_streams), int(max_batch), int(hbm_budget))
+        arr = (_lib.BssParams * self.n)(*[params_from_problem(dict(p, K=K_max, M=M_max, T=T))
+                                          for p in vehicles])
+        srv = C.c_void_p()
+        check(_lib.lib().bss_server_create(C.byref(cfg), arr, C.byref(srv)))
+        self._s = srv
+
+    def submit(self, vehicle, K, M, delta, x0):
+        x = np.ascontiguousarray(x0, dtype=np.float64)
+        rid = C.c_int64()
+        check(_lib.lib().bss_server_submit(self._s, int(vehicle), int(K), int(M), float(delta),
+                                           x.ctypes.data_as(C.c_void_p), C.byref(rid)))
+        return rid.value
+
+    def pump(self):
+        n = C.c_int32()
+        check(_lib.lib().bss_server_pump(self._s, C.byref(n)))
+        return n.value
+
+    def poll(self, max_n=1024):
+        buf = (_lib.BssCompletion * max_n)()
+        got = _lib.lib().bss_server_poll(self._s, buf, max_n)
+        return [{"req": c.req, "vehicle": c.vehicle, "status": c.status,
+                 "u0": np.array(c.u0[:]), "t_done": c.t_done} for c in buf[:got]]
+
+    def drain(self):
+        check(_lib.lib().bss_server_drain(self._s))
+
+    def get_controls(self, vehicle):
+        v = np.zeros((self.T, 2))
+        check(_lib.lib().bss_server_get_controls(self._s, int(vehicle),
+                                                 v.ctypes.data_as(C.c_void_p)))
+        return v
+
+    def set_controls(self, vehicle, v):
+        vv = np.ascontiguousarray(v, dtype=np.float64).reshape(self.T, 2)
+        check(_lib.lib().bss_server_set_controls(self._s, int(vehicle),
+                                                 vv.ctypes.data_as(C.c_void_p)))
+
+    def vehicle_state(self, vehicle):
+        si, pend = C.c_uint32(), C.c_int64()
+        check(_lib.lib().bss_server_vehicle_state(self._s, int(vehicle), C.byref(si),
+                                                  C.byref(pend)))
+        return si.value, pend.value
+
+    def replay(self, t_arrival, vehicle, K, M, delta, x0):
+        """Real-time replay of a request trace; returns (latency_s, u0 [n,2], status)."""
+        t = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        n = t.shape[0]
+        veh = np.ascontiguousarray(vehicle, dtype=np.int32)
+        KK = np.ascontiguousarray(K, dtype=np.int32)
+        MM = np.ascontiguousarray(M, dtype=np.int32)
+        dd = np.ascontiguousarray(delta, dtype=np.float64)
+        xx = np.ascontiguousarray(x0, dtype=np.float64).reshape(n, 6)
+        lat = np.zeros(n)
+        u0 = np.zeros((n, 2))
+        st = np.zeros(n, dtype=np.int32)
+        vp = C.c_void_p
+        check(_lib.lib().bss_server_replay(
+            self._s, n, t.ctypes.data_as(vp), veh.ctypes.data_as(vp), KK.ctypes.data_as(vp),
+            MM.ctypes.data_as(vp), dd.ctypes.data_as(vp), xx.ctypes.data_as(vp),
+            lat.ctypes.data_as(vp), u0.ctypes.data_as(vp), st.ctypes.data_as(vp)))
+        return lat, u0, st
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            _lib.lib().bss_server_destroy(self._s)
+            self._s = None
 
     def __del__(self):
         try:

@@ -72,7 +72,23 @@ EXPORTS = [
     "bss_dev_update_workspace", "bss_dev_update", "bss_dev_repair", "bss_set_shape",
     "bss_batch_create", "bss_batch_states", "bss_batch_set_states", "bss_batch_copy_states", "bss_batch_solve",
     "bss_batch_capture", "bss_batch_tune", "bss_batch_info", "bss_batch_destroy",
+    "bss_server_config_default", "bss_server_create", "bss_server_submit", "bss_server_pump",
+    "bss_server_poll", "bss_server_drain", "bss_server_get_controls", "bss_server_set_controls",
+    "bss_server_vehicle_state", "bss_server_replay", "bss_server_destroy",
 ]
+
+
+class BssServerConfig(C.Structure):
+    """Mirror of ``bss_server_config``."""
+    _fields_ = [("n_vehicles", C.c_int32), ("T", C.c_int32), ("K_max", C.c_int32),
+                ("M_max", C.c_int32), ("ppl", C.c_int32), ("n_streams", C.c_int32),
+                ("max_batch", C.c_int32), ("hbm_budget", C.c_uint64)]
+
+
+class BssCompletion(C.Structure):
+    """Mirror of ``bss_completion``."""
+    _fields_ = [("req", C.c_int64), ("vehicle", C.c_int32), ("status", C.c_int32),
+                ("u0", C.c_double * 2), ("t_done", C.c_double)]
 
 
 def _declare(lib):
@@ -119,6 +135,17 @@ def _declare(lib):
         "bss_batch_tune": (i32, [vp, C.POINTER(i32)]),
         "bss_batch_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "bss_batch_destroy": (None, [vp]),
+        "bss_server_config_default": (None, [C.POINTER(BssServerConfig)]),
+        "bss_server_create": (i32, [C.POINTER(BssServerConfig), P, C.POINTER(vp)]),
+        "bss_server_submit": (i32, [vp, i32, i32, i32, d, vp, C.POINTER(i64)]),
+        "bss_server_pump": (i32, [vp, C.POINTER(i32)]),
+        "bss_server_poll": (i32, [vp, C.POINTER(BssCompletion), i32]),
+        "bss_server_drain": (i32, [vp]),
+        "bss_server_get_controls": (i32, [vp, i32, vp]),
+        "bss_server_set_controls": (i32, [vp, i32, vp]),
+        "bss_server_vehicle_state": (i32, [vp, i32, C.POINTER(u32), C.POINTER(i64)]),
+        "bss_server_replay": (i32, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "bss_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbssmppi.so")
-SOURCES = [os.path.join(HERE, "csrc", "bss_kernels.hip"), os.path.join(HERE, "csrc", "bss_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f)
+           for f in ("bss_kernels.hip", "bss_api.cpp", "bss_server.cpp")]
 
 # gfx950 only; packed-FP32 instructions are disabled (the compiler must not form v_pk_* FP32
 # ops); no fast-math: the kernels rely on IEEE single/double semantics.

@@ -12,13 +12,18 @@
 #include <vector>
 
 #include "../../include/bssmppi.h"
+#include "bss_host.h"
 #include "bss_internal.h"
 
 using namespace bss;
 
-namespace {
+namespace bss {
 
+namespace {
 thread_local std::string g_err;
+}  // namespace
+
+const char* last_error_message() { return g_err.c_str(); }
 
 bss_status fail(bss_status st, const char* fmt, ...)
 {
@@ -124,7 +129,33 @@ CarF32 make_car(const bss_params& p)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-}  // namespace
+InstanceDesc make_desc(const bss_params& p)
+{
+    InstanceDesc d{};
+    d.K = p.K;
+    d.M = p.M;
+    d.T = p.T;
+    d.key0 = (uint32_t)p.seed;
+    d.key1 = (uint32_t)(p.seed >> 32);
+    d.steer_max = (float)p.steer_max;
+    d.accel_max = (float)p.accel_max;
+    d.sig_eps0 = (float)p.sigma_eps[0];
+    d.sig_eps1 = (float)p.sigma_eps[1];
+    d.sig_w0 = (float)p.sigma_w[0];
+    d.sig_w1 = (float)p.sigma_w[1];
+    d.sig_w2 = (float)p.sigma_w[2];
+    d.car = make_car(p);
+    d.sc = make_score(p);
+    return d;
+}
+
+void append_blocks(std::vector<BlockDesc>& out, int inst, int K, int lanes)
+{
+    const int groups = 256 / lanes;
+    for (int k0 = 0; k0 < K; k0 += groups) out.push_back(BlockDesc{inst, k0});
+}
+
+}  // namespace bss
 
 struct bss_ctx {
     bss_params p;
@@ -176,41 +207,18 @@ constexpr size_t kStateBytes = offsetof(InstanceDesc, shift_after) - offsetof(In
 
 size_t max_blocks(int K) { return (size_t)solve_blocks(K, 64); }
 
-// sizes, params and buffer pointers of a context's descriptor (state fields zero)
+// sizes, params and launch shape of a context's descriptor (state fields zero, buffers unset)
 void fill_desc(bss_ctx* c)
 {
-    const bss_params& p = c->p;
-    InstanceDesc& d = c->desc;
-    d.K = p.K;
-    d.M = p.M;
-    d.T = p.T;
-    d.lanes = c->shape.lanes;
-    d.nblocks = solve_blocks(p.K, c->shape.lanes);
-    d.x0_index = 0;
-    d.cur = 0;
-    d.vshift = 0;
-    d.solve_index = 0;
-    d.done = 0;
-    d.shift_after = 0;
-    d.status = 0;
-    d.key0 = (uint32_t)p.seed;
-    d.key1 = (uint32_t)(p.seed >> 32);
-    d.steer_max = (float)p.steer_max;
-    d.accel_max = (float)p.accel_max;
-    d.sig_eps0 = (float)p.sigma_eps[0];
-    d.sig_eps1 = (float)p.sigma_eps[1];
-    d.sig_w0 = (float)p.sigma_w[0];
-    d.sig_w1 = (float)p.sigma_w[1];
-    d.sig_w2 = (float)p.sigma_w[2];
-    d.car = make_car(p);
-    d.sc = make_score(p);
+    c->desc = make_desc(c->p);
+    c->desc.lanes = c->shape.lanes;
+    c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
 }
 
 std::vector<BlockDesc> block_table(int inst, int K, int lanes)
 {
-    const int groups = 256 / lanes;
     std::vector<BlockDesc> out;
-    for (int k0 = 0; k0 < K; k0 += groups) out.push_back(BlockDesc{inst, k0});
+    append_blocks(out, inst, K, lanes);
     return out;
 }
 
@@ -1082,7 +1090,7 @@ void bss_batch_destroy(bss_batch* b)
     batch_free(b);
 }
 
-const char* bss_last_error(void) { return g_err.c_str(); }
+const char* bss_last_error(void) { return last_error_message(); }
 
 // ---- stand-alone kernels -----------------------------------------------------------------------
 bss_status bss_dev_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,

@@ -130,20 +130,55 @@ def config_batch(n: int = 64, seed: int = 4):
     return out
 
 
-def serving_requests(n_vehicles: int = 256, duration_s: float = 60.0, rate_hz: float = 20.0,
-                     seed: int = 5):
-    """Poisson request trace: per vehicle exponential inter-arrival times with mean 1/rate_hz.
-    Each request draws K ~ U[1024, 8192], M ~ U[32, 128], delta ~ U[0.01, 0.1]; T = 50.
-    Returns a list of (arrival_s, vehicle, K, M, delta) sorted by arrival time."""
+def serving_fleet(n_vehicles: int = 256, seed: int = 5):
+    """Vehicles of the serving workload, each with its own problem: ellipse track with semi-axes
+    a ~ U[25, 35] m, b ~ U[18, 22] m and half-width 2 m (the small problem's track type), its own
+    seed, and a start arc length uniform along its track.  Returns (problems, start arc lengths);
+    K, M and delta of a problem are replaced per request."""
     rng = np.random.default_rng(seed)
-    reqs = []
+    probs, s0 = [], []
     for veh in range(n_vehicles):
+        a = float(rng.uniform(25.0, 35.0))
+        b = float(rng.uniform(18.0, 22.0))
+        probs.append(default_problem(T=50, seed=seed * 100000 + veh, ell_a=a, ell_b=b,
+                                     half_width=2.0))
+        _, cum = _arclength_table(a, b)
+        s0.append(float(rng.uniform(0.0, cum[-1])))
+    return probs, np.array(s0)
+
+
+def serving_trace(fleet, duration_s: float = 60.0, rate_hz: float = 20.0, seed: int = 5,
+                  K_range=(1024, 8192), M_range=(32, 128), delta_range=(0.01, 0.1),
+                  speed: float = 5.0):
+    """Poisson request trace of a fleet: per vehicle exponential inter-arrival times with mean
+    1 / rate_hz over duration_s.  Each request draws K ~ U{K_range}, M ~ U{M_range} (inclusive
+    integers) and delta ~ U(delta_range); its state estimate is the vehicle's pose on its
+    centerline after driving `speed` m/s since t = 0.  Returns a dict of arrays sorted by arrival:
+    t, vehicle, K, M, delta, x0 [n, 6]."""
+    probs, s0 = fleet
+    rng = np.random.default_rng(seed + 1)
+    ts, vs = [], []
+    for veh in range(len(probs)):
         t = rng.exponential(1.0 / rate_hz)
         while t < duration_s:
-            K = int(rng.integers(1024, 8193))
-            M = int(rng.integers(32, 129))
-            delta = float(rng.uniform(0.01, 0.1))
-            reqs.append((t, veh, K, M, delta))
+            ts.append(t)
+            vs.append(veh)
             t += rng.exponential(1.0 / rate_hz)
-    reqs.sort(key=lambda r: r[0])
-    return reqs
+    order = np.argsort(np.array(ts), kind="stable")
+    t = np.array(ts)[order]
+    veh = np.array(vs, dtype=np.int32)[order]
+    n = t.shape[0]
+    K = rng.integers(K_range[0], K_range[1] + 1, n).astype(np.int32)
+    M = rng.integers(M_range[0], M_range[1] + 1, n).astype(np.int32)
+    delta = rng.uniform(delta_range[0], delta_range[1], n)
+    x0 = np.zeros((n, 6))
+    tables = {}
+    for i in range(n):
+        p = probs[veh[i]]
+        key = (p["ell_a"], p["ell_b"])
+        if key not in tables:
+            tables[key] = _arclength_table(*key)
+        th, cum = tables[key]
+        sarc = (s0[veh[i]] + speed * t[i]) % cum[-1]
+        x0[i] = pose_on_centerline(p["ell_a"], p["ell_b"], float(np.interp(sarc, cum, th)), speed)
+    return {"t": t, "vehicle": veh, "K": K, "M": M, "delta": delta, "x0": x0}

@@ -41,8 +41,13 @@ def test_struct_layout_matches_header():
         cf = "lambda" if f == "lambda_" else f
         prog.append(f'printf("%zu\\n", offsetof(bss_params, {cf}));')
     for s, fl in (("bss_buffers", _lib.BssBuffers), ("bss_info", _lib.BssInfo),
-                  ("bss_allocator", _lib.BssAllocator)):
+                  ("bss_allocator", _lib.BssAllocator), ("bss_server_config", _lib.BssServerConfig),
+                  ("bss_completion", _lib.BssCompletion)):
         prog.append(f'printf("%zu\\n", sizeof({s}));')
+    for s, fl in (("bss_server_config", _lib.BssServerConfig),
+                  ("bss_completion", _lib.BssCompletion)):
+        for f, _ in fl._fields_:
+            prog.append(f'printf("%zu\\n", offsetof({s}, {f}));')
     prog.append("return 0;}")
     with tempfile.TemporaryDirectory() as tmp:
         c_file = os.path.join(tmp, "layout.c")
@@ -54,8 +59,14 @@ def test_struct_layout_matches_header():
     assert out[0] == C.sizeof(_lib.BssParams)
     for f, off in zip(fields, out[1:1 + len(fields)]):
         assert getattr(_lib.BssParams, f).offset == off, f
-    assert out[1 + len(fields):] == [C.sizeof(_lib.BssBuffers), C.sizeof(_lib.BssInfo),
-                                     C.sizeof(_lib.BssAllocator)]
+    rest = out[1 + len(fields):]
+    sizes = [C.sizeof(_lib.BssBuffers), C.sizeof(_lib.BssInfo), C.sizeof(_lib.BssAllocator),
+             C.sizeof(_lib.BssServerConfig), C.sizeof(_lib.BssCompletion)]
+    assert rest[:len(sizes)] == sizes
+    offs = rest[len(sizes):]
+    want = [getattr(fl, f).offset for fl in (_lib.BssServerConfig, _lib.BssCompletion)
+            for f, _ in fl._fields_]
+    assert offs == want
 
 
 def test_defaults_match_reference_problem():
@@ -129,3 +140,41 @@ def test_null_and_invalid_handles():
     assert lib.bss_dev_update_workspace(0, 5) == 0
     assert lib.bss_dev_update_workspace(300, 5) >= 256 + 2 * (2 * 5 + 4) * 8
     assert "NULL" in lib.bss_last_error().decode() or lib.bss_last_error() is not None
+
+
+def test_server_and_batch_argument_checks():
+    """Argument and configuration errors are reported before any device work."""
+    lib = _lib.lib()
+    lib.bss_server_destroy(None)
+    lib.bss_batch_destroy(None)
+    out = C.c_void_p()
+    assert lib.bss_server_create(None, None, C.byref(out)) == _lib.BSS_E_INVAL
+    cfg = _lib.BssServerConfig()
+    lib.bss_server_config_default(C.byref(cfg))
+    assert (cfg.n_vehicles, cfg.T, cfg.K_max, cfg.M_max) == (256, 50, 8192, 128)
+    assert cfg.hbm_budget == 32 << 30
+    veh = (_lib.BssParams * 1)(_lib.params_from_problem(W.default_problem()))
+    for field, value in (("n_vehicles", 0), ("T", 0), ("T", 257), ("K_max", 0), ("M_max", 513),
+                         ("ppl", 3), ("n_streams", 0), ("n_streams", 17), ("max_batch", 0),
+                         ("hbm_budget", 1 << 20)):
+        bad = _lib.BssServerConfig.from_buffer_copy(cfg)
+        bad.n_vehicles = 1
+        setattr(bad, field, value)
+        assert lib.bss_server_create(C.byref(bad), veh, C.byref(out)) == _lib.BSS_E_INVAL, field
+        assert out.value is None
+    bad = _lib.BssServerConfig.from_buffer_copy(cfg)
+    bad.n_vehicles, bad.M_max, bad.ppl = 1, 512, 4          # 128 lanes per sample
+    assert lib.bss_server_create(C.byref(bad), veh, C.byref(out)) == _lib.BSS_E_INVAL
+    assert "64" in lib.bss_last_error().decode()
+    bad_veh = (_lib.BssParams * 1)(_lib.params_from_problem(W.default_problem(delta=0.7)))
+    one = _lib.BssServerConfig.from_buffer_copy(cfg)
+    one.n_vehicles = 1
+    assert lib.bss_server_create(C.byref(one), bad_veh, C.byref(out)) == _lib.BSS_E_INVAL
+    x0 = (C.c_double * 6)()
+    assert lib.bss_server_submit(None, 0, 1, 1, 0.05, x0, None) == _lib.BSS_E_INVAL
+    assert lib.bss_server_pump(None, None) == _lib.BSS_E_INVAL
+    assert lib.bss_server_poll(None, None, 4) == 0
+    assert lib.bss_server_drain(None) == _lib.BSS_E_INVAL
+    assert lib.bss_batch_create(None, 0, 0, 0, C.byref(out)) == _lib.BSS_E_INVAL
+    assert lib.bss_batch_solve(None) == _lib.BSS_E_INVAL
+    assert lib.bss_set_shape(None, 16, 4) == _lib.BSS_E_INVAL

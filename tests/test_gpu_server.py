@@ -1,0 +1,176 @@
+"""Serving runtime: requests of many vehicles batched as they arrive.
+
+* Every result is the same alone and in the mix: each request's command and each vehicle's final
+  warm start equal, bit for bit, a chain of single solves of that vehicle alone (same launch
+  shape, same warm start, same solve index), whatever the batch composition, slot count or
+  memory budget.
+* Requests meet the oracle bar (controls max |dv| / u_max <= 1e-4).
+* A real-time replay completes every request with sane latencies.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_00494_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_2408_00494_amd as bss  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+T = 20
+K_MAX, M_MAX = 600, 48
+
+
+def _fleet(n, seed=21):
+    probs, s0 = W.serving_fleet(n, seed=seed)
+    return [dict(p, T=T) for p in probs], s0
+
+
+def _requests(fleet, per_vehicle, seed=3):
+    probs, s0 = fleet
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(per_vehicle):
+        for veh in range(len(probs)):
+            p = probs[veh]
+            theta = float(s0[veh] / 30.0 + 0.05 * r)
+            reqs.append(dict(vehicle=veh, K=int(rng.integers(40, K_MAX + 1)),
+                             M=int(rng.integers(5, M_MAX + 1)),
+                             delta=float(rng.uniform(0.01, 0.1)),
+                             x0=W.pose_on_centerline(p["ell_a"], p["ell_b"], theta, 5.0)))
+    return reqs
+
+
+def _serve(fleet, reqs, **cfg):
+    probs, _ = fleet
+    srv = bss.Server(probs, T=T, K_max=K_MAX, M_max=M_MAX, **cfg)
+    ids = [srv.submit(r["vehicle"], r["K"], r["M"], r["delta"], r["x0"]) for r in reqs]
+    srv.drain()
+    done = {c["req"]: c for c in srv.poll(len(reqs) + 8)}
+    assert sorted(done) == ids
+    u0 = np.array([done[i]["u0"] for i in ids])
+    st = np.array([done[i]["status"] for i in ids])
+    final = [srv.get_controls(v) for v in range(len(probs))]
+    states = [srv.vehicle_state(v) for v in range(len(probs))]
+    srv.close()
+    return u0, st, final, states
+
+
+def _alone(fleet, reqs, ppl=4):
+    """Each vehicle's requests as a chain of single solves with the server's launch shape."""
+    probs, _ = fleet
+    u0 = np.zeros((len(reqs), 2))
+    v_prev = {v: np.zeros((T, 2)) for v in range(len(probs))}
+    count = {v: 0 for v in range(len(probs))}
+    for i, r in enumerate(reqs):
+        veh = r["vehicle"]
+        p = dict(probs[veh], K=r["K"], M=r["M"], delta=r["delta"])
+        s = bss.Solver(p)
+        s.set_shape(ppl=ppl)
+        s.set_controls(v_prev[veh])
+        s.solve_index = count[veh]
+        u0[i], _ = s.solve(r["x0"])
+        s.step_shift()
+        v_prev[veh] = s.get_controls()
+        count[veh] += 1
+        s.close()
+    return u0, v_prev, count
+
+
+def test_same_alone_and_in_the_mix():
+    fleet = _fleet(10)
+    reqs = _requests(fleet, per_vehicle=3)
+    u0_ref, v_ref, count = _alone(fleet, reqs)
+    for cfg in (dict(n_streams=2, max_batch=4), dict(n_streams=3, max_batch=64),
+                dict(n_streams=1, max_batch=1)):
+        u0, st, final, states = _serve(fleet, reqs, hbm_budget=256 << 20, **cfg)
+        assert np.all(st == 0)
+        assert np.array_equal(u0, u0_ref), cfg
+        for v in range(len(fleet[0])):
+            assert np.array_equal(final[v], v_ref[v]), (cfg, v)
+            assert states[v] == (count[v], 0)
+
+
+def test_budget_admission_keeps_results():
+    """A budget of one largest request per slot forces one request per launch at most."""
+    fleet = _fleet(6, seed=8)
+    reqs = _requests(fleet, per_vehicle=2, seed=9)
+    u0_ref, _, _ = _alone(fleet, reqs)
+    per_req = (K_MAX * (T + 1) * 9 * 8 + 255) // 256 * 256 + 8 * K_MAX + 64 * 1024
+    u0, st, _, _ = _serve(fleet, reqs, n_streams=2, max_batch=64, hbm_budget=2 * per_req)
+    assert np.all(st == 0)
+    assert np.array_equal(u0, u0_ref)
+    with pytest.raises(bss.BssError):
+        bss.Server(fleet[0], T=T, K_max=K_MAX, M_max=M_MAX, n_streams=2, hbm_budget=per_req)
+
+
+def test_served_requests_match_oracle():
+    fleet = _fleet(4, seed=30)
+    probs, _ = fleet
+    reqs = _requests(fleet, per_vehicle=1, seed=31)
+    srv = bss.Server(probs, T=T, K_max=K_MAX, M_max=M_MAX, hbm_budget=256 << 20)
+    for r in reqs:
+        srv.submit(r["vehicle"], r["K"], r["M"], r["delta"], r["x0"])
+    srv.drain()
+    srv.poll()
+    for r in reqs:
+        veh = r["vehicle"]
+        p = dict(probs[veh], K=r["K"], M=r["M"], delta=r["delta"])
+        ref = oracle.solve(p, 0, r["x0"], np.zeros((T, 2)), nthreads=NTHREADS)
+        got = srv.get_controls(veh)      # v+ shifted by one step
+        want = oracle.step_shift(ref["v"])
+        scale = np.array([p["steer_max"], p["accel_max"]])
+        assert np.max(np.abs(got - want) / scale) <= 1e-4, veh
+    srv.close()
+
+
+def test_state_rules_and_set_controls():
+    fleet = _fleet(2, seed=40)
+    probs, _ = fleet
+    srv = bss.Server(probs, T=T, K_max=K_MAX, M_max=M_MAX, hbm_budget=256 << 20)
+    x0 = W.pose_on_centerline(probs[0]["ell_a"], probs[0]["ell_b"], 0.3, 5.0)
+    srv.submit(0, 100, 16, 0.05, x0)
+    with pytest.raises(bss.BssError) as ei:
+        srv.get_controls(0)
+    assert ei.value.status == 4
+    with pytest.raises(bss.BssError):
+        srv.submit(0, K_MAX + 1, 16, 0.05, x0)
+    with pytest.raises(bss.BssError):
+        srv.submit(5, 100, 16, 0.05, x0)
+    with pytest.raises(bss.BssError):
+        srv.submit(0, 100, 16, 0.5, x0)
+    srv.drain()
+    srv.poll()
+    v = np.column_stack([0.05 * np.ones(T), 0.5 * np.ones(T)])
+    srv.set_controls(1, v)
+    assert np.array_equal(srv.get_controls(1), v)
+    srv.submit(1, 200, 20, 0.02, x0)
+    srv.drain()
+    u0 = srv.poll()[0]["u0"]
+    s = bss.Solver(dict(probs[1], K=200, M=20, delta=0.02))
+    s.set_shape(ppl=4)
+    s.set_controls(v)
+    want, _ = s.solve(x0)
+    s.close()
+    assert np.array_equal(u0, want)
+    srv.close()
+
+
+def test_realtime_replay_completes():
+    fleet = W.serving_fleet(32, seed=50)
+    tr = W.serving_trace(fleet, duration_s=1.5, rate_hz=20.0, seed=50, K_range=(256, 2048),
+                         M_range=(16, 64))
+    srv = bss.Server(fleet[0], T=50, K_max=2048, M_max=64, hbm_budget=2 << 30)
+    lat, u0, st = srv.replay(tr["t"], tr["vehicle"], tr["K"], tr["M"], tr["delta"], tr["x0"])
+    srv.close()
+    n = len(tr["t"])
+    print(f"replay: {n} requests, p50 {np.percentile(lat, 50) * 1e3:.2f} ms, "
+          f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms", flush=True)
+    assert np.all(st == 0)
+    assert np.all(lat > 0) and np.all(lat < 1.0)
+    assert np.all(np.isfinite(u0))
