@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--ppl", type=int, default=0)
+    ap.add_argument("--split", type=int, default=-1,
+                    help="noise-producing waves: -1 automatic, 0 off, 1 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -243,8 +245,8 @@ def main():
     rs_per_solve = K * M * T
     stream = torch.cuda.current_stream()
     solver = bss.Solver(prob, lanes=args.lanes)
-    if args.ppl:
-        solver.set_shape(lanes=args.lanes, ppl=args.ppl)
+    if args.ppl or args.split != -1:
+        solver.set_shape(lanes=args.lanes, ppl=args.ppl, split=args.split)
     solver.set_outputs(controls=False)   # the solve does not need the copy
     x0_dev = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
 
@@ -296,7 +298,8 @@ def main():
         "config": {"workload": "paper-scale single solve: K=4096 samples, M=64 particles, "
                                "T=50 steps, disturbance std x2, seeded start on the 30x20 m "
                                "ellipse track",
-                   "K": K, "M": M, "T": T, "lanes": info["lanes"], "ppl": info["ppl"]},
+                   "K": K, "M": M, "T": T, "lanes": info["lanes"], "ppl": info["ppl"],
+                   "noise_split": info["split"]},
         "roofline": {"bound": "alu", "achieved": slots / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": slots / VALU_PEAK_SLOTS, "traffic": traffic,
                      "kernel": "solve_kernel", "kernel_ms": kernel_ms,

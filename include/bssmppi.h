@@ -119,6 +119,7 @@ typedef struct bss_info {
     double S_min, Z, ess;
     int32_t n_finite;
     int32_t lanes, ppl;       /* launch shape used: lanes per sample, particles per lane */
+    int32_t split;            /* 1 when the disturbance normals came from separate waves */
 } bss_info;
 
 typedef struct bss_ctx bss_ctx;
@@ -193,11 +194,15 @@ bss_status bss_timing_read(bss_ctx* c, double* rollout_ms_total, int32_t* count)
 /* Force the launch shape (lanes per sample 8/16/32/64; 0 restores the automatic choice). */
 bss_status bss_set_lanes(bss_ctx* c, int32_t lanes);
 
-/* Force lanes per sample (0, 8, 16, 32, 64) and particles per lane (0, 1, 2, 4, 8; 0 = automatic)
- * together.  The M particles of a sample are spread over L lanes with P = ceil(M / L) per lane.
- * Results depend on the shape only through the summation order of the per-step moments.
- * Errors: BSS_E_INVAL (values, or M > 64 P), BSS_E_STATE (context in a batch). */
-bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl);
+/* Force lanes per sample (0, 8, 16, 32, 64) and particles per lane (0, 1, 2, 4, 8; 0 = automatic;
+ * a nonzero ppl takes precedence over lanes) and the noise split (-1 automatic, 0 off, 1 on): with
+ * the split, each block of 512 threads has a second set of waves that generates the disturbance
+ * normals one step ahead, which doubles the waves per SIMD of a launch too small to fill the chip
+ * (automatic: when the launch has fewer than two waves per SIMD; never for the shielded loop).
+ * The M particles of a sample are spread over L lanes with P = ceil(M / L) per lane.  Results
+ * depend on the shape only through the summation order of the per-step moments (not on the
+ * split).  Errors: BSS_E_INVAL (values, or M > 64 P), BSS_E_STATE (context in a batch). */
+bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl, int32_t split);
 
 /* Destroy a context and free its buffers (NULL is accepted; a context that belongs to a batch is
  * left alone: destroy the batch first). */
@@ -244,13 +249,14 @@ bss_status bss_batch_solve(bss_batch* b);
  * batch's stream must be a created stream (BSS_E_STATE on the null stream). */
 bss_status bss_batch_capture(bss_batch* b);
 
-/* Time each particles-per-lane candidate on the batch (trial solves whose state changes are undone)
- * and keep the fastest; *ppl_out (may be NULL) receives it.  Call before bss_batch_capture. */
+/* Time each particles-per-lane candidate, with and without the noise split, on the batch (trial
+ * solves whose state changes are undone) and keep the fastest layout; *ppl_out (may be NULL)
+ * receives its particles per lane.  Call before bss_batch_capture. */
 bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out);
 
-/* Number of solve blocks and particles per lane of the batch's current layout (either may be
- * NULL). */
-bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl);
+/* Number of solve blocks, particles per lane and noise split (0/1) of the batch's current layout
+ * (any may be NULL). */
+bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl, int32_t* split);
 
 /* Synchronise the batch's stream, hand each member its state back and free the batch (NULL is
  * accepted). */

@@ -141,9 +141,10 @@ class Solver:
     def set_lanes(self, lanes: int):
         check(_lib.lib().bss_set_lanes(self._ctx, int(lanes)))
 
-    def set_shape(self, lanes: int = 0, ppl: int = 0):
-        """Force lanes per sample and/or particles per lane (0 = automatic; ppl wins)."""
-        check(_lib.lib().bss_set_shape(self._ctx, int(lanes), int(ppl)))
+    def set_shape(self, lanes: int = 0, ppl: int = 0, split: int = -1):
+        """Force lanes per sample and/or particles per lane (0 = automatic; ppl wins) and the
+        noise split (-1 automatic, 0 off, 1 on)."""
+        check(_lib.lib().bss_set_shape(self._ctx, int(lanes), int(ppl), int(split)))
 
     def set_outputs(self, controls: bool = True):
         """Turn the optional per-solve copy of the sampled controls on or off."""
@@ -222,9 +223,9 @@ class Batch:
         return p.value
 
     def layout(self):
-        nb, p = C.c_int32(), C.c_int32()
-        check(_lib.lib().bss_batch_info(self._b, C.byref(nb), C.byref(p)))
-        return {"nblocks": nb.value, "ppl": p.value}
+        nb, p, sp = C.c_int32(), C.c_int32(), C.c_int32()
+        check(_lib.lib().bss_batch_info(self._b, C.byref(nb), C.byref(p), C.byref(sp)))
+        return {"nblocks": nb.value, "ppl": p.value, "split": bool(sp.value)}
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:
@@ -330,7 +331,7 @@ BssAllocator_release = _lib.BssAllocator._fields_[1][1]
 
 def _info_dict(info):
     return {"S_min": info.S_min, "Z": info.Z, "ess": info.ess, "n_finite": info.n_finite,
-            "lanes": info.lanes, "ppl": info.ppl}
+            "lanes": info.lanes, "ppl": info.ppl, "split": bool(info.split)}
 
 
 # ---- stand-alone kernels (device tensors in/out, current stream) --------------------------------

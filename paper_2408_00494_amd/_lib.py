@@ -58,7 +58,8 @@ class BssBuffers(C.Structure):
 
 class BssInfo(C.Structure):
     _fields_ = [("S_min", C.c_double), ("Z", C.c_double), ("ess", C.c_double),
-                ("n_finite", C.c_int32), ("lanes", C.c_int32), ("ppl", C.c_int32)]
+                ("n_finite", C.c_int32), ("lanes", C.c_int32), ("ppl", C.c_int32),
+                ("split", C.c_int32)]
 
 
 # every exported symbol of include/bssmppi.h
@@ -125,7 +126,7 @@ def _declare(lib):
         "bss_dev_update_workspace": (C.c_size_t, [i32, i32]),
         "bss_dev_update": (i32, [P, vp, vp, vp, vp, vp, vp]),
         "bss_dev_repair": (i32, [P, vp, vp, vp, i64, vp]),
-        "bss_set_shape": (i32, [vp, i32, i32]),
+        "bss_set_shape": (i32, [vp, i32, i32, i32]),
         "bss_batch_create": (i32, [C.POINTER(vp), i32, i32, i32, C.POINTER(vp)]),
         "bss_batch_states": (i32, [vp, C.POINTER(vp)]),
         "bss_batch_set_states": (i32, [vp, vp]),
@@ -133,7 +134,7 @@ def _declare(lib):
         "bss_batch_solve": (i32, [vp]),
         "bss_batch_capture": (i32, [vp]),
         "bss_batch_tune": (i32, [vp, C.POINTER(i32)]),
-        "bss_batch_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "bss_batch_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "bss_batch_destroy": (None, [vp]),
         "bss_server_config_default": (None, [C.POINTER(BssServerConfig)]),
         "bss_server_create": (i32, [C.POINTER(BssServerConfig), P, C.POINTER(vp)]),

@@ -192,6 +192,7 @@ struct bss_batch {
     MergeDesc* d_cols;
     double* d_x0;             // [n][6]
     int nblocks, ncols, ppl, shift_after;
+    bool split;               // 512-thread blocks with noise-producing waves
     std::vector<int> lanes;   // lanes per sample of each member in the current layout
     size_t lds;
     bool shield;
@@ -226,7 +227,8 @@ hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
-    c->lds = solve_lds_bytes(c->shape.lanes, c->p.T);
+    c->shape.split = c->shape.split && c->p.shield_iters == 0;
+    c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
     // static leading fields only: the device state is left as it is
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
                              hipMemcpyHostToDevice);
@@ -387,7 +389,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->has_alloc = alloc != nullptr;
     if (alloc) c->alloc = *alloc;
     c->stream = (hipStream_t)stream;
-    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0);
+    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0, -1);
     c->timing = false;
     c->ev_used = 0;
     c->pending_shift = 0;
@@ -509,8 +511,8 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
     e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
-                     c->p.shield_iters > 0, c->lds, x0_dev, Sigma0_dev, c->pending_shift,
-                     c->stream);
+                     c->p.shield_iters > 0, c->shape.split, c->lds, x0_dev, Sigma0_dev,
+                     c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
         e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
@@ -544,9 +546,11 @@ static void fill_info(const bss_ctx* c, const double* stats, bss_info* info)
     if (c->batch) {
         info->lanes = c->batch->lanes[c->batch_index];
         info->ppl = c->batch->ppl;
+        info->split = c->batch->split ? 1 : 0;
     } else {
         info->lanes = c->shape.lanes;
         info->ppl = c->shape.ppl;
+        info->split = c->shape.split ? 1 : 0;
     }
 }
 
@@ -734,7 +738,7 @@ bss_status bss_timing_read(bss_ctx* c, double* rollout_ms_total, int32_t* count)
     return BSS_OK;
 }
 
-bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl)
+bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl, int32_t split)
 {
     bss_status st = check_free(c);
     if (st != BSS_OK) return st;
@@ -747,7 +751,8 @@ bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl)
     if (ppl != 0 && (q.M + ppl - 1) / ppl > 64)
         return fail(BSS_E_INVAL, "M=%d needs more than 64 lanes with %d particles per lane", q.M,
                     ppl);
-    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl);
+    if (split < -1 || split > 1) return fail(BSS_E_INVAL, "split must be -1, 0 or 1");
+    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl, split);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(e, "synchronising");
     c->shape = sh;
@@ -756,7 +761,7 @@ bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl)
     return BSS_OK;
 }
 
-bss_status bss_set_lanes(bss_ctx* c, int32_t lanes) { return bss_set_shape(c, lanes, 0); }
+bss_status bss_set_lanes(bss_ctx* c, int32_t lanes) { return bss_set_shape(c, lanes, 0, -1); }
 
 void bss_destroy(bss_ctx* c)
 {
@@ -773,7 +778,7 @@ void bss_destroy(bss_ctx* c)
 }
 
 // ---- batches ---------------------------------------------------------------------------------
-static hipError_t batch_layout(bss_batch* b, int ppl)
+static hipError_t batch_layout(bss_batch* b, int ppl, int split)
 {
     // launch shape of every instance for a common particles-per-lane count, the solve grid with
     // blocks ordered by horizon (longest first; with P fixed a block's work is proportional to T),
@@ -784,9 +789,8 @@ static hipError_t batch_layout(bss_batch* b, int ppl)
     size_t lds = 0;
     for (int i = 0; i < b->n; ++i) {
         const bss_params& p = b->ctxs[i]->p;
-        const LaunchShape sh = choose_shape(p.K, p.M, p.T, 0, ppl);
+        const LaunchShape sh = choose_shape(p.K, p.M, p.T, 0, ppl, 0);
         lanes[i] = sh.lanes;
-        lds = std::max(lds, solve_lds_bytes(sh.lanes, p.T));
         std::vector<BlockDesc> t = block_table(i, p.K, sh.lanes);
         blocks.insert(blocks.end(), t.begin(), t.end());
         for (int col = 0; col < 2 * p.T; ++col) cols.push_back(MergeDesc{i, col});
@@ -794,6 +798,14 @@ static hipError_t batch_layout(bss_batch* b, int ppl)
     std::stable_sort(blocks.begin(), blocks.end(), [&](const BlockDesc& x, const BlockDesc& y) {
         return b->ctxs[x.inst]->p.T > b->ctxs[y.inst]->p.T;
     });
+    // split blocks (noise generated by a second set of waves) when asked, or automatically when
+    // the whole grid has fewer than two waves per SIMD; every member's ring must fit
+    bool sp = split > 0 || (split < 0 && (int64_t)blocks.size() * 4 < 2 * 1024);
+    sp = sp && !b->shield;
+    for (int i = 0; i < b->n && sp; ++i)
+        sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppl, true) <= kMaxLds;
+    for (int i = 0; i < b->n; ++i)
+        lds = std::max(lds, solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppl, sp));
     hipError_t e = hipSuccess;
     for (int i = 0; i < b->n && e == hipSuccess; ++i) {
         InstanceDesc head = b->ctxs[i]->desc;
@@ -812,13 +824,15 @@ static hipError_t batch_layout(bss_batch* b, int ppl)
     b->ncols = (int)cols.size();
     b->lds = lds;
     b->ppl = ppl;
+    b->split = sp;
     b->lanes = lanes;
     return e;
 }
 
 static hipError_t batch_enqueue(bss_batch* b)
 {
-    hipError_t e = launch_solve(b->d_desc, b->d_blocks, b->nblocks, b->ppl, b->shield, b->lds,
+    hipError_t e = launch_solve(b->d_desc, b->d_blocks, b->nblocks, b->ppl, b->shield,
+                                b->split, b->lds,
                                 b->d_x0, nullptr, 0, b->stream);
     if (e == hipSuccess) e = launch_merge(b->d_desc, b->d_cols, b->ncols, 0, b->stream);
     return e;
@@ -916,7 +930,7 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     }
     if (e == hipSuccess) e = hipMemset(b->d_x0, 0, (size_t)n * 6 * sizeof(double));
     const int ppl0 = ppl != 0 ? ppl : (M_max > 256 ? 8 : 4);
-    if (e == hipSuccess) e = batch_layout(b, ppl0);
+    if (e == hipSuccess) e = batch_layout(b, ppl0, -1);
     if (e != hipSuccess) {
         batch_free(b);
         return device_fail(e, "creating batch");
@@ -1030,24 +1044,30 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
         (void)hipFree(vsave);
         return fail(BSS_E_DEVICE, "hipEventCreate");
     }
-    int best = b->ppl;
+    int best = b->ppl, best_split = b->split ? 1 : 0;
     float best_ms = 1e30f;
     const int cands[] = {1, 2, 4, 8};
     for (int cand : cands) {
         if ((M_max + cand - 1) / cand > 64) continue;
-        e = batch_layout(b, cand);
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
-        if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
-        if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(ev1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-        if (e != hipSuccess) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = cand;
+        for (int sp = 0; sp <= (b->shield ? 0 : 1) && e == hipSuccess; ++sp) {
+            e = batch_layout(b, cand, sp);
+            if (e != hipSuccess) break;
+            if ((sp == 1) != b->split) continue;   // the split ring does not fit this batch
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+            if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+            if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (e != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+                best_split = sp;
+            }
         }
+        if (e != hipSuccess) break;
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
@@ -1058,17 +1078,18 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
                       hipMemcpyDeviceToDevice);
     if (e == hipSuccess) e = copy_v(false);
     (void)hipFree(vsave);
-    if (e == hipSuccess) e = batch_layout(b, best);
+    if (e == hipSuccess) e = batch_layout(b, best, best_split);
     if (e != hipSuccess) return device_fail(e, "autotuning the batch");
     if (ppl_out) *ppl_out = best;
     return BSS_OK;
 }
 
-bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl)
+bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl, int32_t* split)
 {
     if (!b) return fail(BSS_E_INVAL, "batch is NULL");
     if (nblocks) *nblocks = b->nblocks;
     if (ppl) *ppl = b->ppl;
+    if (split) *split = b->split ? 1 : 0;
     return BSS_OK;
 }
 

@@ -89,26 +89,32 @@ struct MergeDesc {
 // samples per block of the partial kernel used for stand-alone K-reductions
 constexpr int kPartialSlice = 16;
 
-// lanes per sample (L) and particles per lane (P) of one rollout launch
+// lanes per sample (L) and particles per lane (P) of one rollout launch; split: 512-thread
+// blocks whose second half generates the disturbance normals one step ahead (non-shielded only)
 struct LaunchShape {
     int lanes;
     int ppl;
+    bool split;
 };
 
 constexpr int kMaxT = 256;
 constexpr size_t kMaxLds = 65536;
 
-// dynamic LDS of one solve block with L lanes per sample
-size_t solve_lds_bytes(int lanes, int T);
-LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl);
+// dynamic LDS of one solve block with L lanes per sample (P = the kernel's particles per lane)
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split);
+// requested_split: -1 automatic (split when the launch has fewer than two waves per SIMD), 0 off,
+// 1 on (when the ring fits)
+LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl,
+                         int requested_split = -1);
+bool split_pays(int nblocks, int lanes, int T, int ppl);
 int solve_blocks(int K, int lanes);
 
 // Solve grid: nblocks blocks described by `blocks`; x0_base holds the state estimates (6 doubles
 // per instance at x0_index), Sigma0_base the covariances (36 doubles) or nullptr; extra_shift is
 // added to every instance's pending shift for this launch.
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
-                        bool shield, size_t lds, const double* x0_base, const double* Sigma0_base,
-                        int extra_shift, hipStream_t stream);
+                        bool shield, bool split, size_t lds, const double* x0_base,
+                        const double* Sigma0_base, int extra_shift, hipStream_t stream);
 hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
                         int extra_shift, hipStream_t stream);
 

@@ -206,7 +206,7 @@ __device__ inline void block_partial(int T, int n, const double* S_sh, double* w
         w_sh[tid] = (isfinite(s) && isfinite(mb)) ? exp(-(s - mb) / lambda) : 0.0;
     }
     __syncthreads();
-    for (int i = tid; i < 2 * T; i += 256) {
+    for (int i = tid; i < 2 * T; i += (int)blockDim.x) {
         const int t = i >> 1;
         const int r = vrow(t, vshift, T);
         const double vi = v[2 * r + (i & 1)];
@@ -236,15 +236,45 @@ __device__ inline void block_partial(int T, int n, const double* S_sh, double* w
 // solve: rollout + scoring + block partial of the K-reduction
 // ----------------------------------------------------------------------------------------------
 // Up to four particles per lane the loop fits 128 registers, which keeps four waves per SIMD;
-// larger P (and the shield's double-precision repair) get the register budget of two.
+// eight particles fit the budget of three, the shield's double-precision repair that of two.
 // One solve block with L lanes per sample (L is a compile-time constant so that the group
 // reductions are straight-line DPP sequences).
-template <int P, bool SHIELD, int L>
+// Disturbance normals of step t for the P particles of one lane, written to slot t & 1 of the
+// ring [2][P][3][256] (lane-contiguous, so the stores and the loads are conflict-free).
+template <int P>
+__device__ __forceinline__ void produce_noise(float* ring, int t, int q, const PhiloxParticle* pp,
+                                              uint32_t c3w, uint32_t lk, uint32_t key0,
+                                              uint32_t key1)
+{
+    const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
+    float* dst = ring + (t & 1) * (P * 3 * 256) + q;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        uint32_t c0, c1, c2, c3;
+        philox10_tail(ps, pp[p], key0, key1, c0, c1, c2, c3);
+        float w0, w1;
+        bm_pair(c0, c1, w0, w1);
+        dst[(p * 3 + 0) * 256] = w0;
+        dst[(p * 3 + 1) * 256] = w1;
+        dst[(p * 3 + 2) * 256] = bm_cos(c2, c3);
+    }
+}
+
+// One solve block with L lanes per sample (L is a compile-time constant so that the group
+// reductions are straight-line DPP sequences).
+//
+// SPLIT (512 threads): threads 256..511 generate the disturbance normals of step t + 1 while
+// threads 0..255 integrate step t, through a two-slot LDS ring and one barrier per step.  This
+// puts two waves on every SIMD when a launch has too few samples to fill the chip otherwise (a
+// lone wave issues at about half the SIMD's rate); the arithmetic and its order are unchanged, so
+// the results are bitwise the same as without the split.
+template <int P, bool SHIELD, int L, bool SPLIT>
 __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDesc bd,
                                             const double* __restrict__ x0_base,
                                             const double* __restrict__ Sigma0_base,
                                             int extra_shift)
 {
+    static_assert(!(SPLIT && SHIELD), "the shielded loop is not split");
     constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
     constexpr int groups = 256 >> log2L;
     const int T = d.T, M = d.M;
@@ -254,8 +284,11 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     double* S_sh = smem;                                     // [groups]
     double* w_sh = S_sh + groups;                            // [groups]
     float2* u_sh = reinterpret_cast<float2*>(w_sh + groups);  // [groups][T]
-    const int g = threadIdx.x >> log2L;
-    const int j = threadIdx.x & (L - 1);
+    float* ring = reinterpret_cast<float*>(u_sh + groups * T);  // SPLIT: [2][P][3][256]
+    const int q = SPLIT ? (int)(threadIdx.x & 255u) : (int)threadIdx.x;
+    const bool producer = SPLIT && threadIdx.x >= 256u;
+    const int g = q >> log2L;
+    const int j = q & (L - 1);
     const int k = bd.k0 + g;
     const bool active = k < d.K;
     float2* us = u_sh + g * T;
@@ -266,7 +299,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     const double* S0p = Sigma0_base ? Sigma0_base + 36 * d.x0_index : nullptr;
 
     // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
-    if (active) {
+    if (active && (!SPLIT || producer)) {
         const float sig0 = d.sig_eps0, sig1 = d.sig_eps1;
         const float smax = d.steer_max, amax = d.accel_max;
         for (int t = j; t < T; t += L) {
@@ -282,9 +315,20 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
             if (!SHIELD && d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = us[t];
         }
     }
+    // disturbance stream of this lane's particles: the first two Philox rounds are partly shared
+    const uint32_t c3w = rng_word3(kTagW, s);
+    const uint64_t pk = (uint64_t)kPhiloxM1 * (uint32_t)k;
+    const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
+    if (SPLIT && producer && active) {
+        PhiloxParticle pp0[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) pp0[p] = philox_particle((uint32_t)(j + p * L), hk, key0, key1);
+        produce_noise<P>(ring, 0, q, pp0, c3w, lk, key0, key1);
+    }
     __syncthreads();
 
-    if (active) {
+    if (SPLIT || active) {
+        const bool consumer = !producer && active;
         double x0[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) x0[i] = x0p[i];
@@ -292,7 +336,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 
         // state relative to the estimate: position and heading as compensated (sum, correction)
         float Xs[P], Xc[P], Ys[P], Yc[P], Ps[P], Pc[P], vx[P], vy[P], vr[P];
-        {
+        if (consumer) {
             double L0[36];
             if (spread) chol6(S0p, L0);
 #pragma unroll
@@ -341,137 +385,148 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         bel[6] = spread ? S0p[0] : 0.0;
         bel[7] = spread ? S0p[1] : 0.0;
         bel[8] = spread ? S0p[7] : 0.0;
-        if (j == 0) {
+        if (consumer && j == 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
         }
-        const uint32_t c3w = rng_word3(kTagW, s);
-        // shared parts of the disturbance stream's first two Philox rounds
-        const uint64_t pk = (uint64_t)kPhiloxM1 * (uint32_t)k;
-        const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
         PhiloxParticle pp[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) pp[p] = philox_particle((uint32_t)(j + p * L), hk, key0, key1);
         const double invM = 1.0 / (double)M;
         const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
 
+        // In split mode every thread runs every iteration and meets exactly one barrier per step,
+        // outside all divergent branches (waves may hold both active and inactive samples).
         for (int t = 0; t < T; ++t) {
-            float2 uu = us[t];
-            if (SHIELD) {
-                const ScoreF64& sc = d.sc;
-                if (sc.shield_iters > 0) {
-                    const BeliefEval be = eval_belief(sc, bel);
-                    const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
-                    const double margin2 = margin * margin;
-                    const double fd = sc.shield_fd;
-                    const int role = j < 5 ? j : 0;
-                    const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
-                    const double o1 = role == 3 ? fd : (role == 4 ? -fd : 0.0);
-                    double us0 = uu.x, us1 = uu.y;
-                    for (int it = 0; it < sc.shield_iters; ++it) {
-                        // lanes 0-4 of the group evaluate r at u and at the four difference points
-                        const double rv =
-                            repair_residual(sc, bel, margin2, be.h, us0 + o0, us1 + o1);
-                        const double r0 = __shfl(rv, 0, L);
-                        const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
-                        const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
-                        if (!(r0 > 0.0)) break;
-                        const double g0 = (rp0 - rm0) / (2.0 * fd);
-                        const double g1 = (rp1 - rm1) / (2.0 * fd);
-                        const double den = g0 * g0 + g1 * g1 + sc.shield_gmin * sc.shield_gmin;
-                        us0 = clampd(us0 - r0 * g0 / den, -sc.steer_max, sc.steer_max);
-                        us1 = clampd(us1 - r0 * g1 / den, -sc.accel_max, sc.accel_max);
+            if (SPLIT && producer) {
+                if (active && t + 1 < T) produce_noise<P>(ring, t + 1, q, pp, c3w, lk, key0, key1);
+            } else if (!SPLIT || consumer) {
+                float2 uu = us[t];
+                if (SHIELD) {
+                    const ScoreF64& sc = d.sc;
+                    if (sc.shield_iters > 0) {
+                        const BeliefEval be = eval_belief(sc, bel);
+                        const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
+                        const double margin2 = margin * margin;
+                        const double fd = sc.shield_fd;
+                        const int role = j < 5 ? j : 0;
+                        const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
+                        const double o1 = role == 3 ? fd : (role == 4 ? -fd : 0.0);
+                        double us0 = uu.x, us1 = uu.y;
+                        for (int it = 0; it < sc.shield_iters; ++it) {
+                            // lanes 0-4 of the group evaluate r at u and at the four difference points
+                            const double rv =
+                                repair_residual(sc, bel, margin2, be.h, us0 + o0, us1 + o1);
+                            const double r0 = __shfl(rv, 0, L);
+                            const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
+                            const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
+                            if (!(r0 > 0.0)) break;
+                            const double g0 = (rp0 - rm0) / (2.0 * fd);
+                            const double g1 = (rp1 - rm1) / (2.0 * fd);
+                            const double den = g0 * g0 + g1 * g1 + sc.shield_gmin * sc.shield_gmin;
+                            us0 = clampd(us0 - r0 * g0 / den, -sc.steer_max, sc.steer_max);
+                            us1 = clampd(us1 - r0 * g1 / den, -sc.accel_max, sc.accel_max);
+                        }
+                        uu = make_float2((float)us0, (float)us1);
                     }
-                    uu = make_float2((float)us0, (float)us1);
+                    if (j == 0) {
+                        us[t] = uu;
+                        if (d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = uu;
+                    }
                 }
-                if (j == 0) {
-                    us[t] = uu;
-                    if (d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = uu;
-                }
-            }
-            const StepF32 st = make_step(car, uu.x, uu.y);
-            const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
-            double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0, sYY = 0;
-            double refX = 0.0, refY = 0.0;
+                const StepF32 st = make_step(car, uu.x, uu.y);
+                PhiloxStep ps{};
+                if (!SPLIT) ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
+                double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0, sYY = 0;
+                double refX = 0.0, refY = 0.0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int m = j + p * L;
-                uint32_t c0, c1, c2, c3;
-                philox10_tail(ps, pp[p], key0, key1, c0, c1, c2, c3);
-                float w0, w1;
-                bm_pair(c0, c1, w0, w1);
-                const float w2 = bm_cos(c2, c3);
+                for (int p = 0; p < P; ++p) {
+                    const int m = j + p * L;
+                    float w0, w1, w2;
+                    if (SPLIT) {
+                        const float* src = ring + (t & 1) * (P * 3 * 256) + q;
+                        w0 = src[(p * 3 + 0) * 256];
+                        w1 = src[(p * 3 + 1) * 256];
+                        w2 = src[(p * 3 + 2) * 256];
+                    } else {
+                        uint32_t c0, c1, c2, c3;
+                        philox10_tail(ps, pp[p], key0, key1, c0, c1, c2, c3);
+                        bm_pair(c0, c1, w0, w1);
+                        w2 = bm_cos(c2, c3);
+                    }
 
-                float dX1, dY1, dvx1, dvy1, dr1;
-                car_field_f32(car, st, fmaf(Ps[p], kInv2Pi, rev0), vx[p], vy[p], vr[p], dX1, dY1,
-                              dvx1, dvy1, dr1);
-                const float pm = fmaf(car.half_dt, vr[p], Ps[p]);
-                const float vxm = fmaf(car.half_dt, dvx1, vx[p]);
-                const float vym = fmaf(car.half_dt, dvy1, vy[p]);
-                const float vrm = fmaf(car.half_dt, dr1, vr[p]);
-                float dX2, dY2, dvx2, dvy2, dr2;
-                car_field_f32(car, st, fmaf(pm, kInv2Pi, rev0), vxm, vym, vrm, dX2, dY2, dvx2,
-                              dvy2, dr2);
-                kahan_add(Xs[p], Xc[p], car.dt * dX2);
-                kahan_add(Ys[p], Yc[p], car.dt * dY2);
-                kahan_add(Ps[p], Pc[p], car.dt * vrm);
-                vx[p] = fmaf(sw0, w0, fmaf(car.dt, dvx2, vx[p]));
-                vy[p] = fmaf(sw1, w1, fmaf(car.dt, dvy2, vy[p]));
-                vr[p] = fmaf(sw2, w2, fmaf(car.dt, dr2, vr[p]));
+                    float dX1, dY1, dvx1, dvy1, dr1;
+                    car_field_f32(car, st, fmaf(Ps[p], kInv2Pi, rev0), vx[p], vy[p], vr[p], dX1, dY1,
+                                  dvx1, dvy1, dr1);
+                    const float pm = fmaf(car.half_dt, vr[p], Ps[p]);
+                    const float vxm = fmaf(car.half_dt, dvx1, vx[p]);
+                    const float vym = fmaf(car.half_dt, dvy1, vy[p]);
+                    const float vrm = fmaf(car.half_dt, dr1, vr[p]);
+                    float dX2, dY2, dvx2, dvy2, dr2;
+                    car_field_f32(car, st, fmaf(pm, kInv2Pi, rev0), vxm, vym, vrm, dX2, dY2, dvx2,
+                                  dvy2, dr2);
+                    kahan_add(Xs[p], Xc[p], car.dt * dX2);
+                    kahan_add(Ys[p], Yc[p], car.dt * dY2);
+                    kahan_add(Ps[p], Pc[p], car.dt * vrm);
+                    vx[p] = fmaf(sw0, w0, fmaf(car.dt, dvx2, vx[p]));
+                    vy[p] = fmaf(sw1, w1, fmaf(car.dt, dvy2, vy[p]));
+                    vr[p] = fmaf(sw2, w2, fmaf(car.dt, dr2, vr[p]));
 
-                if (p == 0) {
-                    // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
-                    refX = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
-                    refY = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
+                    if (p == 0) {
+                        // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
+                        refX = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
+                        refY = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
+                    }
+                    if (m < M) {   // masked particles beyond M contribute nothing
+                        const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
+                        const double Y = ((double)Ys[p] - (double)Yc[p]) - refY;
+                        sX += X;
+                        sY += Y;
+                        sP += (double)Ps[p] - (double)Pc[p];
+                        svx += (double)vx[p];
+                        svy += (double)vy[p];
+                        svr += (double)vr[p];
+                        sXX = fma(X, X, sXX);
+                        sXY = fma(X, Y, sXY);
+                        sYY = fma(Y, Y, sYY);
+                    }
                 }
-                if (m < M) {   // masked particles beyond M contribute nothing
-                    const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
-                    const double Y = ((double)Ys[p] - (double)Yc[p]) - refY;
-                    sX += X;
-                    sY += Y;
-                    sP += (double)Ps[p] - (double)Pc[p];
-                    svx += (double)vx[p];
-                    svy += (double)vy[p];
-                    svr += (double)vr[p];
-                    sXX = fma(X, X, sXX);
-                    sXY = fma(X, Y, sXY);
-                    sYY = fma(Y, Y, sYY);
-                }
-            }
-            sX = group_sum(sX, L);
-            sY = group_sum(sY, L);
-            sP = group_sum(sP, L);
-            svx = group_sum(svx, L);
-            svy = group_sum(svy, L);
-            svr = group_sum(svr, L);
-            sXX = group_sum(sXX, L);
-            sXY = group_sum(sXY, L);
-            sYY = group_sum(sYY, L);
-            // moments: sums of positions shifted by particle 0, heading relative to the estimate
-            const double mX = sX * invM, mY = sY * invM;
-            bel[0] = x0[0] + (refX + mX);
-            bel[1] = x0[1] + (refY + mY);
-            bel[2] = x0[2] + sP * invM;
-            bel[3] = svx * invM;
-            bel[4] = svy * invM;
-            bel[5] = svr * invM;
-            bel[6] = (sXX - sX * mX) * invM1;
-            bel[7] = (sXY - sX * mY) * invM1;
-            bel[8] = (sYY - sY * mY) * invM1;
+                sX = group_sum(sX, L);
+                sY = group_sum(sY, L);
+                sP = group_sum(sP, L);
+                svx = group_sum(svx, L);
+                svy = group_sum(svy, L);
+                svr = group_sum(svr, L);
+                sXX = group_sum(sXX, L);
+                sXY = group_sum(sXY, L);
+                sYY = group_sum(sYY, L);
+                // moments: sums of positions shifted by particle 0, heading relative to the estimate
+                const double mX = sX * invM, mY = sY * invM;
+                bel[0] = x0[0] + (refX + mX);
+                bel[1] = x0[1] + (refY + mY);
+                bel[2] = x0[2] + sP * invM;
+                bel[3] = svx * invM;
+                bel[4] = svy * invM;
+                bel[5] = svr * invM;
+                bel[6] = (sXX - sX * mX) * invM1;
+                bel[7] = (sXY - sX * mY) * invM1;
+                bel[8] = (sYY - sY * mY) * invM1;
 
-            // record t+1, written by lane (t+1) % L of the group (spreads the stores)
-            if (j == ((t + 1) & (L - 1))) {
-                double* rec = mom_k + (size_t)(t + 1) * 9;
+                // record t+1, written by lane (t+1) % L of the group (spreads the stores)
+                if (j == ((t + 1) & (L - 1))) {
+                    double* rec = mom_k + (size_t)(t + 1) * 9;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+                    for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+                }
             }
+            if (SPLIT) __syncthreads();
         }
     }
     // ---- phase 3: score the belief trajectory, L records at a time (one per lane) ----
     __threadfence_block();
     __syncthreads();
     double S_part = 0.0;
-    if (active) {
+    if (active && !producer) {
         double h_carry = 0.0;
         for (int base = 0; base <= T; base += L) {
             const int count = min(L, T + 1 - base);
@@ -481,7 +536,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         }
     }
     const double S_k = group_sum(S_part, L);
-    if (j == 0) {
+    if (j == 0 && !producer) {
         S_sh[g] = active ? S_k : INFINITY;
         if (active) d.S[k] = S_k;
     }
@@ -493,19 +548,19 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 
 // Solve grid: every block looks up its instance and first sample; the lane count is uniform over
 // a block, so the dispatch below is a block-uniform branch.
-template <int P, bool SHIELD>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((P <= 4 && !SHIELD) ? 4 : 2))) void solve_kernel(
+template <int P, bool SHIELD, bool SPLIT>
+__global__ __launch_bounds__(SPLIT ? 512 : 256)
+__attribute__((amdgpu_waves_per_eu(SHIELD ? 2 : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
     const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
     const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
 {
     const BlockDesc bd = blocks[blockIdx.x];
     const InstanceDesc& d = insts[bd.inst];
     switch (d.lanes) {
-    case 8: solve_block<P, SHIELD, 8>(d, bd, x0_base, Sigma0_base, extra_shift); break;
-    case 16: solve_block<P, SHIELD, 16>(d, bd, x0_base, Sigma0_base, extra_shift); break;
-    case 32: solve_block<P, SHIELD, 32>(d, bd, x0_base, Sigma0_base, extra_shift); break;
-    default: solve_block<P, SHIELD, 64>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    case 8: solve_block<P, SHIELD, 8, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    case 16: solve_block<P, SHIELD, 16, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    case 32: solve_block<P, SHIELD, 32, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    default: solve_block<P, SHIELD, 64, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
     }
 }
 
@@ -760,15 +815,18 @@ __global__ void repair_kernel(ScoreF64 sc, const double* mom, const double* u_in
 
 template <int P>
 hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
-                          bool shield, size_t lds, const double* x0_base,
+                          bool shield, bool split, size_t lds, const double* x0_base,
                           const double* Sigma0_base, int extra_shift, hipStream_t stream)
 {
     if (shield)
-        hipLaunchKernelGGL((solve_kernel<P, true>), dim3(nblocks), dim3(256), lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
+        hipLaunchKernelGGL((solve_kernel<P, true, false>), dim3(nblocks), dim3(256), lds, stream,
+                           inst, blocks, x0_base, Sigma0_base, extra_shift);
+    else if (split)
+        hipLaunchKernelGGL((solve_kernel<P, false, true>), dim3(nblocks), dim3(512), lds, stream,
+                           inst, blocks, x0_base, Sigma0_base, extra_shift);
     else
-        hipLaunchKernelGGL((solve_kernel<P, false>), dim3(nblocks), dim3(256), lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
+        hipLaunchKernelGGL((solve_kernel<P, false, false>), dim3(nblocks), dim3(256), lds, stream,
+                           inst, blocks, x0_base, Sigma0_base, extra_shift);
     return hipGetLastError();
 }
 
@@ -785,15 +843,23 @@ static int ppl_for(int M, int lanes)
     return p;
 }
 
-size_t solve_lds_bytes(int lanes, int T)
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split)
 {
     const int groups = 256 / lanes;
-    return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2);
+    return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2) +
+           (split ? (size_t)2 * ppl * 3 * 256 * sizeof(float) : 0);
 }
 
-LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl)
+bool split_pays(int nblocks, int lanes, int T, int ppl)
 {
-    (void)K;
+    // fewer than two waves per SIMD (256 CUs x 4 SIMDs, four waves per block), and room for the
+    // noise ring
+    return (int64_t)nblocks * 4 < 2 * 1024 && solve_lds_bytes(lanes, T, ppl, true) <= kMaxLds;
+}
+
+LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl,
+                         int requested_split)
+{
     LaunchShape s;
     const bool lanes_ok = requested_lanes == 8 || requested_lanes == 16 || requested_lanes == 32 ||
                           requested_lanes == 64;
@@ -812,10 +878,14 @@ LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested
         s.lanes = lanes;
     }
     s.ppl = ppl_for(M, s.lanes);
-    while ((s.ppl > 8 || solve_lds_bytes(s.lanes, T) > kMaxLds) && s.lanes < 64) {
+    while ((s.ppl > 8 || solve_lds_bytes(s.lanes, T, s.ppl, false) > kMaxLds) && s.lanes < 64) {
         s.lanes <<= 1;
         s.ppl = ppl_for(M, s.lanes);
     }
+    const bool fits = solve_lds_bytes(s.lanes, T, s.ppl, true) <= kMaxLds;
+    s.split = requested_split > 0 ? fits
+              : requested_split == 0 ? false
+                                     : split_pays(solve_blocks(K, s.lanes), s.lanes, T, s.ppl);
     return s;
 }
 
@@ -826,19 +896,20 @@ int solve_blocks(int K, int lanes)
 }
 
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
-                        bool shield, size_t lds, const double* x0_base, const double* Sigma0_base,
-                        int extra_shift, hipStream_t stream)
+                        bool shield, bool split, size_t lds, const double* x0_base,
+                        const double* Sigma0_base, int extra_shift, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
+    split = split && !shield;
     switch (ppl) {
-    case 1: return launch_solve_p<1>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
-                                     extra_shift, stream);
-    case 2: return launch_solve_p<2>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
-                                     extra_shift, stream);
-    case 4: return launch_solve_p<4>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
-                                     extra_shift, stream);
-    case 8: return launch_solve_p<8>(inst, blocks, nblocks, shield, lds, x0_base, Sigma0_base,
-                                     extra_shift, stream);
+    case 1: return launch_solve_p<1>(inst, blocks, nblocks, shield, split, lds, x0_base,
+                                     Sigma0_base, extra_shift, stream);
+    case 2: return launch_solve_p<2>(inst, blocks, nblocks, shield, split, lds, x0_base,
+                                     Sigma0_base, extra_shift, stream);
+    case 4: return launch_solve_p<4>(inst, blocks, nblocks, shield, split, lds, x0_base,
+                                     Sigma0_base, extra_shift, stream);
+    case 8: return launch_solve_p<8>(inst, blocks, nblocks, shield, split, lds, x0_base,
+                                     Sigma0_base, extra_shift, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -163,7 +163,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     sl.vehicles.clear();
     std::vector<double> x0s;
     size_t used = 0, lds = 0;
-    bool shield = false;
+    bool shield = false, ring_fits = true;
     // pick requests oldest first; skip a vehicle already in flight or already seen in this scan
     std::deque<Request>& pend = s->pending;
     std::vector<size_t> taken;
@@ -175,7 +175,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
             continue;
         }
         s->seen[r.vehicle] = 1;
-        const LaunchShape sh = choose_shape(r.K, r.M, T, 0, s->ppl);
+        const LaunchShape sh = choose_shape(r.K, r.M, T, 0, s->ppl, 0);
         const size_t need = scratch_bytes(r.K, T, sh.lanes);
         if (used + need > sl.arena_bytes) continue;   // waits for memory (admission)
         const int nb = solve_blocks(r.K, sh.lanes);
@@ -205,7 +205,8 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         d.partial = (double*)a;
         d.stats = sl.d_stats + 8 * i;
         used += need;
-        lds = std::max(lds, solve_lds_bytes(sh.lanes, T));
+        lds = std::max(lds, solve_lds_bytes(sh.lanes, T, s->ppl, false));
+        ring_fits = ring_fits && solve_lds_bytes(sh.lanes, T, s->ppl, true) <= kMaxLds;
         shield = shield || v.p.shield_iters > 0;
         descs.push_back(d);
         append_blocks(blocks, i, r.K, sh.lanes);
@@ -216,6 +217,14 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         taken.push_back(qi);
     }
     if (descs.empty()) return BSS_OK;
+    // a batch too small to put two waves on every SIMD generates its noise in separate waves
+    const bool split = !shield && ring_fits && (int64_t)blocks.size() * 4 < 2 * 1024;
+    if (split) {
+        size_t l2 = 0;
+        for (const InstanceDesc& d : descs)
+            l2 = std::max(l2, solve_lds_bytes(d.lanes, T, s->ppl, true));
+        lds = l2;
+    }
 
     // pack descriptors | blocks | columns | states into the slot's pinned staging, one upload
     const size_t o_desc = 0;
@@ -233,8 +242,8 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     const InstanceDesc* d_desc = (const InstanceDesc*)(sl.d_region + o_desc);
     if (e == hipSuccess)
         e = launch_solve(d_desc, (const BlockDesc*)(sl.d_region + o_blk), (int)blocks.size(),
-                         s->ppl, shield, lds, (const double*)(sl.d_region + o_x0), nullptr, 0,
-                         sl.stream);
+                         s->ppl, shield, split, lds, (const double*)(sl.d_region + o_x0), nullptr,
+                         0, sl.stream);
     if (e == hipSuccess)
         e = launch_merge(d_desc, (const MergeDesc*)(sl.d_region + o_col), (int)cols.size(), 0,
                          sl.stream);

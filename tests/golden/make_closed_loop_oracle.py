@@ -1,0 +1,37 @@
+"""Writes closed_loop_oracle.json: closed-loop statistics of the FP64 oracle controller on the
+shielded workload (K=8192, M=128, T=60, two repair iterations) for every (delta, gamma)
+combination, with the plant and episode rules of tests/closed_loop.py.  Calls only the oracle and
+the input generators.
+
+    python tests/golden/make_closed_loop_oracle.py [steps] [nthreads]
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))            # tests/
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))   # repository root
+
+import closed_loop as CL  # noqa: E402
+
+
+def main():
+    steps = int(sys.argv[1]) if len(sys.argv) > 1 else 250
+    nthreads = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
+    out_path = os.path.join(HERE, "closed_loop_oracle.json")
+    res = {"steps_per_combo": steps, "controller": "oracle", "combos": []}
+    for i, (d, g) in enumerate(CL.COMBOS):
+        prob = CL.combo_problem(i)
+        t0 = time.time()
+        st, _ = CL.run(prob, steps, CL.OracleController(prob, nthreads))
+        st.update({"delta": d, "gamma": g, "seed": prob["seed"]})
+        res["combos"].append(st)
+        print(f"delta={d} gamma={g}: {st} ({time.time() - t0:.0f} s)", flush=True)
+        with open(out_path, "w") as fh:
+            json.dump(res, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,4 +177,4 @@ def test_server_and_batch_argument_checks():
     assert lib.bss_server_drain(None) == _lib.BSS_E_INVAL
     assert lib.bss_batch_create(None, 0, 0, 0, C.byref(out)) == _lib.BSS_E_INVAL
     assert lib.bss_batch_solve(None) == _lib.BSS_E_INVAL
-    assert lib.bss_set_shape(None, 16, 4) == _lib.BSS_E_INVAL
+    assert lib.bss_set_shape(None, 16, 4, -1) == _lib.BSS_E_INVAL

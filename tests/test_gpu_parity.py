@@ -323,6 +323,29 @@ def test_edge_sizes_match_oracle(K, M, T, lanes):
     _compare_solve(prob, x0, v, s=9, lanes=lanes)
 
 
+@pytest.mark.parametrize("K,M,T,ppl", [(4096, 64, 50, 4), (4096, 64, 50, 2), (333, 37, 23, 8),
+                                       (70, 5, 9, 1), (3, 200, 4, 4)])
+def test_noise_split_is_bitwise_identical(K, M, T, ppl):
+    """Generating the disturbance normals in separate waves changes no result bit."""
+    prob, x0, _ = W.config_paper_scale()
+    prob = dict(prob, K=K, M=M, T=T)
+    v = np.column_stack([0.05 * np.sin(np.arange(T)), 0.5 * np.cos(np.arange(T))])
+    out = []
+    for split in (0, 1):
+        s = bss.Solver(prob)
+        s.set_shape(ppl=ppl, split=split)
+        s.set_controls(v)
+        s.solve_index = 7
+        s.solve(x0)
+        s.solve(x0)                 # second solve reads the first one's update
+        b = s.buffers()
+        out.append((s.get_controls(), b["mom"].cpu().numpy(), b["S"].cpu().numpy(),
+                    b["u"].cpu().numpy()))
+        s.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_initial_spread_matches_oracle():
     prob, x0, v = W.config_small()
     rng = np.random.default_rng(5)
