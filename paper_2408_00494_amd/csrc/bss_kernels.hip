@@ -567,37 +567,53 @@ __attribute__((amdgpu_waves_per_eu(SHIELD ? 2 : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))
 // ----------------------------------------------------------------------------------------------
 // merge: one block per control entry
 // ----------------------------------------------------------------------------------------------
-__device__ __forceinline__ double block_reduce_256(double x, double* red, bool is_min)
+// Reduction over the 64 lanes of a wave (DPP within rows, swaps across rows); every lane gets the
+// result, bitwise identical across lanes (each stage combines the same two values).
+struct MinOp {
+    __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct AddOp {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double x, Op op)
 {
-    const int tid = threadIdx.x;
-    red[tid] = x;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) red[tid] = is_min ? fmin(red[tid], red[tid + off]) : red[tid] + red[tid + off];
-        __syncthreads();
+    x = op(x, dpp_f64<kDppQuadSwap1>(x));
+    x = op(x, dpp_f64<kDppQuadSwap2>(x));
+    x = op(x, dpp_f64<kDppHalfRowMirror>(x));
+    x = op(x, dpp_f64<kDppRowMirror>(x));
+    {
+        const uint32_t lo = (uint32_t)__double2loint(x), hi = (uint32_t)__double2hiint(x);
+        const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        x = op(__hiloint2double((int)b[0], (int)a[0]), __hiloint2double((int)b[1], (int)a[1]));
     }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+    {
+        const uint32_t lo = (uint32_t)__double2loint(x), hi = (uint32_t)__double2hiint(x);
+        const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        x = op(__hiloint2double((int)b[0], (int)a[0]), __hiloint2double((int)b[1], (int)a[1]));
+    }
+    return x;
 }
 
-// Merge of one control entry of one instance: global minimum m = min_b m_b, rescale
-// exp(-(m_b - m)/lambda), fixed-order block reductions of Z, sum w^2, #finite and the entry's
-// numerator; returns through the references.
+// Merge of one control entry by one wave: global minimum m = min_b m_b, rescale
+// exp(-(m_b - m)/lambda), fixed-order reductions of Z, sum w^2, #finite and the entry's numerator
+// (lane l takes blocks l, l + 64, ...); results in every lane.
 __device__ inline void merge_entry(const double* partial, int G, int T, int col, double lambda,
-                                   double* red, double& m, double& Z, double& W2, double& nf,
-                                   double& N)
+                                   double& m, double& Z, double& W2, double& nf, double& N)
 {
-    const int tid = threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63u);
     const int stride = 2 * T + 4;
     m = INFINITY;
-    for (int b = tid; b < G; b += 256) m = fmin(m, partial[(size_t)b * stride + 2 * T + 3]);
-    m = block_reduce_256(m, red, true);
+    for (int b = lane; b < G; b += 64) m = fmin(m, partial[(size_t)b * stride + 2 * T + 3]);
+    m = wave_reduce(m, MinOp());
     Z = 0.0;
     W2 = 0.0;
     nf = 0.0;
     N = 0.0;
-    for (int b = tid; b < G; b += 256) {
+    for (int b = lane; b < G; b += 64) {
         const double* pb = partial + (size_t)b * stride;
         const double mb = pb[2 * T + 3];
         const double sc = isfinite(mb) ? exp(-(mb - m) / lambda) : 0.0;
@@ -606,10 +622,10 @@ __device__ inline void merge_entry(const double* partial, int G, int T, int col,
         nf += pb[2 * T + 2];
         N += sc * pb[col];
     }
-    Z = block_reduce_256(Z, red, false);
-    W2 = block_reduce_256(W2, red, false);
-    nf = block_reduce_256(nf, red, false);
-    N = block_reduce_256(N, red, false);
+    Z = wave_reduce(Z, AddOp());
+    W2 = wave_reduce(W2, AddOp());
+    nf = wave_reduce(nf, AddOp());
+    N = wave_reduce(N, AddOp());
 }
 
 __device__ inline void write_stats(double* stats, int col, double vo, bool ok, double m, double Z,
@@ -626,19 +642,20 @@ __device__ inline void write_stats(double* stats, int col, double vo, bool ok, d
     }
 }
 
-// One block per (instance, control entry).  v+ goes to the other buffer of the instance's
-// ping-pong pair; the last block of an instance to finish advances its per-solve state.
+// One wave per (instance, control entry), four per block.  v+ goes to the other buffer of the
+// instance's ping-pong pair; the last wave of an instance to finish advances its per-solve state.
 __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const MergeDesc* cols,
-                                                    int extra_shift)
+                                                    int ncols, int extra_shift)
 {
-    __shared__ double red[256];
-    const MergeDesc md = cols[blockIdx.x];
+    const int idx = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (idx >= ncols) return;
+    const MergeDesc md = cols[idx];
     InstanceDesc& d = insts[md.inst];
     const int T = d.T, col = md.col;
     const int cur = d.cur;
     double m, Z, W2, nf, N;
-    merge_entry(d.partial, d.nblocks, T, col, d.sc.lambda, red, m, Z, W2, nf, N);
-    if (threadIdx.x == 0) {
+    merge_entry(d.partial, d.nblocks, T, col, d.sc.lambda, m, Z, W2, nf, N);
+    if ((threadIdx.x & 63u) == 0) {
         const bool ok = nf > 0.0 && Z > 0.0;
         const int r = vrow(col >> 1, d.vshift + extra_shift, T);
         const double vi = d.v[cur][2 * r + (col & 1)];
@@ -665,11 +682,11 @@ __global__ __launch_bounds__(256) void merge_plain_kernel(int T, int G, double l
                                                           const double* v_in, double* v_out,
                                                           double* stats)
 {
-    __shared__ double red[256];
-    const int col = blockIdx.x;
+    const int col = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (col >= 2 * T) return;
     double m, Z, W2, nf, N;
-    merge_entry(partial, G, T, col, lambda, red, m, Z, W2, nf, N);
-    if (threadIdx.x == 0) {
+    merge_entry(partial, G, T, col, lambda, m, Z, W2, nf, N);
+    if ((threadIdx.x & 63u) == 0) {
         const bool ok = nf > 0.0 && Z > 0.0;
         const double vo = ok ? v_in[col] + N / Z : v_in[col];
         v_out[col] = vo;
@@ -918,8 +935,8 @@ hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int nco
                         int extra_shift, hipStream_t stream)
 {
     if (ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(merge_kernel, dim3(ncols), dim3(256), 0, stream,
-                       const_cast<InstanceDesc*>(inst), cols, extra_shift);
+    hipLaunchKernelGGL(merge_kernel, dim3(blocks_for(ncols, 4)), dim3(256), 0, stream,
+                       const_cast<InstanceDesc*>(inst), cols, ncols, extra_shift);
     return hipGetLastError();
 }
 
@@ -927,8 +944,8 @@ hipError_t launch_merge_plain(int T, int G, double lambda, const double* partial
                               const double* v_in, double* v_out, double* stats,
                               hipStream_t stream)
 {
-    hipLaunchKernelGGL(merge_plain_kernel, dim3(2 * T), dim3(256), 0, stream, T, G, lambda,
-                       partial, v_in, v_out, stats);
+    hipLaunchKernelGGL(merge_plain_kernel, dim3(blocks_for(2 * T, 4)), dim3(256), 0, stream, T,
+                       G, lambda, partial, v_in, v_out, stats);
     return hipGetLastError();
 }
 
