@@ -35,6 +35,7 @@ class OrcParams(C.Structure):
         ("ell_a", C.c_double), ("ell_b", C.c_double), ("half_width", C.c_double),
         ("shield_iters", C.c_int32), ("shield_gmin", C.c_double), ("shield_fd", C.c_double),
         ("seed", C.c_uint64),
+        ("belief", C.c_int32),
         ("model", C.c_int32),
         ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
     ]
@@ -106,6 +107,8 @@ def _load():
     lib.orc_solve.restype = C.c_int32
     lib.orc_step_shift.argtypes = [C.c_int32, _f64p]
     lib.orc_step_shift.restype = None
+    lib.orc_chol_psd6.argtypes = [_f64p, _f64p]
+    lib.orc_chol_psd6.restype = None
     return lib
 
 
@@ -281,3 +284,10 @@ def step_shift(v):
     vv = np.array(v, dtype=np.float64)
     lib().orc_step_shift(int(vv.shape[0]), vv)
     return vv
+
+
+def chol_psd6(A):
+    """Semi-definite lower factor of a 6x6 matrix (the re-sampling draw's factor)."""
+    L = np.zeros(36)
+    lib().orc_chol_psd6(np.ascontiguousarray(A, dtype=np.float64).ravel(), L)
+    return L.reshape(6, 6)

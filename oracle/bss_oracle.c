@@ -90,7 +90,8 @@ void orc_normals_many(uint64_t seed, const uint32_t* ctr, double* z, int64_t n)
 /* Counter layout (the random-number contract shared by both implementations):
  *   word0 = time step t (or the block index for the initial spread), word1 = particle m,
  *   word2 = sample k, word3 = (stream tag << 28) | (solve index & 0x0FFFFFFF).
- * Tags: 0 control noise eps_{k,t}; 1 disturbance w_{k,m,t}; 2 initial spread of particles. */
+ * Tags: 0 control noise eps_{k,t}; 1 disturbance w_{k,m,t}; 2 initial spread of particles;
+ * 4 and 5 the two blocks of standard normals of a Gaussian re-sampling draw (word0 = t). */
 static void rng_counter(uint32_t w0, uint32_t m, uint32_t k, uint32_t tag, uint32_t s,
                         uint32_t ctr[4])
 {
@@ -423,6 +424,61 @@ static void init_particles(const orc_params* p, uint32_t s, int32_t k, const dou
     mom0[8] = Sigma0 ? Sigma0[7] : 0.0;
 }
 
+void orc_chol_psd6(const double* A, double* L)
+{
+    memset(L, 0, sizeof(double) * 36);
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j * 6 + j];
+        for (int q = 0; q < j; ++q) d -= L[j * 6 + q] * L[j * 6 + q];
+        if (d <= 1e-10 * A[j * 6 + j] + 1e-24) continue;
+        double ljj = sqrt(d);
+        L[j * 6 + j] = ljj;
+        for (int i = j + 1; i < 6; ++i) {
+            double acc = A[i * 6 + j];
+            for (int q = 0; q < j; ++q) acc -= L[i * 6 + q] * L[j * 6 + q];
+            L[i * 6 + j] = acc / ljj;
+        }
+    }
+}
+
+/* Gaussian re-sampling of Alg. 2 as printed: the particles of step t are redrawn as
+ * x^n_t = xbar_t + L_t xi^n with xbar_t and the unbiased full 6x6 covariance Sigma_t of the
+ * current set (two-pass; Sigma := 0 for M = 1), L_t its semi-definite factor, and xi^n six
+ * standard normals from tags 4 and 5 with counter (t, n, k). */
+static void resample_particles(const orc_params* p, uint32_t s, int32_t k, int t, double* part)
+{
+    int M = p->M;
+    double mean[6] = {0, 0, 0, 0, 0, 0}, cov[36], L[36];
+    for (int m = 0; m < M; ++m)
+        for (int i = 0; i < 6; ++i) mean[i] += part[m * 6 + i];
+    for (int i = 0; i < 6; ++i) mean[i] /= (double)M;
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+            for (int m = 0; m < M; ++m)
+                acc += (part[m * 6 + i] - mean[i]) * (part[m * 6 + j] - mean[j]);
+            cov[i * 6 + j] = M > 1 ? acc / (double)(M - 1) : 0.0;
+        }
+    orc_chol_psd6(cov, L);
+    uint32_t ctr[4];
+    double z[4];
+    for (int m = 0; m < M; ++m) {
+        double xi[6];
+        for (uint32_t blk = 0; blk < 2; ++blk) {
+            rng_counter((uint32_t)t, (uint32_t)m, (uint32_t)k, 4u + blk, s, ctr);
+            orc_normals(p->seed, ctr, z);
+            xi[blk * 3 + 0] = z[0];
+            xi[blk * 3 + 1] = z[1];
+            xi[blk * 3 + 2] = z[2];
+        }
+        for (int i = 0; i < 6; ++i) {
+            double acc = mean[i];
+            for (int j = 0; j <= i; ++j) acc += L[i * 6 + j] * xi[j];
+            part[m * 6 + i] = acc;
+        }
+    }
+}
+
 /* One step of Alg. 2 with persistent particles: x^n_{t+1} = f(x^n_t, u_t) + [0,0,0, w^n_t]
  * (w from tag 1), then the moments of the new particle set. */
 static void propagate_step(const orc_params* p, uint32_t s, int32_t k, int t, const double u[2],
@@ -465,6 +521,7 @@ double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const 
         orc_repair(p, nu, &mom_out[(size_t)t * ORC_NMOM], u);
         u_out[t * 2 + 0] = u[0];
         u_out[t * 2 + 1] = u[1];
+        if (p->belief == 1 && t > 0) resample_particles(p, s, k, t, part);
         propagate_step(p, s, k, t, u, part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
     }
     free(part);
@@ -481,8 +538,10 @@ void orc_propagate(const orc_params* p, uint32_t s, int32_t k, const double x0[6
     double* part = (double*)malloc(sizeof(double) * 6 * (size_t)M);
     double* nxt = (double*)malloc(sizeof(double) * 6 * (size_t)M);
     init_particles(p, s, k, x0, Sigma0, L0, part, mom_out);
-    for (int t = 0; t < T; ++t)
+    for (int t = 0; t < T; ++t) {
+        if (p->belief == 1 && t > 0) resample_particles(p, s, k, t, part);
         propagate_step(p, s, k, t, &u[t * 2], part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
+    }
     free(part);
     free(nxt);
 }

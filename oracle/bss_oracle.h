@@ -50,6 +50,7 @@ typedef struct orc_params {
     int32_t shield_iters;
     double shield_gmin, shield_fd;
     uint64_t seed;
+    int32_t belief;       /* 0 persistent particles, 1 Gaussian re-sampling every step */
     int32_t model;
     double lin_A[36];
     double lin_B[12];
@@ -66,6 +67,11 @@ double orc_uniform(uint32_t r);
 void   orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
 void   orc_philox_many(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, int64_t n);
 void   orc_normals_many(uint64_t seed, const uint32_t* ctr, double* z, int64_t n);
+
+/* Lower factor L of a symmetric positive semi-definite 6x6 matrix with L L^T = A, by columns; a
+ * pivot d <= 1e-10 A_jj + 1e-24 counts as zero and leaves its column zero (so variances at the
+ * rounding level of an exactly degenerate set are not amplified). */
+void orc_chol_psd6(const double* A, double* L);
 
 /* ---- back-off coefficient (Remark 1) ---------------------------------------------------- */
 double orc_backoff(double delta, int32_t backoff);

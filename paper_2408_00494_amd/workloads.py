@@ -34,8 +34,9 @@ _DEFAULTS = dict(
     ell_a=30.0, ell_b=20.0, half_width=2.0,
     # shield repair (0 iterations = off)
     shield_iters=0, shield_gmin=0.05, shield_fd=1.0e-2,
-    # random numbers and model selector (0 = car)
-    seed=1, model=0,
+    # random numbers, belief propagation (0 persistent particles, 1 Gaussian re-sampling every
+    # step) and model selector (0 = car)
+    seed=1, belief=0, model=0,
 )
 
 

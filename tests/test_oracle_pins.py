@@ -668,3 +668,85 @@ def test_step_shift():
     v = np.arange(10, dtype=float).reshape(5, 2)
     s = oracle.step_shift(v)
     assert s.tolist() == [[2, 3], [4, 5], [6, 7], [8, 9], [8, 9]]
+
+
+# ============================ Gaussian re-sampling reading (Alg. 2) ============================
+def test_semidefinite_factor():
+    """The re-sampling factor: the Cholesky factor on positive definite input, L L^T = A with the
+    rank's number of nonzero pivots on semi-definite input, and a zero column for a variance at
+    the rounding level of an exactly degenerate set."""
+    rng = np.random.default_rng(3)
+    B = rng.normal(size=(6, 6))
+    A = B @ B.T + 0.1 * np.eye(6)
+    assert np.max(np.abs(oracle.chol_psd6(A) - np.linalg.cholesky(A))) <= 1e-13
+    B3 = rng.normal(size=(6, 3))
+    A3 = B3 @ B3.T
+    L3 = oracle.chol_psd6(A3)
+    assert np.max(np.abs(L3 @ L3.T - A3)) <= 1e-12 * np.max(np.abs(A3))
+    assert np.count_nonzero(np.diag(L3)) == 3
+    Z = A.copy()
+    Z[0, :] = 0.0
+    Z[:, 0] = 0.0
+    LZ = oracle.chol_psd6(Z)
+    assert np.all(LZ[:, 0] == 0.0)
+    assert np.max(np.abs(LZ[1:, 1:] - np.linalg.cholesky(A[1:, 1:]))) <= 1e-13
+    R = A.copy()
+    R[0, 0] = 1e-30
+    R[1:, 0] = R[0, 1:] = 1e-18
+    LR = oracle.chol_psd6(R)
+    assert np.all(LR[:, 0] == 0.0)
+
+
+def test_resampling_with_one_particle_is_the_persistent_recursion():
+    """M = 1: the covariance is 0, so every redraw returns the particle itself."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=16, M=1, T=12)
+    a = oracle.solve(prob, 3, x0, v[:12])
+    b = oracle.solve(dict(prob, belief=1), 3, x0, v[:12])
+    for key in ("v", "mom", "S", "u"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_resampling_without_disturbance_is_deterministic_integration():
+    """No disturbance and a known start: every particle stays on the deterministic trajectory, the
+    covariance stays (numerically) zero, and the redraw only moves particles to the mean."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=8, M=7, T=15, sigma_w=[0.0, 0.0, 0.0])
+    a = oracle.solve(prob, 1, x0, v[:15])
+    b = oracle.solve(dict(prob, belief=1), 1, x0, v[:15])
+    assert np.max(np.abs(a["mom"] - b["mom"])) <= 1e-12 * np.max(np.abs(a["mom"]))
+    assert np.max(np.abs(a["S"] - b["S"])) <= 1e-12 * np.max(np.abs(a["S"]))
+
+
+def test_resampling_linear_gaussian_matches_closed_form():
+    """Linear-Gaussian model: redrawing from the sample mean and covariance keeps
+    Sigma_{t+1} = A Sigma_t A^T + Q in expectation; each redraw adds one sampling error, so the
+    bound grows like sqrt(t) standard errors."""
+    M = 1 << 14
+    cfg, A, Q = _linear_problem(M, T=6)
+    cfg = dict(cfg, belief=1)
+    x0 = np.array([1.0, 2.0, 0.0, 3.0, 0.5, 0.1])
+    mom = oracle.propagate(cfg, 0, 0, x0, np.zeros((cfg["T"], 2)))
+    Sig = np.zeros((6, 6))
+    mean = x0.copy()
+    for t in range(1, cfg["T"] + 1):
+        Sig = A @ Sig @ A.T + Q
+        mean = A @ mean
+        got = mom[t]
+        tol = 6.0 * math.sqrt(t)
+        assert np.all(np.abs(got[:6] - mean) <= tol * np.sqrt(np.diag(Sig) / M) + 1e-10)
+        for val, (i, j) in zip(got[6:], ((0, 0), (0, 1), (1, 1))):
+            se = math.sqrt((Sig[i, i] * Sig[j, j] + Sig[i, j] ** 2) / (M - 1))
+            assert abs(val - Sig[i, j]) <= tol * se + 1e-15
+
+
+def test_resampling_changes_a_nonlinear_belief():
+    """On the car the two readings differ (the redraw projects the particle cloud onto a
+    Gaussian every step) while both stay finite and close in the mean."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=4, M=32, T=20)
+    a = oracle.solve(prob, 2, x0, v[:20])
+    b = oracle.solve(dict(prob, belief=1), 2, x0, v[:20])
+    assert np.all(np.isfinite(b["mom"]))
+    assert np.max(np.abs(a["mom"][:, 2:, 6:] - b["mom"][:, 2:, 6:])) > 1e-9
+    assert np.max(np.abs(a["mom"][:, :, :2] - b["mom"][:, :, :2])) < 0.5
