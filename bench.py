@@ -111,6 +111,36 @@ def cpu_baseline(prob, x0, v, seconds):
                       f"T={prob['T']}) in {el:.1f} s, split over K across {nthreads} threads"}
 
 
+def bench_resampling(bss, W, torch, steps=20, warmup=3):
+    """The paper-scale workload with the Gaussian re-sampling reading of Alg. 2 (particles redrawn
+    from the mean and full covariance at every step)."""
+    prob, x0, v = W.config_paper_scale()
+    prob = dict(prob, belief=1)
+    rs = prob["K"] * prob["M"] * prob["T"]
+    s = bss.Solver(prob)
+    s.set_outputs(controls=False)
+    x0_dev = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        s.solve_async(x0_dev)
+        s.step_shift()
+    torch.cuda.synchronize()
+    s.timing(True)
+    s.timing_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.solve_async(x0_dev)
+        s.step_shift()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms, n = s.timing_read()
+    info = s.info()
+    s.close()
+    return {"workload": "paper-scale solve with Gaussian re-sampling every step (K=4096, M=64, "
+                        "T=50)",
+            "value": rs * steps / el, "unit": "rollout-steps/s", "ms_per_step": el * 1e3 / steps,
+            "kernel_ms": kms / max(n, 1), "lanes": info["lanes"], "ppl": info["ppl"]}
+
+
 def bench_batched(bss, W, torch, rounds=20, warmup=3):
     """The 64-instance mixed workload (K 512..8192, M 16..256, T 20..80, own track and disturbance
     per instance): one batched solve of every instance per round, replayed from a captured graph
@@ -310,6 +340,8 @@ def main():
                        "mode": "plain synchronous solve from host inputs"},
     }
     progress(f"single solve: {value:.3e} rollout-steps/s, kernel {kernel_ms:.4f} ms")
+    out["resampling"] = bench_resampling(bss, W, torch)
+    progress(f"re-sampling variant: {out['resampling']['value']:.3e} rollout-steps/s")
     if not args.no_batched:
         out["batched"] = bench_batched(bss, W, torch)
         progress(f"mixed batch: {out['batched']['batched']['value']:.3e} rollout-steps/s")

@@ -61,6 +61,10 @@ typedef enum bss_status {
  *   r(u) = -h(f(xbar_t, u); sigma_t) + (1 - gamma) h_t of each sampled control, g = dr/du by
  *   central differences of step shield_fd; 0 iterations disables it.
  * Launch shape: lanes = lanes per sample (8, 16, 32 or 64), 0 = choose automatically.
+ * Belief propagation (Alg. 2): belief = 0 carries M persistent particles through the steps;
+ *   belief = 1 redraws them at every step t >= 1 from N(xbar_t, Sigma_t), the mean and full 6x6
+ *   sample covariance of the current set (standard normals from Philox tags 4 and 5), before
+ *   propagating them.
  */
 typedef struct bss_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
@@ -76,6 +80,7 @@ typedef struct bss_params {
     double shield_gmin, shield_fd;
     uint64_t seed;
     int32_t lanes;
+    int32_t belief;
 } bss_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a

@@ -41,6 +41,7 @@ class BssParams(C.Structure):
         ("shield_iters", C.c_int32), ("shield_gmin", C.c_double), ("shield_fd", C.c_double),
         ("seed", C.c_uint64),
         ("lanes", C.c_int32),
+        ("belief", C.c_int32),
     ]
 
 

@@ -144,6 +144,7 @@ InstanceDesc make_desc(const bss_params& p)
     d.sig_w0 = (float)p.sigma_w[0];
     d.sig_w1 = (float)p.sigma_w[1];
     d.sig_w2 = (float)p.sigma_w[2];
+    d.belief = p.belief;
     d.car = make_car(p);
     d.sc = make_score(p);
     return d;
@@ -193,6 +194,7 @@ struct bss_batch {
     double* d_x0;             // [n][6]
     int nblocks, ncols, ppl, shift_after;
     bool split;               // 512-thread blocks with noise-producing waves
+    bool resample;            // some member redraws its particles every step
     std::vector<int> lanes;   // lanes per sample of each member in the current layout
     size_t lds;
     bool shield;
@@ -227,7 +229,7 @@ hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
-    c->shape.split = c->shape.split && c->p.shield_iters == 0;
+    c->shape.split = c->shape.split && c->p.shield_iters == 0 && c->p.belief == 0;
     c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
     // static leading fields only: the device state is left as it is
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
@@ -294,6 +296,7 @@ void bss_params_default(bss_params* p)
     p->delta = 0.05;
     p->gamma = 0.2;
     p->backoff = 0;
+    p->belief = 0;
     p->lambda = 1.0;
     p->gamma_u = 1.0;
     p->v_goal = 6.0;
@@ -326,6 +329,7 @@ bss_status bss_validate(const bss_params* p)
     if (!(p->gamma > 0.0 && p->gamma <= 1.0))
         return fail(BSS_E_INVAL, "gamma=%g outside (0, 1]", p->gamma);
     if (p->backoff != 0 && p->backoff != 1) return fail(BSS_E_INVAL, "backoff must be 0 or 1");
+    if (p->belief != 0 && p->belief != 1) return fail(BSS_E_INVAL, "belief must be 0 or 1");
     if (!finite_pos(p->lambda)) return fail(BSS_E_INVAL, "lambda must be finite and > 0");
     if (!finite_pos(p->dt)) return fail(BSS_E_INVAL, "dt must be finite and > 0");
     if (!finite_pos(p->m) || !finite_pos(p->Iz) || !finite_pos(p->lf) || !finite_pos(p->lr))
@@ -511,8 +515,8 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
     e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
-                     c->p.shield_iters > 0, c->shape.split, c->lds, x0_dev, Sigma0_dev,
-                     c->pending_shift, c->stream);
+                     c->p.shield_iters > 0, c->shape.split, c->p.belief == 1, c->lds, x0_dev,
+                     Sigma0_dev, c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
         e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
@@ -801,7 +805,7 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
     // split blocks (noise generated by a second set of waves) when asked, or automatically when
     // the whole grid has fewer than two waves per SIMD; every member's ring must fit
     bool sp = split > 0 || (split < 0 && (int64_t)blocks.size() * 4 < 2 * 1024);
-    sp = sp && !b->shield;
+    sp = sp && !b->shield && !b->resample;
     for (int i = 0; i < b->n && sp; ++i)
         sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppl, true) <= kMaxLds;
     for (int i = 0; i < b->n; ++i)
@@ -832,7 +836,7 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
 static hipError_t batch_enqueue(bss_batch* b)
 {
     hipError_t e = launch_solve(b->d_desc, b->d_blocks, b->nblocks, b->ppl, b->shield,
-                                b->split, b->lds,
+                                b->split, b->resample, b->lds,
                                 b->d_x0, nullptr, 0, b->stream);
     if (e == hipSuccess) e = launch_merge(b->d_desc, b->d_cols, b->ncols, 0, b->stream);
     return e;
@@ -879,11 +883,13 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     b->captured = false;
     b->block = nullptr;
     b->shield = false;
+    b->resample = false;
     size_t nb = 0, nc = 0;
     for (int i = 0; i < n; ++i) {
         nb += max_blocks(ctxs[i]->p.K);
         nc += 2 * (size_t)ctxs[i]->p.T;
         b->shield = b->shield || ctxs[i]->p.shield_iters > 0;
+        b->resample = b->resample || ctxs[i]->p.belief == 1;
     }
     const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));
     const size_t total = 2 * sz_desc + align256(nb * sizeof(BlockDesc)) +
@@ -1049,7 +1055,7 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
     const int cands[] = {1, 2, 4, 8};
     for (int cand : cands) {
         if ((M_max + cand - 1) / cand > 64) continue;
-        for (int sp = 0; sp <= (b->shield ? 0 : 1) && e == hipSuccess; ++sp) {
+        for (int sp = 0; sp <= ((b->shield || b->resample) ? 0 : 1) && e == hipSuccess; ++sp) {
             e = batch_layout(b, cand, sp);
             if (e != hipSuccess) break;
             if ((sp == 1) != b->split) continue;   // the split ring does not fit this batch

@@ -26,6 +26,8 @@ constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 constexpr uint32_t kTagEps = 0u;
 constexpr uint32_t kTagW = 1u;
 constexpr uint32_t kTagInit = 2u;
+constexpr uint32_t kTagResample0 = 4u;   // normals xi_0..2 of a Gaussian re-sampling draw
+constexpr uint32_t kTagResample1 = 5u;   // normals xi_3..5
 
 __device__ __forceinline__ uint32_t rng_word3(uint32_t tag, uint32_t s)
 {

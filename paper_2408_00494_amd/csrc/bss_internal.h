@@ -56,6 +56,8 @@ struct InstanceDesc {
     uint32_t done;                 // merge blocks finished in the current launch
     int32_t shift_after;           // 1: leave one warm-start shift pending after the solve
     int32_t status;                // 0 ok, 5 no finite cost (v unchanged)
+    int32_t belief;                // 0 persistent particles, 1 Gaussian re-sampling every step
+    int32_t pad_;
     // random numbers and model
     uint32_t key0, key1;           // Philox key = (lo32 seed, hi32 seed)
     float steer_max, accel_max;
@@ -113,8 +115,9 @@ int solve_blocks(int K, int lanes);
 // per instance at x0_index), Sigma0_base the covariances (36 doubles) or nullptr; extra_shift is
 // added to every instance's pending shift for this launch.
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
-                        bool shield, bool split, size_t lds, const double* x0_base,
-                        const double* Sigma0_base, int extra_shift, hipStream_t stream);
+                        bool shield, bool split, bool resample, size_t lds,
+                        const double* x0_base, const double* Sigma0_base, int extra_shift,
+                        hipStream_t stream);
 hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
                         int extra_shift, hipStream_t stream);
 

@@ -37,6 +37,32 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float d)
 }
 
 // Cholesky factor of the state-estimate covariance, per lane (6x6, semi-definite tolerated).
+// Semi-definite factor for the Gaussian re-sampling draw: as chol6, but a pivot
+// d <= 1e-10 A_jj + 1e-24 counts as zero (variances at the rounding level of an exactly degenerate
+// particle set are not amplified).  Fully unrolled so that A and L stay in registers.
+__device__ __forceinline__ void chol_psd6(const double (&A)[6][6], double (&L)[6][6])
+{
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) L[i][j] = 0.0;
+        double d = A[j][j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
+        if (d > 1e-10 * A[j][j] + 1e-24) {
+            const double ljj = sqrt(d);
+            L[j][j] = ljj;
+#pragma unroll
+            for (int i = j + 1; i < 6; ++i) {
+                double acc = A[i][j];
+#pragma unroll
+                for (int q = 0; q < j; ++q) acc -= L[i][q] * L[j][q];
+                L[i][j] = acc / ljj;
+            }
+        }
+    }
+}
+
 __device__ inline void chol6(const double* A, double* L)
 {
     for (int i = 0; i < 36; ++i) L[i] = 0.0;
@@ -260,6 +286,111 @@ __device__ __forceinline__ void produce_noise(float* ring, int t, int q, const P
     }
 }
 
+// Gaussian re-sampling of Alg. 2 as printed: the particles of step t are redrawn as
+// xbar_t + L_t xi with xbar_t and the unbiased full 6x6 covariance of the current set of the
+// sample (FP64 group sums of the components shifted by particle 0: 6 sums and 21 products) and
+// L_t its semi-definite factor; xi are six standard normals from tags 4 and 5 with counter
+// (t, m, k).  Positions and heading stay compensated pairs relative to the estimate.
+template <int P, int L>
+__device__ __forceinline__ void resample_particles(int t, int j, int k, int M, uint32_t s,
+                                                   uint32_t key0, uint32_t key1,
+                                                   const double* x0, float* Xs, float* Xc,
+                                                   float* Ys, float* Yc, float* Ps, float* Pc,
+                                                   float* vx, float* vy, float* vr)
+{
+    double ref[6];
+    ref[0] = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
+    ref[1] = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
+    ref[2] = (double)group_first(Ps[0], L) - (double)group_first(Pc[0], L);
+    ref[3] = (double)group_first(vx[0], L);
+    ref[4] = (double)group_first(vy[0], L);
+    ref[5] = (double)group_first(vr[0], L);
+    double sd[6], sq[6][6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        sd[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) sq[a][b] = 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (j + p * L < M) {
+            double dv[6];
+            dv[0] = ((double)Xs[p] - (double)Xc[p]) - ref[0];
+            dv[1] = ((double)Ys[p] - (double)Yc[p]) - ref[1];
+            dv[2] = ((double)Ps[p] - (double)Pc[p]) - ref[2];
+            dv[3] = (double)vx[p] - ref[3];
+            dv[4] = (double)vy[p] - ref[4];
+            dv[5] = (double)vr[p] - ref[5];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                sd[a] += dv[a];
+#pragma unroll
+                for (int b = 0; b <= a; ++b) sq[a][b] = fma(dv[a], dv[b], sq[a][b]);
+            }
+        }
+    }
+    const double invM = 1.0 / (double)M;
+    const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
+    double mean[6], cov[6][6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sd[a] = group_sum(sd[a], L);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        mean[a] = ref[a] + sd[a] * invM;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const double c = (group_sum(sq[a][b], L) - sd[a] * (sd[b] * invM)) * invM1;
+            cov[a][b] = c;
+            cov[b][a] = c;
+        }
+    }
+    double Lf[6][6];
+    chol_psd6(cov, Lf);
+    const uint32_t c3a = rng_word3(kTagResample0, s), c3b = rng_word3(kTagResample1, s);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t m = (uint32_t)(j + p * L);
+        double xi[6];
+        {
+            uint32_t c0 = (uint32_t)t, c1 = m, c2 = (uint32_t)k, c3 = c3a;
+            philox10(c0, c1, c2, c3, key0, key1);
+            float z0, z1;
+            bm_pair(c0, c1, z0, z1);
+            xi[0] = z0;
+            xi[1] = z1;
+            xi[2] = bm_cos(c2, c3);
+        }
+        {
+            uint32_t c0 = (uint32_t)t, c1 = m, c2 = (uint32_t)k, c3 = c3b;
+            philox10(c0, c1, c2, c3, key0, key1);
+            float z0, z1;
+            bm_pair(c0, c1, z0, z1);
+            xi[3] = z0;
+            xi[4] = z1;
+            xi[5] = bm_cos(c2, c3);
+        }
+        double dev[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double acc = mean[a];
+#pragma unroll
+            for (int b = 0; b <= a; ++b) acc = fma(Lf[a][b], xi[b], acc);
+            dev[a] = acc;
+        }
+        Xs[p] = (float)dev[0];
+        Xc[p] = (float)((double)Xs[p] - dev[0]);
+        Ys[p] = (float)dev[1];
+        Yc[p] = (float)((double)Ys[p] - dev[1]);
+        Ps[p] = (float)dev[2];
+        Pc[p] = (float)((double)Ps[p] - dev[2]);
+        vx[p] = (float)dev[3];
+        vy[p] = (float)dev[4];
+        vr[p] = (float)dev[5];
+    }
+    (void)x0;
+}
+
 // One solve block with L lanes per sample (L is a compile-time constant so that the group
 // reductions are straight-line DPP sequences).
 //
@@ -268,13 +399,14 @@ __device__ __forceinline__ void produce_noise(float* ring, int t, int q, const P
 // puts two waves on every SIMD when a launch has too few samples to fill the chip otherwise (a
 // lone wave issues at about half the SIMD's rate); the arithmetic and its order are unchanged, so
 // the results are bitwise the same as without the split.
-template <int P, bool SHIELD, int L, bool SPLIT>
+template <int P, bool SHIELD, int L, bool SPLIT, bool RESAMPLE>
 __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDesc bd,
                                             const double* __restrict__ x0_base,
                                             const double* __restrict__ Sigma0_base,
                                             int extra_shift)
 {
     static_assert(!(SPLIT && SHIELD), "the shielded loop is not split");
+    static_assert(!(SPLIT && RESAMPLE), "the re-sampling loop is not split");
     constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
     constexpr int groups = 256 >> log2L;
     const int T = d.T, M = d.M;
@@ -434,6 +566,9 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         if (d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = uu;
                     }
                 }
+                if (RESAMPLE && d.belief == 1 && t > 0)
+                    resample_particles<P, L>(t, j, k, M, s, key0, key1, x0, Xs, Xc, Ys, Yc, Ps, Pc,
+                                             vx, vy, vr);
                 const StepF32 st = make_step(car, uu.x, uu.y);
                 PhiloxStep ps{};
                 if (!SPLIT) ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
@@ -548,19 +683,28 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 
 // Solve grid: every block looks up its instance and first sample; the lane count is uniform over
 // a block, so the dispatch below is a block-uniform branch.
-template <int P, bool SHIELD, bool SPLIT>
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE>
 __global__ __launch_bounds__(SPLIT ? 512 : 256)
-__attribute__((amdgpu_waves_per_eu(SHIELD ? 2 : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
+__attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE) ? 2
+                                   : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
     const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
     const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
 {
     const BlockDesc bd = blocks[blockIdx.x];
     const InstanceDesc& d = insts[bd.inst];
     switch (d.lanes) {
-    case 8: solve_block<P, SHIELD, 8, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
-    case 16: solve_block<P, SHIELD, 16, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
-    case 32: solve_block<P, SHIELD, 32, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
-    default: solve_block<P, SHIELD, 64, SPLIT>(d, bd, x0_base, Sigma0_base, extra_shift); break;
+    case 8:
+        solve_block<P, SHIELD, 8, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    case 16:
+        solve_block<P, SHIELD, 16, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    case 32:
+        solve_block<P, SHIELD, 32, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    default:
+        solve_block<P, SHIELD, 64, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
     }
 }
 
@@ -832,18 +976,26 @@ __global__ void repair_kernel(ScoreF64 sc, const double* mom, const double* u_in
 
 template <int P>
 hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
-                          bool shield, bool split, size_t lds, const double* x0_base,
-                          const double* Sigma0_base, int extra_shift, hipStream_t stream)
+                          bool shield, bool split, bool resample, size_t lds,
+                          const double* x0_base, const double* Sigma0_base, int extra_shift,
+                          hipStream_t stream)
 {
-    if (shield)
-        hipLaunchKernelGGL((solve_kernel<P, true, false>), dim3(nblocks), dim3(256), lds, stream,
-                           inst, blocks, x0_base, Sigma0_base, extra_shift);
+    const dim3 g(nblocks), b256(256), b512(512);
+    if (shield && resample)
+        hipLaunchKernelGGL((solve_kernel<P, true, false, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (shield)
+        hipLaunchKernelGGL((solve_kernel<P, true, false, false>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (resample)
+        hipLaunchKernelGGL((solve_kernel<P, false, false, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
     else if (split)
-        hipLaunchKernelGGL((solve_kernel<P, false, true>), dim3(nblocks), dim3(512), lds, stream,
-                           inst, blocks, x0_base, Sigma0_base, extra_shift);
+        hipLaunchKernelGGL((solve_kernel<P, false, true, false>), g, b512, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
     else
-        hipLaunchKernelGGL((solve_kernel<P, false, false>), dim3(nblocks), dim3(256), lds, stream,
-                           inst, blocks, x0_base, Sigma0_base, extra_shift);
+        hipLaunchKernelGGL((solve_kernel<P, false, false, false>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
     return hipGetLastError();
 }
 
@@ -913,20 +1065,25 @@ int solve_blocks(int K, int lanes)
 }
 
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
-                        bool shield, bool split, size_t lds, const double* x0_base,
-                        const double* Sigma0_base, int extra_shift, hipStream_t stream)
+                        bool shield, bool split, bool resample, size_t lds,
+                        const double* x0_base, const double* Sigma0_base, int extra_shift,
+                        hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    split = split && !shield;
+    split = split && !shield && !resample;
     switch (ppl) {
-    case 1: return launch_solve_p<1>(inst, blocks, nblocks, shield, split, lds, x0_base,
-                                     Sigma0_base, extra_shift, stream);
-    case 2: return launch_solve_p<2>(inst, blocks, nblocks, shield, split, lds, x0_base,
-                                     Sigma0_base, extra_shift, stream);
-    case 4: return launch_solve_p<4>(inst, blocks, nblocks, shield, split, lds, x0_base,
-                                     Sigma0_base, extra_shift, stream);
-    case 8: return launch_solve_p<8>(inst, blocks, nblocks, shield, split, lds, x0_base,
-                                     Sigma0_base, extra_shift, stream);
+    case 1:
+        return launch_solve_p<1>(inst, blocks, nblocks, shield, split, resample, lds,
+                                    x0_base, Sigma0_base, extra_shift, stream);
+    case 2:
+        return launch_solve_p<2>(inst, blocks, nblocks, shield, split, resample, lds,
+                                    x0_base, Sigma0_base, extra_shift, stream);
+    case 4:
+        return launch_solve_p<4>(inst, blocks, nblocks, shield, split, resample, lds,
+                                    x0_base, Sigma0_base, extra_shift, stream);
+    case 8:
+        return launch_solve_p<8>(inst, blocks, nblocks, shield, split, resample, lds,
+                                    x0_base, Sigma0_base, extra_shift, stream);
     default: return hipErrorInvalidValue;
     }
 }

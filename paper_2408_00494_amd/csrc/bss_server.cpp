@@ -163,7 +163,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     sl.vehicles.clear();
     std::vector<double> x0s;
     size_t used = 0, lds = 0;
-    bool shield = false, ring_fits = true;
+    bool shield = false, ring_fits = true, resample = false;
     // pick requests oldest first; skip a vehicle already in flight or already seen in this scan
     std::deque<Request>& pend = s->pending;
     std::vector<size_t> taken;
@@ -208,6 +208,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         lds = std::max(lds, solve_lds_bytes(sh.lanes, T, s->ppl, false));
         ring_fits = ring_fits && solve_lds_bytes(sh.lanes, T, s->ppl, true) <= kMaxLds;
         shield = shield || v.p.shield_iters > 0;
+        resample = resample || v.p.belief == 1;
         descs.push_back(d);
         append_blocks(blocks, i, r.K, sh.lanes);
         for (int c = 0; c < 2 * T; ++c) cols.push_back(MergeDesc{i, c});
@@ -218,7 +219,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     }
     if (descs.empty()) return BSS_OK;
     // a batch too small to put two waves on every SIMD generates its noise in separate waves
-    const bool split = !shield && ring_fits && (int64_t)blocks.size() * 4 < 2 * 1024;
+    const bool split = !shield && !resample && ring_fits && (int64_t)blocks.size() * 4 < 2 * 1024;
     if (split) {
         size_t l2 = 0;
         for (const InstanceDesc& d : descs)
@@ -242,8 +243,8 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     const InstanceDesc* d_desc = (const InstanceDesc*)(sl.d_region + o_desc);
     if (e == hipSuccess)
         e = launch_solve(d_desc, (const BlockDesc*)(sl.d_region + o_blk), (int)blocks.size(),
-                         s->ppl, shield, split, lds, (const double*)(sl.d_region + o_x0), nullptr,
-                         0, sl.stream);
+                         s->ppl, shield, split, resample, lds,
+                         (const double*)(sl.d_region + o_x0), nullptr, 0, sl.stream);
     if (e == hipSuccess)
         e = launch_merge(d_desc, (const MergeDesc*)(sl.d_region + o_col), (int)cols.size(), 0,
                          sl.stream);

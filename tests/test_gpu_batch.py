@@ -53,6 +53,7 @@ def test_member_equals_solve_alone(ppl):
     base, x0b, _ = W.config_small()
     members.append((dict(base, K=1, M=1, T=1, seed=91), x0b, np.zeros((1, 2))))
     members.append((dict(base, K=37, M=24, T=200, seed=92), x0b, np.zeros((200, 2))))
+    members.append((dict(base, K=300, M=20, T=30, seed=93, belief=1), x0b, np.zeros((30, 2))))
     vs = _warm_starts(members)
     x0s = np.stack([x0 for _, x0, _ in members])
     periods = 3

@@ -408,3 +408,26 @@ def test_non_finite_state_reports_numeric_status():
         solver.solve(np.array([0, np.inf, 0, 5, 0, 0]))
     assert ei.value.status == 1
     solver.close()
+
+
+# ===================== Gaussian re-sampling reading of Alg. 2 (belief = 1) =====================
+@pytest.mark.parametrize("K,M,T,lanes", [(128, 16, 30, 0), (96, 64, 40, 16), (64, 37, 25, 8),
+                                         (40, 128, 20, 32), (1024, 64, 50, 0)])
+def test_resampling_solve_matches_oracle(K, M, T, lanes):
+    prob, x0, _ = W.config_paper_scale()
+    prob = dict(prob, K=K, M=M, T=T, belief=1)
+    v = np.column_stack([0.05 * np.sin(np.arange(T) * 0.4), 0.5 * np.cos(np.arange(T) * 0.3)])
+    _compare_solve(prob, x0, v, s=5, lanes=lanes)
+
+
+def test_resampling_with_one_particle_is_the_persistent_recursion_on_device():
+    prob, x0, v = W.config_small()
+    outs = []
+    for belief in (0, 1):
+        s = bss.Solver(dict(prob, K=64, M=1, belief=belief))
+        s.set_controls(v)
+        s.solve(x0)
+        outs.append((s.get_controls(), s.buffers()["mom"].cpu().numpy()))
+        s.close()
+    assert np.max(np.abs(outs[0][0] - outs[1][0])) <= 1e-12
+    assert np.max(np.abs(outs[0][1] - outs[1][1])) <= 1e-9
