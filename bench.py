@@ -83,6 +83,7 @@ def parse():
                     help="noise-producing waves: -1 automatic, 0 off, 1 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-resampling", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving trace replayed with batching (0 skips serving)")
     ap.add_argument("--plain-seconds", type=float, default=15.0,
@@ -340,8 +341,9 @@ def main():
                        "mode": "plain synchronous solve from host inputs"},
     }
     progress(f"single solve: {value:.3e} rollout-steps/s, kernel {kernel_ms:.4f} ms")
-    out["resampling"] = bench_resampling(bss, W, torch)
-    progress(f"re-sampling variant: {out['resampling']['value']:.3e} rollout-steps/s")
+    if not args.no_resampling:
+        out["resampling"] = bench_resampling(bss, W, torch)
+        progress(f"re-sampling variant: {out['resampling']['value']:.3e} rollout-steps/s")
     if not args.no_batched:
         out["batched"] = bench_batched(bss, W, torch)
         progress(f"mixed batch: {out['batched']['batched']['value']:.3e} rollout-steps/s")

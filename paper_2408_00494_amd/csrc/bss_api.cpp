@@ -893,7 +893,8 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     }
     const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));
     const size_t total = 2 * sz_desc + align256(nb * sizeof(BlockDesc)) +
-                         align256(nc * sizeof(MergeDesc)) + align256((size_t)n * 6 * sizeof(double));
+                         align256(nc * sizeof(MergeDesc)) +
+                         align256((size_t)n * 6 * sizeof(double));
     hipError_t e = hipMalloc(&b->block, total);
     if (e != hipSuccess) {
         b->block = nullptr;

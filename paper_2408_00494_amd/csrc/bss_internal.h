@@ -5,11 +5,11 @@
 //
 // Every solve launch is descriptor-driven: an InstanceDesc in device memory describes one problem
 // (a context), a BlockDesc maps each block of the solve grid to (instance, first sample), and a
-// MergeDesc maps each block of the merge grid to (instance, control entry).  A single context is a
-// batch of one; a batch of uneven instances runs in the same two launches.  The per-solve state
-// (which ping-pong buffer holds the mean sequence, pending warm-start shifts, the solve index) lives
-// in the descriptor and is advanced on the device, so a batched launch can be captured in a graph
-// and replayed.
+// MergeDesc maps each wave of the merge grid to (instance, control entry).  A single context is
+// a batch of one; a batch of uneven instances runs in the same two launches.  The per-solve state
+// (which ping-pong buffer holds the mean sequence, pending warm-start shifts, the solve index)
+// lives in the descriptor and is advanced on the device, so a batched launch can be captured in a
+// graph and replayed.
 #pragma once
 
 #include <hip/hip_runtime.h>

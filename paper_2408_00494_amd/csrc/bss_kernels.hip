@@ -546,7 +546,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         const double o1 = role == 3 ? fd : (role == 4 ? -fd : 0.0);
                         double us0 = uu.x, us1 = uu.y;
                         for (int it = 0; it < sc.shield_iters; ++it) {
-                            // lanes 0-4 of the group evaluate r at u and at the four difference points
+                            // lanes 0-4 of the group evaluate r at u and at the four
+                            // difference points
                             const double rv =
                                 repair_residual(sc, bel, margin2, be.h, us0 + o0, us1 + o1);
                             const double r0 = __shfl(rv, 0, L);
@@ -591,8 +592,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                     }
 
                     float dX1, dY1, dvx1, dvy1, dr1;
-                    car_field_f32(car, st, fmaf(Ps[p], kInv2Pi, rev0), vx[p], vy[p], vr[p], dX1, dY1,
-                                  dvx1, dvy1, dr1);
+                    car_field_f32(car, st, fmaf(Ps[p], kInv2Pi, rev0), vx[p], vy[p], vr[p], dX1,
+                                  dY1, dvx1, dvy1, dr1);
                     const float pm = fmaf(car.half_dt, vr[p], Ps[p]);
                     const float vxm = fmaf(car.half_dt, dvx1, vx[p]);
                     const float vym = fmaf(car.half_dt, dvy1, vy[p]);
@@ -608,7 +609,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                     vr[p] = fmaf(sw2, w2, fmaf(car.dt, dr2, vr[p]));
 
                     if (p == 0) {
-                        // shift for the covariance sums: particle 0 of the sample (lane 0 of the group)
+                        // shift for the covariance sums: particle 0 of the sample (lane 0 of
+                        // the group)
                         refX = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
                         refY = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
                     }
@@ -635,7 +637,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 sXX = group_sum(sXX, L);
                 sXY = group_sum(sXY, L);
                 sYY = group_sum(sYY, L);
-                // moments: sums of positions shifted by particle 0, heading relative to the estimate
+                // moments: sums of positions shifted by particle 0, heading relative to the
+                // estimate
                 const double mX = sX * invM, mY = sY * invM;
                 bel[0] = x0[0] + (refX + mX);
                 bel[1] = x0[1] + (refY + mY);
@@ -750,14 +753,39 @@ __device__ inline void merge_entry(const double* partial, int G, int T, int col,
 {
     const int lane = (int)(threadIdx.x & 63u);
     const int stride = 2 * T + 4;
+    // up to four blocks per lane are loaded in one pass (all loads in flight together); larger
+    // grids fall back to a second pass over the remaining blocks
+    constexpr int kHeld = 4;
+    double hm[kHeld], hz[kHeld], hw[kHeld], hn[kHeld], hc[kHeld];
+#pragma unroll
+    for (int i = 0; i < kHeld; ++i) {
+        const int b = lane + 64 * i;
+        const double* pb = partial + (size_t)(b < G ? b : 0) * stride;
+        hm[i] = b < G ? pb[2 * T + 3] : INFINITY;
+        hz[i] = b < G ? pb[2 * T] : 0.0;
+        hw[i] = b < G ? pb[2 * T + 1] : 0.0;
+        hn[i] = b < G ? pb[2 * T + 2] : 0.0;
+        hc[i] = b < G ? pb[col] : 0.0;
+    }
     m = INFINITY;
-    for (int b = lane; b < G; b += 64) m = fmin(m, partial[(size_t)b * stride + 2 * T + 3]);
+#pragma unroll
+    for (int i = 0; i < kHeld; ++i) m = fmin(m, hm[i]);
+    for (int b = lane + 64 * kHeld; b < G; b += 64)
+        m = fmin(m, partial[(size_t)b * stride + 2 * T + 3]);
     m = wave_reduce(m, MinOp());
     Z = 0.0;
     W2 = 0.0;
     nf = 0.0;
     N = 0.0;
-    for (int b = lane; b < G; b += 64) {
+#pragma unroll
+    for (int i = 0; i < kHeld; ++i) {
+        const double sc = isfinite(hm[i]) ? exp(-(hm[i] - m) / lambda) : 0.0;
+        Z += sc * hz[i];
+        W2 += sc * sc * hw[i];
+        nf += hn[i];
+        N += sc * hc[i];
+    }
+    for (int b = lane + 64 * kHeld; b < G; b += 64) {
         const double* pb = partial + (size_t)b * stride;
         const double mb = pb[2 * T + 3];
         const double sc = isfinite(mb) ? exp(-(mb - m) / lambda) : 0.0;
@@ -797,12 +825,13 @@ __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const M
     InstanceDesc& d = insts[md.inst];
     const int T = d.T, col = md.col;
     const int cur = d.cur;
+    // the entry's current mean value is loaded before the reduction so the load overlaps it
+    const int r = vrow(col >> 1, d.vshift + extra_shift, T);
+    const double vi = d.v[cur][2 * r + (col & 1)];
     double m, Z, W2, nf, N;
     merge_entry(d.partial, d.nblocks, T, col, d.sc.lambda, m, Z, W2, nf, N);
     if ((threadIdx.x & 63u) == 0) {
         const bool ok = nf > 0.0 && Z > 0.0;
-        const int r = vrow(col >> 1, d.vshift + extra_shift, T);
-        const double vi = d.v[cur][2 * r + (col & 1)];
         const double vo = ok ? vi + N / Z : vi;
         d.v[1 - cur][col] = vo;
         write_stats(d.stats, col, vo, ok, m, Z, W2, nf);

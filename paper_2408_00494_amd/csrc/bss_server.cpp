@@ -72,7 +72,8 @@ double now_s()
 size_t scratch_bytes(int K, int T, int lanes)
 {
     const size_t blocks = (size_t)solve_blocks(K, lanes);
-    return align256((size_t)K * (T + 1) * 9 * sizeof(double)) + align256((size_t)K * sizeof(double)) +
+    return align256((size_t)K * (T + 1) * 9 * sizeof(double)) +
+           align256((size_t)K * sizeof(double)) +
            align256(blocks * (2 * (size_t)T + 4) * sizeof(double));
 }
 
@@ -312,9 +313,11 @@ bss_status bss_server_create(const bss_server_config* cfg, const bss_params* veh
         return fail(BSS_E_INVAL, "M_max=%d needs more than 64 lanes with %d particles per lane",
                     c.M_max, ppl);
     if (c.n_streams < 1 || c.n_streams > 16) return fail(BSS_E_INVAL, "n_streams must be 1..16");
-    if (c.max_batch < 1 || c.max_batch > 4096) return fail(BSS_E_INVAL, "max_batch must be 1..4096");
+    if (c.max_batch < 1 || c.max_batch > 4096)
+        return fail(BSS_E_INVAL, "max_batch must be 1..4096");
     size_t worst = 0;
-    for (int lanes = 8; lanes <= 64; lanes *= 2) worst = std::max(worst, scratch_bytes(c.K_max, c.T, lanes));
+    for (int lanes = 8; lanes <= 64; lanes *= 2)
+        worst = std::max(worst, scratch_bytes(c.K_max, c.T, lanes));
     if (c.hbm_budget / (uint64_t)c.n_streams < worst)
         return fail(BSS_E_INVAL, "hbm_budget %llu is below n_streams x %zu bytes (one request of "
                     "K_max per stream)", (unsigned long long)c.hbm_budget, worst);
@@ -369,7 +372,8 @@ bss_status bss_server_create(const bss_server_config* cfg, const bss_params* veh
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc((void**)&sl.d_region, region);
         if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_region, region, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc((void**)&sl.d_stats, (size_t)c.max_batch * 8 * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&sl.d_stats, (size_t)c.max_batch * 8 * sizeof(double));
         if (e == hipSuccess)
             e = hipHostMalloc((void**)&sl.h_stats, (size_t)c.max_batch * 8 * sizeof(double),
                               hipHostMallocDefault);
