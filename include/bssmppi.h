@@ -65,6 +65,9 @@ typedef enum bss_status {
  *   belief = 1 redraws them at every step t >= 1 from N(xbar_t, Sigma_t), the mean and full 6x6
  *   sample covariance of the current set (standard normals from Philox tags 4 and 5), before
  *   propagating them.
+ * Disturbance variants: crn = 1 gives every sample the same disturbance draws (common random
+ *   numbers: the counter's sample word is 0); sigma_w_speed = kappa makes the disturbance depend
+ *   on the state, p(w | x) with std sigma_w (1 + kappa |vx|) at the step's starting state.
  */
 typedef struct bss_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
@@ -81,6 +84,8 @@ typedef struct bss_params {
     uint64_t seed;
     int32_t lanes;
     int32_t belief;
+    int32_t crn;
+    double sigma_w_speed;
 } bss_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a

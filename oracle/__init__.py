@@ -36,6 +36,8 @@ class OrcParams(C.Structure):
         ("shield_iters", C.c_int32), ("shield_gmin", C.c_double), ("shield_fd", C.c_double),
         ("seed", C.c_uint64),
         ("belief", C.c_int32),
+        ("crn", C.c_int32),
+        ("sigma_w_speed", C.c_double),
         ("model", C.c_int32),
         ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
     ]

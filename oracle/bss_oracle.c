@@ -480,20 +480,24 @@ static void resample_particles(const orc_params* p, uint32_t s, int32_t k, int t
 }
 
 /* One step of Alg. 2 with persistent particles: x^n_{t+1} = f(x^n_t, u_t) + [0,0,0, w^n_t]
- * (w from tag 1), then the moments of the new particle set. */
+ * (w from tag 1), then the moments of the new particle set.  The disturbance may depend on the
+ * state (p(w|x)): its std is sigma_w (1 + kappa |vx^n_t|); with common random numbers every sample
+ * draws it with counter word k = 0. */
 static void propagate_step(const orc_params* p, uint32_t s, int32_t k, int t, const double u[2],
                            double* part, double* nxt, double* mom_next)
 {
     uint32_t ctr[4];
     double z[4];
     int M = p->M;
+    uint32_t kw = p->crn ? 0u : (uint32_t)k;
     for (int m = 0; m < M; ++m) {
+        double scale = 1.0 + p->sigma_w_speed * fabs(part[m * 6 + 3]);
         orc_model_step(p, &part[m * 6], u, &nxt[m * 6]);
-        rng_counter((uint32_t)t, (uint32_t)m, (uint32_t)k, 1u, s, ctr);
+        rng_counter((uint32_t)t, (uint32_t)m, kw, 1u, s, ctr);
         orc_normals(p->seed, ctr, z);
-        nxt[m * 6 + 3] += p->sigma_w[0] * z[0];
-        nxt[m * 6 + 4] += p->sigma_w[1] * z[1];
-        nxt[m * 6 + 5] += p->sigma_w[2] * z[2];
+        nxt[m * 6 + 3] += p->sigma_w[0] * scale * z[0];
+        nxt[m * 6 + 4] += p->sigma_w[1] * scale * z[1];
+        nxt[m * 6 + 5] += p->sigma_w[2] * scale * z[2];
     }
     memcpy(part, nxt, sizeof(double) * 6 * (size_t)M);
     orc_moments(part, M, mom_next);

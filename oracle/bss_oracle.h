@@ -51,6 +51,8 @@ typedef struct orc_params {
     double shield_gmin, shield_fd;
     uint64_t seed;
     int32_t belief;       /* 0 persistent particles, 1 Gaussian re-sampling every step */
+    int32_t crn;          /* 1: every sample draws the same disturbances (counter word k = 0) */
+    double sigma_w_speed; /* kappa: disturbance std sigma_w (1 + kappa |vx|) at the step's state */
     int32_t model;
     double lin_A[36];
     double lin_B[12];

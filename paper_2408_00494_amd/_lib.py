@@ -42,6 +42,8 @@ class BssParams(C.Structure):
         ("seed", C.c_uint64),
         ("lanes", C.c_int32),
         ("belief", C.c_int32),
+        ("crn", C.c_int32),
+        ("sigma_w_speed", C.c_double),
     ]
 
 

@@ -145,6 +145,8 @@ InstanceDesc make_desc(const bss_params& p)
     d.sig_w1 = (float)p.sigma_w[1];
     d.sig_w2 = (float)p.sigma_w[2];
     d.belief = p.belief;
+    d.crn = p.crn;
+    d.sig_w_speed = (float)p.sigma_w_speed;
     d.car = make_car(p);
     d.sc = make_score(p);
     return d;
@@ -297,6 +299,8 @@ void bss_params_default(bss_params* p)
     p->gamma = 0.2;
     p->backoff = 0;
     p->belief = 0;
+    p->crn = 0;
+    p->sigma_w_speed = 0.0;
     p->lambda = 1.0;
     p->gamma_u = 1.0;
     p->v_goal = 6.0;
@@ -330,6 +334,9 @@ bss_status bss_validate(const bss_params* p)
         return fail(BSS_E_INVAL, "gamma=%g outside (0, 1]", p->gamma);
     if (p->backoff != 0 && p->backoff != 1) return fail(BSS_E_INVAL, "backoff must be 0 or 1");
     if (p->belief != 0 && p->belief != 1) return fail(BSS_E_INVAL, "belief must be 0 or 1");
+    if (p->crn != 0 && p->crn != 1) return fail(BSS_E_INVAL, "crn must be 0 or 1");
+    if (!finite_nonneg(p->sigma_w_speed))
+        return fail(BSS_E_INVAL, "sigma_w_speed must be finite and >= 0");
     if (!finite_pos(p->lambda)) return fail(BSS_E_INVAL, "lambda must be finite and > 0");
     if (!finite_pos(p->dt)) return fail(BSS_E_INVAL, "dt must be finite and > 0");
     if (!finite_pos(p->m) || !finite_pos(p->Iz) || !finite_pos(p->lf) || !finite_pos(p->lr))

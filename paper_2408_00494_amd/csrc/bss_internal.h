@@ -57,12 +57,13 @@ struct InstanceDesc {
     int32_t shift_after;           // 1: leave one warm-start shift pending after the solve
     int32_t status;                // 0 ok, 5 no finite cost (v unchanged)
     int32_t belief;                // 0 persistent particles, 1 Gaussian re-sampling every step
-    int32_t pad_;
+    int32_t crn;                   // 1: disturbance counters use sample word 0 for every sample
     // random numbers and model
     uint32_t key0, key1;           // Philox key = (lo32 seed, hi32 seed)
     float steer_max, accel_max;
     float sig_eps0, sig_eps1;
     float sig_w0, sig_w1, sig_w2;
+    float sig_w_speed;             // disturbance std factor 1 + sig_w_speed |vx|
     CarF32 car;
     ScoreF64 sc;
     // buffers

@@ -447,9 +447,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
             if (!SHIELD && d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = us[t];
         }
     }
-    // disturbance stream of this lane's particles: the first two Philox rounds are partly shared
+    // disturbance stream of this lane's particles: the first two Philox rounds are partly shared;
+    // with common random numbers every sample draws the stream of sample word 0
     const uint32_t c3w = rng_word3(kTagW, s);
-    const uint64_t pk = (uint64_t)kPhiloxM1 * (uint32_t)k;
+    const uint64_t pk = (uint64_t)kPhiloxM1 * (d.crn ? 0u : (uint32_t)k);
     const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
     if (SPLIT && producer && active) {
         PhiloxParticle pp0[P];
@@ -509,6 +510,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         const float rev0 = (float)(rev0d - rint(rev0d));
         const CarF32 car = d.car;
         const float sw0 = d.sig_w0, sw1 = d.sig_w1, sw2 = d.sig_w2;
+        const float ksp = d.sig_w_speed;
 
         // belief at t = 0 is the given estimate (record 0)
         double bel[9];
@@ -601,6 +603,14 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                     float dX2, dY2, dvx2, dvy2, dr2;
                     car_field_f32(car, st, fmaf(pm, kInv2Pi, rev0), vxm, vym, vrm, dX2, dY2, dvx2,
                                   dvy2, dr2);
+                    if (ksp != 0.0f) {
+                        // state-dependent disturbance: std sigma_w (1 + kappa |vx|) at the step's
+                        // starting state
+                        const float fw = fmaf(ksp, fabsf(vx[p]), 1.0f);
+                        w0 *= fw;
+                        w1 *= fw;
+                        w2 *= fw;
+                    }
                     kahan_add(Xs[p], Xc[p], car.dt * dX2);
                     kahan_add(Ys[p], Yc[p], car.dt * dY2);
                     kahan_add(Ps[p], Pc[p], car.dt * vrm);

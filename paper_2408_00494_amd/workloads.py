@@ -35,8 +35,9 @@ _DEFAULTS = dict(
     # shield repair (0 iterations = off)
     shield_iters=0, shield_gmin=0.05, shield_fd=1.0e-2,
     # random numbers, belief propagation (0 persistent particles, 1 Gaussian re-sampling every
-    # step) and model selector (0 = car)
-    seed=1, belief=0, model=0,
+    # step), common random numbers for the disturbance across samples, speed dependence of the
+    # disturbance std (sigma_w (1 + sigma_w_speed |vx|)) and model selector (0 = car)
+    seed=1, belief=0, crn=0, sigma_w_speed=0.0, model=0,
 )
 
 

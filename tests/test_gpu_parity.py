@@ -346,6 +346,15 @@ def test_noise_split_is_bitwise_identical(K, M, T, ppl):
         assert np.array_equal(a, b)
 
 
+def test_cantelli_backoff_solve_matches_oracle():
+    """Distribution-free back-off nu = sqrt((1 - delta)/delta) (Remark 1) instead of the Gaussian
+    quantile: larger nu, so the barrier binds earlier."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=128, backoff=1, delta=0.1)
+    assert abs(bss.backoff(prob) - 3.0) <= 1e-15
+    _compare_solve(prob, x0, v, s=6)
+
+
 def test_initial_spread_matches_oracle():
     prob, x0, v = W.config_small()
     rng = np.random.default_rng(5)
@@ -431,3 +440,29 @@ def test_resampling_with_one_particle_is_the_persistent_recursion_on_device():
         s.close()
     assert np.max(np.abs(outs[0][0] - outs[1][0])) <= 1e-12
     assert np.max(np.abs(outs[0][1] - outs[1][1])) <= 1e-9
+
+
+# ============== disturbance variants: common random numbers, state-dependent std ==============
+@pytest.mark.parametrize("crn,kappa", [(1, 0.0), (0, 0.15), (1, 0.15)])
+def test_disturbance_variants_match_oracle(crn, kappa):
+    prob, x0, v = W.config_paper_scale()
+    prob = dict(prob, K=512, M=32, T=40, crn=crn, sigma_w_speed=kappa)
+    v = np.column_stack([0.05 * np.sin(np.arange(40) * 0.4), 0.5 * np.cos(np.arange(40) * 0.3)])
+    _compare_solve(prob, x0, v, s=8)
+
+
+def test_common_random_numbers_give_identical_samples_without_control_noise():
+    prob, x0, _ = W.config_small()
+    prob = dict(prob, K=64, sigma_eps=[0.0, 0.0], crn=1)
+    v = np.column_stack([0.05 * np.ones(prob["T"]), 0.5 * np.ones(prob["T"])])
+    s = bss.Solver(prob)
+    s.set_controls(v)
+    s.solve(x0)
+    b = s.buffers()
+    S = b["S"].cpu().numpy()
+    mom = b["mom"].cpu().numpy()
+    assert np.all(S == S[0])
+    assert np.all(mom == mom[0])
+    # v+ = v up to the single-precision storage of the sampled controls
+    assert np.max(np.abs(s.get_controls() - v)) <= 1e-7
+    s.close()

@@ -750,3 +750,49 @@ def test_resampling_changes_a_nonlinear_belief():
     assert np.all(np.isfinite(b["mom"]))
     assert np.max(np.abs(a["mom"][:, 2:, 6:] - b["mom"][:, 2:, 6:])) > 1e-9
     assert np.max(np.abs(a["mom"][:, :, :2] - b["mom"][:, :, :2])) < 0.5
+
+
+# ============== disturbance variants: common random numbers, state-dependent std ==============
+def test_common_random_numbers_leave_sample_zero_unchanged():
+    """With common random numbers every sample draws the disturbance stream of sample 0, so sample
+    0 itself is bit-identical to the independent-stream solve."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=6, M=8, T=10)
+    a = oracle.solve(prob, 4, x0, v[:10])
+    b = oracle.solve(dict(prob, crn=1), 4, x0, v[:10])
+    assert np.array_equal(a["mom"][0], b["mom"][0])
+    assert a["S"][0] == b["S"][0]
+    assert not np.array_equal(a["mom"][1:], b["mom"][1:])
+
+
+def test_common_random_numbers_without_control_noise_give_identical_samples():
+    """No control noise and common disturbances: every sample is the same rollout, all weights are
+    equal and the update returns the mean sequence; independent disturbances separate them."""
+    prob, x0, _ = W.config_small()
+    prob = dict(prob, K=5, M=8, T=12, sigma_eps=[0.0, 0.0], crn=1)
+    v = np.column_stack([0.05 * np.ones(12), 0.5 * np.ones(12)])
+    r = oracle.solve(prob, 0, x0, v)
+    assert np.all(r["S"] == r["S"][0])
+    assert np.all(r["mom"] == r["mom"][0])
+    assert np.max(np.abs(r["v"] - v)) <= 1e-15
+    r2 = oracle.solve(dict(prob, crn=0), 0, x0, v)
+    assert len(set(r2["S"].tolist())) == 5
+
+
+def test_state_dependent_disturbance_scales_the_covariance():
+    """p(w | x) with std sigma_w (1 + kappa |vx|): from a known start every particle has the same
+    vx_0, so the position covariance at t = 2 is the closed form of the linear model with Q scaled
+    by (1 + kappa |vx_0|)^2; kappa = 0 is the plain model."""
+    M = 1 << 16
+    cfg, A, Q = _linear_problem(M, T=2)
+    x0 = np.array([1.0, 2.0, 0.0, 3.0, 0.5, 0.1])
+    kappa = 0.2
+    f0 = 1.0 + kappa * abs(x0[3])
+    mom = oracle.propagate(dict(cfg, sigma_w_speed=kappa), 0, 0, x0, np.zeros((2, 2)))
+    Sig = A @ (f0 * f0 * Q) @ A.T
+    for val, (i, j) in zip(mom[2][6:], ((0, 0), (0, 1), (1, 1))):
+        se = math.sqrt((Sig[i, i] * Sig[j, j] + Sig[i, j] ** 2) / (M - 1))
+        assert abs(val - Sig[i, j]) <= 5 * se + 1e-15
+    base = oracle.propagate(cfg, 0, 0, x0, np.zeros((2, 2)))
+    same = oracle.propagate(dict(cfg, sigma_w_speed=0.0), 0, 0, x0, np.zeros((2, 2)))
+    assert np.array_equal(base, same)
