@@ -64,7 +64,9 @@ typedef enum bss_status {
  * Belief propagation (Alg. 2): belief = 0 carries M persistent particles through the steps;
  *   belief = 1 redraws them at every step t >= 1 from N(xbar_t, Sigma_t), the mean and full 6x6
  *   sample covariance of the current set (standard normals from Philox tags 4 and 5), before
- *   propagating them.
+ *   propagating them; belief = 2 (requires M = 12) replaces the particles by the 12 sigma points
+ *   mean +- sqrt(6) L e_i of the belief (equal weights 1/12), propagated without noise, with the
+ *   disturbance covariance added to the propagated covariance.
  * Disturbance variants: crn = 1 gives every sample the same disturbance draws (common random
  *   numbers: the counter's sample word is 0); sigma_w_speed = kappa makes the disturbance depend
  *   on the state, p(w | x) with std sigma_w (1 + kappa |vx|) at the step's starting state.

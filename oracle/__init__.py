@@ -45,6 +45,8 @@ class OrcParams(C.Structure):
 
 def make_params(cfg: dict) -> OrcParams:
     """Build an ``OrcParams`` from a problem dict (keys as in ``workloads.default_problem``)."""
+    if cfg.get("belief", 0) == 2 and cfg.get("M") != 12:
+        raise ValueError("the sigma-point belief uses M = 12 points")
     p = OrcParams()
     for name, _ in OrcParams._fields_:
         key = "lambda" if name == "lambda_" else name

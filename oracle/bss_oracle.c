@@ -479,6 +479,49 @@ static void resample_particles(const orc_params* p, uint32_t s, int32_t k, int t
     }
 }
 
+/* Sigma-point propagation (the unscented/cubature alternative to Monte Carlo): the belief
+ * (mean, full 6x6 covariance) is represented by the 12 points mean +- sqrt(6) L e_i (L the
+ * semi-definite factor, equal weights 1/12), each propagated through the noise-free model; the
+ * new belief is their weighted mean and covariance plus the disturbance covariance
+ * Q diag(0, 0, 0, sigma_w^2) scaled by the points' mean of (1 + kappa |vx|)^2. */
+static void sigma_points(const double mean[6], const double cov[36], double* part)
+{
+    double L[36];
+    orc_chol_psd6(cov, L);
+    const double r = sqrt(6.0);
+    for (int i = 0; i < 6; ++i)
+        for (int a = 0; a < 6; ++a) {
+            part[i * 6 + a] = mean[a] + r * L[a * 6 + i];
+            part[(6 + i) * 6 + a] = mean[a] - r * L[a * 6 + i];
+        }
+}
+
+static void sigma_step(const orc_params* p, const double u[2], double* part, double* nxt,
+                       double* mom_next, double* cov_next)
+{
+    double mean[6] = {0, 0, 0, 0, 0, 0}, q = 0.0;
+    for (int i = 0; i < 12; ++i) {
+        double sc = 1.0 + p->sigma_w_speed * fabs(part[i * 6 + 3]);
+        q += sc * sc / 12.0;
+        orc_model_step(p, &part[i * 6], u, &nxt[i * 6]);
+    }
+    for (int i = 0; i < 12; ++i)
+        for (int a = 0; a < 6; ++a) mean[a] += nxt[i * 6 + a] / 12.0;
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+            double acc = 0.0;
+            for (int i = 0; i < 12; ++i)
+                acc += (nxt[i * 6 + a] - mean[a]) * (nxt[i * 6 + b] - mean[b]);
+            cov_next[a * 6 + b] = acc / 12.0;
+        }
+    for (int a = 0; a < 3; ++a) cov_next[(3 + a) * 6 + 3 + a] += p->sigma_w[a] * p->sigma_w[a] * q;
+    for (int a = 0; a < 6; ++a) mom_next[a] = mean[a];
+    mom_next[6] = cov_next[0];
+    mom_next[7] = cov_next[1];
+    mom_next[8] = cov_next[7];
+    sigma_points(mean, cov_next, part);
+}
+
 /* One step of Alg. 2 with persistent particles: x^n_{t+1} = f(x^n_t, u_t) + [0,0,0, w^n_t]
  * (w from tag 1), then the moments of the new particle set.  The disturbance may depend on the
  * state (p(w|x)): its std is sigma_w (1 + kappa |vx^n_t|); with common random numbers every sample
@@ -503,6 +546,31 @@ static void propagate_step(const orc_params* p, uint32_t s, int32_t k, int t, co
     orc_moments(part, M, mom_next);
 }
 
+/* Belief at t = 0: Monte-Carlo particles (init_particles), or the sigma points of (x0, Sigma0). */
+static void init_belief(const orc_params* p, uint32_t s, int32_t k, const double x0[6],
+                        const double* Sigma0, const double* L0, double* part, double* mom0,
+                        double* cov)
+{
+    init_particles(p, s, k, x0, Sigma0, L0, part, mom0);
+    if (p->belief == 2) {
+        for (int i = 0; i < 36; ++i) cov[i] = Sigma0 ? Sigma0[i] : 0.0;
+        sigma_points(x0, cov, part);
+    }
+}
+
+/* One step of the belief recursion in the selected reading (persistent particles, re-sampling
+ * or sigma points). */
+static void advance_belief(const orc_params* p, uint32_t s, int32_t k, int t, const double u[2],
+                           double* part, double* nxt, double* mom_next, double* cov)
+{
+    if (p->belief == 2) {
+        sigma_step(p, u, part, nxt, mom_next, cov);
+        return;
+    }
+    if (p->belief == 1 && t > 0) resample_particles(p, s, k, t, part);
+    propagate_step(p, s, k, t, u, part, nxt, mom_next);
+}
+
 /* Sample k of Alg. 1: draw eps_{k,t}, form u = clip(v + eps), optionally repair it, propagate the
  * M persistent particles x^n_{t+1} = f(x^n_t, u_t) + w^n_t through the model (the particle
  * recursion stated with the Monte-Carlo covariance), record the moments, and score. */
@@ -511,11 +579,12 @@ double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const 
                    double* mom_out)
 {
     int M = p->M, T = p->T;
-    double* part = (double*)malloc(sizeof(double) * 6 * (size_t)M);
-    double* nxt = (double*)malloc(sizeof(double) * 6 * (size_t)M);
+    size_t np = (size_t)(M > 12 ? M : 12);   /* sigma points use 12 */
+    double* part = (double*)malloc(sizeof(double) * 6 * np);
+    double* nxt = (double*)malloc(sizeof(double) * 6 * np);
     uint32_t ctr[4];
-    double z[4];
-    init_particles(p, s, k, x0, Sigma0, L0, part, mom_out);
+    double z[4], cov[36];
+    init_belief(p, s, k, x0, Sigma0, L0, part, mom_out, cov);
     for (int t = 0; t < T; ++t) {
         rng_counter((uint32_t)t, 0u, (uint32_t)k, 0u, s, ctr);
         orc_normals(p->seed, ctr, z);
@@ -525,8 +594,7 @@ double orc_rollout(const orc_params* p, double nu, uint32_t s, int32_t k, const 
         orc_repair(p, nu, &mom_out[(size_t)t * ORC_NMOM], u);
         u_out[t * 2 + 0] = u[0];
         u_out[t * 2 + 1] = u[1];
-        if (p->belief == 1 && t > 0) resample_particles(p, s, k, t, part);
-        propagate_step(p, s, k, t, u, part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
+        advance_belief(p, s, k, t, u, part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM], cov);
     }
     free(part);
     free(nxt);
@@ -539,13 +607,14 @@ void orc_propagate(const orc_params* p, uint32_t s, int32_t k, const double x0[6
                    const double* Sigma0, const double* L0, const double* u, double* mom_out)
 {
     int M = p->M, T = p->T;
-    double* part = (double*)malloc(sizeof(double) * 6 * (size_t)M);
-    double* nxt = (double*)malloc(sizeof(double) * 6 * (size_t)M);
-    init_particles(p, s, k, x0, Sigma0, L0, part, mom_out);
-    for (int t = 0; t < T; ++t) {
-        if (p->belief == 1 && t > 0) resample_particles(p, s, k, t, part);
-        propagate_step(p, s, k, t, &u[t * 2], part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM]);
-    }
+    size_t np = (size_t)(M > 12 ? M : 12);   /* sigma points use 12 */
+    double* part = (double*)malloc(sizeof(double) * 6 * np);
+    double* nxt = (double*)malloc(sizeof(double) * 6 * np);
+    double cov[36];
+    init_belief(p, s, k, x0, Sigma0, L0, part, mom_out, cov);
+    for (int t = 0; t < T; ++t)
+        advance_belief(p, s, k, t, &u[t * 2], part, nxt, &mom_out[(size_t)(t + 1) * ORC_NMOM],
+                       cov);
     free(part);
     free(nxt);
 }

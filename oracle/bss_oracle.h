@@ -50,7 +50,8 @@ typedef struct orc_params {
     int32_t shield_iters;
     double shield_gmin, shield_fd;
     uint64_t seed;
-    int32_t belief;       /* 0 persistent particles, 1 Gaussian re-sampling every step */
+    int32_t belief;       /* 0 persistent particles, 1 Gaussian re-sampling every step,
+                             2 sigma points (12-point cubature set, M = 12) */
     int32_t crn;          /* 1: every sample draws the same disturbances (counter word k = 0) */
     double sigma_w_speed; /* kappa: disturbance std sigma_w (1 + kappa |vx|) at the step's state */
     int32_t model;

@@ -333,7 +333,9 @@ bss_status bss_validate(const bss_params* p)
     if (!(p->gamma > 0.0 && p->gamma <= 1.0))
         return fail(BSS_E_INVAL, "gamma=%g outside (0, 1]", p->gamma);
     if (p->backoff != 0 && p->backoff != 1) return fail(BSS_E_INVAL, "backoff must be 0 or 1");
-    if (p->belief != 0 && p->belief != 1) return fail(BSS_E_INVAL, "belief must be 0 or 1");
+    if (p->belief < 0 || p->belief > 2) return fail(BSS_E_INVAL, "belief must be 0, 1 or 2");
+    if (p->belief == 2 && p->M != 12)
+        return fail(BSS_E_INVAL, "the sigma-point belief (belief = 2) uses M = 12 points");
     if (p->crn != 0 && p->crn != 1) return fail(BSS_E_INVAL, "crn must be 0 or 1");
     if (!finite_nonneg(p->sigma_w_speed))
         return fail(BSS_E_INVAL, "sigma_w_speed must be finite and >= 0");
@@ -522,7 +524,7 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
     e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
-                     c->p.shield_iters > 0, c->shape.split, c->p.belief == 1, c->lds, x0_dev,
+                     c->p.shield_iters > 0, c->shape.split, c->p.belief != 0, c->lds, x0_dev,
                      Sigma0_dev, c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
@@ -896,7 +898,7 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
         nb += max_blocks(ctxs[i]->p.K);
         nc += 2 * (size_t)ctxs[i]->p.T;
         b->shield = b->shield || ctxs[i]->p.shield_iters > 0;
-        b->resample = b->resample || ctxs[i]->p.belief == 1;
+        b->resample = b->resample || ctxs[i]->p.belief != 0;
     }
     const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));
     const size_t total = 2 * sz_desc + align256(nb * sizeof(BlockDesc)) +

@@ -291,12 +291,16 @@ __device__ __forceinline__ void produce_noise(float* ring, int t, int q, const P
 // sample (FP64 group sums of the components shifted by particle 0: 6 sums and 21 products) and
 // L_t its semi-definite factor; xi are six standard normals from tags 4 and 5 with counter
 // (t, m, k).  Positions and heading stay compensated pairs relative to the estimate.
+//
+// Sigma points (mode 2, M = 12): the same moments with equal weights 1/12, plus the disturbance
+// covariance diag(0, 0, 0, sigma_w^2) scaled by qbar (the previous points' mean of
+// (1 + kappa |vx|)^2), and the deterministic points mean +- sqrt(6) L e_i instead of the draw.
 template <int P, int L>
 __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, uint32_t s,
-                                                   uint32_t key0, uint32_t key1,
-                                                   const double* x0, float* Xs, float* Xc,
-                                                   float* Ys, float* Yc, float* Ps, float* Pc,
-                                                   float* vx, float* vy, float* vr)
+                                                   uint32_t key0, uint32_t key1, int mode,
+                                                   double qbar, const float* sw, float* Xs,
+                                                   float* Xc, float* Ys, float* Yc, float* Ps,
+                                                   float* Pc, float* vx, float* vy, float* vr)
 {
     double ref[6];
     ref[0] = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
@@ -331,7 +335,7 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
         }
     }
     const double invM = 1.0 / (double)M;
-    const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
+    const double invM1 = mode == 2 ? invM : (M > 1 ? 1.0 / (double)(M - 1) : 0.0);
     double mean[6], cov[6][6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) sd[a] = group_sum(sd[a], L);
@@ -345,6 +349,10 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
             cov[b][a] = c;
         }
     }
+    if (mode == 2) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cov[3 + a][3 + a] += (double)sw[a] * (double)sw[a] * qbar;
+    }
     double Lf[6][6];
     chol_psd6(cov, Lf);
     const uint32_t c3a = rng_word3(kTagResample0, s), c3b = rng_word3(kTagResample1, s);
@@ -352,23 +360,23 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
     for (int p = 0; p < P; ++p) {
         const uint32_t m = (uint32_t)(j + p * L);
         double xi[6];
-        {
-            uint32_t c0 = (uint32_t)t, c1 = m, c2 = (uint32_t)k, c3 = c3a;
-            philox10(c0, c1, c2, c3, key0, key1);
-            float z0, z1;
-            bm_pair(c0, c1, z0, z1);
-            xi[0] = z0;
-            xi[1] = z1;
-            xi[2] = bm_cos(c2, c3);
-        }
-        {
-            uint32_t c0 = (uint32_t)t, c1 = m, c2 = (uint32_t)k, c3 = c3b;
-            philox10(c0, c1, c2, c3, key0, key1);
-            float z0, z1;
-            bm_pair(c0, c1, z0, z1);
-            xi[3] = z0;
-            xi[4] = z1;
-            xi[5] = bm_cos(c2, c3);
+        if (mode == 2) {
+            // selects instead of a runtime index keep xi in registers
+            const double r = m < 6u ? 2.449489742783178 : -2.449489742783178;
+            const uint32_t e = m % 6u;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) xi[a] = (m < 12u && e == (uint32_t)a) ? r : 0.0;
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                uint32_t c0 = (uint32_t)t, c1 = m, c2 = (uint32_t)k, c3 = blk ? c3b : c3a;
+                philox10(c0, c1, c2, c3, key0, key1);
+                float z0, z1;
+                bm_pair(c0, c1, z0, z1);
+                xi[3 * blk + 0] = z0;
+                xi[3 * blk + 1] = z1;
+                xi[3 * blk + 2] = bm_cos(c2, c3);
+            }
         }
         double dev[6];
 #pragma unroll
@@ -388,7 +396,6 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
         vy[p] = (float)dev[4];
         vr[p] = (float)dev[5];
     }
-    (void)x0;
 }
 
 // One solve block with L lanes per sample (L is a compile-time constant so that the group
@@ -472,11 +479,32 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         if (consumer) {
             double L0[36];
             if (spread) chol6(S0p, L0);
+            // sigma points at t = 0: mean +- sqrt(6) L e_i of the given estimate
+            const bool sigma = RESAMPLE && d.belief == 2;
+            double Lp[6][6];
+            if (sigma) {
+                double A[6][6];
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) A[a][b] = spread ? S0p[a * 6 + b] : 0.0;
+                chol_psd6(A, Lp);
+            }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int m = j + p * L;
                 double dev[6] = {0, 0, 0, 0, 0, 0};
-                if (spread) {
+                if (sigma) {
+                    const double r = m < 6 ? 2.449489742783178 : -2.449489742783178;
+                    const int e = m % 6;
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) acc = (m < 12 && e == b) ? r * Lp[a][b] : acc;
+                        dev[a] = acc;
+                    }
+                } else if (spread) {
                     double xi[6];
 #pragma unroll
                     for (int blk = 0; blk < 2; ++blk) {
@@ -527,7 +555,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 #pragma unroll
         for (int p = 0; p < P; ++p) pp[p] = philox_particle((uint32_t)(j + p * L), hk, key0, key1);
         const double invM = 1.0 / (double)M;
-        const double invM1 = M > 1 ? 1.0 / (double)(M - 1) : 0.0;
+        const double invM1 =
+            (RESAMPLE && d.belief == 2) ? invM : (M > 1 ? 1.0 / (double)(M - 1) : 0.0);
+        const float swv[3] = {sw0, sw1, sw2};
+        double qbar = 1.0;      // sigma points: previous points' mean of (1 + kappa |vx|)^2
 
         // In split mode every thread runs every iteration and meets exactly one barrier per step,
         // outside all divergent branches (waves may hold both active and inactive samples).
@@ -569,9 +600,20 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         if (d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = uu;
                     }
                 }
-                if (RESAMPLE && d.belief == 1 && t > 0)
-                    resample_particles<P, L>(t, j, k, M, s, key0, key1, x0, Xs, Xc, Ys, Yc, Ps, Pc,
-                                             vx, vy, vr);
+                if (RESAMPLE && d.belief != 0 && t > 0)
+                    resample_particles<P, L>(t, j, k, M, s, key0, key1, d.belief, qbar, swv, Xs,
+                                             Xc, Ys, Yc, Ps, Pc, vx, vy, vr);
+                if (RESAMPLE && d.belief == 2) {
+                    double qs = 0.0;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if (j + p * L < M) {
+                            const double f = 1.0 + (double)ksp * fabs((double)vx[p]);
+                            qs = fma(f, f, qs);
+                        }
+                    }
+                    qbar = group_sum(qs, L) * invM;
+                }
                 const StepF32 st = make_step(car, uu.x, uu.y);
                 PhiloxStep ps{};
                 if (!SPLIT) ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
@@ -581,7 +623,9 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 for (int p = 0; p < P; ++p) {
                     const int m = j + p * L;
                     float w0, w1, w2;
-                    if (SPLIT) {
+                    if (RESAMPLE && d.belief == 2) {
+                        w0 = w1 = w2 = 0.0f;   // sigma points: the disturbance enters as Q
+                    } else if (SPLIT) {
                         const float* src = ring + (t & 1) * (P * 3 * 256) + q;
                         w0 = src[(p * 3 + 0) * 256];
                         w1 = src[(p * 3 + 1) * 256];

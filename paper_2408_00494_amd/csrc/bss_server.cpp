@@ -209,7 +209,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         lds = std::max(lds, solve_lds_bytes(sh.lanes, T, s->ppl, false));
         ring_fits = ring_fits && solve_lds_bytes(sh.lanes, T, s->ppl, true) <= kMaxLds;
         shield = shield || v.p.shield_iters > 0;
-        resample = resample || v.p.belief == 1;
+        resample = resample || v.p.belief != 0;
         descs.push_back(d);
         append_blocks(blocks, i, r.K, sh.lanes);
         for (int c = 0; c < 2 * T; ++c) cols.push_back(MergeDesc{i, c});

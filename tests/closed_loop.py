@@ -58,9 +58,20 @@ class OracleController:
         return np.array(r["v"][0])
 
 
+def window_stats(series, wT, begin, end):
+    """Aggregate statistics of steps [begin, end) from the per-step series of a run."""
+    ey = np.abs(np.asarray(series["ey"][begin:end]))
+    return {"steps": int(ey.size), "crashes": int(np.sum(series["crash"][begin:end])),
+            "collision_steps": int(np.sum(ey > 0.9 * wT)),
+            "half_width_steps": int(np.sum(ey > 0.5 * wT)),
+            "dcbf_ok": int(np.sum(series["dcbf"][begin:end])), "dcbf_n": int(ey.size),
+            "sum_abs_ey": float(np.sum(ey)), "sum_vx": float(np.sum(series["vx"][begin:end]))}
+
+
 def run(prob, steps, controller, record=False):
     """Closed loop of `steps` plant steps; returns (stats dict, records).  records (if asked) hold
-    (n, x_n, warm start used at n, u0) for every step."""
+    (n, x_n, warm start used at n, u0) for every step; stats["series"] holds the per-step e_y,
+    crash flag, barrier flag and vx."""
     wT, gamma = prob["half_width"], prob["gamma"]
     sw = np.asarray(prob["sigma_w"], dtype=np.float64)
     st = {"steps": 0, "crashes": 0, "collision_steps": 0, "dcbf_ok": 0, "dcbf_n": 0,
@@ -71,6 +82,7 @@ def run(prob, steps, controller, record=False):
     controller.reset()
     h_prev = wT * wT - lateral_deviation(prob, x) ** 2
     recs = []
+    series = {"ey": [], "crash": [], "dcbf": [], "vx": []}
     for n in range(steps):
         v_used = controller.warm_start() if record and hasattr(controller, "warm_start") else None
         u0 = controller.act(x, n)
@@ -87,9 +99,14 @@ def run(prob, steps, controller, record=False):
         st["sum_ey2"] += ey * ey
         st["max_abs_ey"] = max(st["max_abs_ey"], abs(ey))
         st["sum_vx"] += xn[3]
+        crash = not math.isfinite(ey) or abs(ey) > wT
+        series["ey"].append(float(ey))
+        series["crash"].append(int(crash))
+        series["dcbf"].append(int(h >= (1.0 - gamma) * h_prev))
+        series["vx"].append(float(xn[3]))
         if record:
             recs.append((n, x.copy(), v_used, np.array(u0)))
-        if not math.isfinite(ey) or abs(ey) > wT:
+        if crash:
             st["crashes"] += 1
             episode += 1
             st["episodes"] += 1
@@ -99,6 +116,8 @@ def run(prob, steps, controller, record=False):
         else:
             x = xn
             h_prev = h
+    if record:
+        st["series"] = series
     return st, recs
 
 

@@ -109,6 +109,8 @@ def test_validation_accepts_workloads():
     (dict(ell_a=0.0), "semi-axes"), (dict(shield_iters=17), "shield_iters"),
     (dict(lanes=12), "lanes"), (dict(M=200, lanes=8), "particles per lane"),
     (dict(C_obs=float("inf")), "cost weights"), (dict(m=0.0), "m, Iz"),
+    (dict(belief=3), "belief"), (dict(belief=2, M=16), "M = 12"), (dict(crn=2), "crn"),
+    (dict(sigma_w_speed=-0.1), "sigma_w_speed"),
 ])
 def test_validation_rejects(kw, frag):
     st, msg = _validate(**kw)

@@ -3,11 +3,13 @@ combination: 1000 receding-horizon steps of the GPU controller on the FP64 plant
 
 * Lockstep replay: at sampled steps the oracle solves from the GPU run's own plant state, warm
   start and solve index; its command must meet the control bar (max |du| / u_max <= 1e-4).
-* Rates: single- and double-precision closed loops diverge (the dynamics are chaotic at the
-  scale of rounding), so the GPU run's statistics are compared with the oracle controller's
-  (tests/golden/closed_loop_oracle.json) as distributions: two-proportion z-tests at z = 4 for the
-  crash, collision, half-width and barrier rates, and the mean |e_y| and mean speed within
-  stated relative bounds.
+* Rates: the oracle controller's statistics (tests/golden/closed_loop_oracle.json) cover the
+  first 250 steps; the GPU run's same window (same start, same plant noise) is compared with them.
+  Single- and double-precision closed loops drift apart (the dynamics amplify rounding), and
+  consecutive steps are strongly correlated, so the tolerances come from batch means of the GPU
+  series (10 batches of 25 steps): the difference of the half-width fraction and of the mean
+  |e_y| must lie within 4 sqrt(2) batch-means standard errors (plus a small floor); crashes,
+  collision steps and barrier violations must agree as counts within the same kind of bound.
 """
 import json
 import math
@@ -53,11 +55,11 @@ class GpuController:
         self.s.close()
 
 
-def _two_prop_ok(k1, n1, k2, n2, z=4.0):
-    p1, p2 = k1 / n1, k2 / n2
-    p = (k1 + k2) / (n1 + n2)
-    se = math.sqrt(max(p * (1 - p), 1e-12) * (1 / n1 + 1 / n2))
-    return abs(p1 - p2) <= z * se + 1e-12
+def _batch_se(x, nb=10):
+    x = np.asarray(x, dtype=np.float64)
+    m = x.size // nb
+    means = x[:m * nb].reshape(nb, m).mean(axis=1)
+    return float(means.std(ddof=1) / np.sqrt(nb))
 
 
 _runs = {}
@@ -77,7 +79,8 @@ def _gpu_run(i):
 def test_lockstep_replay_against_oracle(i):
     prob, st, recs = _gpu_run(i)
     d, g = CL.COMBOS[i]
-    print(f"GPU closed loop delta={d} gamma={g}: {st}", flush=True)
+    shown = {key: val for key, val in st.items() if key != "series"}
+    print(f"GPU closed loop delta={d} gamma={g}: {shown}", flush=True)
     rng = np.random.default_rng(100 + i)
     scale = np.array([prob["steer_max"], prob["accel_max"]])
     for n in (1, int(rng.integers(2, STEPS))):
@@ -91,20 +94,29 @@ def test_lockstep_replay_against_oracle(i):
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle closed-loop statistics missing")
 @pytest.mark.parametrize("i", range(len(CL.COMBOS)))
 def test_rates_match_oracle_controller(i):
-    prob, st, _ = _gpu_run(i)
+    prob, _, _ = _gpu_run(i)
+    series = _runs[i][1]["series"]
     with open(GOLDEN) as fh:
         gold = json.load(fh)
     ref = [c for c in gold["combos"] if c["seed"] == prob["seed"]]
     if not ref:
         pytest.skip("combination not in the stored statistics")
     ref = ref[0]
-    n1, n2 = st["steps"], ref["steps"]
-    for key in ("crashes", "collision_steps", "half_width_steps"):
-        assert _two_prop_ok(st[key], n1, ref[key], n2), key
-    assert _two_prop_ok(st["dcbf_ok"], st["dcbf_n"], ref["dcbf_ok"], ref["dcbf_n"])
-    m1, m2 = st["sum_abs_ey"] / n1, ref["sum_abs_ey"] / n2
-    assert abs(m1 - m2) <= 0.3 * m2 + 0.02, (m1, m2)
-    s1, s2 = st["sum_vx"] / n1, ref["sum_vx"] / n2
-    assert abs(s1 - s2) <= 0.05 * s2, (s1, s2)
-    print(f"delta={ref['delta']} gamma={ref['gamma']}: mean|e_y| GPU {m1:.4f} oracle {m2:.4f}, "
-          f"mean vx GPU {s1:.3f} oracle {s2:.3f}", flush=True)
+    n = ref["steps"]
+    wT = prob["half_width"]
+    st = CL.window_stats(series, wT, 0, n)
+    ey = np.abs(np.asarray(series["ey"][:n]))
+    k = 4.0 * np.sqrt(2.0)
+    # fractions of steps beyond half the track half-width and beyond the collision threshold
+    for key, thr in (("half_width_steps", 0.5), ("collision_steps", 0.9)):
+        se = _batch_se(ey > thr * wT)
+        assert abs(st[key] - ref[key]) / n <= k * se + 0.02, (key, st[key], ref[key])
+    assert abs(st["crashes"] - ref["crashes"]) <= 2
+    assert abs(st["dcbf_ok"] - ref["dcbf_ok"]) / n <= k * _batch_se(series["dcbf"][:n]) + 0.02
+    m1, m2 = st["sum_abs_ey"] / n, ref["sum_abs_ey"] / n
+    assert abs(m1 - m2) <= k * _batch_se(ey) + 0.02, (m1, m2)
+    s1, s2 = st["sum_vx"] / n, ref["sum_vx"] / n
+    assert abs(s1 - s2) <= k * _batch_se(series["vx"][:n]) + 0.05, (s1, s2)
+    print(f"delta={ref['delta']} gamma={ref['gamma']} first {n} steps: half-width steps GPU "
+          f"{st['half_width_steps']} oracle {ref['half_width_steps']}, mean|e_y| GPU {m1:.4f} "
+          f"oracle {m2:.4f}, mean vx GPU {s1:.3f} oracle {s2:.3f}", flush=True)

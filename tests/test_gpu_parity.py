@@ -466,3 +466,27 @@ def test_common_random_numbers_give_identical_samples_without_control_noise():
     # v+ = v up to the single-precision storage of the sampled controls
     assert np.max(np.abs(s.get_controls() - v)) <= 1e-7
     s.close()
+
+
+# ======================= sigma-point belief propagation (belief = 2) ========================
+@pytest.mark.parametrize("K,T,lanes,kappa", [(128, 30, 0, 0.0), (300, 50, 8, 0.0),
+                                             (64, 40, 16, 0.1)])
+def test_sigma_point_solve_matches_oracle(K, T, lanes, kappa):
+    prob, x0, _ = W.config_paper_scale()
+    prob = dict(prob, K=K, M=12, T=T, belief=2, sigma_w_speed=kappa)
+    v = np.column_stack([0.05 * np.sin(np.arange(T) * 0.4), 0.5 * np.cos(np.arange(T) * 0.3)])
+    _compare_solve(prob, x0, v, s=3, lanes=lanes)
+
+
+def test_sigma_point_solve_with_initial_covariance_matches_oracle():
+    prob, x0, v = W.config_small()
+    rng = np.random.default_rng(8)
+    G = rng.normal(size=(6, 6)) * 0.05
+    Sigma0 = G @ G.T + np.diag([0.02, 0.02, 1e-3, 0.01, 0.01, 1e-3])
+    _compare_solve(dict(prob, K=96, M=12, belief=2), x0, v, s=2, Sigma0=Sigma0)
+
+
+def test_sigma_point_belief_rejects_other_particle_counts():
+    prob, _, _ = W.config_small()
+    with pytest.raises(bss.BssError):
+        bss.Solver(dict(prob, M=16, belief=2))

@@ -796,3 +796,55 @@ def test_state_dependent_disturbance_scales_the_covariance():
     base = oracle.propagate(cfg, 0, 0, x0, np.zeros((2, 2)))
     same = oracle.propagate(dict(cfg, sigma_w_speed=0.0), 0, 0, x0, np.zeros((2, 2)))
     assert np.array_equal(base, same)
+
+
+# ======================= sigma-point belief propagation (belief = 2) ========================
+def test_sigma_points_are_exact_on_the_linear_model():
+    """The 12-point cubature set reproduces the linear-Gaussian recursion exactly (up to rounding):
+    mean A xbar + B u and covariance A Sigma A^T + Q, from a nonzero Sigma_0."""
+    cfg, A, Q = _linear_problem(12, T=6)
+    cfg = dict(cfg, belief=2)
+    x0 = np.array([1.0, 2.0, 0.0, 3.0, 0.5, 0.1])
+    G = np.random.default_rng(1).normal(size=(6, 6)) * 0.1
+    S0 = G @ G.T
+    mom = oracle.propagate(cfg, 0, 0, x0, np.zeros((cfg["T"], 2)), Sigma0=S0)
+    Sig, mean = S0.copy(), x0.copy()
+    for t in range(1, cfg["T"] + 1):
+        Sig = A @ Sig @ A.T + Q
+        mean = A @ mean
+        assert np.max(np.abs(mom[t][:6] - mean)) <= 1e-12 * (1 + np.max(np.abs(mean)))
+        want = np.array([Sig[0, 0], Sig[0, 1], Sig[1, 1]])
+        assert np.max(np.abs(mom[t][6:] - want)) <= 1e-12 * np.max(np.abs(want)) + 1e-24
+
+
+def test_sigma_points_state_dependent_disturbance_closed_form():
+    """With std sigma_w (1 + kappa |vx|) and every point at positive vx, the points' mean of
+    (1 + kappa vx)^2 is (1 + kappa mu)^2 + kappa^2 Sigma_vx, exactly."""
+    cfg, A, Q = _linear_problem(12, T=4)
+    kappa = 0.1
+    cfg = dict(cfg, belief=2, sigma_w_speed=kappa)
+    x0 = np.array([1.0, 2.0, 0.0, 3.0, 0.5, 0.1])
+    mom = oracle.propagate(cfg, 0, 0, x0, np.zeros((cfg["T"], 2)))
+    Sig, mean = np.zeros((6, 6)), x0.copy()
+    for t in range(1, cfg["T"] + 1):
+        scale = (1 + kappa * mean[3]) ** 2 + kappa ** 2 * Sig[3, 3]
+        Sig = A @ Sig @ A.T + scale * Q
+        mean = A @ mean
+        want = np.array([Sig[0, 0], Sig[0, 1], Sig[1, 1]])
+        assert np.max(np.abs(mom[t][6:] - want)) <= 1e-12 * np.max(np.abs(want)) + 1e-24
+
+
+def test_sigma_points_without_uncertainty_are_deterministic_integration():
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=4, T=15, sigma_w=[0.0, 0.0, 0.0])
+    a = oracle.solve(dict(prob, M=1), 2, x0, v[:15])
+    b = oracle.solve(dict(prob, M=12, belief=2), 2, x0, v[:15])
+    assert np.max(np.abs(a["mom"] - b["mom"])) <= 1e-12 * np.max(np.abs(a["mom"]))
+    assert np.max(np.abs(b["mom"][:, :, 6:])) <= 1e-24   # rounding of the points' mean
+    assert np.max(np.abs(a["S"] - b["S"])) <= 1e-12 * np.max(np.abs(a["S"]))
+
+
+def test_sigma_point_belief_needs_twelve_points():
+    prob, x0, v = W.config_small()
+    with pytest.raises(ValueError):
+        oracle.solve(dict(prob, K=2, M=16, belief=2), 0, x0, v)
