@@ -40,8 +40,8 @@ FP32_PEAK = 157.3e12
 # HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a 1 GiB device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "fbcb53a70a81b2af", "lanes": 16,
-                    "fetch_bytes": 7545.125 * 1024 * 2.0, "write_bytes": 15035.9125 * 1024 * 1.0}
+MEASURED_TRAFFIC = {"sources_sha256_16": "3565fabd10dd3b25", "lanes": 16, "ppl": 4, "split": True,
+                    "fetch_bytes": 7612.5 * 1024 * 2.0, "write_bytes": 15036.1 * 1024 * 1.0}
 KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_kernels.hip",
                   "paper_2408_00494_amd/csrc/bss_device.h",
                   "paper_2408_00494_amd/csrc/bss_internal.h"]
@@ -55,15 +55,17 @@ def ALG_BYTES_PER_SOLVE(K, M, T, lanes):
     return 2 * K * (T + 1) * 9 * 8 + K * 8 + blocks * (2 * T + 4) * 8 + T * 2 * 8
 
 
-def measured_traffic(lanes):
-    """Counter-measured HBM bytes per solve-kernel launch, or None if the kernel changed since."""
+def measured_traffic(lanes, ppl, split):
+    """Counter-measured HBM bytes per solve-kernel launch, or None if the kernel or the launch
+    shape changed since."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest()[:16] != MEASURED_TRAFFIC["sources_sha256_16"] or \
-            lanes != MEASURED_TRAFFIC["lanes"]:
+            (lanes, ppl, split) != (MEASURED_TRAFFIC["lanes"], MEASURED_TRAFFIC["ppl"],
+                                    MEASURED_TRAFFIC["split"]):
         return None
     return MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
 
@@ -303,7 +305,7 @@ def main():
     value = rs_per_solve * args.steps / elapsed
     kernel_ms = kernel_ms_total / max(n_meas, 1)
     slots = SLOTS_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3)
-    traffic = measured_traffic(info["lanes"])
+    traffic = measured_traffic(info["lanes"], info["ppl"], info["split"])
 
     # plain synchronous solves from host inputs (latency of one control period)
     lat = []
