@@ -40,8 +40,8 @@ FP32_PEAK = 157.3e12
 # HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a 1 GiB device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "3565fabd10dd3b25", "lanes": 16, "ppl": 4, "split": True,
-                    "fetch_bytes": 7612.5 * 1024 * 2.0, "write_bytes": 15036.1 * 1024 * 1.0}
+MEASURED_TRAFFIC = {"sources_sha256_16": "f664617384ed22bc", "lanes": 16, "ppl": 4, "split": True,
+                    "fetch_bytes": 7641.4 * 1024 * 2.0, "write_bytes": 15035.5 * 1024 * 1.0}
 KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_kernels.hip",
                   "paper_2408_00494_amd/csrc/bss_device.h",
                   "paper_2408_00494_amd/csrc/bss_internal.h"]

@@ -67,6 +67,11 @@ typedef enum bss_status {
  *   propagating them; belief = 2 (requires M = 12) replaces the particles by the 12 sigma points
  *   mean +- sqrt(6) L e_i of the belief (equal weights 1/12), propagated without noise, with the
  *   disturbance covariance added to the propagated covariance.
+ * Obstacles: n_obs (0..4) circular obstacles, obs[3i..3i+2] = centre x, y and radius, each a
+ *   further chance constraint (eq. 16: h = min over the constraints): with d the distance of the
+ *   mean position to the centre and sigma the spread along the direction from the centre,
+ *   h_i = max(d - nu sigma, 0)^2 - r^2 (the quadratic form of eq. 33), and the collision indicator
+ *   adds C_obs while the mean is inside.
  * Disturbance variants: crn = 1 gives every sample the same disturbance draws (common random
  *   numbers: the counter's sample word is 0); sigma_w_speed = kappa makes the disturbance depend
  *   on the state, p(w | x) with std sigma_w (1 + kappa |vx|) at the step's starting state.
@@ -88,6 +93,8 @@ typedef struct bss_params {
     int32_t belief;
     int32_t crn;
     double sigma_w_speed;
+    int32_t n_obs;
+    double obs[12];
 } bss_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a

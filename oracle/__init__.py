@@ -38,6 +38,7 @@ class OrcParams(C.Structure):
         ("belief", C.c_int32),
         ("crn", C.c_int32),
         ("sigma_w_speed", C.c_double),
+        ("n_obs", C.c_int32), ("obs", C.c_double * 12),
         ("model", C.c_int32),
         ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
     ]
@@ -53,7 +54,7 @@ def make_params(cfg: dict) -> OrcParams:
         if key not in cfg:
             continue
         val = cfg[key]
-        if name in ("sigma_eps", "sigma_w", "lin_A", "lin_B"):
+        if name in ("sigma_eps", "sigma_w", "lin_A", "lin_B", "obs"):
             arr = getattr(p, name)
             flat = np.asarray(val, dtype=np.float64).ravel()
             for i, x in enumerate(flat):

@@ -251,15 +251,49 @@ void orc_ellipse_sdf(double a, double b, double X, double Y, double* sd, double 
  * position, sigma_y^2 = n^T Sigma_pos n with n = grad e_y (eta in eq. 11), and
  * h = max(w_T - nu sigma_y, 0)^2 - e_y^2.  The clamp at 0 keeps h decreasing in sigma_y once the
  * back-off exceeds the half-width (the literal square is non-monotone there). */
-double orc_barrier(const orc_params* p, double nu, const double mom[9])
+/* Spread of each constraint at a belief (eq. 11, eta the constraint's gradient direction):
+ * sig[0] for the track walls (the outward normal of the nearest centerline point), sig[1 + i] for
+ * obstacle i (the unit vector from its centre to the mean position; (1, 0) at the centre). */
+static void constraint_sigmas(const orc_params* p, const double mom[9], double* sig)
 {
     double ey, n[2];
     orc_ellipse_sdf(p->ell_a, p->ell_b, mom[0], mom[1], &ey, n);
     double var = n[0] * n[0] * mom[6] + 2.0 * n[0] * n[1] * mom[7] + n[1] * n[1] * mom[8];
-    double sigma = sqrt(var > 0.0 ? var : 0.0);
-    double margin = p->half_width - nu * sigma;
+    sig[0] = sqrt(var > 0.0 ? var : 0.0);
+    for (int i = 0; i < p->n_obs; ++i) {
+        double dx = mom[0] - p->obs[3 * i], dy = mom[1] - p->obs[3 * i + 1];
+        double d = sqrt(dx * dx + dy * dy);
+        double ex = d > 0.0 ? dx / d : 1.0, ey2 = d > 0.0 ? dy / d : 0.0;
+        double v = ex * ex * mom[6] + 2.0 * ex * ey2 * mom[7] + ey2 * ey2 * mom[8];
+        sig[1 + i] = sqrt(v > 0.0 ? v : 0.0);
+    }
+}
+
+/* h = min over the constraints (eq. 16) at mean position (X, Y) with the given spreads: the track
+ * walls as eq. 33, h_0 = max(w_T - nu sig_0, 0)^2 - e_y^2, and each obstacle in the same form,
+ * h_i = max(d_i - nu sig_i, 0)^2 - r_i^2 with d_i the distance to its centre. */
+static double barrier_at(const orc_params* p, double nu, double X, double Y, const double* sig)
+{
+    double ey, n[2];
+    orc_ellipse_sdf(p->ell_a, p->ell_b, X, Y, &ey, n);
+    double margin = p->half_width - nu * sig[0];
     if (margin < 0.0) margin = 0.0;
-    return margin * margin - ey * ey;
+    double h = margin * margin - ey * ey;
+    for (int i = 0; i < p->n_obs; ++i) {
+        double dx = X - p->obs[3 * i], dy = Y - p->obs[3 * i + 1], r = p->obs[3 * i + 2];
+        double m = sqrt(dx * dx + dy * dy) - nu * sig[1 + i];
+        if (m < 0.0) m = 0.0;
+        double hi = m * m - r * r;
+        if (hi < h) h = hi;
+    }
+    return h;
+}
+
+double orc_barrier(const orc_params* p, double nu, const double mom[9])
+{
+    double sig[5];
+    constraint_sigmas(p, mom, sig);
+    return barrier_at(p, nu, mom[0], mom[1], sig);
 }
 
 /* Running state cost on the mean state (eqs. 27-28, evaluated at xbar as Alg. 1 does):
@@ -276,6 +310,10 @@ double orc_stage_cost(const orc_params* p, const double mom[9])
     double q = p->q_vx * dv * dv + p->q_vy * mom[4] * mom[4] + p->q_r * mom[5] * mom[5] +
                p->q_ey * ey * ey + p->q_epsi * 2.0 * (1.0 - cos_epsi);
     if (fabs(ey) >= p->half_width) q += p->C_obs;
+    for (int i = 0; i < p->n_obs; ++i) {
+        double dx = mom[0] - p->obs[3 * i], dy = mom[1] - p->obs[3 * i + 1], r = p->obs[3 * i + 2];
+        if (dx * dx + dy * dy <= r * r) q += p->C_obs;
+    }
     return q;
 }
 
@@ -312,15 +350,11 @@ void orc_moments(const double* particles, int32_t M, double out[9])
  *   r(u) = -h(f(xbar_t, u); sigma_t) + (1 - gamma) h_t.
  * r <= 0 means the linear class-kappa condition (eq. 24) is predicted to hold. */
 static double repair_residual(const orc_params* p, double nu, const double mom_t[9],
-                              double sigma_t, double h_t, const double u[2])
+                              const double* sig_t, double h_t, const double u[2])
 {
     double xn[6];
     orc_model_step(p, mom_t, u, xn);
-    double ey, n[2];
-    orc_ellipse_sdf(p->ell_a, p->ell_b, xn[0], xn[1], &ey, n);
-    double margin = p->half_width - nu * sigma_t;
-    if (margin < 0.0) margin = 0.0;
-    double h_next = margin * margin - ey * ey;
+    double h_next = barrier_at(p, nu, xn[0], xn[1], sig_t);
     return -h_next + (1.0 - p->gamma) * h_t;
 }
 
@@ -335,10 +369,8 @@ static double repair_residual(const orc_params* p, double nu, const double mom_t
 void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[2])
 {
     if (p->shield_iters <= 0) return;
-    double ey, n[2];
-    orc_ellipse_sdf(p->ell_a, p->ell_b, mom_t[0], mom_t[1], &ey, n);
-    double var = n[0] * n[0] * mom_t[6] + 2.0 * n[0] * n[1] * mom_t[7] + n[1] * n[1] * mom_t[8];
-    double sigma_t = sqrt(var > 0.0 ? var : 0.0);
+    double sigma_t[5];
+    constraint_sigmas(p, mom_t, sigma_t);
     double h_t = orc_barrier(p, nu, mom_t);
     double fd = p->shield_fd;
     for (int it = 0; it < p->shield_iters; ++it) {

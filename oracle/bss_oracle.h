@@ -54,6 +54,8 @@ typedef struct orc_params {
                              2 sigma points (12-point cubature set, M = 12) */
     int32_t crn;          /* 1: every sample draws the same disturbances (counter word k = 0) */
     double sigma_w_speed; /* kappa: disturbance std sigma_w (1 + kappa |vx|) at the step's state */
+    int32_t n_obs;        /* circular obstacles (0..4), each a further chance constraint */
+    double obs[12];       /* obstacle i: centre (obs[3i], obs[3i+1]), radius obs[3i+2] */
     int32_t model;
     double lin_A[36];
     double lin_B[12];

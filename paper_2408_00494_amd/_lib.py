@@ -44,6 +44,8 @@ class BssParams(C.Structure):
         ("belief", C.c_int32),
         ("crn", C.c_int32),
         ("sigma_w_speed", C.c_double),
+        ("n_obs", C.c_int32),
+        ("obs", C.c_double * 12),
     ]
 
 
@@ -189,7 +191,7 @@ def params_from_problem(problem: dict) -> BssParams:
         if key not in problem:
             continue
         val = problem[key]
-        if name in ("sigma_eps", "sigma_w"):
+        if name in ("sigma_eps", "sigma_w", "obs"):
             arr = getattr(p, name)
             for i, x in enumerate(val):
                 arr[i] = float(x)

@@ -107,6 +107,8 @@ ScoreF64 make_score(const bss_params& p)
     s.shield_iters = p.shield_iters;
     s.shield_gmin = p.shield_gmin;
     s.shield_fd = p.shield_fd;
+    s.n_obs = p.n_obs;
+    for (int i = 0; i < 3 * kMaxObstacles; ++i) s.obs[i] = p.obs[i];
     return s;
 }
 
@@ -301,6 +303,8 @@ void bss_params_default(bss_params* p)
     p->belief = 0;
     p->crn = 0;
     p->sigma_w_speed = 0.0;
+    p->n_obs = 0;
+    for (int i = 0; i < 12; ++i) p->obs[i] = 0.0;
     p->lambda = 1.0;
     p->gamma_u = 1.0;
     p->v_goal = 6.0;
@@ -337,6 +341,12 @@ bss_status bss_validate(const bss_params* p)
     if (p->belief == 2 && p->M != 12)
         return fail(BSS_E_INVAL, "the sigma-point belief (belief = 2) uses M = 12 points");
     if (p->crn != 0 && p->crn != 1) return fail(BSS_E_INVAL, "crn must be 0 or 1");
+    if (p->n_obs < 0 || p->n_obs > kMaxObstacles)
+        return fail(BSS_E_INVAL, "n_obs must be 0..%d", kMaxObstacles);
+    for (int i = 0; i < p->n_obs; ++i)
+        if (!std::isfinite(p->obs[3 * i]) || !std::isfinite(p->obs[3 * i + 1]) ||
+            !finite_pos(p->obs[3 * i + 2]))
+            return fail(BSS_E_INVAL, "obstacle %d needs a finite centre and a radius > 0", i);
     if (!finite_nonneg(p->sigma_w_speed))
         return fail(BSS_E_INVAL, "sigma_w_speed must be finite and >= 0");
     if (!finite_pos(p->lambda)) return fail(BSS_E_INVAL, "lambda must be finite and > 0");

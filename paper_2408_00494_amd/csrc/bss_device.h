@@ -369,7 +369,24 @@ __device__ inline void ellipse_sdf(double a, double b, double X, double Y, doubl
 // barrier value h = max(w_T - nu sigma_y, 0)^2 - e_y^2.
 struct BeliefEval {
     double ey, nx, ny, sigma, h;
+    double sig_obs[kMaxObstacles];   // spread along each obstacle's gradient direction
 };
+
+// Barrier at mean position (X, Y) with given spreads: h = min over the constraints (eq. 16) of the
+// track walls as eq. 33 and each obstacle in the same quadratic form,
+// max(d_i - nu sigma_i, 0)^2 - r_i^2 with d_i the distance to its centre.
+__device__ inline double barrier_at(const ScoreF64& p, double X, double Y, double ey,
+                                    double sigma, const double* sig_obs)
+{
+    const double margin = fmax(p.half_width - p.nu * sigma, 0.0);
+    double h = margin * margin - ey * ey;
+    for (int i = 0; i < p.n_obs; ++i) {
+        const double dx = X - p.obs[3 * i], dy = Y - p.obs[3 * i + 1], r = p.obs[3 * i + 2];
+        const double m = fmax(sqrt(dx * dx + dy * dy) - p.nu * sig_obs[i], 0.0);
+        h = fmin(h, m * m - r * r);
+    }
+    return h;
+}
 
 __device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom)
 {
@@ -377,8 +394,15 @@ __device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom)
     ellipse_sdf(p.ell_a, p.ell_b, mom[0], mom[1], &b.ey, &b.nx, &b.ny);
     const double var = b.nx * b.nx * mom[6] + 2.0 * b.nx * b.ny * mom[7] + b.ny * b.ny * mom[8];
     b.sigma = sqrt(fmax(var, 0.0));
-    const double margin = fmax(p.half_width - p.nu * b.sigma, 0.0);
-    b.h = margin * margin - b.ey * b.ey;
+    for (int i = 0; i < p.n_obs; ++i) {
+        // eta = unit vector from the centre to the mean position ((1, 0) at the centre)
+        const double dx = mom[0] - p.obs[3 * i], dy = mom[1] - p.obs[3 * i + 1];
+        const double d = sqrt(dx * dx + dy * dy);
+        const double ex = d > 0.0 ? dx / d : 1.0, ez = d > 0.0 ? dy / d : 0.0;
+        const double v = ex * ex * mom[6] + 2.0 * ex * ez * mom[7] + ez * ez * mom[8];
+        b.sig_obs[i] = sqrt(fmax(v, 0.0));
+    }
+    b.h = barrier_at(p, mom[0], mom[1], b.ey, b.sigma, b.sig_obs);
     return b;
 }
 
@@ -394,19 +418,25 @@ __device__ inline double stage_cost(const ScoreF64& p, const double* mom, const 
     double q = p.q_vx * dv * dv + p.q_vy * mom[4] * mom[4] + p.q_r * mom[5] * mom[5] +
                p.q_ey * b.ey * b.ey + p.q_epsi * 2.0 * (1.0 - cos_epsi);
     if (fabs(b.ey) >= p.half_width) q += p.C_obs;
+    for (int i = 0; i < p.n_obs; ++i) {
+        const double dx = mom[0] - p.obs[3 * i], dy = mom[1] - p.obs[3 * i + 1];
+        const double r = p.obs[3 * i + 2];
+        if (dx * dx + dy * dy <= r * r) q += p.C_obs;
+    }
     return q;
 }
 
 // One-step residual of the linear class-kappa condition for a candidate control: the mean is
 // pushed through the noise-free model and re-scored with the spread frozen at step t.
-__device__ inline double repair_residual(const ScoreF64& p, const double* xbar, double margin2,
-                                         double h_t, double steer, double accel)
+__device__ inline double repair_residual(const ScoreF64& p, const double* xbar,
+                                         const BeliefEval& be, double h_t, double steer,
+                                         double accel)
 {
     double xn[6];
     car_step_f64(p, xbar, steer, accel, xn);
     double ey, nx, ny;
     ellipse_sdf(p.ell_a, p.ell_b, xn[0], xn[1], &ey, &nx, &ny);
-    return -(margin2 - ey * ey) + (1.0 - p.gamma) * h_t;
+    return -barrier_at(p, xn[0], xn[1], ey, be.sigma, be.sig_obs) + (1.0 - p.gamma) * h_t;
 }
 
 }  // namespace bss

@@ -19,6 +19,8 @@
 
 namespace bss {
 
+constexpr int kMaxObstacles = 4;
+
 // Constants of the single-track car in the form the single-precision particle integrator uses:
 // forces are divided by the mass, so the saturations and stiffnesses are accelerations.
 struct CarF32 {
@@ -41,6 +43,8 @@ struct ScoreF64 {
     double nu, gamma, lambda;
     int32_t shield_iters;
     double shield_gmin, shield_fd;
+    int32_t n_obs;                  // circular obstacles: centre (obs[3i], obs[3i+1]), radius obs[3i+2]
+    double obs[3 * kMaxObstacles];
 };
 
 // One problem instance (device memory).

@@ -571,8 +571,6 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                     const ScoreF64& sc = d.sc;
                     if (sc.shield_iters > 0) {
                         const BeliefEval be = eval_belief(sc, bel);
-                        const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
-                        const double margin2 = margin * margin;
                         const double fd = sc.shield_fd;
                         const int role = j < 5 ? j : 0;
                         const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
@@ -582,7 +580,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                             // lanes 0-4 of the group evaluate r at u and at the four
                             // difference points
                             const double rv =
-                                repair_residual(sc, bel, margin2, be.h, us0 + o0, us1 + o1);
+                                repair_residual(sc, bel, be, be.h, us0 + o0, us1 + o1);
                             const double r0 = __shfl(rv, 0, L);
                             const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
                             const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
@@ -1038,16 +1036,14 @@ __global__ void repair_kernel(ScoreF64 sc, const double* mom, const double* u_in
     double us0 = u_in[2 * i], us1 = u_in[2 * i + 1];
     if (sc.shield_iters > 0) {
         const BeliefEval be = eval_belief(sc, bel);
-        const double margin = fmax(sc.half_width - sc.nu * be.sigma, 0.0);
-        const double margin2 = margin * margin;
         const double fd = sc.shield_fd;
         for (int it = 0; it < sc.shield_iters; ++it) {
-            const double r0 = repair_residual(sc, bel, margin2, be.h, us0, us1);
+            const double r0 = repair_residual(sc, bel, be, be.h, us0, us1);
             if (!(r0 > 0.0)) break;
-            const double g0 = (repair_residual(sc, bel, margin2, be.h, us0 + fd, us1) -
-                               repair_residual(sc, bel, margin2, be.h, us0 - fd, us1)) / (2.0 * fd);
-            const double g1 = (repair_residual(sc, bel, margin2, be.h, us0, us1 + fd) -
-                               repair_residual(sc, bel, margin2, be.h, us0, us1 - fd)) / (2.0 * fd);
+            const double g0 = (repair_residual(sc, bel, be, be.h, us0 + fd, us1) -
+                               repair_residual(sc, bel, be, be.h, us0 - fd, us1)) / (2.0 * fd);
+            const double g1 = (repair_residual(sc, bel, be, be.h, us0, us1 + fd) -
+                               repair_residual(sc, bel, be, be.h, us0, us1 - fd)) / (2.0 * fd);
             const double den = g0 * g0 + g1 * g1 + sc.shield_gmin * sc.shield_gmin;
             us0 = clampd(us0 - r0 * g0 / den, -sc.steer_max, sc.steer_max);
             us1 = clampd(us1 - r0 * g1 / den, -sc.accel_max, sc.accel_max);

@@ -38,6 +38,8 @@ _DEFAULTS = dict(
     # step), common random numbers for the disturbance across samples, speed dependence of the
     # disturbance std (sigma_w (1 + sigma_w_speed |vx|)) and model selector (0 = car)
     seed=1, belief=0, crn=0, sigma_w_speed=0.0, model=0,
+    # circular obstacles (up to 4): n_obs and the flat list (x, y, radius) per obstacle
+    n_obs=0, obs=[0.0] * 12,
 )
 
 

@@ -79,7 +79,7 @@ def test_defaults_match_reference_problem():
             assert p.lanes == 0
             continue
         val = getattr(p, name)
-        if name in ("sigma_eps", "sigma_w"):
+        if name in ("sigma_eps", "sigma_w", "obs"):
             assert list(val) == ref[key]
         else:
             assert val == ref[key], name
@@ -110,7 +110,8 @@ def test_validation_accepts_workloads():
     (dict(lanes=12), "lanes"), (dict(M=200, lanes=8), "particles per lane"),
     (dict(C_obs=float("inf")), "cost weights"), (dict(m=0.0), "m, Iz"),
     (dict(belief=3), "belief"), (dict(belief=2, M=16), "M = 12"), (dict(crn=2), "crn"),
-    (dict(sigma_w_speed=-0.1), "sigma_w_speed"),
+    (dict(sigma_w_speed=-0.1), "sigma_w_speed"), (dict(n_obs=5), "n_obs"),
+    (dict(n_obs=1, obs=[1.0, 2.0, 0.0] + [0.0] * 9), "obstacle 0"),
 ])
 def test_validation_rejects(kw, frag):
     st, msg = _validate(**kw)

@@ -848,3 +848,68 @@ def test_sigma_point_belief_needs_twelve_points():
     prob, x0, v = W.config_small()
     with pytest.raises(ValueError):
         oracle.solve(dict(prob, K=2, M=16, belief=2), 0, x0, v)
+
+
+# ======================= more constraints: circular obstacles (eq. 16) ========================
+def _obstacle_problem(obstacles, **kw):
+    prob, x0, v = W.config_small()
+    flat = [c for ob in obstacles for c in ob] + [0.0] * (12 - 3 * len(obstacles))
+    return dict(prob, n_obs=len(obstacles), obs=flat, **kw), x0, v
+
+
+def test_far_obstacle_changes_nothing():
+    """h = min over the constraints: an obstacle far from the track never attains the minimum and
+    never holds the mean, so the solve is bit-identical to the track-only one."""
+    base, x0, v = W.config_small()
+    base = dict(base, K=32, shield_iters=2)
+    prob, _, _ = _obstacle_problem([(500.0, 500.0, 2.0)], K=32, shield_iters=2)
+    a = oracle.solve(base, 1, x0, v)
+    b = oracle.solve(prob, 1, x0, v)
+    for key in ("v", "mom", "S", "u"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_obstacle_barrier_closed_form():
+    """h_i = max(d_i - nu sqrt(eta^T Sigma_pos eta), 0)^2 - r_i^2 with eta the unit vector from the
+    centre to the mean, and h = min(track, obstacles)."""
+    prob, _, _ = _obstacle_problem([(31.0, 2.0, 0.8), (29.0, -3.0, 0.5)])
+    nu = 1.6448536269514722
+    mom = np.array([30.2, 0.4, 1.5, 5.0, 0.0, 0.0, 0.04, 0.01, 0.09])
+    S = np.array([[mom[6], mom[7]], [mom[7], mom[8]]])
+    hs = []
+    for ox, oy, r in ((31.0, 2.0, 0.8), (29.0, -3.0, 0.5)):
+        d = np.hypot(mom[0] - ox, mom[1] - oy)
+        eta = np.array([mom[0] - ox, mom[1] - oy]) / d
+        sig = math.sqrt(eta @ S @ eta)
+        hs.append(max(d - nu * sig, 0.0) ** 2 - r * r)
+    h_track = oracle.barrier(dict(prob, n_obs=0), nu, mom)
+    assert abs(oracle.barrier(prob, nu, mom) - min([h_track] + hs)) <= 1e-12
+    assert min(hs) < h_track          # the near obstacle binds here
+
+
+def test_obstacle_collision_indicator():
+    prob, _, _ = _obstacle_problem([(30.0, 0.5, 1.0)])
+    inside = np.array([30.2, 0.4, 1.5, 5.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    base = oracle.stage_cost(dict(prob, n_obs=0), inside)
+    assert oracle.stage_cost(prob, inside) - base == prob["C_obs"]
+    outside = inside.copy()
+    outside[1] = 3.0
+    assert oracle.stage_cost(prob, outside) == oracle.stage_cost(dict(prob, n_obs=0), outside)
+
+
+def test_repair_steers_away_from_an_obstacle():
+    """An obstacle just ahead of the one-step prediction violates the condition; the repaired
+    control raises the barrier of the predicted mean (known state, so the spreads are zero)."""
+    prob, _, _ = _obstacle_problem([(30.35, 0.45, 0.3)], shield_iters=4)
+    nu = oracle.backoff(prob["delta"])
+    mom = np.array([30.0, 0.0, math.pi / 2, 5.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    u = np.array([0.0, 0.0])
+
+    def h_pred(uu):
+        xn = oracle.model_step(prob, mom[:6], uu)
+        return oracle.barrier(prob, nu, np.concatenate([xn, [0.0, 0.0, 0.0]]))
+
+    h_t = oracle.barrier(prob, nu, mom)
+    assert -h_pred(u) + (1 - prob["gamma"]) * h_t > 0      # violated before the repair
+    u_rep = oracle.repair(prob, nu, mom, u)
+    assert h_pred(u_rep) > h_pred(u)
