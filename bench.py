@@ -27,21 +27,22 @@ if ROOT not in sys.path:
 # the operations of the method: a 32-bit float or integer operation is 1 slot, a double-precision
 # operation 2, a transcendental (log, sqrt, sin, cos, rcp) or a 32x32->64-bit multiply 4 (they
 # issue at a quarter of the full rate).  Breakdown: Philox4x32-10 100, uniforms 8, Box-Muller 33,
-# two vector-field evaluations 116, midpoint combination and noise 13, double-precision moment
-# accumulation 34.
-SLOTS_PER_ROLLOUT_STEP = 304
+# two vector-field evaluations 116, midpoint combination and noise 13, moment accumulation 9
+# (six sums and three products, single precision as the kernel accumulates them).
+SLOTS_PER_ROLLOUT_STEP = 279
 # MI355X: 256 CUs x 128 lane-slots per clock (4 SIMDs x 32 lanes, the rate behind the published
 # 157.3 TFLOP/s FP32 vector peak with FMA = 2 FLOP) x 2.4 GHz = 78.6e12 lane-slots/s
 VALU_PEAK_SLOTS = 256 * 128 * 2.4e9
-# FP32 FLOPs of the particle dynamics per rollout-step (FMA = 2), and MI355X's FP32 vector peak
-FP32_FLOP_PER_ROLLOUT_STEP = 206
+# FP32 FLOPs per rollout-step (FMA = 2): particle dynamics 206 and moment sums 12; MI355X's FP32
+# vector peak
+FP32_FLOP_PER_ROLLOUT_STEP = 218
 FP32_PEAK = 157.3e12
 
 # HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a 1 GiB device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "f664617384ed22bc", "lanes": 16, "ppl": 4, "split": True,
-                    "fetch_bytes": 7641.4 * 1024 * 2.0, "write_bytes": 15035.5 * 1024 * 1.0}
+MEASURED_TRAFFIC = {"sources_sha256_16": "0ace72fb99e57514", "lanes": 16, "ppl": 4, "split": True,
+                    "fetch_bytes": 7621.4 * 1024 * 2.0, "write_bytes": 15035.4 * 1024 * 1.0}
 KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_kernels.hip",
                   "paper_2408_00494_amd/csrc/bss_device.h",
                   "paper_2408_00494_amd/csrc/bss_internal.h"]

@@ -553,9 +553,6 @@ bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma
     bss_status st = check_free(c);
     if (st != BSS_OK) return st;
     if (!x0_dev) return fail(BSS_E_INVAL, "x0 is NULL");
-    if (c->outputs & BSS_OUT_CONTROLS) {
-        // the copy pointer lives in the descriptor; keep it in sync with the flag
-    }
     return enqueue_solve(c, x0_dev, Sigma0_dev);
 }
 

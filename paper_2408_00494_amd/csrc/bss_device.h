@@ -182,18 +182,12 @@ __device__ __forceinline__ float atan_f32(float x)
     return copysignf(r, x);
 }
 
-// Both slip-angle arctangents of one field evaluation.  When no lane of the wave has an argument
-// outside [-1, 1] (the usual case: the body-frame lateral speeds are small against
-// max(vx, v_min)), the folding is skipped; the result is the same function either way.
-__device__ __forceinline__ void atan_pair(float xa, float xb, float& ra, float& rb)
+// min(max(x, lo), hi) for lo <= hi as one median-of-three: a NaN x gives lo, as the min/max pair
+// does (the instruction returns the minimum of the other two inputs then), and no operand needs
+// the quieting move that the min/max pair gets for values the compiler cannot prove canonical.
+__device__ __forceinline__ float clamp_f32(float x, float lo, float hi)
 {
-    if (__all(fmaxf(fabsf(xa), fabsf(xb)) <= 1.0f)) {
-        ra = atan_poly(xa);
-        rb = atan_poly(xb);
-    } else {
-        ra = atan_f32(xa);
-        rb = atan_f32(xb);
-    }
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 
 // Quantities of one (sample, step) that every particle of the sample shares.
@@ -218,27 +212,73 @@ __device__ __forceinline__ StepF32 make_step(const CarF32& car, float steer, flo
     return s;
 }
 
-// Vector field of the velocity/heading part.  `rev` is the heading in revolutions (the global
-// position derivative needs sin/cos of the heading).  Outputs: dX, dY, dvx, dvy, dr (dpsi = r).
+// Vector field of the velocity/heading part for P particles of one sample at once (arrays of P
+// registers after inlining).  `rev` is the
+// heading in revolutions (the global position derivative needs sin/cos of the heading).  Outputs:
+// dX, dY, dvx, dvy, dr (dpsi = r).  The slip-angle arctangents skip the |x| > 1 folding when no
+// argument of any of the P particles in any lane of the wave needs it (the usual case: the
+// body-frame lateral speeds are small against max(vx, v_min)); both forms give the same value
+// on [-1, 1], so the result does not depend on the branch.  Deciding once for all P particles
+// keeps their evaluations in one straight-line block, where the compiler interleaves them.
+template <int P>
+__device__ __forceinline__ void car_field_f32_n(const CarF32& car, const StepF32& st,
+                                                const float* rev, const float* vx,
+                                                const float* vy, const float* r, float* dX,
+                                                float* dY, float* dvx, float* dvy, float* dr)
+{
+    float xa[P], xb[P];
+    float big = 0.0f;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const float inv_vx = __builtin_amdgcn_rcpf(clamp_f32(vx[p], car.v_min, INFINITY));
+        xa[p] = fmaf(car.lf, r[p], vy[p]) * inv_vx;
+        xb[p] = fmaf(-car.lr, r[p], vy[p]) * inv_vx;
+        big = fmaxf(big, fmaxf(fabsf(xa[p]), fabsf(xb[p])));
+    }
+    float atf[P], atr[P];
+    if (__all(big <= 1.0f)) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            atf[p] = atan_poly(xa[p]);
+            atr[p] = atan_poly(xb[p]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            atf[p] = atan_f32(xa[p]);
+            atr[p] = atan_f32(xb[p]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const float af = st.steer - atf[p];
+        const float ar = -atr[p];
+        const float fF = clamp_f32(car.cf_m * af, -car.fF_max, car.fF_max);   // F_f / m
+        const float fR = clamp_f32(car.cr_m * ar, -car.fR_max, car.fR_max);   // F_r / m
+        const float rr = rev[p] - rintf(rev[p]);
+        const float sp = __builtin_amdgcn_sinf(rr);
+        const float cp = __builtin_amdgcn_cosf(rr);
+        dX[p] = fmaf(vx[p], cp, -vy[p] * sp);
+        dY[p] = fmaf(vx[p], sp, vy[p] * cp);
+        dvx[p] = fmaf(-fF, st.sd, fmaf(vy[p], r[p], st.accel));
+        dvy[p] = fmaf(fF, st.cd, fmaf(-vx[p], r[p], fR));
+        dr[p] = fmaf(fF, st.kz_lf_cd, -st.kz_lr * fR);
+    }
+}
+
+// One particle.
 __device__ __forceinline__ void car_field_f32(const CarF32& car, const StepF32& st, float rev,
                                               float vx, float vy, float r, float& dX, float& dY,
                                               float& dvx, float& dvy, float& dr)
 {
-    const float inv_vx = __builtin_amdgcn_rcpf(fmaxf(vx, car.v_min));
-    float atf, atr;
-    atan_pair(fmaf(car.lf, r, vy) * inv_vx, fmaf(-car.lr, r, vy) * inv_vx, atf, atr);
-    const float af = st.steer - atf;
-    const float ar = -atr;
-    const float fF = fminf(fmaxf(car.cf_m * af, -car.fF_max), car.fF_max);   // F_f / m
-    const float fR = fminf(fmaxf(car.cr_m * ar, -car.fR_max), car.fR_max);   // F_r / m
-    const float rr = rev - rintf(rev);
-    const float sp = __builtin_amdgcn_sinf(rr);
-    const float cp = __builtin_amdgcn_cosf(rr);
-    dX = fmaf(vx, cp, -vy * sp);
-    dY = fmaf(vx, sp, vy * cp);
-    dvx = fmaf(-fF, st.sd, fmaf(vy, r, st.accel));
-    dvy = fmaf(fF, st.cd, fmaf(-vx, r, fR));
-    dr = fmaf(fF, st.kz_lf_cd, -st.kz_lr * fR);
+    float a[1] = {rev}, b[1] = {vx}, c[1] = {vy}, e[1] = {r};
+    float o0[1], o1[1], o2[1], o3[1], o4[1];
+    car_field_f32_n<1>(car, st, a, b, c, e, o0, o1, o2, o3, o4);
+    dX = o0[0];
+    dY = o1[0];
+    dvx = o2[0];
+    dvy = o3[0];
+    dr = o4[0];
 }
 
 // ------------------------------------------------------------------------------------------------
