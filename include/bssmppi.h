@@ -75,6 +75,15 @@ typedef enum bss_status {
  * Disturbance variants: crn = 1 gives every sample the same disturbance draws (common random
  *   numbers: the counter's sample word is 0); sigma_w_speed = kappa makes the disturbance depend
  *   on the state, p(w | x) with std sigma_w (1 + kappa |vx|) at the step's starting state.
+ * Repair of the updated sequence (the local repair of v+ from the state estimate in Alg. 2):
+ *   local_repair = 1 or 2 runs, after the update, one more rollout from (xbar_0, Sigma_0) whose
+ *   control at step t is clip(v+_t) repaired as above (shield_iters >= 1 required) against the
+ *   belief of that rollout, and replaces v+ by the repaired sequence v_safe (held in single
+ *   precision before it is widened back; v_safe_0 is the returned command and the next warm
+ *   start is v_safe).  The rollout's M particles draw their disturbance from their own stream:
+ *   the Philox key of seed ^ 0x5DEECE66DA3B9F1B, sample word 0.  local_repair = 1 keeps the
+ *   repair of every sampled control as well; 2 samples without it (repair of the update only).
+ *   Not available in batches (bss_batch_create rejects such contexts).
  */
 typedef struct bss_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
@@ -95,6 +104,7 @@ typedef struct bss_params {
     double sigma_w_speed;
     int32_t n_obs;
     double obs[12];
+    int32_t local_repair;
 } bss_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a

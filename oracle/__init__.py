@@ -39,6 +39,7 @@ class OrcParams(C.Structure):
         ("crn", C.c_int32),
         ("sigma_w_speed", C.c_double),
         ("n_obs", C.c_int32), ("obs", C.c_double * 12),
+        ("local_repair", C.c_int32),
         ("model", C.c_int32),
         ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
     ]
@@ -48,6 +49,10 @@ def make_params(cfg: dict) -> OrcParams:
     """Build an ``OrcParams`` from a problem dict (keys as in ``workloads.default_problem``)."""
     if cfg.get("belief", 0) == 2 and cfg.get("M") != 12:
         raise ValueError("the sigma-point belief uses M = 12 points")
+    if cfg.get("local_repair", 0) not in (0, 1, 2):
+        raise ValueError("local_repair is 0, 1 or 2")
+    if cfg.get("local_repair", 0) and cfg.get("shield_iters", 0) < 1:
+        raise ValueError("the repair of the update needs shield_iters >= 1")
     p = OrcParams()
     for name, _ in OrcParams._fields_:
         key = "lambda" if name == "lambda_" else name
@@ -110,6 +115,8 @@ def _load():
     lib.orc_solve.argtypes = [P, C.c_uint32, _f64p, C.c_void_p, _f64p, C.c_void_p, C.c_void_p,
                               C.c_void_p, _f64p, C.c_int32]
     lib.orc_solve.restype = C.c_int32
+    lib.orc_local_repair.argtypes = [P, C.c_uint32, _f64p, C.c_void_p, _f64p, _f64p, _f64p]
+    lib.orc_local_repair.restype = None
     lib.orc_step_shift.argtypes = [C.c_int32, _f64p]
     lib.orc_step_shift.restype = None
     lib.orc_chol_psd6.argtypes = [_f64p, _f64p]
@@ -283,6 +290,19 @@ def solve(cfg, s, x0, v, Sigma0=None, want_traces=True, nthreads=None):
     rc = lib().orc_solve(C.byref(p), int(s), np.ascontiguousarray(x0, dtype=np.float64),
                          _ptr(S0), vv, _ptr(u), _ptr(mom), _ptr(S), stats, int(nthreads))
     return {"rc": rc, "v": vv, "u": u, "mom": mom, "S": S, "stats": stats}
+
+
+def local_repair(cfg, s, x0, v_plus, Sigma0=None):
+    """Repair of an updated sequence v+ [T][2] from the estimate (solve index s): returns
+    (v_safe [T][2], the repair rollout's belief [T+1][9])."""
+    p = make_params(cfg)
+    T = cfg["T"]
+    v_safe = np.zeros((T, 2))
+    mom = np.zeros((T + 1, 9))
+    S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
+    lib().orc_local_repair(C.byref(p), int(s), np.ascontiguousarray(x0, dtype=np.float64),
+                           _ptr(S0), np.ascontiguousarray(v_plus, dtype=np.float64), v_safe, mom)
+    return v_safe, mom
 
 
 def step_shift(v):

@@ -714,6 +714,35 @@ static void cholesky6(const double* A, double* L)
     }
 }
 
+/* Repair of the updated sequence from the state estimate (the local repair of v+ that Alg. 2
+ * carries between the update and the executed command): one more rollout from (xbar_0, Sigma_0)
+ * whose control at step t is clip(v+_t), repaired against that rollout's belief at t exactly as
+ * a sampled control is (orc_repair), then propagated; the repaired controls form v_safe.  The
+ * rollout's particles draw their disturbance and initial spread from a stream of their own: the
+ * Philox key of seed ^ ORC_LOCAL_REPAIR_KEY with sample word 0 and the solve's index s.
+ * mom_out [T+1][9] may be NULL. */
+#define ORC_LOCAL_REPAIR_KEY 0x5DEECE66DA3B9F1Bull
+
+void orc_local_repair(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
+                      const double* v_plus, double* v_safe, double* mom_out)
+{
+    orc_params q = *p;
+    q.seed = p->seed ^ ORC_LOCAL_REPAIR_KEY;
+    q.sigma_eps[0] = 0.0;
+    q.sigma_eps[1] = 0.0;
+    double nu = orc_backoff(p->delta, p->backoff);
+    double L0[36];
+    int use_spread = 0;
+    if (Sigma0) {
+        cholesky6(Sigma0, L0);
+        for (int i = 0; i < 36; ++i) use_spread |= (Sigma0[i] != 0.0);
+    }
+    double* mom = mom_out ? mom_out
+                          : (double*)malloc(sizeof(double) * (size_t)(p->T + 1) * ORC_NMOM);
+    (void)orc_rollout(&q, nu, s, 0, x0, Sigma0, use_spread ? L0 : NULL, v_plus, v_safe, mom);
+    if (!mom_out) free(mom);
+}
+
 typedef struct {
     const orc_params* p;
     double nu;
@@ -743,7 +772,9 @@ static void* rollout_worker(void* arg)
 }
 
 /* One BSS-MPPI solve (Alg. 1, one pass of the while-loop body): all K rollouts, then the
- * update of v in place.  Sigma0 (6x6, row-major) may be NULL for a known initial state.
+ * update of v in place, then (local_repair 1 or 2) the repair of the updated sequence from the
+ * estimate; with local_repair = 2 the sampled controls are not repaired.  Sigma0 (6x6,
+ * row-major) may be NULL for a known initial state.
  * u_out [K][T][2], mom_out [K][T+1][9] and S_out [K] may be NULL.  Work is split over K across
  * nthreads threads; results do not depend on the split. Returns 0, or 1 when no cost is finite. */
 int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
@@ -763,12 +794,14 @@ int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const dou
                           : (double*)malloc(sizeof(double) * (size_t)K * (T + 1) * ORC_NMOM);
     double* S = S_out ? S_out : (double*)malloc(sizeof(double) * (size_t)K);
 
+    orc_params ps = *p;   /* the samples' settings */
+    if (p->local_repair == 2) ps.shield_iters = 0;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > K) nthreads = K;
     pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
     rollout_job* jobs = (rollout_job*)malloc(sizeof(rollout_job) * (size_t)nthreads);
     for (int i = 0; i < nthreads; ++i) {
-        rollout_job j = {p, nu, s, x0, Sigma0, use_spread ? L0 : NULL, v,
+        rollout_job j = {&ps, nu, s, x0, Sigma0, use_spread ? L0 : NULL, v,
                          u, mom, S, (int)((long)K * i / nthreads),
                          (int)((long)K * (i + 1) / nthreads)};
         jobs[i] = j;
@@ -781,6 +814,12 @@ int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const dou
     free(jobs);
 
     int32_t rc = orc_update(p, S, u, v, stats);
+    if (p->local_repair) {
+        double* v_safe = (double*)malloc(sizeof(double) * (size_t)T * 2);
+        orc_local_repair(p, s, x0, Sigma0, v, v_safe, NULL);
+        memcpy(v, v_safe, sizeof(double) * (size_t)T * 2);
+        free(v_safe);
+    }
     if (!u_out) free(u);
     if (!mom_out) free(mom);
     if (!S_out) free(S);

@@ -56,6 +56,9 @@ typedef struct orc_params {
     double sigma_w_speed; /* kappa: disturbance std sigma_w (1 + kappa |vx|) at the step's state */
     int32_t n_obs;        /* circular obstacles (0..4), each a further chance constraint */
     double obs[12];       /* obstacle i: centre (obs[3i], obs[3i+1]), radius obs[3i+2] */
+    int32_t local_repair; /* repair of the updated sequence from the estimate (the local repair
+                             of v+ in Alg. 2): 0 off, 1 after the update and in every sample,
+                             2 after the update only */
     int32_t model;
     double lin_A[36];
     double lin_B[12];
@@ -114,6 +117,11 @@ int32_t orc_update(const orc_params* p, const double* S, const double* u, double
 int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
                   double* v, double* u_out, double* mom_out, double* S_out, double stats[4],
                   int32_t nthreads);
+
+/* repair of the updated sequence from the estimate (local_repair; v_safe [T][2], mom_out
+ * [T+1][9] or NULL) */
+void orc_local_repair(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
+                      const double* v_plus, double* v_safe, double* mom_out);
 
 void orc_step_shift(int32_t T, double* v);
 

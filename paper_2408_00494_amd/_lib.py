@@ -46,6 +46,7 @@ class BssParams(C.Structure):
         ("sigma_w_speed", C.c_double),
         ("n_obs", C.c_int32),
         ("obs", C.c_double * 12),
+        ("local_repair", C.c_int32),
     ]
 
 

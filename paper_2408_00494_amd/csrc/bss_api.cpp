@@ -184,6 +184,12 @@ struct bss_ctx {
     size_t ev_used;
     bss_batch* batch;         // batch that currently owns the context, or nullptr
     int batch_index;          // index of the context in that batch
+    // repair of the updated sequence (local_repair != 0): its descriptor (host copy and device),
+    // one-block grid and the LDS of its unsplit launch
+    InstanceDesc rdesc;
+    InstanceDesc* d_rdesc;
+    BlockDesc* d_rblock;
+    size_t rlds;
 };
 
 struct bss_batch {
@@ -229,16 +235,25 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
     return out;
 }
 
+// the sampled controls are repaired (the per-sample shield) unless only the update is repaired
+bool samples_shielded(const bss_params& p) { return p.shield_iters > 0 && p.local_repair != 2; }
+
 hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
-    c->shape.split = c->shape.split && c->p.shield_iters == 0 && c->p.belief == 0;
+    c->shape.split = c->shape.split && !samples_shielded(c->p) && c->p.belief == 0;
     c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
     // static leading fields only: the device state is left as it is
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
+    if (c->d_rdesc) {
+        c->rdesc.lanes = c->shape.lanes;
+        c->rlds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, false);
+        e = hipMemcpy(c->d_rdesc, &c->rdesc, offsetof(InstanceDesc, cur), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
     const std::vector<BlockDesc> tab = block_table(0, c->p.K, c->shape.lanes);
     return hipMemcpy(c->d_blocks, tab.data(), tab.size() * sizeof(BlockDesc),
                      hipMemcpyHostToDevice);
@@ -305,6 +320,7 @@ void bss_params_default(bss_params* p)
     p->sigma_w_speed = 0.0;
     p->n_obs = 0;
     for (int i = 0; i < 12; ++i) p->obs[i] = 0.0;
+    p->local_repair = 0;
     p->lambda = 1.0;
     p->gamma_u = 1.0;
     p->v_goal = 6.0;
@@ -349,6 +365,8 @@ bss_status bss_validate(const bss_params* p)
             return fail(BSS_E_INVAL, "obstacle %d needs a finite centre and a radius > 0", i);
     if (!finite_nonneg(p->sigma_w_speed))
         return fail(BSS_E_INVAL, "sigma_w_speed must be finite and >= 0");
+    if (p->local_repair < 0 || p->local_repair > 2)
+        return fail(BSS_E_INVAL, "local_repair must be 0, 1 or 2");
     if (!finite_pos(p->lambda)) return fail(BSS_E_INVAL, "lambda must be finite and > 0");
     if (!finite_pos(p->dt)) return fail(BSS_E_INVAL, "dt must be finite and > 0");
     if (!finite_pos(p->m) || !finite_pos(p->Iz) || !finite_pos(p->lf) || !finite_pos(p->lr))
@@ -377,6 +395,8 @@ bss_status bss_validate(const bss_params* p)
     }
     if (p->shield_iters < 0 || p->shield_iters > 16)
         return fail(BSS_E_INVAL, "shield_iters outside [0, 16]");
+    if (p->local_repair != 0 && p->shield_iters < 1)
+        return fail(BSS_E_INVAL, "the repair of the update (local_repair) needs shield_iters >= 1");
     if (p->shield_iters > 0 && (!finite_pos(p->shield_fd) || !finite_nonneg(p->shield_gmin)))
         return fail(BSS_E_INVAL, "shield_fd must be > 0 and shield_gmin >= 0");
     if (p->lanes != 0 && p->lanes != 8 && p->lanes != 16 && p->lanes != 32 && p->lanes != 64)
@@ -434,8 +454,15 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     const size_t sz_desc = align256(sizeof(InstanceDesc));
     const size_t sz_blk = align256(G * sizeof(BlockDesc));
     const size_t sz_col = align256(2 * T * sizeof(MergeDesc));
+    // repair of the update: descriptor, grid, controls [T][2] f32, beliefs [T+1][9], cost,
+    // partial [2T+4], stats [8]
+    const size_t sz_rep = p->local_repair == 0
+                              ? 0
+                              : sz_desc + 256 + align256(T * 2 * sizeof(float)) +
+                                    align256((T + 1) * 9 * sizeof(double)) + 256 +
+                                    align256((2 * T + 4) * sizeof(double)) + sz_stats;
     const size_t total = 2 * sz_v + sz_u + sz_mom + sz_S + sz_stats + sz_part + sz_x0 + sz_sig +
-                         sz_desc + sz_blk + sz_col;
+                         sz_desc + sz_blk + sz_col + sz_rep;
 
     void* block = nullptr;
     if (c->has_alloc) {
@@ -477,6 +504,38 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->d_blocks = (BlockDesc*)b;
     b += sz_blk;
     c->d_cols = (MergeDesc*)b;
+    b += sz_col;
+    c->d_rdesc = nullptr;
+    c->d_rblock = nullptr;
+    c->rlds = 0;
+    if (p->local_repair != 0) {
+        // one sample, no exploration noise, its own Philox key (seed ^ 0x5DEECE66DA3B9F1B, sample
+        // word 0) and buffers; both mean-sequence pointers are the context's
+        InstanceDesc& r = c->rdesc;
+        r = c->desc;
+        r.K = 1;
+        r.nblocks = 1;
+        r.sig_eps0 = 0.0f;
+        r.sig_eps1 = 0.0f;
+        r.shift_after = 0;
+        const uint64_t rkey = p->seed ^ 0x5DEECE66DA3B9F1Bull;
+        r.key0 = (uint32_t)rkey;
+        r.key1 = (uint32_t)(rkey >> 32);
+        c->d_rdesc = (InstanceDesc*)b;
+        b += sz_desc;
+        c->d_rblock = (BlockDesc*)b;
+        b += 256;
+        r.u = (float*)b;
+        b += align256(T * 2 * sizeof(float));
+        r.mom = (double*)b;
+        b += align256((T + 1) * 9 * sizeof(double));
+        r.S = (double*)b;
+        b += 256;
+        r.partial = (double*)b;
+        b += align256((2 * T + 4) * sizeof(double));
+        r.stats = (double*)b;
+        c->rlds = solve_lds_bytes(c->shape.lanes, p->T, c->shape.ppl, false);
+    }
 
     hipError_t e = hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -489,6 +548,12 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess)
         e = hipMemcpy(c->d_desc, &c->desc, sizeof(InstanceDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess && c->d_rdesc) {
+        const BlockDesc rb{0, 0};
+        e = hipMemcpy(c->d_rdesc, &c->rdesc, sizeof(InstanceDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_rblock, &rb, sizeof(BlockDesc), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = upload_shape(c);
     if (e == hipSuccess) {
         std::vector<MergeDesc> cols;
@@ -534,7 +599,7 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
     e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
-                     c->p.shield_iters > 0, c->shape.split, c->p.belief != 0, c->lds, x0_dev,
+                     samples_shielded(c->p), c->shape.split, c->p.belief != 0, c->lds, x0_dev,
                      Sigma0_dev, c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
@@ -545,6 +610,11 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
     e = launch_merge(c->d_desc, c->d_cols, 2 * c->p.T, c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "merge launch");
     c->pending_shift = 0;
+    if (c->d_rdesc) {
+        e = launch_local_repair(c->d_desc, c->d_rdesc, c->d_rblock, c->p.T, c->shape.ppl,
+                                c->p.belief != 0, c->rlds, x0_dev, Sigma0_dev, c->stream);
+        if (e != hipSuccess) return device_fail(e, "repair of the update");
+    }
     return BSS_OK;
 }
 
@@ -883,6 +953,9 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return fail(BSS_E_INVAL, "context %d is NULL", i);
         if (ctxs[i]->batch) return fail(BSS_E_STATE, "context %d already belongs to a batch", i);
+        if (ctxs[i]->p.local_repair != 0)
+            return fail(BSS_E_INVAL, "context %d repairs its update (local_repair), which runs per "
+                        "context, not in batches", i);
         for (int q = 0; q < i; ++q)
             if (ctxs[q] == ctxs[i]) return fail(BSS_E_INVAL, "context %d appears twice", i);
         M_max = std::max(M_max, ctxs[i]->p.M);
@@ -904,7 +977,7 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     for (int i = 0; i < n; ++i) {
         nb += max_blocks(ctxs[i]->p.K);
         nc += 2 * (size_t)ctxs[i]->p.T;
-        b->shield = b->shield || ctxs[i]->p.shield_iters > 0;
+        b->shield = b->shield || samples_shielded(ctxs[i]->p);
         b->resample = b->resample || ctxs[i]->p.belief != 0;
     }
     const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));

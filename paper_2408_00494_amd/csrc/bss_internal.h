@@ -125,6 +125,12 @@ hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int n
                         hipStream_t stream);
 hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
                         int extra_shift, hipStream_t stream);
+// Repair of the updated sequence of one instance after its merge: `rep` is the instance's repair
+// descriptor (one sample, no exploration noise, own key and buffers), `rep_block` its one-block
+// grid {0, 0}; lds is the dynamic LDS of an unsplit launch of the instance's shape.
+hipError_t launch_local_repair(InstanceDesc* inst, InstanceDesc* rep, const BlockDesc* rep_block,
+                               int T, int ppl, bool resample, size_t lds, const double* x0_base,
+                               const double* Sigma0_base, hipStream_t stream);
 
 // stand-alone kernels for staged checks
 hipError_t launch_score(int K, int T, const ScoreF64& sc, const double* mom, const float* u,

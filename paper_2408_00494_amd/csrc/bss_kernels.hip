@@ -975,6 +975,33 @@ __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const M
     }
 }
 
+// Repair of the updated sequence (local repair of v+): the repair descriptor is a copy of the
+// instance's with one sample, no exploration noise, its own Philox key and its own buffers, and
+// both mean-sequence pointers of the instance.  Before its rollout it takes the instance's state
+// as the merge left it: the buffer holding v+, no pending shift (v+ is read as it stands), and
+// the index of the solve just done (the merge advanced it).
+__global__ void repair_prep_kernel(const InstanceDesc* inst, InstanceDesc* rep)
+{
+    if (threadIdx.x == 0) {
+        rep->cur = inst->cur;
+        rep->vshift = 0;
+        rep->solve_index = inst->solve_index - 1u;
+    }
+}
+
+// The repaired controls (the rollout's single-precision record of them) replace v+ in place, and
+// v_safe_0 becomes the returned command.
+__global__ __launch_bounds__(256) void repair_finish_kernel(InstanceDesc* inst,
+                                                            const InstanceDesc* rep)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < 2 * inst->T) {
+        const double val = (double)rep->u[i];
+        inst->v[inst->cur][i] = val;
+        if (i < 2) inst->stats[5 + i] = val;
+    }
+}
+
 // Merge for the stand-alone K-reduction (explicit buffers, no instance state).
 __global__ __launch_bounds__(256) void merge_plain_kernel(int T, int G, double lambda,
                                                           const double* partial,
@@ -1247,6 +1274,21 @@ hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int nco
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(merge_kernel, dim3(blocks_for(ncols, 4)), dim3(256), 0, stream,
                        const_cast<InstanceDesc*>(inst), cols, ncols, extra_shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_repair(InstanceDesc* inst, InstanceDesc* rep, const BlockDesc* rep_block,
+                               int T, int ppl, bool resample, size_t lds, const double* x0_base,
+                               const double* Sigma0_base, hipStream_t stream)
+{
+    hipLaunchKernelGGL(repair_prep_kernel, dim3(1), dim3(64), 0, stream, inst, rep);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_solve(rep, rep_block, 1, ppl, true, false, resample, lds, x0_base, Sigma0_base, 0,
+                     stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(repair_finish_kernel, dim3(blocks_for(2 * T, 256)), dim3(256), 0, stream,
+                       inst, rep);
     return hipGetLastError();
 }
 

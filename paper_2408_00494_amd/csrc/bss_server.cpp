@@ -328,6 +328,9 @@ bss_status bss_server_create(const bss_server_config* cfg, const bss_params* veh
         q.T = c.T;
         bss_status st = bss_validate(&q);
         if (st != BSS_OK) return st;
+        if (q.local_repair != 0)
+            return fail(BSS_E_INVAL, "vehicle %d: the repair of the update (local_repair) runs per "
+                        "context, not in the server's batched launches", i);
     }
 
     bss_server* s = new (std::nothrow) bss_server();

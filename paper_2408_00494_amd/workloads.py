@@ -40,6 +40,9 @@ _DEFAULTS = dict(
     seed=1, belief=0, crn=0, sigma_w_speed=0.0, model=0,
     # circular obstacles (up to 4): n_obs and the flat list (x, y, radius) per obstacle
     n_obs=0, obs=[0.0] * 12,
+    # repair of the updated sequence from the state estimate: 0 off, 1 in addition to the repair
+    # of every sample, 2 instead of it (uses the shield_* settings)
+    local_repair=0,
 )
 
 

@@ -112,6 +112,7 @@ def test_validation_accepts_workloads():
     (dict(belief=3), "belief"), (dict(belief=2, M=16), "M = 12"), (dict(crn=2), "crn"),
     (dict(sigma_w_speed=-0.1), "sigma_w_speed"), (dict(n_obs=5), "n_obs"),
     (dict(n_obs=1, obs=[1.0, 2.0, 0.0] + [0.0] * 9), "obstacle 0"),
+    (dict(local_repair=3), "local_repair"), (dict(local_repair=1), "shield_iters >= 1"),
 ])
 def test_validation_rejects(kw, frag):
     st, msg = _validate(**kw)
@@ -173,6 +174,11 @@ def test_server_and_batch_argument_checks():
     one = _lib.BssServerConfig.from_buffer_copy(cfg)
     one.n_vehicles = 1
     assert lib.bss_server_create(C.byref(one), bad_veh, C.byref(out)) == _lib.BSS_E_INVAL
+    # the repair of the update runs per context, not in the server's batched launches
+    lr_veh = (_lib.BssParams * 1)(_lib.params_from_problem(
+        W.default_problem(shield_iters=2, local_repair=1)))
+    assert lib.bss_server_create(C.byref(one), lr_veh, C.byref(out)) == _lib.BSS_E_INVAL
+    assert "local_repair" in lib.bss_last_error().decode()
     x0 = (C.c_double * 6)()
     assert lib.bss_server_submit(None, 0, 1, 1, 0.05, x0, None) == _lib.BSS_E_INVAL
     assert lib.bss_server_pump(None, None) == _lib.BSS_E_INVAL

@@ -8,6 +8,7 @@ checks compare whole solves.  Tolerances (floating point; integer work is bit-ex
 The single-precision rollout against the double-precision oracle is the only source of
 difference; staged double-precision stages are held to ~1e-12.
 """
+import math
 import os
 
 import numpy as np
@@ -571,3 +572,46 @@ def test_far_obstacle_changes_nothing_on_device():
         s.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_local_repair_matches_oracle(mode):
+    """Repair of the updated sequence (local_repair): one shielded rollout of v+ from the estimate
+    on its own stream replaces v+ by v_safe.  Staged: the GPU's v_safe against the oracle's repair
+    of the GPU's own v+ (the same solve with the repair of the update off: the samples run the
+    same launch, with the per-sample repair for mode 1 and without for mode 2); the returned
+    command is v_safe_0; end to end against the oracle's solve with the same setting."""
+    prob, _, v = W.config_small()
+    prob = dict(prob, shield_iters=4, gamma=0.3)
+    x0 = np.array([prob["ell_a"] + 0.8, 0.0, math.pi / 2 - 0.3, 6.0, 0.0, 0.0])
+    s = 4
+    pre_prob = dict(prob, local_repair=0) if mode == 1 else dict(prob, shield_iters=0)
+    outs = {}
+    for name, p in (("pre", pre_prob), ("repaired", dict(prob, local_repair=mode))):
+        solver = bss.Solver(p)
+        solver.set_controls(v)
+        solver.solve_index = s
+        u0, _ = solver.solve(x0)
+        outs[name] = (solver.get_controls(), np.asarray(u0))
+        solver.close()
+    v_plus = outs["pre"][0]
+    v_safe, u0 = outs["repaired"]
+    assert np.array_equal(u0, v_safe[0])
+    ref_safe, _ = oracle.local_repair(prob, s, x0, v_plus)
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    assert np.max(np.abs(ref_safe - np.clip(v_plus, -scale, scale))) > 1e-2   # the repair acted
+    e_stage = ctrl_err(v_safe, ref_safe, prob)
+    ref = oracle.solve(dict(prob, local_repair=mode), s, x0, v, want_traces=False,
+                       nthreads=NTHREADS)
+    e_end = ctrl_err(v_safe, ref["v"], prob)
+    print(f"local repair mode {mode}: stage {e_stage:.2e} end-to-end {e_end:.2e}", flush=True)
+    assert e_stage <= 1e-4
+    assert e_end <= 1e-4
+
+
+def test_local_repair_is_rejected_in_batches():
+    prob, _, _ = W.config_small()
+    solver = bss.Solver(dict(prob, shield_iters=2, local_repair=1))
+    with pytest.raises(RuntimeError, match="local_repair"):
+        bss.Batch([solver])
+    solver.close()

@@ -913,3 +913,91 @@ def test_repair_steers_away_from_an_obstacle():
     assert -h_pred(u) + (1 - prob["gamma"]) * h_t > 0      # violated before the repair
     u_rep = oracle.repair(prob, nu, mom, u)
     assert h_pred(u_rep) > h_pred(u)
+
+
+# ---- repair of the updated sequence from the estimate (local repair of v+, Alg. 2) ----------
+
+LOCAL_REPAIR_KEY = 0x5DEECE66DA3B9F1B     # documented stream of the repair rollout
+
+
+def _local_repair_problem(**kw):
+    base = dict(K=64, M=4, T=20, shield_iters=8, gamma=0.3, sigma_w=[0.0, 0.0, 0.0])
+    base.update(kw)
+    return W.default_problem(**base)
+
+
+def test_local_repair_on_a_deterministic_belief():
+    """No disturbance and no initial spread: every particle is the mean, so each belief step is
+    the model step of the control the repair chose.  Heading outward near the outer wall with
+    v+ = 0, the unrepaired controls violate the discrete barrier condition from some step on.
+    Where they satisfy it the control is clip(v+_t) unchanged; where they do not it is the shield
+    repair of clip(v+_t) against the repair rollout's own belief at t (pinned above), the first
+    such repair lowers the one-step violation, and the repaired trajectory ends with a larger
+    barrier value than the unrepaired one (one-step repairs with little steering authority cannot
+    always restore the condition; the control box binds here)."""
+    prob = _local_repair_problem()
+    nu = oracle.backoff(prob["delta"])
+    a = prob["ell_a"]
+    x0 = np.array([a + 0.8, 0.0, math.pi / 2 - 0.35, 6.0, 0.0, 0.0])
+    v_plus = np.zeros((prob["T"], 2))
+    v_safe, mom = oracle.local_repair(prob, 7, x0, v_plus)
+    assert np.all(mom[:, 6:] == 0.0)
+    active = []
+    for t in range(prob["T"]):
+        assert np.array_equal(mom[t + 1, :6], oracle.model_step(prob, mom[t, :6], v_safe[t]))
+        resid = _residual_fn(prob, nu, mom[t])
+        r_before = resid(v_plus[t])
+        if r_before > 0:
+            active.append(t)
+            assert np.array_equal(v_safe[t], oracle.repair(prob, nu, mom[t], v_plus[t]))
+        else:
+            assert np.array_equal(v_safe[t], v_plus[t])
+    assert len(active) >= 3
+    first = active[0]
+    resid = _residual_fn(prob, nu, mom[first])
+    assert resid(v_safe[first]) < 0.9 * resid(v_plus[first])
+    unrepaired = oracle.propagate(prob, 7, 0, x0, v_plus)
+    assert np.array_equal(unrepaired[:first + 1], mom[:first + 1])
+    assert oracle.barrier(prob, nu, mom[-1]) > oracle.barrier(prob, nu, unrepaired[-1]) + 1.0
+
+
+def test_local_repair_rollout_draws_its_own_stream():
+    """With disturbance and an initial spread, the repair rollout's belief is the propagation of
+    v_safe by sample 0 under the key seed ^ 0x5DEECE66DA3B9F1B (and not the samples' stream)."""
+    prob = _local_repair_problem(sigma_w=[0.3, 0.3, 0.2], M=16, seed=11)
+    x0 = np.array([prob["ell_a"] + 0.8, 0.0, math.pi / 2 - 0.35, 6.0, 0.0, 0.0])
+    Sigma0 = np.diag([0.01, 0.01, 0.001, 0.02, 0.01, 0.005])
+    v_plus = np.tile([0.05, 0.3], (prob["T"], 1))
+    v_safe, mom = oracle.local_repair(prob, 5, x0, v_plus, Sigma0=Sigma0)
+    same = oracle.propagate(dict(prob, seed=prob["seed"] ^ LOCAL_REPAIR_KEY), 5, 0, x0, v_safe,
+                            Sigma0=Sigma0)
+    assert np.array_equal(mom, same)
+    other = oracle.propagate(prob, 5, 0, x0, v_safe, Sigma0=Sigma0)
+    assert np.max(np.abs(other[1:, :2] - mom[1:, :2])) > 1e-6
+    assert not np.array_equal(v_safe, v_plus)       # the repair was active somewhere
+
+
+def test_solve_with_local_repair_is_update_then_repair():
+    """local_repair = 1: the solve's v is the repair of the update of the shielded solve; = 2:
+    the repair of the update of the solve whose samples are not repaired."""
+    prob = _local_repair_problem(sigma_w=[0.3, 0.3, 0.2], K=48, M=8, T=15,
+                                 sigma_eps=[0.1, 1.0])
+    x0 = np.array([prob["ell_a"] + 1.0, 0.0, math.pi / 2 - 0.3, 6.0, 0.0, 0.0])
+    v = np.tile([0.0, 0.5], (prob["T"], 1))
+    s = 3
+    plain = oracle.solve(prob, s, x0, v, want_traces=False, nthreads=2)
+    with_lr = oracle.solve(dict(prob, local_repair=1), s, x0, v, want_traces=False, nthreads=2)
+    assert np.array_equal(with_lr["v"], oracle.local_repair(prob, s, x0, plain["v"])[0])
+    assert np.array_equal(with_lr["stats"], plain["stats"])
+    unrepaired = oracle.solve(dict(prob, shield_iters=0), s, x0, v, want_traces=False,
+                              nthreads=2)
+    only_lr = oracle.solve(dict(prob, local_repair=2), s, x0, v, want_traces=False, nthreads=2)
+    assert np.array_equal(only_lr["v"], oracle.local_repair(prob, s, x0, unrepaired["v"])[0])
+    assert not np.array_equal(only_lr["v"], with_lr["v"])
+
+
+def test_local_repair_argument_checks():
+    with pytest.raises(ValueError):
+        oracle.make_params(W.default_problem(local_repair=3))
+    with pytest.raises(ValueError):
+        oracle.make_params(W.default_problem(local_repair=1, shield_iters=0))
