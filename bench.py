@@ -27,15 +27,14 @@ if ROOT not in sys.path:
 # the operations of the method: a 32-bit float or integer operation is 1 slot, a double-precision
 # operation 2, a transcendental (log, sqrt, sin, cos, rcp) or a 32x32->64-bit multiply 4 (they
 # issue at a quarter of the full rate).  Breakdown: Philox4x32-10 100, uniforms 8, Box-Muller 33,
-# two vector-field evaluations 116, midpoint combination and noise 13, moment accumulation 9
-# (six sums and three products, single precision as the kernel accumulates them).
-SLOTS_PER_ROLLOUT_STEP = 279
+# two vector-field evaluations 116, midpoint combination and noise 13, double-precision moment
+# accumulation 34.
+SLOTS_PER_ROLLOUT_STEP = 304
 # MI355X: 256 CUs x 128 lane-slots per clock (4 SIMDs x 32 lanes, the rate behind the published
 # 157.3 TFLOP/s FP32 vector peak with FMA = 2 FLOP) x 2.4 GHz = 78.6e12 lane-slots/s
 VALU_PEAK_SLOTS = 256 * 128 * 2.4e9
-# FP32 FLOPs per rollout-step (FMA = 2): particle dynamics 206 and moment sums 12; MI355X's FP32
-# vector peak
-FP32_FLOP_PER_ROLLOUT_STEP = 218
+# FP32 FLOPs of the particle dynamics per rollout-step (FMA = 2), and MI355X's FP32 vector peak
+FP32_FLOP_PER_ROLLOUT_STEP = 206
 FP32_PEAK = 157.3e12
 
 # HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
@@ -110,9 +109,38 @@ def cpu_baseline(prob, x0, v, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or n >= 50:
             break
+    # the same oracle on one thread, over a quarter of the samples (the rate is per sample)
+    one = dict(prob, K=max(1, prob["K"] // 4))
+    n1, t1 = 0, time.perf_counter()
+    while True:
+        oracle.solve(one, n1, x0, v, want_traces=False, nthreads=1)
+        n1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= seconds / 2 or n1 >= 10:
+            break
     return {"value": rs * n / el, "unit": "rollout-steps/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{n} full solves of the same workload (K={prob['K']}, M={prob['M']}, "
-                      f"T={prob['T']}) in {el:.1f} s, split over K across {nthreads} threads"}
+                      f"T={prob['T']}) in {el:.1f} s, split over K across {nthreads} threads",
+            "single_thread": {"value": one["K"] * one["M"] * one["T"] * n1 / el1,
+                              "sample": f"{n1} solves with K={one['K']} on one thread in "
+                                        f"{el1:.1f} s"},
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical core count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None}
 
 
 def bench_resampling(bss, W, torch, steps=20, warmup=3):

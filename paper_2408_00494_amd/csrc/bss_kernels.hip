@@ -157,41 +157,6 @@ __device__ __forceinline__ double group_sum(double x, int L)
     return x;
 }
 
-// Sum over the L lanes of a group of FP32 per-lane partial sums: FP32 inside a row of 16 (each
-// DPP move folds into the add), FP64 across rows; bitwise identical in every lane of the group
-// for the same reason as group_sum.
-__device__ __forceinline__ double moment_sum(float x, int L)
-{
-    if (L > 1) x += dpp_f32<kDppQuadSwap1>(x);
-    if (L > 2) x += dpp_f32<kDppQuadSwap2>(x);
-    if (L > 4) x += dpp_f32<kDppHalfRowMirror>(x);
-    if (L > 8) x += dpp_f32<kDppRowMirror>(x);
-    double s = (double)x;
-    if (L > 16) s = xor16_sum(s);
-    if (L > 32) s = xor32_sum(s);
-    return s;
-}
-
-// FP32 sum over the L lanes of a group, bitwise identical in every lane of the group.
-__device__ __forceinline__ float group_sum_f32(float x, int L)
-{
-    if (L > 1) x += dpp_f32<kDppQuadSwap1>(x);
-    if (L > 2) x += dpp_f32<kDppQuadSwap2>(x);
-    if (L > 4) x += dpp_f32<kDppHalfRowMirror>(x);
-    if (L > 8) x += dpp_f32<kDppRowMirror>(x);
-    if (L > 16) {
-        float even, odd;
-        pair_rows16(x, even, odd);
-        x = even + odd;
-    }
-    if (L > 32) {
-        float lower, upper;
-        pair_halves32(x, lower, upper);
-        x = lower + upper;
-    }
-    return x;
-}
-
 // Value of lane 0 of the group in every lane of the group.
 __device__ __forceinline__ float group_first(float x, int L)
 {
@@ -650,17 +615,11 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 const StepF32 st = make_step(car, uu.x, uu.y);
                 PhiloxStep ps{};
                 if (!SPLIT) ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
-                // Moments.  Per-lane partial sums over the lane's particles are FP32; the
-                // heading is shifted by particle 0 of the sample (lane 0 of the group; its
-                // compensated pair stays exact in the FP64 shift).  Position mean and
-                // covariance use the corrected two-pass scheme (Chan, Golub and LeVeque): the
-                // first pass gives a provisional mean c (FP32, any shift near the mean will do);
-                // the second sums the deviations d = x - c, formed from the compensated pairs,
-                // and their products, so that no large shift cancels in FP32:
-                // mean = c + sum(d)/M, covariance = (sum(d d') - sum(d) sum(d')/M) / (M - 1).
-                // Particles beyond M contribute nothing.
-                float fX = 0, fY = 0, fP = 0, fvx = 0, fvy = 0, fvr = 0;
-                float rPs = 0, rPc = 0;
+                // FP64 moment sums of the lane's particles; positions shifted by particle 0 of
+                // the sample (lane 0 of the group), taken after its update in the first chunk
+                double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0,
+                       sYY = 0;
+                double refX = 0.0, refY = 0.0;
                 // With up to four particles per lane the step runs in stages over all of them
                 // (disturbance normals, first field evaluation, midpoint, second evaluation,
                 // update), each stage one straight-line block with no per-particle branch, so
@@ -726,55 +685,48 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         vr[p] = fmaf(sw2, w2[i], fmaf(car.dt, dr[i], vr[p]));
                     }
                     if (p0 == 0) {
-                        rPs = group_first(Ps[0], L);
-                        rPc = group_first(Pc[0], L);
+                        refX = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
+                        refY = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
                     }
-                    // first pass (one particle at a time when Q = 1, inside the step)
+                    // accumulate the chunk (particles beyond M contribute nothing)
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
                         const int p = p0 + i;
                         if (j + p * L < M) {
-                            fX += Xs[p];
-                            fY += Ys[p];
-                            fP += (Ps[p] - rPs) - (Pc[p] - rPc);
-                            fvx += vx[p];
-                            fvy += vy[p];
-                            fvr += vr[p];
+                            const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
+                            const double Y = ((double)Ys[p] - (double)Yc[p]) - refY;
+                            sX += X;
+                            sY += Y;
+                            sP += (double)Ps[p] - (double)Pc[p];
+                            svx += (double)vx[p];
+                            svy += (double)vy[p];
+                            svr += (double)vr[p];
+                            sXX = fma(X, X, sXX);
+                            sXY = fma(X, Y, sXY);
+                            sYY = fma(Y, Y, sYY);
                         }
                     }
                 }
-                const float cX = group_sum_f32(fX, L) * (float)invM;
-                const float cY = group_sum_f32(fY, L) * (float)invM;
-                float fdx = 0, fdy = 0, fXX = 0, fXY = 0, fYY = 0;
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    if (j + p * L < M) {
-                        const float dx = (Xs[p] - cX) - Xc[p];
-                        const float dy = (Ys[p] - cY) - Yc[p];
-                        fdx += dx;
-                        fdy += dy;
-                        fXX = fmaf(dx, dx, fXX);
-                        fXY = fmaf(dx, dy, fXY);
-                        fYY = fmaf(dy, dy, fYY);
-                    }
-                }
-                const double refP = (double)rPs - (double)rPc;
-                const double sdx = moment_sum(fdx, L), sdy = moment_sum(fdy, L);
-                const double sP = moment_sum(fP, L);
-                const double svx = moment_sum(fvx, L), svy = moment_sum(fvy, L);
-                const double svr = moment_sum(fvr, L);
-                const double sXX = moment_sum(fXX, L), sXY = moment_sum(fXY, L);
-                const double sYY = moment_sum(fYY, L);
-                const double mdx = sdx * invM, mdy = sdy * invM;
-                bel[0] = x0[0] + ((double)cX + mdx);
-                bel[1] = x0[1] + ((double)cY + mdy);
-                bel[2] = x0[2] + (refP + sP * invM);   // heading: shifted by particle 0
+                // moments: FP64 sums over the L lanes (DPP inside a row, swaps across rows)
+                sX = group_sum(sX, L);
+                sY = group_sum(sY, L);
+                sP = group_sum(sP, L);
+                svx = group_sum(svx, L);
+                svy = group_sum(svy, L);
+                svr = group_sum(svr, L);
+                sXX = group_sum(sXX, L);
+                sXY = group_sum(sXY, L);
+                sYY = group_sum(sYY, L);
+                const double mX = sX * invM, mY = sY * invM;
+                bel[0] = x0[0] + (refX + mX);
+                bel[1] = x0[1] + (refY + mY);
+                bel[2] = x0[2] + sP * invM;
                 bel[3] = svx * invM;
                 bel[4] = svy * invM;
                 bel[5] = svr * invM;
-                bel[6] = (sXX - sdx * mdx) * invM1;
-                bel[7] = (sXY - sdx * mdy) * invM1;
-                bel[8] = (sYY - sdy * mdy) * invM1;
+                bel[6] = (sXX - sX * mX) * invM1;
+                bel[7] = (sXY - sX * mY) * invM1;
+                bel[8] = (sYY - sY * mY) * invM1;
 
                 // record t+1, written by lane (t+1) % L of the group (spreads the stores)
                 if (j == ((t + 1) & (L - 1))) {
