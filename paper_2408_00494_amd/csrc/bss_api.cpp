@@ -589,9 +589,11 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
     if (c->timing) {
         if (c->ev_used + 2 > c->ev.size()) {
             for (int i = 0; i < 64; ++i) {
+                // timing only (read after a stream synchronisation): no system-scope fence, so
+                // a record does not write back and invalidate the caches between the launches
                 hipEvent_t ev;
-                e = hipEventCreate(&ev);
-                if (e != hipSuccess) return device_fail(e, "hipEventCreate");
+                e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
+                if (e != hipSuccess) return device_fail(e, "hipEventCreateWithFlags");
                 c->ev.push_back(ev);
             }
         }
