@@ -68,10 +68,10 @@ def window_stats(series, wT, begin, end):
             "sum_abs_ey": float(np.sum(ey)), "sum_vx": float(np.sum(series["vx"][begin:end]))}
 
 
-def run(prob, steps, controller, record=False):
+def run(prob, steps, controller, record=False, keep_series=False):
     """Closed loop of `steps` plant steps; returns (stats dict, records).  records (if asked) hold
-    (n, x_n, warm start used at n, u0) for every step; stats["series"] holds the per-step e_y,
-    crash flag, barrier flag and vx."""
+    (n, x_n, warm start used at n, u0) for every step; stats["series"] (with record or
+    keep_series) holds the per-step e_y, crash flag, barrier flag and vx."""
     wT, gamma = prob["half_width"], prob["gamma"]
     sw = np.asarray(prob["sigma_w"], dtype=np.float64)
     st = {"steps": 0, "crashes": 0, "collision_steps": 0, "dcbf_ok": 0, "dcbf_n": 0,
@@ -116,7 +116,7 @@ def run(prob, steps, controller, record=False):
         else:
             x = xn
             h_prev = h
-    if record:
+    if record or keep_series:
         st["series"] = series
     return st, recs
 

@@ -1,7 +1,8 @@
 """Writes closed_loop_oracle.json: closed-loop statistics of the FP64 oracle controller on the
 shielded workload (K=8192, M=128, T=60, two repair iterations) for every (delta, gamma)
-combination, with the plant and episode rules of tests/closed_loop.py.  Calls only the oracle and
-the input generators.
+combination, with the plant and episode rules of tests/closed_loop.py, and the per-step series
+(e_y, crash flag, barrier flag, vx) they come from.  Calls only the oracle and the input
+generators.
 
     python tests/golden/make_closed_loop_oracle.py [steps] [nthreads]
 """
@@ -25,10 +26,11 @@ def main():
     for i, (d, g) in enumerate(CL.COMBOS):
         prob = CL.combo_problem(i)
         t0 = time.time()
-        st, _ = CL.run(prob, steps, CL.OracleController(prob, nthreads))
+        st, _ = CL.run(prob, steps, CL.OracleController(prob, nthreads), keep_series=True)
         st.update({"delta": d, "gamma": g, "seed": prob["seed"]})
         res["combos"].append(st)
-        print(f"delta={d} gamma={g}: {st} ({time.time() - t0:.0f} s)", flush=True)
+        shown = {key: val for key, val in st.items() if key != "series"}
+        print(f"delta={d} gamma={g}: {shown} ({time.time() - t0:.0f} s)", flush=True)
         with open(out_path, "w") as fh:
             json.dump(res, fh, indent=1)
 
