@@ -615,3 +615,33 @@ def test_local_repair_is_rejected_in_batches():
     with pytest.raises(RuntimeError, match="local_repair"):
         bss.Batch([solver])
     solver.close()
+
+
+@pytest.mark.parametrize("belief", [0, 1])
+def test_local_repair_with_initial_spread_matches_oracle(belief):
+    """The repair of the update from an uncertain estimate (Sigma0), with persistent particles and
+    with the Gaussian re-sampling reading (the repair rollout's own key also drives its
+    re-sampling draws): staged against the oracle's repair of the GPU's own v+."""
+    prob, _, v = W.config_small()
+    prob = dict(prob, K=128, M=16, T=20, shield_iters=4, gamma=0.3, belief=belief)
+    x0 = np.array([prob["ell_a"] + 0.8, 0.0, math.pi / 2 - 0.3, 6.0, 0.0, 0.0])
+    Sigma0 = np.diag([0.02, 0.02, 0.002, 0.05, 0.02, 0.01])
+    v = v[:prob["T"]]
+    s = 6
+    outs = {}
+    for name, p in (("pre", prob), ("repaired", dict(prob, local_repair=1))):
+        solver = bss.Solver(p)
+        solver.set_controls(v)
+        solver.solve_index = s
+        u0, _ = solver.solve(x0, Sigma0)
+        outs[name] = (solver.get_controls(), np.asarray(u0))
+        solver.close()
+    v_plus = outs["pre"][0]
+    v_safe, u0 = outs["repaired"]
+    assert np.array_equal(u0, v_safe[0])
+    ref_safe, _ = oracle.local_repair(prob, s, x0, v_plus, Sigma0=Sigma0)
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    assert np.max(np.abs(ref_safe - np.clip(v_plus, -scale, scale))) > 1e-2   # the repair acted
+    e_stage = ctrl_err(v_safe, ref_safe, prob)
+    print(f"local repair, Sigma0, belief {belief}: stage {e_stage:.2e}", flush=True)
+    assert e_stage <= 1e-4
