@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-resampling", action="store_true")
+    ap.add_argument("--no-shielded", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving trace replayed with batching (0 skips serving)")
     ap.add_argument("--plain-seconds", type=float, default=15.0,
@@ -171,6 +172,40 @@ def bench_resampling(bss, W, torch, steps=20, warmup=3):
                         "T=50)",
             "value": rs * steps / el, "unit": "rollout-steps/s", "ms_per_step": el * 1e3 / steps,
             "kernel_ms": kms / max(n, 1), "lanes": info["lanes"], "ppl": info["ppl"]}
+
+
+def bench_shielded(bss, W, torch, steps=20, warmup=3):
+    """The shielded workload of the closed-loop statistics (K=8192, M=128, T=60, two repair
+    iterations per sampled control and step), solved from a device-resident state; and the same
+    solve followed by the repair of its update (local_repair = 1)."""
+    out = {"workload": "shielded solve (K=8192, M=128, T=60, 2 repair iterations, delta=0.05, "
+                       "gamma=0.1)"}
+    for key, extra in (("shielded", {}), ("with_update_repair", {"local_repair": 1})):
+        prob, x0, v = W.config_shielded()
+        prob = dict(prob, **extra)
+        rs = prob["K"] * prob["M"] * prob["T"]
+        s = bss.Solver(prob)
+        s.set_outputs(controls=False)
+        x0_dev = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            s.solve_async(x0_dev)
+            s.step_shift()
+        torch.cuda.synchronize()
+        s.timing(True)
+        s.timing_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.solve_async(x0_dev)
+            s.step_shift()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kms, n = s.timing_read()
+        info = s.info()
+        s.close()
+        out[key] = {"value": rs * steps / el, "unit": "rollout-steps/s",
+                    "ms_per_step": el * 1e3 / steps, "kernel_ms": kms / max(n, 1),
+                    "lanes": info["lanes"], "ppl": info["ppl"]}
+    return out
 
 
 def bench_batched(bss, W, torch, rounds=20, warmup=3):
@@ -375,6 +410,10 @@ def main():
     if not args.no_resampling:
         out["resampling"] = bench_resampling(bss, W, torch)
         progress(f"re-sampling variant: {out['resampling']['value']:.3e} rollout-steps/s")
+    if not args.no_shielded:
+        out["shielded"] = bench_shielded(bss, W, torch)
+        progress(f"shielded: {out['shielded']['shielded']['value']:.3e} rollout-steps/s, with "
+                 f"the repair of the update {out['shielded']['with_update_repair']['value']:.3e}")
     if not args.no_batched:
         out["batched"] = bench_batched(bss, W, torch)
         progress(f"mixed batch: {out['batched']['batched']['value']:.3e} rollout-steps/s")
