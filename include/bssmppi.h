@@ -75,7 +75,7 @@ typedef enum bss_status {
  * Disturbance variants: crn = 1 gives every sample the same disturbance draws (common random
  *   numbers: the counter's sample word is 0); sigma_w_speed = kappa makes the disturbance depend
  *   on the state, p(w | x) with std sigma_w (1 + kappa |vx|) at the step's starting state.
- * Repair of the updated sequence (the local repair of v+ from the state estimate in Alg. 2):
+ * Repair of the updated sequence (the local repair of v+ from the state estimate in Alg. 1):
  *   local_repair = 1 or 2 runs, after the update, one more rollout from (xbar_0, Sigma_0) whose
  *   control at step t is clip(v+_t) repaired as above (shield_iters >= 1 required) against the
  *   belief of that rollout, and replaces v+ by the repaired sequence v_safe (held in single

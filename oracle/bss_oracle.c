@@ -714,7 +714,7 @@ static void cholesky6(const double* A, double* L)
     }
 }
 
-/* Repair of the updated sequence from the state estimate (the local repair of v+ that Alg. 2
+/* Repair of the updated sequence from the state estimate (the local repair of v+ that Alg. 1
  * carries between the update and the executed command): one more rollout from (xbar_0, Sigma_0)
  * whose control at step t is clip(v+_t), repaired against that rollout's belief at t exactly as
  * a sampled control is (orc_repair), then propagated; the repaired controls form v_safe.  The

@@ -57,7 +57,7 @@ typedef struct orc_params {
     int32_t n_obs;        /* circular obstacles (0..4), each a further chance constraint */
     double obs[12];       /* obstacle i: centre (obs[3i], obs[3i+1]), radius obs[3i+2] */
     int32_t local_repair; /* repair of the updated sequence from the estimate (the local repair
-                             of v+ in Alg. 2): 0 off, 1 after the update and in every sample,
+                             of v+ in Alg. 1): 0 off, 1 after the update and in every sample,
                              2 after the update only */
     int32_t model;
     double lin_A[36];

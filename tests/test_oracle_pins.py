@@ -915,7 +915,7 @@ def test_repair_steers_away_from_an_obstacle():
     assert h_pred(u_rep) > h_pred(u)
 
 
-# ---- repair of the updated sequence from the estimate (local repair of v+, Alg. 2) ----------
+# ---- repair of the updated sequence from the estimate (local repair of v+, Alg. 1) ----------
 
 LOCAL_REPAIR_KEY = 0x5DEECE66DA3B9F1B     # documented stream of the repair rollout
 
