@@ -432,7 +432,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->has_alloc = alloc != nullptr;
     if (alloc) c->alloc = *alloc;
     c->stream = (hipStream_t)stream;
-    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0, -1);
+    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0, -1, samples_shielded(*p));
     c->timing = false;
     c->ev_used = 0;
     c->pending_shift = 0;
@@ -844,7 +844,7 @@ bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl, int32_t split)
         return fail(BSS_E_INVAL, "M=%d needs more than 64 lanes with %d particles per lane", q.M,
                     ppl);
     if (split < -1 || split > 1) return fail(BSS_E_INVAL, "split must be -1, 0 or 1");
-    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl, split);
+    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl, split, samples_shielded(q));
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(e, "synchronising");
     c->shape = sh;

@@ -110,9 +110,10 @@ constexpr size_t kMaxLds = 65536;
 // dynamic LDS of one solve block with L lanes per sample (P = the kernel's particles per lane)
 size_t solve_lds_bytes(int lanes, int T, int ppl, bool split);
 // requested_split: -1 automatic (split when the launch has fewer than two waves per SIMD), 0 off,
-// 1 on (when the ring fits)
+// 1 on (when the ring fits); shield: the sampled controls are repaired (the automatic shape then
+// puts eight particles in a lane)
 LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl,
-                         int requested_split = -1);
+                         int requested_split = -1, bool shield = false);
 bool split_pays(int nblocks, int lanes, int T, int ppl);
 int solve_blocks(int K, int lanes);
 

@@ -1159,7 +1159,7 @@ bool split_pays(int nblocks, int lanes, int T, int ppl)
 }
 
 LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl,
-                         int requested_split)
+                         int requested_split, bool shield)
 {
     LaunchShape s;
     const bool lanes_ok = requested_lanes == 8 || requested_lanes == 16 || requested_lanes == 32 ||
@@ -1172,6 +1172,13 @@ LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested
         s.lanes = lanes;
     } else if (lanes_ok) {
         s.lanes = requested_lanes;
+    } else if (shield) {
+        // default with the repair: eight particles per lane, so that a wave holds as many samples
+        // as possible (the repair runs in five lanes of every group while the wave executes it
+        // once for all its groups: its cost is per wave, not per sample)
+        int lanes = 8;
+        while (lanes < 64 && lanes * 8 < M) lanes <<= 1;
+        s.lanes = lanes;
     } else {
         // default: about four particles per lane, 16..64 lanes per sample
         int lanes = 16;
