@@ -109,6 +109,11 @@ ScoreF64 make_score(const bss_params& p)
     s.shield_fd = p.shield_fd;
     s.n_obs = p.n_obs;
     for (int i = 0; i < 3 * kMaxObstacles; ++i) s.obs[i] = p.obs[i];
+    const double L = p.lf + p.lr;
+    s.Ffm = p.mu * p.m * p.g * p.lr / L;
+    s.Frm = p.mu * p.m * p.g * p.lf / L;
+    s.inv_m = 1.0 / p.m;
+    s.inv_Iz = 1.0 / p.Iz;
     return s;
 }
 

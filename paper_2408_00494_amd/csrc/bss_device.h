@@ -293,23 +293,22 @@ __device__ inline void car_deriv_f64(const ScoreF64& p, const double* x, double 
                                      double accel, double* dx)
 {
     const double psi = x[2], vx = x[3], vy = x[4], r = x[5];
-    const double vxs = fmax(vx, p.v_min);
-    const double af = steer - atan((vy + p.lf * r) / vxs);
-    const double ar = -atan((vy - p.lr * r) / vxs);
-    const double L = p.lf + p.lr;
-    const double Ffm = p.mu * p.m * p.g * p.lr / L;
-    const double Frm = p.mu * p.m * p.g * p.lf / L;
-    const double Ff = clampd(p.Cf * af, -Ffm, Ffm);
-    const double Fr = clampd(p.Cr * ar, -Frm, Frm);
+    // one reciprocal for both slip angles; force limits, 1/m and 1/Iz come precomputed (FP64
+    // division is a long instruction sequence on this GPU)
+    const double inv_vxs = 1.0 / fmax(vx, p.v_min);
+    const double af = steer - atan((vy + p.lf * r) * inv_vxs);
+    const double ar = -atan((vy - p.lr * r) * inv_vxs);
+    const double Ff = clampd(p.Cf * af, -p.Ffm, p.Ffm);
+    const double Fr = clampd(p.Cr * ar, -p.Frm, p.Frm);
     double sp, cp, sd, cd;
     sincos(psi, &sp, &cp);
     sincos(steer, &sd, &cd);
     dx[0] = vx * cp - vy * sp;
     dx[1] = vx * sp + vy * cp;
     dx[2] = r;
-    dx[3] = accel + vy * r - Ff * sd / p.m;
-    dx[4] = (Ff * cd + Fr) / p.m - vx * r;
-    dx[5] = (p.lf * Ff * cd - p.lr * Fr) / p.Iz;
+    dx[3] = accel + vy * r - Ff * sd * p.inv_m;
+    dx[4] = (Ff * cd + Fr) * p.inv_m - vx * r;
+    dx[5] = (p.lf * Ff * cd - p.lr * Fr) * p.inv_Iz;
 }
 
 // explicit midpoint step of the noise-free model in double precision
@@ -348,10 +347,11 @@ __device__ inline void ellipse_nearest_q1(double e0, double e1, double y0, doubl
                 double s = (0.5 * g / gn) / (e1 * e1 * gn);
                 if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
                 for (int it = 0; it < 200; ++it) {
-                    const double a0 = n0 / (s + r0), a1 = z1 / (s + 1.0);
+                    const double i0 = 1.0 / (s + r0), i1 = 1.0 / (s + 1.0);
+                    const double a0 = n0 * i0, a1 = z1 * i1;
                     const double F = a0 * a0 + a1 * a1 - 1.0;
                     if (F > 0.0) lo = s; else if (F < 0.0) hi = s; else break;
-                    const double dF = -2.0 * (a0 * a0 / (s + r0) + a1 * a1 / (s + 1.0));
+                    const double dF = -2.0 * (a0 * a0 * i0 + a1 * a1 * i1);
                     double sn = s - F / dF;
                     if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
                     const double step = fabs(sn - s);

@@ -45,6 +45,9 @@ struct ScoreF64 {
     double shield_gmin, shield_fd;
     int32_t n_obs;                  // circular obstacles: centre (obs[3i], obs[3i+1]), radius obs[3i+2]
     double obs[3 * kMaxObstacles];
+    // derived on the host: lateral force limits mu m g lr / (lf + lr), mu m g lf / (lf + lr), and
+    // 1 / m, 1 / Iz (the double-precision model multiplies instead of dividing)
+    double Ffm, Frm, inv_m, inv_Iz;
 };
 
 // One problem instance (device memory).
