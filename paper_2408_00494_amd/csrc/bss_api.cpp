@@ -190,10 +190,11 @@ struct bss_ctx {
     bss_batch* batch;         // batch that currently owns the context, or nullptr
     int batch_index;          // index of the context in that batch
     // repair of the updated sequence (local_repair != 0): its descriptor (host copy and device),
-    // one-block grid and the LDS of its unsplit launch
+    // one-block grid, its own launch shape and the LDS of that launch
     InstanceDesc rdesc;
     InstanceDesc* d_rdesc;
     BlockDesc* d_rblock;
+    LaunchShape rshape;
     size_t rlds;
 };
 
@@ -253,12 +254,6 @@ hipError_t upload_shape(bss_ctx* c)
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
-    if (c->d_rdesc) {
-        c->rdesc.lanes = c->shape.lanes;
-        c->rlds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, false);
-        e = hipMemcpy(c->d_rdesc, &c->rdesc, offsetof(InstanceDesc, cur), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return e;
-    }
     const std::vector<BlockDesc> tab = block_table(0, c->p.K, c->shape.lanes);
     return hipMemcpy(c->d_blocks, tab.data(), tab.size() * sizeof(BlockDesc),
                      hipMemcpyHostToDevice);
@@ -539,7 +534,11 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         r.partial = (double*)b;
         b += align256((2 * T + 4) * sizeof(double));
         r.stats = (double*)b;
-        c->rlds = solve_lds_bytes(c->shape.lanes, p->T, c->shape.ppl, false);
+        // a single sample is latency-bound: as many lanes as the particles can use (up to the
+        // wave), so that each lane steps few particles, whatever the shape of the sampled solve
+        c->rshape = choose_shape(1, p->M, p->T, 0, 1, 0, true);
+        r.lanes = c->rshape.lanes;
+        c->rlds = solve_lds_bytes(r.lanes, p->T, c->rshape.ppl, false);
     }
 
     hipError_t e = hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault);
@@ -618,7 +617,7 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
     if (e != hipSuccess) return device_fail(e, "merge launch");
     c->pending_shift = 0;
     if (c->d_rdesc) {
-        e = launch_local_repair(c->d_desc, c->d_rdesc, c->d_rblock, c->p.T, c->shape.ppl,
+        e = launch_local_repair(c->d_desc, c->d_rdesc, c->d_rblock, c->p.T, c->rshape.ppl,
                                 c->p.belief != 0, c->rlds, x0_dev, Sigma0_dev, c->stream);
         if (e != hipSuccess) return device_fail(e, "repair of the update");
     }
