@@ -42,7 +42,13 @@ class OrcParams(C.Structure):
         ("local_repair", C.c_int32),
         ("model", C.c_int32),
         ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
+        ("n_con", C.c_int32), ("con_a", C.c_double * 24), ("con_b", C.c_double * 4),
     ]
+
+
+# one belief record: mean (6), position covariance (3), a_i^T Sigma a_i of the half-space
+# constraints (4, zero beyond n_con)
+NMOM = 13
 
 
 def make_params(cfg: dict) -> OrcParams:
@@ -53,13 +59,15 @@ def make_params(cfg: dict) -> OrcParams:
         raise ValueError("local_repair is 0, 1 or 2")
     if cfg.get("local_repair", 0) and cfg.get("shield_iters", 0) < 1:
         raise ValueError("the repair of the update needs shield_iters >= 1")
+    if not 0 <= cfg.get("n_con", 0) <= 4:
+        raise ValueError("n_con is 0..4")
     p = OrcParams()
     for name, _ in OrcParams._fields_:
         key = "lambda" if name == "lambda_" else name
         if key not in cfg:
             continue
         val = cfg[key]
-        if name in ("sigma_eps", "sigma_w", "lin_A", "lin_B", "obs"):
+        if name in ("sigma_eps", "sigma_w", "lin_A", "lin_B", "obs", "con_a", "con_b"):
             arr = getattr(p, name)
             flat = np.asarray(val, dtype=np.float64).ravel()
             for i, x in enumerate(flat):
@@ -100,6 +108,10 @@ def _load():
     lib.orc_stage_cost.restype = C.c_double
     lib.orc_moments.argtypes = [_f64p, C.c_int32, _f64p]
     lib.orc_moments.restype = None
+    lib.orc_full_cov.argtypes = [_f64p, C.c_int32, _f64p]
+    lib.orc_full_cov.restype = None
+    lib.orc_con_spreads.argtypes = [P, _f64p, _f64p]
+    lib.orc_con_spreads.restype = None
     lib.orc_repair.argtypes = [P, C.c_double, _f64p, _f64p]
     lib.orc_repair.restype = None
     lib.orc_score.argtypes = [P, C.c_double, _f64p, _f64p, _f64p]
@@ -200,9 +212,23 @@ def ellipse_sdf(a, b, X, Y):
     return sd.value, n
 
 
-def barrier(cfg, nu, mom):
+def _records(mom, con_var=None):
+    """Belief records [..., NMOM] from position records [..., 9] and the constraint variances
+    [..., n_con] (zero when not given)."""
+    mom = np.asarray(mom, dtype=np.float64)
+    rec = np.zeros(mom.shape[:-1] + (NMOM,))
+    rec[..., :9] = mom[..., :9]
+    if con_var is not None:
+        cv = np.asarray(con_var, dtype=np.float64)
+        rec[..., 9:9 + cv.shape[-1]] = cv
+    return rec
+
+
+def barrier(cfg, nu, mom, con_var=None):
+    """Belief heuristic h of one record (9 entries), with the variances a_i^T Sigma a_i of the
+    half-space constraints when there are any."""
     p = make_params(cfg)
-    return lib().orc_barrier(C.byref(p), float(nu), np.ascontiguousarray(mom, dtype=np.float64))
+    return lib().orc_barrier(C.byref(p), float(nu), _records(mom, con_var))
 
 
 def stage_cost(cfg, mom):
@@ -217,28 +243,50 @@ def moments(particles):
     return out
 
 
-def repair(cfg, nu, mom_t, u):
+def full_cov(particles):
+    """Unbiased full 6x6 covariance of a particle set [M][6] (zero for one particle)."""
+    particles = np.ascontiguousarray(particles, dtype=np.float64)
+    out = np.zeros(36)
+    lib().orc_full_cov(particles, int(particles.shape[0]), out)
+    return out.reshape(6, 6)
+
+
+def con_spreads(cfg, cov):
+    """a_i^T Sigma a_i of the half-space constraints (four entries, zero beyond n_con)."""
+    p = make_params(cfg)
+    rec = np.zeros(NMOM)
+    lib().orc_con_spreads(C.byref(p), np.ascontiguousarray(cov, dtype=np.float64).ravel(), rec)
+    return rec[9:]
+
+
+def repair(cfg, nu, mom_t, u, con_var=None):
     p = make_params(cfg)
     uu = np.array(u, dtype=np.float64)
-    lib().orc_repair(C.byref(p), float(nu), np.ascontiguousarray(mom_t, dtype=np.float64), uu)
+    lib().orc_repair(C.byref(p), float(nu), _records(mom_t, con_var), uu)
     return uu
 
 
-def score(cfg, nu, mom, u, v):
-    """Trajectory cost of one sample from injected moments [T+1][9], controls [T][2], v [T][2]."""
+def score(cfg, nu, mom, u, v, con_var=None):
+    """Trajectory cost of one sample from injected moments [T+1][9] (and constraint variances
+    [T+1][n_con]), controls [T][2], v [T][2]."""
     p = make_params(cfg)
-    return lib().orc_score(C.byref(p), float(nu), np.ascontiguousarray(mom, dtype=np.float64),
+    return lib().orc_score(C.byref(p), float(nu), _records(mom, con_var),
                            np.ascontiguousarray(u, dtype=np.float64),
                            np.ascontiguousarray(v, dtype=np.float64))
 
 
-def rollout(cfg, s, k, x0, v, Sigma0=None):
-    """One sample's rollout: returns (S_k, u [T][2], moments [T+1][9])."""
+def _split(rec, n_con):
+    return rec[..., :9], rec[..., 9:9 + n_con]
+
+
+def rollout(cfg, s, k, x0, v, Sigma0=None, with_con=False):
+    """One sample's rollout: returns (S_k, u [T][2], moments [T+1][9]), and the constraint
+    variances [T+1][n_con] as a fourth item with with_con."""
     p = make_params(cfg)
     T = cfg["T"]
     nu = backoff(cfg["delta"], cfg.get("backoff", 0))
     u = np.zeros((T, 2))
-    mom = np.zeros((T + 1, 9))
+    mom = np.zeros((T + 1, NMOM))
     L0 = None
     S0 = None
     if Sigma0 is not None:
@@ -248,21 +296,24 @@ def rollout(cfg, s, k, x0, v, Sigma0=None):
                            np.ascontiguousarray(x0, dtype=np.float64), _ptr(S0),
                            _ptr(None if L0 is None else np.ascontiguousarray(L0)),
                            np.ascontiguousarray(v, dtype=np.float64), u, mom)
-    return Sk, u, mom
+    m9, cv = _split(mom, cfg.get("n_con", 0))
+    return (Sk, u, m9, cv) if with_con else (Sk, u, m9)
 
 
-def propagate(cfg, s, k, x0, u, Sigma0=None):
-    """Belief trajectory [T+1][9] of sample k under the given controls u [T][2]."""
+def propagate(cfg, s, k, x0, u, Sigma0=None, with_con=False):
+    """Belief trajectory [T+1][9] of sample k under the given controls u [T][2] (and the
+    constraint variances [T+1][n_con] with with_con)."""
     p = make_params(cfg)
     T = cfg["T"]
-    mom = np.zeros((T + 1, 9))
+    mom = np.zeros((T + 1, NMOM))
     S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
     L0 = None
     if S0 is not None and np.any(S0 != 0):
         L0 = np.ascontiguousarray(np.linalg.cholesky(S0))
     lib().orc_propagate(C.byref(p), int(s), int(k), np.ascontiguousarray(x0, dtype=np.float64),
                         _ptr(S0), _ptr(L0), np.ascontiguousarray(u, dtype=np.float64), mom)
-    return mom
+    m9, cv = _split(mom, cfg.get("n_con", 0))
+    return (m9, cv) if with_con else m9
 
 
 def update(cfg, S, u, v):
@@ -276,20 +327,21 @@ def update(cfg, S, u, v):
 
 
 def solve(cfg, s, x0, v, Sigma0=None, want_traces=True, nthreads=None):
-    """One full solve.  Returns dict(rc, v (updated), u, mom, S, stats)."""
+    """One full solve.  Returns dict(rc, v (updated), u, mom, con_var, S, stats)."""
     p = make_params(cfg)
     K, T = cfg["K"], cfg["T"]
     vv = np.array(v, dtype=np.float64).reshape(T, 2).copy()
     stats = np.zeros(4)
     u = np.zeros((K, T, 2)) if want_traces else None
-    mom = np.zeros((K, T + 1, 9)) if want_traces else None
+    mom = np.zeros((K, T + 1, NMOM)) if want_traces else None
     S = np.zeros(K)
     S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
     if nthreads is None:
         nthreads = min(8, os.cpu_count() or 1)
     rc = lib().orc_solve(C.byref(p), int(s), np.ascontiguousarray(x0, dtype=np.float64),
                          _ptr(S0), vv, _ptr(u), _ptr(mom), _ptr(S), stats, int(nthreads))
-    return {"rc": rc, "v": vv, "u": u, "mom": mom, "S": S, "stats": stats}
+    m9, cv = _split(mom, cfg.get("n_con", 0)) if want_traces else (None, None)
+    return {"rc": rc, "v": vv, "u": u, "mom": m9, "con_var": cv, "S": S, "stats": stats}
 
 
 def local_repair(cfg, s, x0, v_plus, Sigma0=None):
@@ -298,11 +350,11 @@ def local_repair(cfg, s, x0, v_plus, Sigma0=None):
     p = make_params(cfg)
     T = cfg["T"]
     v_safe = np.zeros((T, 2))
-    mom = np.zeros((T + 1, 9))
+    mom = np.zeros((T + 1, NMOM))
     S0 = None if Sigma0 is None else np.ascontiguousarray(Sigma0, dtype=np.float64)
     lib().orc_local_repair(C.byref(p), int(s), np.ascontiguousarray(x0, dtype=np.float64),
                            _ptr(S0), np.ascontiguousarray(v_plus, dtype=np.float64), v_safe, mom)
-    return v_safe, mom
+    return v_safe, mom[:, :9]
 
 
 def step_shift(v):

@@ -253,8 +253,11 @@ void orc_ellipse_sdf(double a, double b, double X, double Y, double* sd, double 
  * back-off exceeds the half-width (the literal square is non-monotone there). */
 /* Spread of each constraint at a belief (eq. 11, eta the constraint's gradient direction):
  * sig[0] for the track walls (the outward normal of the nearest centerline point), sig[1 + i] for
- * obstacle i (the unit vector from its centre to the mean position; (1, 0) at the centre). */
-static void constraint_sigmas(const orc_params* p, const double mom[9], double* sig)
+ * obstacle i (the unit vector from its centre to the mean position; (1, 0) at the centre),
+ * sig[5 + i] for half-space constraint i (eta = a_i, its variance a_i^T Sigma a_i held in the
+ * record). */
+#define SIG_CON 5
+static void constraint_sigmas(const orc_params* p, const double mom[ORC_NMOM], double* sig)
 {
     double ey, n[2];
     orc_ellipse_sdf(p->ell_a, p->ell_b, mom[0], mom[1], &ey, n);
@@ -267,13 +270,20 @@ static void constraint_sigmas(const orc_params* p, const double mom[9], double* 
         double v = ex * ex * mom[6] + 2.0 * ex * ey2 * mom[7] + ey2 * ey2 * mom[8];
         sig[1 + i] = sqrt(v > 0.0 ? v : 0.0);
     }
+    for (int i = 0; i < p->n_con; ++i) {
+        double v = mom[9 + i];
+        sig[SIG_CON + i] = sqrt(v > 0.0 ? v : 0.0);
+    }
 }
 
-/* h = min over the constraints (eq. 16) at mean position (X, Y) with the given spreads: the track
- * walls as eq. 33, h_0 = max(w_T - nu sig_0, 0)^2 - e_y^2, and each obstacle in the same form,
- * h_i = max(d_i - nu sig_i, 0)^2 - r_i^2 with d_i the distance to its centre. */
-static double barrier_at(const orc_params* p, double nu, double X, double Y, const double* sig)
+/* h = min over the constraints (eq. 16) at mean state x with the given spreads: the track walls
+ * as eq. 33, h_0 = max(w_T - nu sig_0, 0)^2 - e_y^2, each obstacle in the same form,
+ * h_i = max(d_i - nu sig_i, 0)^2 - r_i^2 with d_i the distance to its centre, and each half-space
+ * constraint as the heuristic of eq. 13 itself, h_i = -c_i(xbar) - nu sig_i = b_i - a_i^T xbar -
+ * nu sig_i (in the units of c_i: a_i and b_i set its weight against the squared-metre terms). */
+static double barrier_at(const orc_params* p, double nu, const double x[6], const double* sig)
 {
+    double X = x[0], Y = x[1];
     double ey, n[2];
     orc_ellipse_sdf(p->ell_a, p->ell_b, X, Y, &ey, n);
     double margin = p->half_width - nu * sig[0];
@@ -286,14 +296,21 @@ static double barrier_at(const orc_params* p, double nu, double X, double Y, con
         double hi = m * m - r * r;
         if (hi < h) h = hi;
     }
+    for (int i = 0; i < p->n_con; ++i) {
+        const double* a = &p->con_a[6 * i];
+        double ax = 0.0;
+        for (int j = 0; j < 6; ++j) ax += a[j] * x[j];
+        double hi = p->con_b[i] - ax - nu * sig[SIG_CON + i];
+        if (hi < h) h = hi;
+    }
     return h;
 }
 
-double orc_barrier(const orc_params* p, double nu, const double mom[9])
+double orc_barrier(const orc_params* p, double nu, const double mom[ORC_NMOM])
 {
-    double sig[5];
+    double sig[SIG_CON + ORC_MAX_CON];
     constraint_sigmas(p, mom, sig);
-    return barrier_at(p, nu, mom[0], mom[1], sig);
+    return barrier_at(p, nu, mom, sig);
 }
 
 /* Running state cost on the mean state (eqs. 27-28, evaluated at xbar as Alg. 1 does):
@@ -344,17 +361,51 @@ void orc_moments(const double* particles, int32_t M, double out[9])
     }
 }
 
+/* Full unbiased covariance 1/(M-1) sum (x^n - xbar)(x^n - xbar)^T of a particle set, two-pass
+ * (0 for a single particle): the covariance half of the belief z = [xbar; vec Sigma] (eq. 12). */
+void orc_full_cov(const double* particles, int32_t M, double cov[36])
+{
+    double mean[6];
+    for (int i = 0; i < 6; ++i) {
+        double acc = 0.0;
+        for (int m = 0; m < M; ++m) acc += particles[m * 6 + i];
+        mean[i] = acc / M;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+            for (int m = 0; m < M; ++m)
+                acc += (particles[m * 6 + i] - mean[i]) * (particles[m * 6 + j] - mean[j]);
+            cov[i * 6 + j] = M > 1 ? acc / (double)(M - 1) : 0.0;
+        }
+}
+
+/* The record's constraint entries from a full covariance: rec[9 + i] = a_i^T Sigma a_i, the
+ * variance along the gradient eta_i = a_i of half-space constraint i (eq. 11); 0 beyond n_con. */
+void orc_con_spreads(const orc_params* p, const double cov[36], double rec[ORC_NMOM])
+{
+    for (int i = 0; i < ORC_MAX_CON; ++i) {
+        double q = 0.0;
+        if (i < p->n_con) {
+            const double* a = &p->con_a[6 * i];
+            for (int r = 0; r < 6; ++r)
+                for (int c = 0; c < 6; ++c) q += a[r] * cov[r * 6 + c] * a[c];
+        }
+        rec[9 + i] = q;
+    }
+}
+
 /* ======================================= shield repair ====================================== */
 /* One-step DCBF residual of a candidate control at step t: the mean is pushed through the
  * noise-free model and the belief heuristic is re-evaluated with the spread frozen at step t:
  *   r(u) = -h(f(xbar_t, u); sigma_t) + (1 - gamma) h_t.
  * r <= 0 means the linear class-kappa condition (eq. 24) is predicted to hold. */
-static double repair_residual(const orc_params* p, double nu, const double mom_t[9],
+static double repair_residual(const orc_params* p, double nu, const double mom_t[ORC_NMOM],
                               const double* sig_t, double h_t, const double u[2])
 {
     double xn[6];
     orc_model_step(p, mom_t, u, xn);
-    double h_next = barrier_at(p, nu, xn[0], xn[1], sig_t);
+    double h_next = barrier_at(p, nu, xn, sig_t);
     return -h_next + (1.0 - p->gamma) * h_t;
 }
 
@@ -366,10 +417,10 @@ static double repair_residual(const orc_params* p, double nu, const double mom_t
  * condition is returned unchanged; the damping gmin bounds the step where the control has little
  * authority over the next belief, and the map from (u, belief) to the repaired control is
  * continuous. */
-void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[2])
+void orc_repair(const orc_params* p, double nu, const double mom_t[ORC_NMOM], double u[2])
 {
     if (p->shield_iters <= 0) return;
-    double sigma_t[5];
+    double sigma_t[SIG_CON + ORC_MAX_CON];
     constraint_sigmas(p, mom_t, sigma_t);
     double h_t = orc_barrier(p, nu, mom_t);
     double fd = p->shield_fd;
@@ -454,6 +505,9 @@ static void init_particles(const orc_params* p, uint32_t s, int32_t k, const dou
     mom0[6] = Sigma0 ? Sigma0[0] : 0.0;
     mom0[7] = Sigma0 ? Sigma0[1] : 0.0;
     mom0[8] = Sigma0 ? Sigma0[7] : 0.0;
+    double cov0[36];
+    for (int i = 0; i < 36; ++i) cov0[i] = Sigma0 ? Sigma0[i] : 0.0;
+    orc_con_spreads(p, cov0, mom0);
 }
 
 void orc_chol_psd6(const double* A, double* L)
@@ -551,6 +605,7 @@ static void sigma_step(const orc_params* p, const double u[2], double* part, dou
     mom_next[6] = cov_next[0];
     mom_next[7] = cov_next[1];
     mom_next[8] = cov_next[7];
+    orc_con_spreads(p, cov_next, mom_next);
     sigma_points(mean, cov_next, part);
 }
 
@@ -576,6 +631,9 @@ static void propagate_step(const orc_params* p, uint32_t s, int32_t k, int t, co
     }
     memcpy(part, nxt, sizeof(double) * 6 * (size_t)M);
     orc_moments(part, M, mom_next);
+    double cov[36];
+    orc_full_cov(part, M, cov);
+    orc_con_spreads(p, cov, mom_next);
 }
 
 /* Belief at t = 0: Monte-Carlo particles (init_particles), or the sigma points of (x0, Sigma0). */
@@ -720,7 +778,7 @@ static void cholesky6(const double* A, double* L)
  * a sampled control is (orc_repair), then propagated; the repaired controls form v_safe.  The
  * rollout's particles draw their disturbance and initial spread from a stream of their own: the
  * Philox key of seed ^ ORC_LOCAL_REPAIR_KEY with sample word 0 and the solve's index s.
- * mom_out [T+1][9] may be NULL. */
+ * mom_out [T+1][ORC_NMOM] may be NULL. */
 #define ORC_LOCAL_REPAIR_KEY 0x5DEECE66DA3B9F1Bull
 
 void orc_local_repair(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
@@ -775,8 +833,9 @@ static void* rollout_worker(void* arg)
  * update of v in place, then (local_repair 1 or 2) the repair of the updated sequence from the
  * estimate; with local_repair = 2 the sampled controls are not repaired.  Sigma0 (6x6,
  * row-major) may be NULL for a known initial state.
- * u_out [K][T][2], mom_out [K][T+1][9] and S_out [K] may be NULL.  Work is split over K across
- * nthreads threads; results do not depend on the split. Returns 0, or 1 when no cost is finite. */
+ * u_out [K][T][2], mom_out [K][T+1][ORC_NMOM] and S_out [K] may be NULL.  Work is split over K
+ * across nthreads threads; results do not depend on the split. Returns 0, or 1 when no cost is
+ * finite. */
 int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
                   double* v, double* u_out, double* mom_out, double* S_out, double stats[4],
                   int32_t nthreads)

@@ -36,6 +36,10 @@ extern "C" {
  *    damping and its finite-difference step
  *  seed: Philox key
  *  model: 0 = car with explicit-midpoint RK2, 1 = linear test model x+ = A x + B u (+ noise)
+ *  n_con, con_a, con_b: up to four half-space constraints on the whole state,
+ *    c_i(x) = a_i^T x - b_i <= 0 with a_i = con_a[6i..6i+5] over (X, Y, psi, vx, vy, r), each a
+ *    further chance constraint with gradient eta_i = a_i and heuristic
+ *    h_i = b_i - a_i^T xbar - nu sqrt(a_i^T Sigma a_i) over the full 6x6 covariance Sigma
  */
 typedef struct orc_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
@@ -62,12 +66,19 @@ typedef struct orc_params {
     int32_t model;
     double lin_A[36];
     double lin_B[12];
+    int32_t n_con;        /* half-space state constraints (0..4) */
+    double con_a[24];     /* constraint i: a_i = con_a[6i..6i+5] */
+    double con_b[4];      /* constraint i: bound b_i */
 } orc_params;
 
-/* Layout of one moment record (9 doubles): mean X, Y, psi, vx, vy, r, then the position
- * covariance Sxx, Sxy, Syy.  Only the position block of the covariance enters the belief
- * heuristic, so only it is kept (the paper notes a reduced covariance may suffice). */
-#define ORC_NMOM 9
+#define ORC_MAX_CON 4
+
+/* Layout of one belief record (13 doubles): mean X, Y, psi, vx, vy, r, then the position
+ * covariance Sxx, Sxy, Syy, then a_i^T Sigma a_i for the half-space constraints i < n_con (0 in
+ * the unused entries).  The belief z = [xbar; vec Sigma] of eq. 12 enters the heuristic only
+ * through these projections of Sigma, so only they are kept; the last four come from the full
+ * 6x6 covariance. */
+#define ORC_NMOM 13
 
 /* ---- random numbers: Philox4x32-10 (Salmon et al., SC'11) and Box-Muller --------------- */
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -90,14 +101,16 @@ void orc_model_step(const orc_params* p, const double x[6], const double u[2], d
 
 /* ---- track geometry and belief heuristic ------------------------------------------------ */
 void   orc_ellipse_sdf(double a, double b, double X, double Y, double* sd, double n[2]);
-double orc_barrier(const orc_params* p, double nu, const double mom[9]);
+double orc_barrier(const orc_params* p, double nu, const double mom[ORC_NMOM]);
 double orc_stage_cost(const orc_params* p, const double mom[9]);
 
 /* ---- Monte-Carlo moments (Alg. 2) --------------------------------------------------------- */
 void orc_moments(const double* particles, int32_t M, double out[9]);
+void orc_full_cov(const double* particles, int32_t M, double cov[36]);
+void orc_con_spreads(const orc_params* p, const double cov[36], double rec[ORC_NMOM]);
 
 /* ---- shield repair of one control ------------------------------------------------------- */
-void orc_repair(const orc_params* p, double nu, const double mom_t[9], double u[2]);
+void orc_repair(const orc_params* p, double nu, const double mom_t[ORC_NMOM], double u[2]);
 
 /* ---- one sample's rollout and its cost ---------------------------------------------------- */
 double orc_score(const orc_params* p, double nu, const double* mom, const double* u,
@@ -119,7 +132,7 @@ int32_t orc_solve(const orc_params* p, uint32_t s, const double x0[6], const dou
                   int32_t nthreads);
 
 /* repair of the updated sequence from the estimate (local_repair; v_safe [T][2], mom_out
- * [T+1][9] or NULL) */
+ * [T+1][ORC_NMOM] or NULL) */
 void orc_local_repair(const orc_params* p, uint32_t s, const double x0[6], const double* Sigma0,
                       const double* v_plus, double* v_safe, double* mom_out);
 

@@ -43,6 +43,9 @@ _DEFAULTS = dict(
     # repair of the updated sequence from the state estimate: 0 off, 1 in addition to the repair
     # of every sample, 2 instead of it (uses the shield_* settings)
     local_repair=0,
+    # half-space constraints on the whole state (up to 4): a_i^T x <= b_i with
+    # a_i = con_a[6i..6i+5] over (X, Y, psi, vx, vy, r) and b_i = con_b[i]
+    n_con=0, con_a=[0.0] * 24, con_b=[0.0] * 4,
 )
 
 

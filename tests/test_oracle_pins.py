@@ -1001,3 +1001,194 @@ def test_local_repair_argument_checks():
         oracle.make_params(W.default_problem(local_repair=3))
     with pytest.raises(ValueError):
         oracle.make_params(W.default_problem(local_repair=1, shield_iters=0))
+
+
+# ============================ half-space constraints on the state ============================
+def _con_problem(rows, bounds, **kw):
+    """Problem with len(rows) half-space constraints a_i^T x <= b_i."""
+    a = np.zeros(24)
+    b = np.zeros(4)
+    for i, (row, bound) in enumerate(zip(rows, bounds)):
+        a[6 * i:6 * i + 6] = row
+        b[i] = bound
+    return W.default_problem(n_con=len(rows), con_a=list(a), con_b=list(b), **kw)
+
+
+def test_full_covariance_matches_library():
+    """The full 6x6 estimate equals NumPy's unbiased covariance, its position block is the
+    record's (same two-pass sums), and a single particle gives zero."""
+    rng = np.random.default_rng(7)
+    P = rng.normal(size=(50, 6)) * [3.0, 2.0, 0.5, 1.0, 0.2, 0.1] + [100.0, -40.0, 1.0, 6.0, 0, 0]
+    cov = oracle.full_cov(P)
+    want = np.cov(P.T, ddof=1)
+    assert np.max(np.abs(cov - want)) <= 1e-12 * np.max(np.abs(want))
+    m = oracle.moments(P)
+    assert [cov[0, 0], cov[0, 1], cov[1, 1]] == list(m[6:])
+    assert np.array_equal(oracle.full_cov(P[:1]), np.zeros((6, 6)))
+
+
+def test_constraint_spread_is_variance_of_the_projection():
+    """a^T Sigma a equals the unbiased variance of the projected particles a^T x^n (brute force
+    on the scalars); entries beyond n_con are zero."""
+    rng = np.random.default_rng(8)
+    P = rng.normal(size=(40, 6)) * [3.0, 2.0, 0.5, 1.0, 0.2, 0.1]
+    rows = [rng.normal(size=6), [0, 0, 0, 1.0, 0, 0], rng.normal(size=6)]
+    cfg = _con_problem(rows, [1.0, 2.0, 3.0])
+    got = oracle.con_spreads(cfg, oracle.full_cov(P))
+    for i, a in enumerate(rows):
+        y = P @ np.asarray(a, dtype=np.float64)
+        want = np.sum((y - y.mean()) ** 2) / (len(y) - 1)
+        assert got[i] == pytest.approx(want, rel=1e-12)
+    assert got[3] == 0.0
+
+
+def test_constraint_variance_linear_model_closed_form():
+    """On the linear-Gaussian model the recorded a^T Sigma_t a of constraints on the velocity
+    states and on mixed directions follows a^T (A Sigma A^T + Q) a within 5 standard errors of a
+    sample variance (sqrt(2 / (M - 1)) relative) at M = 2^16."""
+    M = 1 << 16
+    base, A, Q = _linear_problem(M)
+    rows = [np.array([0, 0, 0, 1.0, 0, 0]), np.array([0, 0, 1.0, 0, 0, 2.0]),
+            np.array([0.5, 0, 0, 0, -1.0, 0]), np.array([1.0, 1.0, 0, 0.3, 0, 0])]
+    cfg = dict(_con_problem(rows, [10.0] * 4), **{k: base[k] for k in
+                                                  ("model", "lin_A", "lin_B", "K", "M", "T",
+                                                   "sigma_w", "sigma_eps")})
+    x0 = np.array([1.0, 2.0, 0.0, 3.0, 0.5, 0.1])
+    mom, cv = oracle.propagate(cfg, 0, 0, x0, np.zeros((cfg["T"], 2)), with_con=True)
+    assert cv.shape == (cfg["T"] + 1, 4)
+    assert np.array_equal(cv[0], np.zeros(4))
+    Sig = np.zeros((6, 6))
+    for t in range(1, cfg["T"] + 1):
+        Sig = A @ Sig @ A.T + Q
+        for i, a in enumerate(rows):
+            want = a @ Sig @ a
+            assert abs(cv[t, i] - want) <= 5 * want * math.sqrt(2.0 / (M - 1)) + 1e-15
+
+
+def test_constraint_variance_sigma_points_exact_with_initial_spread():
+    """Sigma points on the linear model: the recorded a^T Sigma_t a equals the exact recursion from
+    a nonzero Sigma_0 (record 0 is a^T Sigma_0 a), disturbance covariance included."""
+    base, A, Q = _linear_problem(12, T=6)
+    rows = [np.array([0, 0, 0, 1.0, 0, 0]), np.array([0.3, -0.2, 0.1, 0.5, 1.0, -2.0])]
+    cfg = dict(_con_problem(rows, [10.0, 10.0]), belief=2,
+               **{k: base[k] for k in ("model", "lin_A", "lin_B", "K", "M", "T", "sigma_w",
+                                       "sigma_eps")})
+    x0 = np.array([1.0, 2.0, 0.0, 3.0, 0.5, 0.1])
+    G = np.random.default_rng(1).normal(size=(6, 6)) * 0.1
+    S0 = G @ G.T
+    _, cv = oracle.propagate(cfg, 0, 0, x0, np.zeros((cfg["T"], 2)), Sigma0=S0, with_con=True)
+    Sig = S0.copy()
+    for t in range(cfg["T"] + 1):
+        if t > 0:
+            Sig = A @ Sig @ A.T + Q
+        want = np.array([a @ Sig @ a for a in rows])
+        assert np.max(np.abs(cv[t] - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_position_constraints_reproduce_the_position_block():
+    """On the car with persistent particles, constraints along X, along Y and along X + Y record
+    Sigma_XX, Sigma_YY and Sigma_XX + 2 Sigma_XY + Sigma_YY of the same particle sets."""
+    rows = [np.array([1.0, 0, 0, 0, 0, 0]), np.array([0, 1.0, 0, 0, 0, 0]),
+            np.array([1.0, 1.0, 0, 0, 0, 0])]
+    cfg = _con_problem(rows, [1e3] * 3, K=4, M=24, T=20, sigma_w=[0.3, 0.3, 0.2])
+    x0 = W.pose_on_centerline(cfg["ell_a"], cfg["ell_b"], 0.4, vx=6.0)
+    Sigma0 = np.diag([0.04, 0.09, 0.01, 0.2, 0.05, 0.02])
+    mom, cv = oracle.propagate(cfg, 3, 1, x0, np.tile([0.05, 0.5], (20, 1)), Sigma0=Sigma0,
+                               with_con=True)
+    assert np.array_equal(cv[:, 0], mom[:, 6])
+    assert np.array_equal(cv[:, 1], mom[:, 8])
+    s = mom[:, 6] + 2 * mom[:, 7] + mom[:, 8]
+    assert np.max(np.abs(cv[:, 2] - s)) <= 1e-12 * np.max(np.abs(s))
+    assert np.all(cv[1:, 2] > 0)
+
+
+def test_constraint_barrier_closed_form_and_minimum():
+    """h = min(track, constraints): with a wide track a speed limit vx <= b is the minimum and
+    equals b - vx - nu sqrt(var); a far bound leaves the track's h; a negative rounding variance
+    counts as zero."""
+    nu = oracle.backoff(0.05)
+    rows = [np.array([0, 0, 0, 1.0, 0, 0])]
+    rec = np.array([30.5, 0.2, 1.7, 6.0, 0.1, 0.02, 0.04, 0.01, 0.09])
+    wide = _con_problem(rows, [6.5], half_width=50.0)
+    h = oracle.barrier(wide, nu, rec, [0.16])
+    assert h == pytest.approx(6.5 - 6.0 - nu * 0.4, rel=1e-14)
+    track_only = oracle.barrier(dict(wide, n_con=0), nu, rec)
+    assert track_only > h
+    far = _con_problem(rows, [1e6], half_width=50.0)
+    assert oracle.barrier(far, nu, rec, [0.16]) == track_only
+    assert oracle.barrier(wide, nu, rec, [-1e-18]) == pytest.approx(0.5, rel=1e-14)
+    mixed = _con_problem([np.array([0.5, 0, 0, -1.0, 0, 2.0])], [0.0], half_width=50.0)
+    want = 0.0 - (0.5 * 30.5 - 6.0 + 2 * 0.02) - nu * math.sqrt(0.25)
+    assert oracle.barrier(mixed, nu, rec, [0.25]) == pytest.approx(want, rel=1e-14)
+
+
+def test_constraint_repair_brakes_at_a_speed_limit():
+    """A speed limit that the full-throttle control would cross: the repair lowers the
+    acceleration, reduces the one-step residual r(u) = -h(f(xbar, u)) + (1 - gamma) h_t (spread
+    frozen; zero position covariance so the track term is spread-free) and leaves a control that
+    already satisfies the condition unchanged."""
+    nu = oracle.backoff(0.05)
+    limit = 6.3
+    cfg = _con_problem([np.array([0, 0, 0, 1.0, 0, 0])], [limit], half_width=50.0,
+                       shield_iters=6)
+    xb = W.pose_on_centerline(cfg["ell_a"], cfg["ell_b"], 0.3, vx=6.0)
+    rec = np.concatenate([xb, [0.0, 0.0, 0.0]])
+    cvar = [0.01]
+    h_t = oracle.barrier(cfg, nu, rec, cvar)
+
+    def resid(u):
+        xn = oracle.model_step(cfg, xb, u)
+        return -oracle.barrier(cfg, nu, np.concatenate([xn, [0.0, 0.0, 0.0]]), cvar) + \
+            (1 - cfg["gamma"]) * h_t
+
+    u = np.array([0.0, 4.0])
+    assert resid(u) > 0
+    ur = oracle.repair(cfg, nu, rec, u, cvar)
+    assert ur[1] < u[1]
+    assert resid(ur) < 0.05 * resid(u)
+    ok = np.array([0.0, -2.0])
+    assert resid(ok) <= 0
+    assert np.array_equal(oracle.repair(cfg, nu, rec, ok, cvar), ok)
+
+
+def test_constraint_score_term_closed_form():
+    """With the constraint as the minimum everywhere, the score's safety part is
+    C sum_{t>=1} max(-h_t + (1 - gamma) h_{t-1}, 0) with h_t = b - vx_t - nu sqrt(var_t)."""
+    nu = oracle.backoff(0.05)
+    T = 12
+    rng = np.random.default_rng(3)
+    cfg = _con_problem([np.array([0, 0, 0, 1.0, 0, 0])], [7.0], half_width=50.0, T=T)
+    mom = np.zeros((T + 1, 9))
+    mom[:, 0] = cfg["ell_a"]
+    mom[:, 2] = math.pi / 2
+    mom[:, 3] = 6.0 + 0.08 * np.arange(T + 1) + 0.05 * rng.normal(size=T + 1)
+    var = 0.01 + 0.002 * np.arange(T + 1)
+    u = rng.normal(size=(T, 2)) * 0.1
+    v = rng.normal(size=(T, 2)) * 0.1
+    with_c = oracle.score(cfg, nu, mom, u, v, var[:, None])
+    without = oracle.score(dict(cfg, C_cbf=0.0), nu, mom, u, v, var[:, None])
+    h = 7.0 - mom[:, 3] - nu * np.sqrt(var)
+    viol = np.maximum(-h[1:] + (1 - cfg["gamma"]) * h[:-1], 0.0)
+    assert viol.sum() > 0
+    assert with_c - without == pytest.approx(cfg["C_cbf"] * viol.sum(), rel=1e-12)
+
+
+def test_inactive_constraint_leaves_the_solve_unchanged():
+    """A bound no belief comes near gives h = the track's everywhere: the solve is bitwise the
+    unconstrained one."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, K=32, T=12, shield_iters=2)
+    v = v[:12]
+    a = oracle.solve(prob, 1, x0, v, nthreads=2)
+    rows = [np.array([0, 0, 0, 1.0, 0, 0])]
+    far = dict(prob, n_con=1, con_a=list(np.concatenate([rows[0], np.zeros(18)])),
+               con_b=[1e9, 0.0, 0.0, 0.0])
+    b = oracle.solve(far, 1, x0, v, nthreads=2)
+    for key in ("v", "u", "mom", "S", "stats"):
+        assert np.array_equal(a[key], b[key]), key
+    assert b["con_var"].shape == (32, 13, 1)
+
+
+def test_constraint_argument_checks():
+    with pytest.raises(ValueError):
+        oracle.make_params(W.default_problem(n_con=5))
