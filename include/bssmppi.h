@@ -84,6 +84,16 @@ typedef enum bss_status {
  *   the Philox key of seed ^ 0x5DEECE66DA3B9F1B, sample word 0.  local_repair = 1 keeps the
  *   repair of every sampled control as well; 2 samples without it (repair of the update only).
  *   Not available in batches (bss_batch_create rejects such contexts).
+ * Half-space constraints on the whole state (the general back-off constraint of eq. 11 with the
+ *   heuristic of eq. 13 on the belief z = [xbar; vec Sigma] of eq. 12): n_con (0..4) constraints
+ *   c_i(x) = a_i^T x - b_i <= 0, a_i = con_a[6i..6i+5] over (X, Y, psi, vx, vy, r), b_i =
+ *   con_b[i].  Each is a further term of h = min_i h_i (eq. 16) with
+ *   h_i = b_i - a_i^T xbar - nu sqrt(a_i^T Sigma a_i), Sigma the full 6x6 covariance of the belief,
+ *   in the units of c_i (scale a_i and b_i to weigh it against the track's squared-metre form).
+ *   The belief keeps a_i^T Sigma a_i per record (the variance of the particles' projections
+ *   a_i^T x^n, the same unbiased estimate as the covariance; with sigma points plus a_i^T Q a_i of
+ *   the disturbance).  Such instances run in the generic rollout variant (no separate noise
+ *   waves); the staged bss_dev_score and bss_dev_repair reject n_con > 0.
  */
 typedef struct bss_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
@@ -105,6 +115,9 @@ typedef struct bss_params {
     int32_t n_obs;
     double obs[12];
     int32_t local_repair;
+    int32_t n_con;
+    double con_a[24];
+    double con_b[4];
 } bss_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a
@@ -127,7 +140,9 @@ typedef struct bss_allocator {
  *   stats  [8]          double  S_min, Z = sum_k w_k, ESS = Z^2/sum w^2, #finite costs,
  *                               status (0 ok, 5 numeric), v+_0 (steer, accel), unused
  *   x0     [6]          double  staging slot for the state estimate
- *   Sigma0 [36]         double  staging slot for the state-estimate covariance            */
+ *   Sigma0 [36]         double  staging slot for the state-estimate covariance
+ *   con_var [K][T+1][n_con] double  a_i^T Sigma a_i of the half-space constraints per record
+ *                               (NULL when n_con = 0); record 0 holds a_i^T Sigma0 a_i     */
 typedef struct bss_buffers {
     double* v;
     float* u;
@@ -138,6 +153,8 @@ typedef struct bss_buffers {
     double* Sigma0;
     int32_t v_shift;   /* warm-start shifts pending on v: the mean sequence is
                           v[min(t + v_shift, T - 1)] */
+    double* con_var;   /* [K][T+1][n_con] a_i^T Sigma a_i of the half-space constraints per
+                          sample and record, or NULL when n_con = 0 */
 } bss_buffers;
 
 /* Optional per-solve copy to device memory (bss_set_outputs); the solve itself does not need it. */

@@ -59,6 +59,7 @@ class Solver:
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
         self.problem = dict(problem)
         self.K, self.M, self.T = int(problem["K"]), int(problem["M"]), int(problem["T"])
+        self._n_con = int(problem.get("n_con", 0))
         self._params = params_from_problem(dict(problem, lanes=lanes))
         self._device = torch.device("cuda", torch.cuda.current_device())
         self._stream = stream if stream is not None else torch.cuda.current_stream()
@@ -152,7 +153,8 @@ class Solver:
 
     def buffers(self):
         """Torch views of the context's device buffers: v (current mean sequence, before any
-        pending warm-start shift), u, mom, S, stats.  Query again after each solve (the mean
+        pending warm-start shift), u, mom, S, stats, and con_var (a_i^T Sigma a_i of the half-space
+        constraints, [K][T+1][n_con]) when there are any.  Query again after each solve (the mean
         sequence alternates between two buffers)."""
         torch = _torch()
         b = _lib.BssBuffers()
@@ -163,7 +165,7 @@ class Solver:
         def view(ptr, nbytes, dtype, shape):
             off = ptr - base_ptr
             return blk[off:off + nbytes].view(dtype).reshape(shape)
-        return {
+        out = {
             "v": view(b.v, T * 2 * 8, torch.float64, (T, 2)),
             "u": view(b.u, K * T * 2 * 4, torch.float32, (K, T, 2)),
             "mom": view(b.mom, K * (T + 1) * 9 * 8, torch.float64, (K, T + 1, 9)),
@@ -171,6 +173,10 @@ class Solver:
             "stats": view(b.stats, 8 * 8, torch.float64, (8,)),
             "v_shift": b.v_shift,
         }
+        if b.con_var:
+            n = self._n_con
+            out["con_var"] = view(b.con_var, K * (T + 1) * n * 8, torch.float64, (K, T + 1, n))
+        return out
 
     # ---- timing -------------------------------------------------------------------------------
     def timing(self, enable: bool):

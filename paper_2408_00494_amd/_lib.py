@@ -47,6 +47,9 @@ class BssParams(C.Structure):
         ("n_obs", C.c_int32),
         ("obs", C.c_double * 12),
         ("local_repair", C.c_int32),
+        ("n_con", C.c_int32),
+        ("con_a", C.c_double * 24),
+        ("con_b", C.c_double * 4),
     ]
 
 
@@ -59,7 +62,7 @@ class BssAllocator(C.Structure):
 class BssBuffers(C.Structure):
     _fields_ = [("v", C.c_void_p), ("u", C.c_void_p), ("mom", C.c_void_p), ("S", C.c_void_p),
                 ("stats", C.c_void_p), ("x0", C.c_void_p), ("Sigma0", C.c_void_p),
-                ("v_shift", C.c_int32)]
+                ("v_shift", C.c_int32), ("con_var", C.c_void_p)]
 
 
 class BssInfo(C.Structure):
@@ -192,7 +195,7 @@ def params_from_problem(problem: dict) -> BssParams:
         if key not in problem:
             continue
         val = problem[key]
-        if name in ("sigma_eps", "sigma_w", "obs"):
+        if name in ("sigma_eps", "sigma_w", "obs", "con_a", "con_b"):
             arr = getattr(p, name)
             for i, x in enumerate(val):
                 arr[i] = float(x)

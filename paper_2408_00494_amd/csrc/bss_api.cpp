@@ -109,6 +109,9 @@ ScoreF64 make_score(const bss_params& p)
     s.shield_fd = p.shield_fd;
     s.n_obs = p.n_obs;
     for (int i = 0; i < 3 * kMaxObstacles; ++i) s.obs[i] = p.obs[i];
+    s.n_con = p.n_con;
+    for (int i = 0; i < 6 * kMaxCon; ++i) s.con_a[i] = p.con_a[i];
+    for (int i = 0; i < kMaxCon; ++i) s.con_b[i] = p.con_b[i];
     const double L = p.lf + p.lr;
     s.Ffm = p.mu * p.m * p.g * p.lr / L;
     s.Frm = p.mu * p.m * p.g * p.lf / L;
@@ -211,6 +214,7 @@ struct bss_batch {
     int nblocks, ncols, ppl, shift_after;
     bool split;               // 512-thread blocks with noise-producing waves
     bool resample;            // some member redraws its particles every step
+    bool con;                 // some member has half-space constraints
     std::vector<int> lanes;   // lanes per sample of each member in the current layout
     size_t lds;
     bool shield;
@@ -226,12 +230,17 @@ constexpr size_t kStateBytes = offsetof(InstanceDesc, shift_after) - offsetof(In
 
 size_t max_blocks(int K) { return (size_t)solve_blocks(K, 64); }
 
-// sizes, params and launch shape of a context's descriptor (state fields zero, buffers unset)
+// the sampled controls are repaired (the per-sample shield) unless only the update is repaired
+bool samples_shielded(const bss_params& p) { return p.shield_iters > 0 && p.local_repair != 2; }
+
+// sizes, params and launch shape of a context's descriptor (state fields zero, buffers unset);
+// its repair iterations are those of the sampled controls (none when only the update is repaired)
 void fill_desc(bss_ctx* c)
 {
     c->desc = make_desc(c->p);
     c->desc.lanes = c->shape.lanes;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
+    if (!samples_shielded(c->p)) c->desc.sc.shield_iters = 0;
 }
 
 std::vector<BlockDesc> block_table(int inst, int K, int lanes)
@@ -241,14 +250,21 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
     return out;
 }
 
-// the sampled controls are repaired (the per-sample shield) unless only the update is repaired
-bool samples_shielded(const bss_params& p) { return p.shield_iters > 0 && p.local_repair != 2; }
+// Kernel variant flags of an instance.  Half-space constraints live only in a variant of the
+// generic kernel (shield and re-sampling both compiled in, each switched at run time by the
+// descriptor: no repair while sc.shield_iters is 0, persistent particles while belief is 0).
+bool launch_shield(const bss_params& p) { return samples_shielded(p) || p.n_con > 0; }
+bool launch_resample(const bss_params& p) { return p.belief != 0 || p.n_con > 0; }
+
+// the automatic shape's eight particles per lane for the repair: the plain shielded variant only
+// (the generic ones run out of registers at eight)
+bool shape_for_shield(const bss_params& p) { return samples_shielded(p) && !launch_resample(p); }
 
 hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
-    c->shape.split = c->shape.split && !samples_shielded(c->p) && c->p.belief == 0;
+    c->shape.split = c->shape.split && !launch_shield(c->p) && !launch_resample(c->p);
     c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
     // static leading fields only: the device state is left as it is
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
@@ -321,6 +337,9 @@ void bss_params_default(bss_params* p)
     p->n_obs = 0;
     for (int i = 0; i < 12; ++i) p->obs[i] = 0.0;
     p->local_repair = 0;
+    p->n_con = 0;
+    for (int i = 0; i < 6 * kMaxCon; ++i) p->con_a[i] = 0.0;
+    for (int i = 0; i < kMaxCon; ++i) p->con_b[i] = 0.0;
     p->lambda = 1.0;
     p->gamma_u = 1.0;
     p->v_goal = 6.0;
@@ -367,6 +386,15 @@ bss_status bss_validate(const bss_params* p)
         return fail(BSS_E_INVAL, "sigma_w_speed must be finite and >= 0");
     if (p->local_repair < 0 || p->local_repair > 2)
         return fail(BSS_E_INVAL, "local_repair must be 0, 1 or 2");
+    if (p->n_con < 0 || p->n_con > kMaxCon)
+        return fail(BSS_E_INVAL, "n_con must be 0..%d", kMaxCon);
+    for (int i = 0; i < p->n_con; ++i) {
+        for (int j = 0; j < 6; ++j)
+            if (!std::isfinite(p->con_a[6 * i + j]))
+                return fail(BSS_E_INVAL, "half-space constraint %d: a must be finite", i);
+        if (!std::isfinite(p->con_b[i]))
+            return fail(BSS_E_INVAL, "half-space constraint %d: b must be finite", i);
+    }
     if (!finite_pos(p->lambda)) return fail(BSS_E_INVAL, "lambda must be finite and > 0");
     if (!finite_pos(p->dt)) return fail(BSS_E_INVAL, "dt must be finite and > 0");
     if (!finite_pos(p->m) || !finite_pos(p->Iz) || !finite_pos(p->lf) || !finite_pos(p->lr))
@@ -432,7 +460,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->has_alloc = alloc != nullptr;
     if (alloc) c->alloc = *alloc;
     c->stream = (hipStream_t)stream;
-    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0, -1, samples_shielded(*p));
+    c->shape = choose_shape(p->K, p->M, p->T, p->lanes, 0, -1, shape_for_shield(*p));
     c->timing = false;
     c->ev_used = 0;
     c->pending_shift = 0;
@@ -446,6 +474,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     const size_t sz_v = align256(T * 2 * sizeof(double));
     const size_t sz_u = align256(K * T * 2 * sizeof(float));
     const size_t sz_mom = align256(K * (T + 1) * 9 * sizeof(double));
+    const size_t sz_cvar = align256(K * (T + 1) * (size_t)p->n_con * sizeof(double));
     const size_t sz_S = align256(K * sizeof(double));
     const size_t sz_stats = align256(8 * sizeof(double));
     const size_t sz_part = align256(G * (2 * T + 4) * sizeof(double));
@@ -454,15 +483,16 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     const size_t sz_desc = align256(sizeof(InstanceDesc));
     const size_t sz_blk = align256(G * sizeof(BlockDesc));
     const size_t sz_col = align256(2 * T * sizeof(MergeDesc));
-    // repair of the update: descriptor, grid, controls [T][2] f32, beliefs [T+1][9], cost,
-    // partial [2T+4], stats [8]
+    // repair of the update: descriptor, grid, controls [T][2] f32, beliefs [T+1][9], constraint
+    // variances [T+1][n_con], cost, partial [2T+4], stats [8]
     const size_t sz_rep = p->local_repair == 0
                               ? 0
                               : sz_desc + 256 + align256(T * 2 * sizeof(float)) +
-                                    align256((T + 1) * 9 * sizeof(double)) + 256 +
+                                    align256((T + 1) * 9 * sizeof(double)) +
+                                    align256((T + 1) * (size_t)p->n_con * sizeof(double)) + 256 +
                                     align256((2 * T + 4) * sizeof(double)) + sz_stats;
-    const size_t total = 2 * sz_v + sz_u + sz_mom + sz_S + sz_stats + sz_part + sz_x0 + sz_sig +
-                         sz_desc + sz_blk + sz_col + sz_rep;
+    const size_t total = 2 * sz_v + sz_u + sz_mom + sz_cvar + sz_S + sz_stats + sz_part + sz_x0 +
+                         sz_sig + sz_desc + sz_blk + sz_col + sz_rep;
 
     void* block = nullptr;
     if (c->has_alloc) {
@@ -489,6 +519,8 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     b += sz_u;
     c->desc.mom = (double*)b;
     b += sz_mom;
+    c->desc.cvar = p->n_con > 0 ? (double*)b : nullptr;
+    b += sz_cvar;
     c->desc.S = (double*)b;
     b += sz_S;
     c->desc.stats = (double*)b;
@@ -529,6 +561,9 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         b += align256(T * 2 * sizeof(float));
         r.mom = (double*)b;
         b += align256((T + 1) * 9 * sizeof(double));
+        r.cvar = p->n_con > 0 ? (double*)b : nullptr;
+        b += align256((T + 1) * (size_t)p->n_con * sizeof(double));
+        r.sc.shield_iters = p->shield_iters;   // the repair pass always repairs
         r.S = (double*)b;
         b += 256;
         r.partial = (double*)b;
@@ -604,8 +639,8 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         e = hipEventRecord(c->ev[c->ev_used], c->stream);
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
-    e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
-                     samples_shielded(c->p), c->shape.split, c->p.belief != 0, c->lds, x0_dev,
+    e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl, launch_shield(c->p),
+                     c->shape.split, launch_resample(c->p), c->p.n_con > 0, c->lds, x0_dev,
                      Sigma0_dev, c->pending_shift, c->stream);
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
@@ -618,7 +653,8 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
     c->pending_shift = 0;
     if (c->d_rdesc) {
         e = launch_local_repair(c->d_desc, c->d_rdesc, c->d_rblock, c->p.T, c->rshape.ppl,
-                                c->p.belief != 0, c->rlds, x0_dev, Sigma0_dev, c->stream);
+                                launch_resample(c->p), c->p.n_con > 0, c->rlds, x0_dev,
+                                Sigma0_dev, c->stream);
         if (e != hipSuccess) return device_fail(e, "repair of the update");
     }
     return BSS_OK;
@@ -723,6 +759,7 @@ bss_status bss_get_buffers(const bss_ctx* cc, bss_buffers* out)
     out->v = c->desc.v[cur];
     out->u = (float*)((char*)c->desc.v[1] + align256((size_t)c->p.T * 2 * sizeof(double)));
     out->mom = c->desc.mom;
+    out->con_var = c->desc.cvar;
     out->S = c->desc.S;
     out->stats = c->desc.stats;
     out->x0 = c->x0;
@@ -848,7 +885,7 @@ bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl, int32_t split)
         return fail(BSS_E_INVAL, "M=%d needs more than 64 lanes with %d particles per lane", q.M,
                     ppl);
     if (split < -1 || split > 1) return fail(BSS_E_INVAL, "split must be -1, 0 or 1");
-    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl, split, samples_shielded(q));
+    const LaunchShape sh = choose_shape(q.K, q.M, q.T, lanes, ppl, split, shape_for_shield(q));
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(e, "synchronising");
     c->shape = sh;
@@ -928,7 +965,7 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
 static hipError_t batch_enqueue(bss_batch* b)
 {
     hipError_t e = launch_solve(b->d_desc, b->d_blocks, b->nblocks, b->ppl, b->shield,
-                                b->split, b->resample, b->lds,
+                                b->split, b->resample, b->con, b->lds,
                                 b->d_x0, nullptr, 0, b->stream);
     if (e == hipSuccess) e = launch_merge(b->d_desc, b->d_cols, b->ncols, 0, b->stream);
     return e;
@@ -979,12 +1016,14 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     b->block = nullptr;
     b->shield = false;
     b->resample = false;
+    b->con = false;
     size_t nb = 0, nc = 0;
     for (int i = 0; i < n; ++i) {
         nb += max_blocks(ctxs[i]->p.K);
         nc += 2 * (size_t)ctxs[i]->p.T;
-        b->shield = b->shield || samples_shielded(ctxs[i]->p);
-        b->resample = b->resample || ctxs[i]->p.belief != 0;
+        b->shield = b->shield || launch_shield(ctxs[i]->p);
+        b->resample = b->resample || launch_resample(ctxs[i]->p);
+        b->con = b->con || ctxs[i]->p.n_con > 0;
     }
     const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));
     const size_t total = 2 * sz_desc + align256(nb * sizeof(BlockDesc)) +
@@ -1262,6 +1301,8 @@ bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u,
     bss_status st = bss_validate(p);
     if (st != BSS_OK) return st;
     if (!mom || !u || !v || !S) return fail(BSS_E_INVAL, "NULL buffer");
+    if (p->n_con > 0)
+        return fail(BSS_E_INVAL, "the staged score takes no constraint variances (n_con must be 0)");
     hipError_t e = launch_score(p->K, p->T, make_score(*p), mom, u, v, S, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "score launch");
     return BSS_OK;
@@ -1298,6 +1339,8 @@ bss_status bss_dev_repair(const bss_params* p, const double* mom, const double* 
     bss_status st = bss_validate(p);
     if (st != BSS_OK) return st;
     if (n < 0 || (n > 0 && (!mom || !u_in || !u_out))) return fail(BSS_E_INVAL, "bad arguments");
+    if (p->n_con > 0)
+        return fail(BSS_E_INVAL, "the staged repair takes no constraint variances (n_con must be 0)");
     hipError_t e = launch_repair(make_score(*p), mom, u_in, u_out, n, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "repair launch");
     return BSS_OK;

@@ -412,12 +412,21 @@ struct BeliefEval {
     double sig_obs[kMaxObstacles];   // spread along each obstacle's gradient direction
 };
 
-// Barrier at mean position (X, Y) with given spreads: h = min over the constraints (eq. 16) of the
-// track walls as eq. 33 and each obstacle in the same quadratic form,
-// max(d_i - nu sigma_i, 0)^2 - r_i^2 with d_i the distance to its centre.
-__device__ inline double barrier_at(const ScoreF64& p, double X, double Y, double ey,
-                                    double sigma, const double* sig_obs)
+// Spreads sqrt(a_i^T Sigma a_i) of the half-space constraints from their variances.
+__device__ inline void con_sigmas(const ScoreF64& p, const double* cvar, double* sig)
 {
+#pragma unroll
+    for (int i = 0; i < kMaxCon; ++i) sig[i] = i < p.n_con ? sqrt(fmax(cvar[i], 0.0)) : 0.0;
+}
+
+// Barrier at mean state x with given spreads: h = min over the constraints (eq. 16) of the track
+// walls as eq. 33, each obstacle in the same quadratic form, max(d_i - nu sigma_i, 0)^2 - r_i^2
+// with d_i the distance to its centre, and (sig_con non-null) each half-space constraint as the
+// heuristic of eq. 13 itself, b_i - a_i^T x - nu sigma_i.
+__device__ inline double barrier_at(const ScoreF64& p, const double* x, double ey, double sigma,
+                                    const double* sig_obs, const double* sig_con)
+{
+    const double X = x[0], Y = x[1];
     const double margin = fmax(p.half_width - p.nu * sigma, 0.0);
     double h = margin * margin - ey * ey;
     for (int i = 0; i < p.n_obs; ++i) {
@@ -425,10 +434,25 @@ __device__ inline double barrier_at(const ScoreF64& p, double X, double Y, doubl
         const double m = fmax(sqrt(dx * dx + dy * dy) - p.nu * sig_obs[i], 0.0);
         h = fmin(h, m * m - r * r);
     }
+    if (sig_con) {
+#pragma unroll
+        for (int i = 0; i < kMaxCon; ++i) {
+            if (i < p.n_con) {
+                const double* a = p.con_a + 6 * i;
+                double ax = a[0] * x[0];
+#pragma unroll
+                for (int j = 1; j < 6; ++j) ax = fma(a[j], x[j], ax);
+                h = fmin(h, p.con_b[i] - ax - p.nu * sig_con[i]);
+            }
+        }
+    }
     return h;
 }
 
-__device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom)
+// sig_con: spreads of the half-space constraints (con_sigmas), or nullptr where the launch
+// carries none
+__device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom,
+                                         const double* sig_con = nullptr)
 {
     BeliefEval b;
     ellipse_sdf(p.ell_a, p.ell_b, mom[0], mom[1], &b.ey, &b.nx, &b.ny);
@@ -442,7 +466,7 @@ __device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom)
         const double v = ex * ex * mom[6] + 2.0 * ex * ez * mom[7] + ez * ez * mom[8];
         b.sig_obs[i] = sqrt(fmax(v, 0.0));
     }
-    b.h = barrier_at(p, mom[0], mom[1], b.ey, b.sigma, b.sig_obs);
+    b.h = barrier_at(p, mom, b.ey, b.sigma, b.sig_obs, sig_con);
     return b;
 }
 
@@ -467,16 +491,17 @@ __device__ inline double stage_cost(const ScoreF64& p, const double* mom, const 
 }
 
 // One-step residual of the linear class-kappa condition for a candidate control: the mean is
-// pushed through the noise-free model and re-scored with the spread frozen at step t.
+// pushed through the noise-free model and re-scored with the spreads frozen at step t (sig_con:
+// those of the half-space constraints, or nullptr).
 __device__ inline double repair_residual(const ScoreF64& p, const double* xbar,
                                          const BeliefEval& be, double h_t, double steer,
-                                         double accel)
+                                         double accel, const double* sig_con = nullptr)
 {
     double xn[6];
     car_step_f64(p, xbar, steer, accel, xn);
     double ey, nx, ny;
     ellipse_sdf(p.ell_a, p.ell_b, xn[0], xn[1], &ey, &nx, &ny);
-    return -barrier_at(p, xn[0], xn[1], ey, be.sigma, be.sig_obs) + (1.0 - p.gamma) * h_t;
+    return -barrier_at(p, xn, ey, be.sigma, be.sig_obs, sig_con) + (1.0 - p.gamma) * h_t;
 }
 
 }  // namespace bss

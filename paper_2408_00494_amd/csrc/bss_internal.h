@@ -20,6 +20,7 @@
 namespace bss {
 
 constexpr int kMaxObstacles = 4;
+constexpr int kMaxCon = 4;         // half-space constraints a_i^T x <= b_i on the whole state
 
 // Constants of the single-track car in the form the single-precision particle integrator uses:
 // forces are divided by the mass, so the saturations and stiffnesses are accelerations.
@@ -48,6 +49,10 @@ struct ScoreF64 {
     // derived on the host: lateral force limits mu m g lr / (lf + lr), mu m g lf / (lf + lr), and
     // 1 / m, 1 / Iz (the double-precision model multiplies instead of dividing)
     double Ffm, Frm, inv_m, inv_Iz;
+    // half-space constraints: a_i = con_a[6i..6i+5] over (X, Y, psi, vx, vy, r), bound con_b[i]
+    int32_t n_con;
+    double con_a[6 * kMaxCon];
+    double con_b[kMaxCon];
 };
 
 // One problem instance (device memory).
@@ -77,6 +82,8 @@ struct InstanceDesc {
     double* v[2];                  // ping-pong pair of mean sequences [T][2]
     float* u;                      // [K][T][2] copy of the sampled controls, or nullptr
     double* mom;                   // [K][T+1][9] beliefs (written by the loop, read by scoring)
+    double* cvar;                  // [K][T+1][n_con] a_i^T Sigma a_i, or nullptr without
+                                   // half-space constraints
     double* S;                     // [K] trajectory costs
     double* partial;               // [nblocks][2T + 4] per-block log-sum-exp partials
     double* stats;                 // [8]: S_min, Z, ESS, #finite, status, v+_0 (2), unused
@@ -122,9 +129,11 @@ int solve_blocks(int K, int lanes);
 
 // Solve grid: nblocks blocks described by `blocks`; x0_base holds the state estimates (6 doubles
 // per instance at x0_index), Sigma0_base the covariances (36 doubles) or nullptr; extra_shift is
-// added to every instance's pending shift for this launch.
+// added to every instance's pending shift for this launch.  Variant flags: shield (some instance
+// repairs its samples), split (separate noise waves), resample (some instance redraws its
+// particles), con (some instance has half-space constraints: the generic variant with them).
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
-                        bool shield, bool split, bool resample, size_t lds,
+                        bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,
                         hipStream_t stream);
 hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
@@ -133,8 +142,9 @@ hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int nco
 // descriptor (one sample, no exploration noise, own key and buffers), `rep_block` its one-block
 // grid {0, 0}; lds is the dynamic LDS of an unsplit launch of the instance's shape.
 hipError_t launch_local_repair(InstanceDesc* inst, InstanceDesc* rep, const BlockDesc* rep_block,
-                               int T, int ppl, bool resample, size_t lds, const double* x0_base,
-                               const double* Sigma0_base, hipStream_t stream);
+                               int T, int ppl, bool resample, bool con, size_t lds,
+                               const double* x0_base, const double* Sigma0_base,
+                               hipStream_t stream);
 
 // stand-alone kernels for staged checks
 hipError_t launch_score(int K, int T, const ScoreF64& sc, const double* mom, const float* u,

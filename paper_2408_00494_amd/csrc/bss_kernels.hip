@@ -187,15 +187,18 @@ __device__ __forceinline__ int vrow(int t, int vshift, int T)
 // phi_scale on the terminal record), control cost on records < T, and C_safe on the transition
 // into the record (record 0 has none).  `h_carry` holds h of the record before the chunk and is
 // advanced to the chunk's last record.  Returns this lane's contribution.
+// crec: the record's half-space constraint variances, or nullptr where the launch carries none.
 __device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int rec_idx, int count,
                                      int lane, int W, int T, const float2* u_row, const double* v,
-                                     int vshift, double& h_carry)
+                                     int vshift, double& h_carry, const double* crec = nullptr)
 {
     const bool valid = lane < count;
     double part = 0.0;
     double h = 0.0;
     if (valid) {
-        const BeliefEval be = eval_belief(sc, rec);
+        double scon[kMaxCon];
+        if (crec) con_sigmas(sc, crec, scon);
+        const BeliefEval be = eval_belief(sc, rec, crec ? scon : nullptr);
         double q = stage_cost(sc, rec, be);
         if (rec_idx == T) {
             q *= sc.phi_scale;
@@ -406,7 +409,7 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
 // puts two waves on every SIMD when a launch has too few samples to fill the chip otherwise (a
 // lone wave issues at about half the SIMD's rate); the arithmetic and its order are unchanged, so
 // the results are bitwise the same as without the split.
-template <int P, bool SHIELD, int L, bool SPLIT, bool RESAMPLE>
+template <int P, bool SHIELD, int L, bool SPLIT, bool RESAMPLE, bool CON>
 __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDesc bd,
                                             const double* __restrict__ x0_base,
                                             const double* __restrict__ Sigma0_base,
@@ -414,6 +417,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 {
     static_assert(!(SPLIT && SHIELD), "the shielded loop is not split");
     static_assert(!(SPLIT && RESAMPLE), "the re-sampling loop is not split");
+    static_assert(!CON || (SHIELD && RESAMPLE && !SPLIT),
+                  "half-space constraints are compiled into the generic variant only");
     constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
     constexpr int groups = 256 >> log2L;
     const int T = d.T, M = d.M;
@@ -436,6 +441,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     const uint32_t key0 = d.key0, key1 = d.key1;
     const double* x0p = x0_base + 6 * d.x0_index;
     const double* S0p = Sigma0_base ? Sigma0_base + 36 * d.x0_index : nullptr;
+    // half-space constraints on the whole state (only the CON variant, the generic one with them,
+    // compiles them in): their variances a_i^T Sigma a_i per record
+    const int ncon = CON ? d.sc.n_con : 0;
+    double* cvar_k = ncon > 0 ? d.cvar + (size_t)(active ? k : 0) * (T + 1) * ncon : nullptr;
 
     // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
     if (active && (!SPLIT || producer)) {
@@ -547,9 +556,28 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         bel[6] = spread ? S0p[0] : 0.0;
         bel[7] = spread ? S0p[1] : 0.0;
         bel[8] = spread ? S0p[7] : 0.0;
+        // a_i^T Sigma a_i of each half-space constraint (eq. 11 with eta_i = a_i); at t = 0 from
+        // the given covariance
+        double bcv[kMaxCon];
+#pragma unroll
+        for (int c = 0; c < kMaxCon; ++c) {
+            double q = 0.0;
+            if (c < ncon && spread) {
+                const double* a = d.sc.con_a + 6 * c;
+                for (int r = 0; r < 6; ++r) {
+                    double row = 0.0;
+                    for (int e = 0; e < 6; ++e) row = fma(S0p[r * 6 + e], a[e], row);
+                    q = fma(a[r], row, q);
+                }
+            }
+            bcv[c] = q;
+        }
         if (consumer && j == 0) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
+#pragma unroll
+            for (int c = 0; c < kMaxCon; ++c)
+                if (c < ncon) cvar_k[c] = bcv[c];
         }
         PhiloxParticle pp[P];
 #pragma unroll
@@ -570,7 +598,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 if (SHIELD) {
                     const ScoreF64& sc = d.sc;
                     if (sc.shield_iters > 0) {
-                        const BeliefEval be = eval_belief(sc, bel);
+                        double scon[kMaxCon];
+                        if (ncon > 0) con_sigmas(sc, bcv, scon);
+                        const double* sc_con = ncon > 0 ? scon : nullptr;
+                        const BeliefEval be = eval_belief(sc, bel, sc_con);
                         const double fd = sc.shield_fd;
                         const int role = j < 5 ? j : 0;
                         const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
@@ -579,8 +610,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         for (int it = 0; it < sc.shield_iters; ++it) {
                             // lanes 0-4 of the group evaluate r at u and at the four
                             // difference points
-                            const double rv =
-                                repair_residual(sc, bel, be, be.h, us0 + o0, us1 + o1);
+                            const double rv = repair_residual(sc, bel, be, be.h, us0 + o0,
+                                                              us1 + o1, sc_con);
                             const double r0 = __shfl(rv, 0, L);
                             const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
                             const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
@@ -620,6 +651,11 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0,
                        sYY = 0;
                 double refX = 0.0, refY = 0.0;
+                // sums of squares of the constraint projections y = a_i^T (x - xref), xref the
+                // estimate with particle 0's position (the sums of y follow from the moment sums)
+                double c2[kMaxCon];
+#pragma unroll
+                for (int c = 0; c < kMaxCon; ++c) c2[c] = 0.0;
                 // With up to four particles per lane the step runs in stages over all of them
                 // (disturbance normals, first field evaluation, midpoint, second evaluation,
                 // update), each stage one straight-line block with no per-particle branch, so
@@ -704,6 +740,20 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                             sXX = fma(X, X, sXX);
                             sXY = fma(X, Y, sXY);
                             sYY = fma(Y, Y, sYY);
+#pragma unroll
+                            for (int c = 0; c < kMaxCon; ++c) {
+                                if (c < ncon) {
+                                    const double* a = d.sc.con_a + 6 * c;
+                                    const double y = fma(
+                                        a[0], X,
+                                        fma(a[1], Y,
+                                            fma(a[2], (double)Ps[p] - (double)Pc[p],
+                                                fma(a[3], (double)vx[p] - x0[3],
+                                                    fma(a[4], (double)vy[p] - x0[4],
+                                                        a[5] * ((double)vr[p] - x0[5]))))));
+                                    c2[c] = fma(y, y, c2[c]);
+                                }
+                            }
                         }
                     }
                 }
@@ -727,12 +777,39 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 bel[6] = (sXX - sX * mX) * invM1;
                 bel[7] = (sXY - sX * mY) * invM1;
                 bel[8] = (sYY - sY * mY) * invM1;
+#pragma unroll
+                for (int c = 0; c < kMaxCon; ++c) {
+                    if (c < ncon) {
+                        // sum of the projections from the moment sums, then the unbiased variance
+                        const double* a = d.sc.con_a + 6 * c;
+                        const double s1 =
+                            fma(a[0], sX,
+                                fma(a[1], sY,
+                                    fma(a[2], sP,
+                                        fma(a[3], fma(-(double)M, x0[3], svx),
+                                            fma(a[4], fma(-(double)M, x0[4], svy),
+                                                a[5] * fma(-(double)M, x0[5], svr))))));
+                        const double s2 = group_sum(c2[c], L);
+                        double var = (s2 - s1 * (s1 * invM)) * invM1;
+                        if (d.belief == 2) {
+                            // sigma points: plus a_i^T Q a_i of the disturbance covariance,
+                            // scaled like Q by the points' mean of (1 + kappa |vx|)^2
+                            const double q0 = a[3] * (double)sw0, q1 = a[4] * (double)sw1,
+                                         q2 = a[5] * (double)sw2;
+                            var = fma(qbar, fma(q0, q0, fma(q1, q1, q2 * q2)), var);
+                        }
+                        bcv[c] = var;
+                    }
+                }
 
                 // record t+1, written by lane (t+1) % L of the group (spreads the stores)
                 if (j == ((t + 1) & (L - 1))) {
                     double* rec = mom_k + (size_t)(t + 1) * 9;
 #pragma unroll
                     for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+#pragma unroll
+                    for (int c = 0; c < kMaxCon; ++c)
+                        if (c < ncon) cvar_k[(size_t)(t + 1) * ncon + c] = bcv[c];
                 }
             }
             if (SPLIT) __syncthreads();
@@ -748,7 +825,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
             const int count = min(L, T + 1 - base);
             const int rec = base + min(j, count - 1);
             S_part += score_chunk(d.sc, mom_k + (size_t)rec * 9, base + j, count, j, L, T, us, v,
-                                  vshift, h_carry);
+                                  vshift, h_carry,
+                                  ncon > 0 ? cvar_k + (size_t)rec * ncon : nullptr);
         }
     }
     const double S_k = group_sum(S_part, L);
@@ -764,7 +842,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 
 // Solve grid: every block looks up its instance and first sample; the lane count is uniform over
 // a block, so the dispatch below is a block-uniform branch.
-template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE>
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false>
 __global__ __launch_bounds__(SPLIT ? 512 : 256)
 __attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE) ? 2
                                    : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
@@ -775,16 +853,16 @@ __attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE) ? 2
     const InstanceDesc& d = insts[bd.inst];
     switch (d.lanes) {
     case 8:
-        solve_block<P, SHIELD, 8, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        solve_block<P, SHIELD, 8, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
         break;
     case 16:
-        solve_block<P, SHIELD, 16, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        solve_block<P, SHIELD, 16, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
         break;
     case 32:
-        solve_block<P, SHIELD, 32, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        solve_block<P, SHIELD, 32, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
         break;
     default:
-        solve_block<P, SHIELD, 64, SPLIT, RESAMPLE>(d, bd, x0_base, Sigma0_base, extra_shift);
+        solve_block<P, SHIELD, 64, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
         break;
     }
 }
@@ -1108,12 +1186,15 @@ __global__ void repair_kernel(ScoreF64 sc, const double* mom, const double* u_in
 
 template <int P>
 hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
-                          bool shield, bool split, bool resample, size_t lds,
+                          bool shield, bool split, bool resample, bool con, size_t lds,
                           const double* x0_base, const double* Sigma0_base, int extra_shift,
                           hipStream_t stream)
 {
     const dim3 g(nblocks), b256(256), b512(512);
-    if (shield && resample)
+    if (con)
+        hipLaunchKernelGGL((solve_kernel<P, true, false, true, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (shield && resample)
         hipLaunchKernelGGL((solve_kernel<P, true, false, true>), g, b256, lds, stream, inst,
                            blocks, x0_base, Sigma0_base, extra_shift);
     else if (shield)
@@ -1204,25 +1285,25 @@ int solve_blocks(int K, int lanes)
 }
 
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
-                        bool shield, bool split, bool resample, size_t lds,
+                        bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,
                         hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    split = split && !shield && !resample;
+    split = split && !shield && !resample && !con;
     switch (ppl) {
     case 1:
-        return launch_solve_p<1>(inst, blocks, nblocks, shield, split, resample, lds,
-                                    x0_base, Sigma0_base, extra_shift, stream);
+        return launch_solve_p<1>(inst, blocks, nblocks, shield, split, resample, con,
+                                    lds, x0_base, Sigma0_base, extra_shift, stream);
     case 2:
-        return launch_solve_p<2>(inst, blocks, nblocks, shield, split, resample, lds,
-                                    x0_base, Sigma0_base, extra_shift, stream);
+        return launch_solve_p<2>(inst, blocks, nblocks, shield, split, resample, con,
+                                    lds, x0_base, Sigma0_base, extra_shift, stream);
     case 4:
-        return launch_solve_p<4>(inst, blocks, nblocks, shield, split, resample, lds,
-                                    x0_base, Sigma0_base, extra_shift, stream);
+        return launch_solve_p<4>(inst, blocks, nblocks, shield, split, resample, con,
+                                    lds, x0_base, Sigma0_base, extra_shift, stream);
     case 8:
-        return launch_solve_p<8>(inst, blocks, nblocks, shield, split, resample, lds,
-                                    x0_base, Sigma0_base, extra_shift, stream);
+        return launch_solve_p<8>(inst, blocks, nblocks, shield, split, resample, con,
+                                    lds, x0_base, Sigma0_base, extra_shift, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1237,14 +1318,15 @@ hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int nco
 }
 
 hipError_t launch_local_repair(InstanceDesc* inst, InstanceDesc* rep, const BlockDesc* rep_block,
-                               int T, int ppl, bool resample, size_t lds, const double* x0_base,
-                               const double* Sigma0_base, hipStream_t stream)
+                               int T, int ppl, bool resample, bool con, size_t lds,
+                               const double* x0_base, const double* Sigma0_base,
+                               hipStream_t stream)
 {
     hipLaunchKernelGGL(repair_prep_kernel, dim3(1), dim3(64), 0, stream, inst, rep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_solve(rep, rep_block, 1, ppl, true, false, resample, lds, x0_base, Sigma0_base, 0,
-                     stream);
+    e = launch_solve(rep, rep_block, 1, ppl, true, false, resample, con, lds, x0_base,
+                     Sigma0_base, 0, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(repair_finish_kernel, dim3(blocks_for(2 * T, 256)), dim3(256), 0, stream,
                        inst, rep);

@@ -164,7 +164,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     sl.vehicles.clear();
     std::vector<double> x0s;
     size_t used = 0, lds = 0;
-    bool shield = false, ring_fits = true, resample = false;
+    bool shield = false, ring_fits = true, resample = false, con = false;
     // pick requests oldest first; skip a vehicle already in flight or already seen in this scan
     std::deque<Request>& pend = s->pending;
     std::vector<size_t> taken;
@@ -177,7 +177,10 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         }
         s->seen[r.vehicle] = 1;
         const LaunchShape sh = choose_shape(r.K, r.M, T, 0, s->ppl, 0);
-        const size_t need = scratch_bytes(r.K, T, sh.lanes);
+        const size_t con_bytes =
+            align256((size_t)r.K * (T + 1) * (size_t)v.p.n_con * sizeof(double));
+        const size_t base_bytes = scratch_bytes(r.K, T, sh.lanes);
+        const size_t need = base_bytes + con_bytes;   // beliefs, costs, partials | variances
         if (used + need > sl.arena_bytes) continue;   // waits for memory (admission)
         const int nb = solve_blocks(r.K, sh.lanes);
         if (blocks.size() + (size_t)nb > s->max_blocks) continue;
@@ -204,12 +207,15 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         d.S = (double*)a;
         a += align256((size_t)r.K * sizeof(double));
         d.partial = (double*)a;
+        d.cvar = v.p.n_con > 0 ? (double*)(sl.arena + used + base_bytes) : nullptr;
         d.stats = sl.d_stats + 8 * i;
         used += need;
         lds = std::max(lds, solve_lds_bytes(sh.lanes, T, s->ppl, false));
         ring_fits = ring_fits && solve_lds_bytes(sh.lanes, T, s->ppl, true) <= kMaxLds;
-        shield = shield || v.p.shield_iters > 0;
-        resample = resample || v.p.belief != 0;
+        // half-space constraints run in the generic variant (shield and re-sampling compiled in)
+        shield = shield || v.p.shield_iters > 0 || v.p.n_con > 0;
+        resample = resample || v.p.belief != 0 || v.p.n_con > 0;
+        con = con || v.p.n_con > 0;
         descs.push_back(d);
         append_blocks(blocks, i, r.K, sh.lanes);
         for (int c = 0; c < 2 * T; ++c) cols.push_back(MergeDesc{i, c});
@@ -244,7 +250,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     const InstanceDesc* d_desc = (const InstanceDesc*)(sl.d_region + o_desc);
     if (e == hipSuccess)
         e = launch_solve(d_desc, (const BlockDesc*)(sl.d_region + o_blk), (int)blocks.size(),
-                         s->ppl, shield, split, resample, lds,
+                         s->ppl, shield, split, resample, con, lds,
                          (const double*)(sl.d_region + o_x0), nullptr, 0, sl.stream);
     if (e == hipSuccess)
         e = launch_merge(d_desc, (const MergeDesc*)(sl.d_region + o_col), (int)cols.size(), 0,

@@ -79,7 +79,7 @@ def test_defaults_match_reference_problem():
             assert p.lanes == 0
             continue
         val = getattr(p, name)
-        if name in ("sigma_eps", "sigma_w", "obs"):
+        if name in ("sigma_eps", "sigma_w", "obs", "con_a", "con_b"):
             assert list(val) == ref[key]
         else:
             assert val == ref[key], name
@@ -113,6 +113,9 @@ def test_validation_accepts_workloads():
     (dict(sigma_w_speed=-0.1), "sigma_w_speed"), (dict(n_obs=5), "n_obs"),
     (dict(n_obs=1, obs=[1.0, 2.0, 0.0] + [0.0] * 9), "obstacle 0"),
     (dict(local_repair=3), "local_repair"), (dict(local_repair=1), "shield_iters >= 1"),
+    (dict(n_con=5), "n_con"), (dict(n_con=-1), "n_con"),
+    (dict(n_con=1, con_a=[float("nan")] + [0.0] * 23), "half-space constraint 0: a"),
+    (dict(n_con=2, con_b=[1.0, float("inf"), 0.0, 0.0]), "half-space constraint 1: b"),
 ])
 def test_validation_rejects(kw, frag):
     st, msg = _validate(**kw)
