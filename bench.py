@@ -40,8 +40,8 @@ FP32_PEAK = 157.3e12
 # HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a 1 GiB device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "f0515921e8955f91", "lanes": 16, "ppl": 4, "split": True,
-                    "fetch_bytes": 7629.1 * 1024 * 2.0, "write_bytes": 15035.3 * 1024 * 1.0}
+MEASURED_TRAFFIC = {"sources_sha256_16": "1b017ad64043c818", "lanes": 16, "ppl": 4, "split": True,
+                    "fetch_bytes": 7622.1 * 1024 * 2.0, "write_bytes": 15035.4 * 1024 * 1.0}
 KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_kernels.hip",
                   "paper_2408_00494_amd/csrc/bss_device.h",
                   "paper_2408_00494_amd/csrc/bss_internal.h"]
@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-resampling", action="store_true")
+    ap.add_argument("--no-constraints", action="store_true")
     ap.add_argument("--no-shielded", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving trace replayed with batching (0 skips serving)")
@@ -147,8 +148,24 @@ def host_cpu():
 def bench_resampling(bss, W, torch, steps=20, warmup=3):
     """The paper-scale workload with the Gaussian re-sampling reading of Alg. 2 (particles redrawn
     from the mean and full covariance at every step)."""
-    prob, x0, v = W.config_paper_scale()
-    prob = dict(prob, belief=1)
+    prob, x0, _ = W.config_paper_scale()
+    return dict(_bench_variant(bss, torch, dict(prob, belief=1), x0, steps, warmup),
+                workload="paper-scale solve with Gaussian re-sampling every step (K=4096, M=64, "
+                         "T=50)")
+
+
+def bench_constraints(bss, W, torch, steps=20, warmup=3):
+    """The paper-scale workload with four half-space chance constraints on the state (speed
+    limit, yaw rate both ways, a lateral-velocity combination), each scored on the variance
+    a^T Sigma a of the full covariance."""
+    prob, x0, _ = W.config_constrained()
+    return dict(_bench_variant(bss, torch, prob, x0, steps, warmup),
+                workload="paper-scale solve with four half-space constraints on the state "
+                         "(K=4096, M=64, T=50)")
+
+
+def _bench_variant(bss, torch, prob, x0, steps, warmup):
+    """Solves of one variant from a device-resident state, each followed by the shift."""
     rs = prob["K"] * prob["M"] * prob["T"]
     s = bss.Solver(prob)
     s.set_outputs(controls=False)
@@ -168,9 +185,7 @@ def bench_resampling(bss, W, torch, steps=20, warmup=3):
     kms, n = s.timing_read()
     info = s.info()
     s.close()
-    return {"workload": "paper-scale solve with Gaussian re-sampling every step (K=4096, M=64, "
-                        "T=50)",
-            "value": rs * steps / el, "unit": "rollout-steps/s", "ms_per_step": el * 1e3 / steps,
+    return {"value": rs * steps / el, "unit": "rollout-steps/s", "ms_per_step": el * 1e3 / steps,
             "kernel_ms": kms / max(n, 1), "lanes": info["lanes"], "ppl": info["ppl"]}
 
 
@@ -410,6 +425,9 @@ def main():
     if not args.no_resampling:
         out["resampling"] = bench_resampling(bss, W, torch)
         progress(f"re-sampling variant: {out['resampling']['value']:.3e} rollout-steps/s")
+    if not args.no_constraints:
+        out["constraints"] = bench_constraints(bss, W, torch)
+        progress(f"half-space constraints: {out['constraints']['value']:.3e} rollout-steps/s")
     if not args.no_shielded:
         out["shielded"] = bench_shielded(bss, W, torch)
         progress(f"shielded: {out['shielded']['shielded']['value']:.3e} rollout-steps/s, with "

@@ -250,15 +250,18 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
     return out;
 }
 
-// Kernel variant flags of an instance.  Half-space constraints live only in a variant of the
-// generic kernel (shield and re-sampling both compiled in, each switched at run time by the
-// descriptor: no repair while sc.shield_iters is 0, persistent particles while belief is 0).
-bool launch_shield(const bss_params& p) { return samples_shielded(p) || p.n_con > 0; }
-bool launch_resample(const bss_params& p) { return p.belief != 0 || p.n_con > 0; }
+// Kernel variant flags of an instance (half-space constraints add the CON flag to the plain or
+// split variant, or, with the repair or the re-sampling, to the generic one).
+bool launch_shield(const bss_params& p) { return samples_shielded(p); }
+bool launch_resample(const bss_params& p) { return p.belief != 0; }
 
 // the automatic shape's eight particles per lane for the repair: the plain shielded variant only
-// (the generic ones run out of registers at eight)
-bool shape_for_shield(const bss_params& p) { return samples_shielded(p) && !launch_resample(p); }
+// (the generic one, which the constraints or the re-sampling select, runs out of registers at
+// eight)
+bool shape_for_shield(const bss_params& p)
+{
+    return samples_shielded(p) && p.belief == 0 && p.n_con == 0;
+}
 
 hipError_t upload_shape(bss_ctx* c)
 {

@@ -131,7 +131,8 @@ int solve_blocks(int K, int lanes);
 // per instance at x0_index), Sigma0_base the covariances (36 doubles) or nullptr; extra_shift is
 // added to every instance's pending shift for this launch.  Variant flags: shield (some instance
 // repairs its samples), split (separate noise waves), resample (some instance redraws its
-// particles), con (some instance has half-space constraints: the generic variant with them).
+// particles), con (some instance has half-space constraints: the variant with them compiled in;
+// with shield or resample that is the generic one, both of those switched at run time).
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
                         bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,

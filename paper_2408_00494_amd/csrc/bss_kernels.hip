@@ -417,8 +417,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 {
     static_assert(!(SPLIT && SHIELD), "the shielded loop is not split");
     static_assert(!(SPLIT && RESAMPLE), "the re-sampling loop is not split");
-    static_assert(!CON || (SHIELD && RESAMPLE && !SPLIT),
-                  "half-space constraints are compiled into the generic variant only");
+    static_assert(!CON || (SHIELD && RESAMPLE && !SPLIT) || (!SHIELD && !RESAMPLE),
+                  "half-space constraints: the plain, split and generic variants only");
     constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
     constexpr int groups = 256 >> log2L;
     const int T = d.T, M = d.M;
@@ -441,8 +441,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     const uint32_t key0 = d.key0, key1 = d.key1;
     const double* x0p = x0_base + 6 * d.x0_index;
     const double* S0p = Sigma0_base ? Sigma0_base + 36 * d.x0_index : nullptr;
-    // half-space constraints on the whole state (only the CON variant, the generic one with them,
-    // compiles them in): their variances a_i^T Sigma a_i per record
+    // half-space constraints on the whole state (compiled into the CON variants only): their
+    // variances a_i^T Sigma a_i per record
     const int ncon = CON ? d.sc.n_con : 0;
     double* cvar_k = ncon > 0 ? d.cvar + (size_t)(active ? k : 0) * (T + 1) * ncon : nullptr;
 
@@ -844,7 +844,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 // a block, so the dispatch below is a block-uniform branch.
 template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false>
 __global__ __launch_bounds__(SPLIT ? 512 : 256)
-__attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE) ? 2
+__attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE || CON) ? 2
                                    : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
     const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
     const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
@@ -1191,8 +1191,14 @@ hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int
                           hipStream_t stream)
 {
     const dim3 g(nblocks), b256(256), b512(512);
-    if (con)
+    if (con && (shield || resample))
         hipLaunchKernelGGL((solve_kernel<P, true, false, true, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (con && split)
+        hipLaunchKernelGGL((solve_kernel<P, false, true, false, true>), g, b512, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (con)
+        hipLaunchKernelGGL((solve_kernel<P, false, false, false, true>), g, b256, lds, stream, inst,
                            blocks, x0_base, Sigma0_base, extra_shift);
     else if (shield && resample)
         hipLaunchKernelGGL((solve_kernel<P, true, false, true>), g, b256, lds, stream, inst,
@@ -1290,7 +1296,7 @@ hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int n
                         hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    split = split && !shield && !resample && !con;
+    split = split && !shield && !resample;
     switch (ppl) {
     case 1:
         return launch_solve_p<1>(inst, blocks, nblocks, shield, split, resample, con,

@@ -212,9 +212,8 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         used += need;
         lds = std::max(lds, solve_lds_bytes(sh.lanes, T, s->ppl, false));
         ring_fits = ring_fits && solve_lds_bytes(sh.lanes, T, s->ppl, true) <= kMaxLds;
-        // half-space constraints run in the generic variant (shield and re-sampling compiled in)
-        shield = shield || v.p.shield_iters > 0 || v.p.n_con > 0;
-        resample = resample || v.p.belief != 0 || v.p.n_con > 0;
+        shield = shield || v.p.shield_iters > 0;
+        resample = resample || v.p.belief != 0;
         con = con || v.p.n_con > 0;
         descs.push_back(d);
         append_blocks(blocks, i, r.K, sh.lanes);
@@ -321,12 +320,7 @@ bss_status bss_server_create(const bss_server_config* cfg, const bss_params* veh
     if (c.n_streams < 1 || c.n_streams > 16) return fail(BSS_E_INVAL, "n_streams must be 1..16");
     if (c.max_batch < 1 || c.max_batch > 4096)
         return fail(BSS_E_INVAL, "max_batch must be 1..4096");
-    size_t worst = 0;
-    for (int lanes = 8; lanes <= 64; lanes *= 2)
-        worst = std::max(worst, scratch_bytes(c.K_max, c.T, lanes));
-    if (c.hbm_budget / (uint64_t)c.n_streams < worst)
-        return fail(BSS_E_INVAL, "hbm_budget %llu is below n_streams x %zu bytes (one request of "
-                    "K_max per stream)", (unsigned long long)c.hbm_budget, worst);
+    int max_con = 0;
     for (int i = 0; i < c.n_vehicles; ++i) {
         bss_params q = vehicles[i];
         q.K = c.K_max;
@@ -337,7 +331,16 @@ bss_status bss_server_create(const bss_server_config* cfg, const bss_params* veh
         if (q.local_repair != 0)
             return fail(BSS_E_INVAL, "vehicle %d: the repair of the update (local_repair) runs per "
                         "context, not in the server's batched launches", i);
+        max_con = std::max(max_con, (int)q.n_con);
     }
+    // one request of K_max per stream must fit, with the variances of the most constrained vehicle
+    size_t worst = 0;
+    for (int lanes = 8; lanes <= 64; lanes *= 2)
+        worst = std::max(worst, scratch_bytes(c.K_max, c.T, lanes));
+    worst += align256((size_t)c.K_max * (c.T + 1) * (size_t)max_con * sizeof(double));
+    if (c.hbm_budget / (uint64_t)c.n_streams < worst)
+        return fail(BSS_E_INVAL, "hbm_budget %llu is below n_streams x %zu bytes (one request of "
+                    "K_max per stream)", (unsigned long long)c.hbm_budget, worst);
 
     bss_server* s = new (std::nothrow) bss_server();
     if (!s) return fail(BSS_E_NOMEM, "host allocation failed");

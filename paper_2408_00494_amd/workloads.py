@@ -119,6 +119,19 @@ def config_shielded(delta: float = 0.05, gamma: float = 0.1, seed: int = 3000):
     return prob, x0, v
 
 
+def config_constrained(seed: int = 2):
+    """The paper-scale solve with four half-space constraints on the state: a speed limit
+    vx <= 6.5, the yaw rate within +-0.8 (two half-spaces) and vy + 0.5 r <= 1.0."""
+    prob, x0, v = config_paper_scale(seed)
+    a = np.zeros(24)
+    a[3] = 1.0                 # vx
+    a[6 + 5] = 1.0             # r
+    a[12 + 5] = -1.0           # -r
+    a[18 + 4], a[18 + 5] = 1.0, 0.5
+    prob = dict(prob, n_con=4, con_a=list(a), con_b=[6.5, 0.8, 0.8, 1.0])
+    return prob, x0, v
+
+
 def config_batch(n: int = 64, seed: int = 4):
     """64 independent instances with K in {512..8192}, M in {16..256}, T uniform in [20, 80],
     ellipse semi-axes uniform 15-50 m, half-width 1.5-3 m, disturbance std x U[0.5, 3]."""

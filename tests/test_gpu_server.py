@@ -96,6 +96,39 @@ def test_same_alone_and_in_the_mix():
             assert states[v] == (count[v], 0)
 
 
+def _constrained(fleet):
+    """Every other vehicle of the fleet gets half-space constraints (speed limit, yaw rate)."""
+    probs, s0 = fleet
+    a = np.zeros(24)
+    a[3], a[6 + 5], a[12 + 5] = 1.0, 1.0, -1.0
+    out = [dict(p, n_con=3, con_a=list(a), con_b=[5.7, 0.7, 0.7, 0.0]) if i % 2 == 0 else p
+           for i, p in enumerate(probs)]
+    return out, s0
+
+
+def test_constrained_vehicles_same_alone_and_in_the_mix():
+    """Vehicles with half-space constraints share launches with unconstrained ones (the launch
+    carries the constraint variant); every command and warm start equals the vehicle's chain of
+    single solves, and the budget check counts the constraint variances of the worst request."""
+    fleet = _constrained(_fleet(6, seed=12))
+    reqs = _requests(fleet, per_vehicle=3, seed=13)
+    u0_ref, v_ref, count = _alone(fleet, reqs)
+    for cfg in (dict(n_streams=2, max_batch=4), dict(n_streams=1, max_batch=64)):
+        u0, st, final, states = _serve(fleet, reqs, hbm_budget=256 << 20, **cfg)
+        assert np.all(st == 0)
+        assert np.array_equal(u0, u0_ref), cfg
+        for v in range(len(fleet[0])):
+            assert np.array_equal(final[v], v_ref[v]), (cfg, v)
+            assert states[v] == (count[v], 0)
+    worst_plain = 0
+    for lanes in (8, 16, 32, 64):
+        blocks = (K_MAX + 256 // lanes - 1) // (256 // lanes)
+        worst_plain = max(worst_plain, sum((b + 255) // 256 * 256 for b in (
+            K_MAX * (T + 1) * 9 * 8, K_MAX * 8, blocks * (2 * T + 4) * 8)))
+    with pytest.raises(bss.BssError, match="hbm_budget"):
+        bss.Server(fleet[0], T=T, K_max=K_MAX, M_max=M_MAX, n_streams=1, hbm_budget=worst_plain)
+
+
 def test_budget_admission_keeps_results():
     """A budget of one largest request per slot forces one request per launch at most."""
     fleet = _fleet(6, seed=8)
