@@ -92,8 +92,9 @@ typedef enum bss_status {
  *   in the units of c_i (scale a_i and b_i to weigh it against the track's squared-metre form).
  *   The belief keeps a_i^T Sigma a_i per record (the variance of the particles' projections
  *   a_i^T x^n, the same unbiased estimate as the covariance; with sigma points plus a_i^T Q a_i of
- *   the disturbance).  Such instances run in the generic rollout variant (no separate noise
- *   waves); the staged bss_dev_score and bss_dev_repair reject n_con > 0.
+ *   the disturbance).  Such instances run in rollout variants with the constraints compiled in
+ *   (batches and the server run them for all their members when one is constrained); the staged
+ *   bss_dev_score and bss_dev_repair reject n_con > 0.
  */
 typedef struct bss_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;

@@ -94,7 +94,7 @@ def _warm(T):
 
 
 @pytest.mark.parametrize("K,M,T,lanes", [(512, 32, 30, 0), (96, 64, 40, 16), (64, 37, 25, 8),
-                                         (40, 128, 20, 32)])
+                                         (40, 128, 20, 32), (24, 300, 15, 0), (1, 20, 12, 0)])
 def test_constraint_solve_matches_oracle(K, M, T, lanes):
     """Persistent particles, several shapes and ragged particle counts; the constraints are
     active: they change the costs (v+ may not move where one sample carries the weight)."""
@@ -102,6 +102,8 @@ def test_constraint_solve_matches_oracle(K, M, T, lanes):
     prob = _with_constraints(dict(prob, K=K, M=M, T=T, sigma_w=[0.2, 0.2, 0.1]))
     v = _warm(T)
     got, ref = _compare(prob, x0, v, s=3, lanes=lanes)
+    if M > 256:
+        assert got["info"]["ppl"] == 8
     free = oracle.solve(dict(prob, n_con=0), 3, x0, v, want_traces=False, nthreads=NTHREADS)
     assert np.max(np.abs(free["S"] - ref["S"]) / np.abs(ref["S"])) > 1e-3
 
