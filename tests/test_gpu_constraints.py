@@ -108,6 +108,15 @@ def test_constraint_solve_matches_oracle(K, M, T, lanes):
     assert np.max(np.abs(free["S"] - ref["S"]) / np.abs(ref["S"])) > 1e-3
 
 
+def test_constrained_paper_scale_matches_oracle():
+    """The constrained workload the benchmark times (K=4096, M=64, T=50, four constraints), in the
+    benchmark's launch shape: every cost, v+, and the beliefs and constraint variances of every
+    sample against the oracle."""
+    prob, x0, v = W.config_constrained()
+    got, ref = _compare(prob, x0, v, s=0)
+    assert got["info"]["split"] == 1 and (got["info"]["lanes"], got["info"]["ppl"]) == (16, 4)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3])
 def test_fewer_constraints_match_oracle(n):
     prob, x0, _ = W.config_small()
