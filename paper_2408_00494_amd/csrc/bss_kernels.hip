@@ -972,6 +972,9 @@ __device__ inline void write_stats(double* stats, int col, double vo, bool ok, d
 
 // One wave per (instance, control entry), four per block.  v+ goes to the other buffer of the
 // instance's ping-pong pair; the last wave of an instance to finish advances its per-solve state.
+// Nothing in this launch reads what the others write (the counter only elects the last wave; v+,
+// the statistics and the state are read by later launches, which the launch boundary orders), so
+// no fence is issued: a device-scope release writes back the chip-level cache.
 __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const MergeDesc* cols,
                                                     int ncols, int extra_shift)
 {
@@ -991,7 +994,6 @@ __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const M
         const double vo = ok ? vi + N / Z : vi;
         d.v[1 - cur][col] = vo;
         write_stats(d.stats, col, vo, ok, m, Z, W2, nf);
-        __threadfence();
         const uint32_t prev = atomicAdd(&d.done, 1u);
         if (prev == (uint32_t)(2 * T - 1)) {
             // every entry of this instance is written: publish the new state
@@ -1000,7 +1002,6 @@ __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const M
             d.vshift = d.shift_after;
             d.solve_index = d.solve_index + 1u;
             d.status = ok ? 0 : 5;
-            __threadfence();
         }
     }
 }
