@@ -101,6 +101,7 @@ ScoreF64 make_score(const bss_params& p)
     s.ell_a = p.ell_a;
     s.ell_b = p.ell_b;
     s.half_width = p.half_width;
+    s.ell = make_ellipse(p.ell_a, p.ell_b);
     s.nu = backoff_of(p);
     s.gamma = p.gamma;
     s.lambda = p.lambda;

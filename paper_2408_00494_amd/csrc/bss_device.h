@@ -329,22 +329,24 @@ __device__ inline void car_step_f64(const ScoreF64& p, const double* x, double s
 // problem into the root of the convex decreasing F(s) = (r0 z0/(s+r0))^2 + (z1/(s+1))^2 - 1 on
 // (z1 - 1, |(r0 z0, z1)| - 1]; it is found by Newton's method safeguarded by that bracket,
 // started from the first-order distance estimate.
-__device__ inline void ellipse_nearest_q1(double e0, double e1, double y0, double y1, double* c0,
+// The divisions by the semi-axes are multiplications by the precomputed reciprocals.
+__device__ inline void ellipse_nearest_q1(const EllipseF64& E, double y0, double y1, double* c0,
                                           double* c1)
 {
+    const double e0 = E.e0, e1 = E.e1;
     if (y1 > 0.0) {
         if (y0 > 0.0) {
-            const double z0 = y0 / e0, z1 = y1 / e1;
+            const double z0 = y0 * E.inv_e0, z1 = y1 * E.inv_e1;
             const double g = z0 * z0 + z1 * z1 - 1.0;
             if (g != 0.0) {
-                const double r0 = (e0 / e1) * (e0 / e1);
+                const double r0 = E.r0;
                 const double n0 = r0 * z0;
                 double lo = z1 - 1.0;
                 double hi = g < 0.0 ? 0.0 : sqrt(n0 * n0 + z1 * z1) - 1.0;
-                // first-order signed distance d ~ (F(p) - 1) / |grad F| and s = d / (e1^2 |n|)
-                const double gx = y0 / (e0 * e0), gy = y1 / (e1 * e1);
-                const double gn = sqrt(gx * gx + gy * gy);
-                double s = (0.5 * g / gn) / (e1 * e1 * gn);
+                // first-order signed distance d ~ (F(p) - 1) / |grad F| and s = d / (e1^2 |n|),
+                // i.e. s = g / (2 e1^2 |grad F|^2) with grad F / 2 = (y0/e0^2, y1/e1^2)
+                const double gx = y0 * E.inv_e0sq, gy = y1 * E.inv_e1sq;
+                double s = 0.5 * g * E.inv_e1sq / (gx * gx + gy * gy);
                 if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
                 for (int it = 0; it < 200; ++it) {
                     const double i0 = 1.0 / (s + r0), i1 = 1.0 / (s + 1.0);
@@ -371,7 +373,7 @@ __device__ inline void ellipse_nearest_q1(double e0, double e1, double y0, doubl
     } else {
         const double numer0 = e0 * y0, denom0 = e0 * e0 - e1 * e1;
         if (numer0 < denom0) {
-            const double xde0 = numer0 / denom0;
+            const double xde0 = numer0 * E.inv_denom0;
             *c0 = e0 * xde0;
             *c1 = e1 * sqrt(1.0 - xde0 * xde0);
         } else {
@@ -383,26 +385,26 @@ __device__ inline void ellipse_nearest_q1(double e0, double e1, double y0, doubl
 
 // Signed distance of (X, Y) to the ellipse (X/a)^2 + (Y/b)^2 = 1 (positive outside) and the
 // outward unit normal at the nearest point.
-__device__ inline void ellipse_sdf(double a, double b, double X, double Y, double* sd, double* nx,
-                                   double* ny)
+__device__ inline void ellipse_sdf(const EllipseF64& E, double X, double Y, double* sd,
+                                   double* nx, double* ny)
 {
     const double ax = fabs(X), ay = fabs(Y);
     double cx, cy;
-    if (a >= b) {
-        ellipse_nearest_q1(a, b, ax, ay, &cx, &cy);
+    if (!E.swap) {
+        ellipse_nearest_q1(E, ax, ay, &cx, &cy);
     } else {
-        ellipse_nearest_q1(b, a, ay, ax, &cy, &cx);
+        ellipse_nearest_q1(E, ay, ax, &cy, &cx);
     }
     cx = X < 0.0 ? -cx : cx;
     cy = Y < 0.0 ? -cy : cy;
     const double dx = X - cx, dy = Y - cy;
     const double dist = sqrt(dx * dx + dy * dy);
-    const double level = (X / a) * (X / a) + (Y / b) * (Y / b);
+    const double level = X * X * E.inv_a2 + Y * Y * E.inv_b2;
     *sd = level < 1.0 ? -dist : dist;
-    const double gx = cx / (a * a), gy = cy / (b * b);
-    const double gn = sqrt(gx * gx + gy * gy);
-    *nx = gx / gn;
-    *ny = gy / gn;
+    const double gx = cx * E.inv_a2, gy = cy * E.inv_b2;
+    const double ign = 1.0 / sqrt(gx * gx + gy * gy);
+    *nx = gx * ign;
+    *ny = gy * ign;
 }
 
 // Belief of one step, evaluated once: lateral deviation, normal, spread along the normal and the
@@ -455,7 +457,7 @@ __device__ inline BeliefEval eval_belief(const ScoreF64& p, const double* mom,
                                          const double* sig_con = nullptr)
 {
     BeliefEval b;
-    ellipse_sdf(p.ell_a, p.ell_b, mom[0], mom[1], &b.ey, &b.nx, &b.ny);
+    ellipse_sdf(p.ell, mom[0], mom[1], &b.ey, &b.nx, &b.ny);
     const double var = b.nx * b.nx * mom[6] + 2.0 * b.nx * b.ny * mom[7] + b.ny * b.ny * mom[8];
     b.sigma = sqrt(fmax(var, 0.0));
     for (int i = 0; i < p.n_obs; ++i) {
@@ -500,7 +502,7 @@ __device__ inline double repair_residual(const ScoreF64& p, const double* xbar,
     double xn[6];
     car_step_f64(p, xbar, steer, accel, xn);
     double ey, nx, ny;
-    ellipse_sdf(p.ell_a, p.ell_b, xn[0], xn[1], &ey, &nx, &ny);
+    ellipse_sdf(p.ell, xn[0], xn[1], &ey, &nx, &ny);
     return -barrier_at(p, xn, ey, be.sigma, be.sig_obs, sig_con) + (1.0 - p.gamma) * h_t;
 }
 

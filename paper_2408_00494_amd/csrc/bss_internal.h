@@ -33,6 +33,35 @@ struct CarF32 {
     float v_min;
 };
 
+// The centerline ellipse in the form the signed distance uses (built on the host): semi-axes
+// ordered e0 >= e1 for the nearest-point solve, and the reciprocals it multiplies by.
+struct EllipseF64 {
+    double inv_a2, inv_b2;                      // 1/a^2, 1/b^2 (a along X, b along Y)
+    double e0, e1;                              // larger and smaller semi-axis
+    double inv_e0, inv_e1, inv_e0sq, inv_e1sq;  // 1/e0, 1/e1, 1/e0^2, 1/e1^2
+    double r0;                                  // (e0/e1)^2
+    double inv_denom0;                          // 1/(e0^2 - e1^2) (0 for a circle)
+    int32_t swap;                               // 1 when b > a: the solve runs on (Y, X)
+};
+
+inline EllipseF64 make_ellipse(double a, double b)
+{
+    EllipseF64 E;
+    E.inv_a2 = 1.0 / (a * a);
+    E.inv_b2 = 1.0 / (b * b);
+    E.swap = b > a ? 1 : 0;
+    E.e0 = E.swap ? b : a;
+    E.e1 = E.swap ? a : b;
+    E.inv_e0 = 1.0 / E.e0;
+    E.inv_e1 = 1.0 / E.e1;
+    E.inv_e0sq = 1.0 / (E.e0 * E.e0);
+    E.inv_e1sq = 1.0 / (E.e1 * E.e1);
+    E.r0 = (E.e0 / E.e1) * (E.e0 / E.e1);
+    const double den = E.e0 * E.e0 - E.e1 * E.e1;
+    E.inv_denom0 = den > 0.0 ? 1.0 / den : 0.0;
+    return E;
+}
+
 // Everything the double-precision per-(sample, step) code needs: model (for the shield's mean
 // prediction), costs, barrier and repair settings.
 struct ScoreF64 {
@@ -41,6 +70,7 @@ struct ScoreF64 {
     double inv_var0, inv_var1;      // 1 / sigma_eps^2 (0 where the std is 0)
     double gamma_u, v_goal, q_vx, q_vy, q_r, q_ey, q_epsi, C_cbf, C_obs, phi_scale;
     double ell_a, ell_b, half_width;
+    EllipseF64 ell;                 // the same ellipse, prepared for the signed distance
     double nu, gamma, lambda;
     int32_t shield_iters;
     double shield_gmin, shield_fd;

@@ -1148,12 +1148,12 @@ __global__ void model_step_kernel(CarF32 car, const float* x, const float* u, fl
     o[5] = fmaf(car.dt, dr2, vr);
 }
 
-__global__ void sdf_kernel(double a, double b, const double* pts, double* out, int64_t n)
+__global__ void sdf_kernel(EllipseF64 E, const double* pts, double* out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double sd, nx, ny;
-    ellipse_sdf(a, b, pts[2 * i], pts[2 * i + 1], &sd, &nx, &ny);
+    ellipse_sdf(E, pts[2 * i], pts[2 * i + 1], &sd, &nx, &ny);
     out[3 * i] = sd;
     out[3 * i + 1] = nx;
     out[3 * i + 2] = ny;
@@ -1400,8 +1400,8 @@ hipError_t launch_sdf(double a, double b, const double* pts, double* out, int64_
                       hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sdf_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, a, b, pts, out,
-                       n);
+    hipLaunchKernelGGL(sdf_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream,
+                       make_ellipse(a, b), pts, out, n);
     return hipGetLastError();
 }
 
