@@ -160,7 +160,7 @@ def test_constraint_single_particle_has_zero_spread():
     assert np.all(got["con_var"] == 0.0)
 
 
-@pytest.mark.parametrize("scenario", ["yaw", "all"])
+@pytest.mark.parametrize("scenario", ["yaw", "yaw_resampled", "all"])
 def test_shielded_constraint_solve_matches_oracle(scenario):
     """The repair against the constraints as well as the walls, checked as a stage from the GPU's
     own beliefs, constraint variances and pre-repair controls (bar 1e-6), and end to end on what
@@ -170,16 +170,20 @@ def test_shielded_constraint_solve_matches_oracle(scenario):
     slowly (the speed limit: d vx / d accel = dt) turns a small difference of the belief into a
     large one of the control, at every step where it acts.  "yaw" (|r| <= 0.6: steering has
     authority) keeps the bars of the other shielded checks: every cost within 1e-3, controls past
-    1e-4 in at most 2 % of the samples.  "all" (all four constraints, the repair acting at most
+    1e-4 in at most 2 % of the samples.  "yaw_resampled" (the same with the particles re-sampled
+    every step: the generic variant with the repair, the re-sampling and the constraints all
+    active) keeps every cost within 1e-3; there the oracle's own control drift is already near 2 %,
+    so the controls are held to the sensitivity bar below.  "all" (all four constraints, the repair acting at most
     steps) is held to the method's own sensitivity: the oracle against itself with the estimate
     moved by ~1e-6 gives the share of samples past each bar, and the GPU may exceed neither share
     by more than a factor 2 plus 1 %."""
     prob, x0, _ = W.config_small()
     prob = dict(prob, K=512, M=32, shield_iters=2)
-    if scenario == "yaw":
+    if scenario.startswith("yaw"):
         a = np.zeros(24)
         a[5], a[11] = 1.0, -1.0
-        prob = dict(prob, n_con=2, con_a=list(a), con_b=[0.6, 0.6, 0.0, 0.0])
+        prob = dict(prob, n_con=2, con_a=list(a), con_b=[0.6, 0.6, 0.0, 0.0],
+                    belief=1 if scenario == "yaw_resampled" else 0)
     else:
         prob = dict(_with_constraints(prob), con_b=[5.8, 0.8, 0.8, 3.4])
     v = _warm(prob["T"])
@@ -216,14 +220,17 @@ def test_shielded_constraint_solve_matches_oracle(scenario):
     if scenario == "yaw":
         assert np.max(per_S) <= 1e-3
         assert np.mean(per_k > 1e-4) <= 0.02
+        return
+    dx = np.array([1e-6, 1e-6, 1e-7, 1e-6, 1e-7, 1e-7])
+    moved = oracle.solve(prob, s, x0 + dx, v, nthreads=NTHREADS)
+    sens_u = np.mean(np.max(np.abs(moved["u"] - ref["u"]) / scale, axis=(1, 2)) > 1e-4)
+    sens_S = np.mean(np.abs(moved["S"] - ref["S"]) / np.abs(ref["S"]) > 1e-3)
+    print(f"oracle against itself (estimate moved by ~1e-6): u drift > 1e-4 {sens_u:.2%}, "
+          f"|dS|/|S| > 1e-3 {sens_S:.2%}", flush=True)
+    assert np.mean(per_k > 1e-4) <= 2 * sens_u + 0.01
+    if scenario == "yaw_resampled":
+        assert np.max(per_S) <= 1e-3
     else:
-        dx = np.array([1e-6, 1e-6, 1e-7, 1e-6, 1e-7, 1e-7])
-        moved = oracle.solve(prob, s, x0 + dx, v, nthreads=NTHREADS)
-        sens_u = np.mean(np.max(np.abs(moved["u"] - ref["u"]) / scale, axis=(1, 2)) > 1e-4)
-        sens_S = np.mean(np.abs(moved["S"] - ref["S"]) / np.abs(ref["S"]) > 1e-3)
-        print(f"oracle against itself (estimate moved by ~1e-6): u drift > 1e-4 {sens_u:.2%}, "
-              f"|dS|/|S| > 1e-3 {sens_S:.2%}", flush=True)
-        assert np.mean(per_k > 1e-4) <= 2 * sens_u + 0.01
         assert np.mean(per_S > 1e-3) <= 2 * sens_S + 0.01
 
 
