@@ -1306,7 +1306,8 @@ bss_status bss_dev_score(const bss_params* p, const double* mom, const float* u,
     if (st != BSS_OK) return st;
     if (!mom || !u || !v || !S) return fail(BSS_E_INVAL, "NULL buffer");
     if (p->n_con > 0)
-        return fail(BSS_E_INVAL, "the staged score takes no constraint variances (n_con must be 0)");
+        return fail(BSS_E_INVAL,
+                    "the staged score takes no constraint variances (n_con must be 0)");
     hipError_t e = launch_score(p->K, p->T, make_score(*p), mom, u, v, S, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "score launch");
     return BSS_OK;
@@ -1344,7 +1345,8 @@ bss_status bss_dev_repair(const bss_params* p, const double* mom, const double* 
     if (st != BSS_OK) return st;
     if (n < 0 || (n > 0 && (!mom || !u_in || !u_out))) return fail(BSS_E_INVAL, "bad arguments");
     if (p->n_con > 0)
-        return fail(BSS_E_INVAL, "the staged repair takes no constraint variances (n_con must be 0)");
+        return fail(BSS_E_INVAL,
+                    "the staged repair takes no constraint variances (n_con must be 0)");
     hipError_t e = launch_repair(make_score(*p), mom, u_in, u_out, n, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "repair launch");
     return BSS_OK;

@@ -173,10 +173,10 @@ def test_shielded_constraint_solve_matches_oracle(scenario):
     1e-4 in at most 2 % of the samples.  "yaw_resampled" (the same with the particles re-sampled
     every step: the generic variant with the repair, the re-sampling and the constraints all
     active) keeps every cost within 1e-3; there the oracle's own control drift is already near 2 %,
-    so the controls are held to the sensitivity bar below.  "all" (all four constraints, the repair acting at most
-    steps) is held to the method's own sensitivity: the oracle against itself with the estimate
-    moved by ~1e-6 gives the share of samples past each bar, and the GPU may exceed neither share
-    by more than a factor 2 plus 1 %."""
+    so the controls are held to the sensitivity bar below.  "all" (all four constraints, the
+    repair acting at most steps) is held to the method's own sensitivity: the oracle against
+    itself with the estimate moved by ~1e-6 gives the share of samples past each bar, and the GPU
+    may exceed neither share by more than a factor 2 plus 1 %."""
     prob, x0, _ = W.config_small()
     prob = dict(prob, K=512, M=32, shield_iters=2)
     if scenario.startswith("yaw"):
