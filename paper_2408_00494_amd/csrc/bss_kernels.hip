@@ -662,8 +662,9 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 // that the compiler interleaves the particles' independent dependency chains.
                 // With eight, the staged form does not fit the registers of three waves per
                 // SIMD; those particles are stepped one after the other (several waves per SIMD
-                // hide the latency instead).
-                constexpr int Q = P <= 4 ? P : 1;
+                // hide the latency instead), except in the repair's variant, whose two waves per
+                // SIMD leave room for stages over four particles at a time.
+                constexpr int Q = P <= 4 ? P : (SHIELD && !RESAMPLE && !CON ? 4 : 1);
 #pragma unroll
                 for (int p0 = 0; p0 < P; p0 += Q) {
                     float w0[Q], w1[Q], w2[Q];
