@@ -93,6 +93,9 @@ def _load():
     lib.orc_uniform.restype = C.c_double
     lib.orc_normals.argtypes = [C.c_uint64, _u32p, _f64p]
     lib.orc_normals.restype = None
+    lib.orc_disturbance_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                            C.c_uint32, _f64p]
+    lib.orc_disturbance_normals.restype = None
     lib.orc_backoff.argtypes = [C.c_double, C.c_int32]
     lib.orc_backoff.restype = C.c_double
     lib.orc_car_deriv.argtypes = [P, _f64p, _f64p, _f64p]
@@ -179,6 +182,13 @@ def normals(seed, ctr):
     z = np.zeros(4)
     lib().orc_normals(int(seed), np.ascontiguousarray(ctr, dtype=np.uint32), z)
     return z
+
+
+def disturbance_normals(seed, s, k, t, m):
+    """The three disturbance normals of particle m at step t of sample word k (solve index s)."""
+    w = np.zeros(3)
+    lib().orc_disturbance_normals(int(seed), int(s), int(k), int(t), int(m), w)
+    return w
 
 
 def uniform(r):

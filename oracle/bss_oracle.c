@@ -88,7 +88,8 @@ void orc_normals_many(uint64_t seed, const uint32_t* ctr, double* z, int64_t n)
 }
 
 /* Counter layout (the random-number contract shared by both implementations):
- *   word0 = time step t (or the block index for the initial spread), word1 = particle m,
+ *   word0 = time step t (or the block index for the initial spread), word1 = particle m (for
+ *   the disturbance: the block index 3q + b of particle quad q, see disturbance_normals),
  *   word2 = sample k, word3 = (stream tag << 28) | (solve index & 0x0FFFFFFF).
  * Tags: 0 control noise eps_{k,t}; 1 disturbance w_{k,m,t}; 2 initial spread of particles;
  * 4 and 5 the two blocks of standard normals of a Gaussian re-sampling draw (word0 = t). */
@@ -609,22 +610,38 @@ static void sigma_step(const orc_params* p, const double u[2], double* part, dou
     sigma_points(mean, cov_next, part);
 }
 
+/* The three standard normals of the disturbance of particle m at step t (tag 1).  Particles come
+ * in quads: quad q = m / 4 owns the three Philox blocks with counter words (t, 3q + b, k) for
+ * b = 0, 1, 2, whose twelve normals (block b gives normals 4b .. 4b+3) are dealt out three per
+ * particle in order: particle 4q + i takes normals 3i, 3i + 1 and 3i + 2.  Every normal of a block
+ * is used. */
+void orc_disturbance_normals(uint64_t seed, uint32_t s, uint32_t k, uint32_t t, uint32_t m,
+                             double w[3])
+{
+    uint32_t q = m / 4u, i = m % 4u;
+    double z12[12];
+    for (uint32_t b = 0; b < 3; ++b) {
+        uint32_t ctr[4];
+        rng_counter(t, 3u * q + b, k, 1u, s, ctr);
+        orc_normals(seed, ctr, &z12[4 * b]);
+    }
+    for (int c = 0; c < 3; ++c) w[c] = z12[3 * i + c];
+}
+
 /* One step of Alg. 2 with persistent particles: x^n_{t+1} = f(x^n_t, u_t) + [0,0,0, w^n_t]
- * (w from tag 1), then the moments of the new particle set.  The disturbance may depend on the
- * state (p(w|x)): its std is sigma_w (1 + kappa |vx^n_t|); with common random numbers every sample
- * draws it with counter word k = 0. */
+ * (w from tag 1, orc_disturbance_normals), then the moments of the new particle set.  The
+ * disturbance may depend on the state (p(w|x)): its std is sigma_w (1 + kappa |vx^n_t|); with
+ * common random numbers every sample draws it with counter word k = 0. */
 static void propagate_step(const orc_params* p, uint32_t s, int32_t k, int t, const double u[2],
                            double* part, double* nxt, double* mom_next)
 {
-    uint32_t ctr[4];
-    double z[4];
+    double z[3];
     int M = p->M;
     uint32_t kw = p->crn ? 0u : (uint32_t)k;
     for (int m = 0; m < M; ++m) {
         double scale = 1.0 + p->sigma_w_speed * fabs(part[m * 6 + 3]);
         orc_model_step(p, &part[m * 6], u, &nxt[m * 6]);
-        rng_counter((uint32_t)t, (uint32_t)m, kw, 1u, s, ctr);
-        orc_normals(p->seed, ctr, z);
+        orc_disturbance_normals(p->seed, s, kw, (uint32_t)t, (uint32_t)m, z);
         nxt[m * 6 + 3] += p->sigma_w[0] * scale * z[0];
         nxt[m * 6 + 4] += p->sigma_w[1] * scale * z[1];
         nxt[m * 6 + 5] += p->sigma_w[2] * scale * z[2];

@@ -86,6 +86,11 @@ double orc_uniform(uint32_t r);
 void   orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
 void   orc_philox_many(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, int64_t n);
 void   orc_normals_many(uint64_t seed, const uint32_t* ctr, double* z, int64_t n);
+/* Disturbance normals w[3] of particle m at step t of sample word k under solve index s: particle
+ * quad q = m / 4 owns the blocks with counter (t, 3q + b, k, (1 << 28) | s), b = 0..2, whose twelve
+ * normals are dealt out three per particle (particle 4q + i takes normals 3i .. 3i + 2). */
+void   orc_disturbance_normals(uint64_t seed, uint32_t s, uint32_t k, uint32_t t, uint32_t m,
+                               double w[3]);
 
 /* Lower factor L of a symmetric positive semi-definite 6x6 matrix with L L^T = A, by columns; a
  * pivot d <= 1e-10 A_jj + 1e-24 counts as zero and leaves its column zero (so variances at the

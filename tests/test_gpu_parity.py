@@ -47,15 +47,17 @@ def cost_err(S_gpu, S_ref):
 
 # ================================= random numbers (bit-exact) ==================================
 def _counters_of(prob, s, n_sample=None, rng=None):
-    """Counters a solve of `prob` at solve index s draws (tag 0: (t,0,k); tag 1: (t,m,k))."""
+    """Counters a solve of `prob` at solve index s draws (tag 0: (t, 0, k); tag 1: (t, 3q + b, k)
+    for the particle quads q < ceil(M / 4) and b < 3)."""
     K, M, T = prob["K"], prob["M"], prob["T"]
+    nb = 3 * ((M + 3) // 4)
     if n_sample is None:
-        t, m, k = np.meshgrid(np.arange(T), np.arange(M), np.arange(K), indexing="ij")
+        t, m, k = np.meshgrid(np.arange(T), np.arange(nb), np.arange(K), indexing="ij")
         t, m, k = t.ravel(), m.ravel(), k.ravel()
         te, ke = np.meshgrid(np.arange(T), np.arange(K), indexing="ij")
         te, ke = te.ravel(), ke.ravel()
     else:
-        t, m, k = rng.integers(0, T, n_sample), rng.integers(0, M, n_sample), rng.integers(0, K, n_sample)
+        t, m, k = rng.integers(0, T, n_sample), rng.integers(0, nb, n_sample), rng.integers(0, K, n_sample)
         te, ke = rng.integers(0, T, n_sample), rng.integers(0, K, n_sample)
     w = np.stack([t, m, k, np.full_like(t, (1 << 28) | (s & 0x0FFFFFFF))], axis=1)
     e = np.stack([te, np.zeros_like(te), ke, np.full_like(te, s & 0x0FFFFFFF)], axis=1)

@@ -482,11 +482,13 @@ def test_special_case_is_plain_mppi():
 
 
 def test_brute_force_tiny_solve():
-    """K = 2, M = 3, T = 2 with Sigma_0 != 0: a literal evaluator that stores every particle and
-    uses the unshifted weights in extended precision agrees with the solve."""
+    """K = 2, M = 5, T = 2 with Sigma_0 != 0: a literal evaluator that stores every particle and
+    uses the unshifted weights in extended precision agrees with the solve.  The disturbance
+    normals of step t are dealt from the twelve normals of each particle quad's three blocks
+    (t, 3q + b, k), three per particle; M = 5 spans two quads."""
     prob, x0, _ = W.config_small()
-    prob = dict(prob, K=2, M=3, T=2, C_cbf=50.0)
-    T, K, M = 2, 2, 3
+    prob = dict(prob, K=2, M=5, T=2, C_cbf=50.0)
+    T, K, M = 2, 2, 5
     s = 11
     v = np.array([[0.05, 0.5], [-0.02, -0.3]])
     Sigma0 = np.diag([0.04, 0.09, 0.001, 0.01, 0.01, 0.001])
@@ -506,8 +508,10 @@ def test_brute_force_tiny_solve():
             U[t] = np.clip(v[t] + np.array(prob["sigma_eps"]) * z[:2], [-0.4, -4], [0.4, 4])
             for m in range(M):
                 X[t + 1, m] = oracle.model_step(prob, X[t, m], U[t])
-                w = oracle.normals(prob["seed"], [t, m, k, (1 << 28) | s])
-                X[t + 1, m, 3:] += np.array(prob["sigma_w"]) * w[:3]
+                q, i = divmod(m, 4)
+                z12 = np.concatenate([oracle.normals(prob["seed"], [t, 3 * q + b, k, (1 << 28) | s])
+                                      for b in range(3)])
+                X[t + 1, m, 3:] += np.array(prob["sigma_w"]) * z12[3 * i:3 * i + 3]
             mean = X[t + 1].mean(axis=0)
             C = np.cov(X[t + 1, :, :2].T, ddof=1)
             moms.append(np.concatenate([mean, [C[0, 0], C[0, 1], C[1, 1]]]))
