@@ -645,6 +645,52 @@ def test_repair_step_is_the_damped_gauss_newton_step():
     assert got == pytest.approx(want, abs=1e-6)
 
 
+@pytest.mark.parametrize("iters", [1, 2, 5])
+def test_repair_on_an_affine_residual_contracts_in_closed_form(iters):
+    """Linear test model x+ = A x + B u with one binding speed limit a^T x <= b (a = e_vx) and the
+    track term slack (the mean on the centerline, positions independent of u).  Then
+    r(u) = a^T (A xbar + B u) - b + nu sigma + (1 - gamma) h_t is affine with gradient
+    g = B^T a, each damped step multiplies r by rho = gmin^2 / (|g|^2 + gmin^2), and n unclipped
+    steps give u_n = u_0 - r_0 (1 - rho^n) g / |g|^2 and r(u_n) = rho^n r_0.  Every quantity
+    below is computed from the model's matrices and the heuristic of eq. 13, not from the
+    oracle's repair."""
+    dt = 0.05
+    A = np.eye(6)
+    A[3, 3], A[3, 4], A[5, 5] = 0.98, 0.01, 0.9
+    B = np.zeros((6, 2))
+    B[3, 0], B[3, 1] = 0.02, dt          # both controls act on vx; positions are not touched
+    B[5, 0] = 0.5
+    gmin, gam, b_lim, var_c = 0.05, 0.2, 6.0, 1e-4
+    a_con = np.array([0.0, 0.0, 0.0, 1.0, 0.0, 0.0])
+    prob = W.default_problem(model=1, shield_iters=iters, shield_gmin=gmin, gamma=gam, n_con=1,
+                             con_a=list(np.concatenate([a_con, np.zeros(18)])),
+                             con_b=[b_lim, 0.0, 0.0, 0.0])
+    prob["lin_A"], prob["lin_B"] = A, B
+    nu = oracle.backoff(prob["delta"])
+    xbar = np.array([prob["ell_a"], 0.0, math.pi / 2, 5.9, 0.1, 0.0])
+    mom = np.concatenate([xbar, [0.0, 0.0, 0.0]])
+    sig = math.sqrt(var_c)
+    h_track = prob["half_width"] ** 2            # e_y = 0 and Sigma_pos = 0 on the centerline
+    h_t = min(h_track, b_lim - a_con @ xbar - nu * sig)
+
+    def r_of(u):
+        return a_con @ (A @ xbar + B @ u) - b_lim + nu * sig + (1.0 - gam) * h_t
+
+    u0 = np.array([0.05, 3.0])
+    g = B.T @ a_con
+    r0 = r_of(u0)
+    assert r0 > 0
+    rho = gmin ** 2 / (g @ g + gmin ** 2)
+    want = u0 - r0 * (1.0 - rho ** iters) * g / (g @ g)
+    got = oracle.repair(prob, nu, mom, u0, con_var=[var_c])
+    assert np.all(np.abs(want) < [prob["steer_max"], prob["accel_max"]])      # no clipping
+    assert got == pytest.approx(want, rel=1e-9, abs=1e-12)
+    assert r_of(got) == pytest.approx(rho ** iters * r0, rel=1e-7)
+    # the track term stays slack at every point the repair evaluates
+    xn = A @ xbar + B @ got
+    assert h_track > b_lim - a_con @ xn - nu * sig
+
+
 def test_repair_is_continuous():
     """Small changes of the sampled control or of the belief change the repaired control by a
     bounded multiple (the damping caps the gain where the control has little authority)."""
