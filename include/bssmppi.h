@@ -406,6 +406,18 @@ bss_status bss_dev_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int
 /* Four Box-Muller normals per counter: z[n][4] (single precision) from the block's words
  * (r0, r1) and (r2, r3) with uniforms ((r >> 9) + 1/2) 2^-23. */
 bss_status bss_dev_normals(uint64_t seed, const uint32_t* ctr, float* z, int64_t n, void* stream);
+/* The disturbance normals of a solve (the "sample w" line of the propagation algorithm, Alg. 2,
+ * under the counter contract of bss_dev_philox: word 0 = t, word 1 = 3q + b, word 2 = k, or 0
+ * with crn != 0, word 3 = (1 << 28) | (solve_index & 0x0FFFFFFF)), computed by the solve
+ * kernel's own code path for a launch of `lanes` lanes per sample and `ppl` particles per lane
+ * (lanes in {8, 16, 32, 64}, ppl in {1, 2, 4, 8}, lanes * ppl >= M; BSS_E_INVAL otherwise).
+ * Particle quad q = m / 4 draws the three blocks b = 0, 1, 2 and particle 4q + i takes normals
+ * 3i .. 3i + 2 of their twelve (block b: normals 4b .. 4b + 3 as bss_dev_normals).
+ * Outputs (device, caller-owned): words[K][T][3 ceil(M / 4)][4] (the raw Philox words of every
+ * block), w[K][T][M][3] (single precision, before the scaling by sigma_w). */
+bss_status bss_dev_disturbance(uint64_t seed, uint32_t solve_index, int32_t K, int32_t M,
+                               int32_t T, int32_t crn, int32_t lanes, int32_t ppl, float* w,
+                               uint32_t* words, void* stream);
 /* One noise-free single-precision RK2 step of the car: x[n][6], u[n][2] -> xn[n][6]. */
 bss_status bss_dev_model_step(const bss_params* p, const float* x, const float* u, float* xn,
                               int64_t n, void* stream);

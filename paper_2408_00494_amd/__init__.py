@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import BssError, check, params_from_problem
 
-__all__ = ["Solver", "Batch", "Server", "BssError", "backoff", "validate", "dev_philox", "dev_normals",
+__all__ = ["Solver", "Batch", "Server", "BssError", "backoff", "validate", "dev_philox", "dev_normals", "dev_disturbance",
            "dev_model_step", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
 
 
@@ -353,6 +353,20 @@ def dev_normals(seed: int, ctr):
     z = torch.empty((ctr.shape[0], 4), dtype=torch.float32, device=ctr.device)
     check(_lib.lib().bss_dev_normals(int(seed), _ptr(ctr), _ptr(z), ctr.shape[0], _stream_ptr()))
     return z
+
+
+def dev_disturbance(seed: int, s: int, K: int, M: int, T: int, lanes: int, ppl: int,
+                    crn: bool = False, device="cuda"):
+    """Disturbance normals of a solve through the solve kernel's own noise path: returns
+    (w [K][T][M][3] float32, words [K][T][3 ceil(M/4)][4] uint32 as int32 bits)."""
+    torch = _torch()
+    nblk = 3 * ((M + 3) // 4)
+    w = torch.empty((K, T, M, 3), dtype=torch.float32, device=device)
+    words = torch.empty((K, T, nblk, 4), dtype=torch.int32, device=device)
+    check(_lib.lib().bss_dev_disturbance(int(seed), int(s), int(K), int(M), int(T),
+                                         1 if crn else 0, int(lanes), int(ppl), _ptr(w),
+                                         _ptr(words), _stream_ptr()))
+    return w, words
 
 
 def dev_model_step(problem: dict, x, u):

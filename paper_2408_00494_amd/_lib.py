@@ -78,7 +78,7 @@ EXPORTS = [
     "bss_get_controls",
     "bss_set_controls", "bss_set_solve_index", "bss_get_solve_index", "bss_get_info",
     "bss_timing_enable", "bss_timing_read", "bss_set_lanes", "bss_destroy", "bss_last_error",
-    "bss_dev_philox", "bss_dev_normals", "bss_dev_model_step", "bss_dev_sdf", "bss_dev_score",
+    "bss_dev_philox", "bss_dev_normals", "bss_dev_disturbance", "bss_dev_model_step", "bss_dev_sdf", "bss_dev_score",
     "bss_dev_update_workspace", "bss_dev_update", "bss_dev_repair", "bss_set_shape",
     "bss_batch_create", "bss_batch_states", "bss_batch_set_states", "bss_batch_copy_states", "bss_batch_solve",
     "bss_batch_capture", "bss_batch_tune", "bss_batch_info", "bss_batch_destroy",
@@ -129,6 +129,7 @@ def _declare(lib):
         "bss_last_error": (C.c_char_p, []),
         "bss_dev_philox": (i32, [u64, vp, vp, i64, vp]),
         "bss_dev_normals": (i32, [u64, vp, vp, i64, vp]),
+        "bss_dev_disturbance": (i32, [u64, u32, i32, i32, i32, i32, i32, i32, vp, vp, vp]),
         "bss_dev_model_step": (i32, [P, vp, vp, vp, i64, vp]),
         "bss_dev_sdf": (i32, [d, d, vp, vp, i64, vp]),
         "bss_dev_score": (i32, [P, vp, vp, vp, vp, vp]),

@@ -1278,6 +1278,26 @@ bss_status bss_dev_normals(uint64_t seed, const uint32_t* ctr, float* z, int64_t
     return BSS_OK;
 }
 
+bss_status bss_dev_disturbance(uint64_t seed, uint32_t solve_index, int32_t K, int32_t M,
+                               int32_t T, int32_t crn, int32_t lanes, int32_t ppl, float* w,
+                               uint32_t* words, void* stream)
+{
+    if (K < 0 || M < 0 || T < 0) return fail(BSS_E_INVAL, "K, M, T must be >= 0");
+    if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64)
+        return fail(BSS_E_INVAL, "lanes must be 8, 16, 32 or 64 (got %d)", lanes);
+    if (ppl != 1 && ppl != 2 && ppl != 4 && ppl != 8)
+        return fail(BSS_E_INVAL, "ppl must be 1, 2, 4 or 8 (got %d)", ppl);
+    if ((int64_t)lanes * ppl < M)
+        return fail(BSS_E_INVAL, "lanes * ppl = %d holds fewer than M = %d particles",
+                    lanes * ppl, M);
+    if ((int64_t)K * M * T > 0 && (!w || !words)) return fail(BSS_E_INVAL, "bad arguments");
+    hipError_t e = launch_disturbance(lanes, ppl, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                      solve_index, K, M, T, crn ? 1 : 0, w, words,
+                                      (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "disturbance launch");
+    return BSS_OK;
+}
+
 bss_status bss_dev_model_step(const bss_params* p, const float* x, const float* u, float* xn,
                               int64_t n, void* stream)
 {

@@ -153,6 +153,110 @@ __device__ __forceinline__ float bm_cos(uint32_t ra, uint32_t rb)
     return bm_radius(ra) * __builtin_amdgcn_cosf(uniform01(rb));
 }
 
+// ---- disturbance normals, dealt from particle quads ----
+// Particle quad q = m / 4 owns the three Philox blocks whose counter word 1 is 3q + b (b = 0, 1,
+// 2).  Block b yields the normals 4b .. 4b + 3 (Box-Muller on words (0, 1), then on (2, 3)); the
+// twelve are dealt three per particle in order, particle 4q + i taking normals 3i .. 3i + 2.  So
+// particle i of a quad reads block i's first normals and what block i - 1 left over.
+//
+// Placement of particles in a group of L lanes with P particles per lane: with four or more, a
+// lane holds whole quads (slots 4h .. 4h + 3 are quad j + h L); with one or two, the 4 / P lanes
+// of an aligned lane quad share one particle quad (slot p of lane j is particle P j + p).
+template <int P, int L>
+__device__ __forceinline__ int particle_of(int j, int p)
+{
+    return P >= 4 ? 4 * (j + L * (p >> 2)) + (p & 3) : P * j + p;
+}
+
+// Philox blocks a lane draws per step, and the counter word 1 of its block i.  With one particle
+// per lane, lane i of a lane quad draws block min(i, 2) (lanes 2 and 3 draw the same block).
+template <int P>
+constexpr int noise_blocks()
+{
+    return P >= 4 ? 3 * (P / 4) : (P == 2 ? 2 : 1);
+}
+
+template <int P, int L>
+__device__ __forceinline__ uint32_t noise_block_word(int j, int i)
+{
+    if (P >= 4) return (uint32_t)(3 * (j + L * (i / 3)) + i % 3);
+    if (P == 2) return (uint32_t)(3 * (j >> 1) + (j & 1) + i);
+    return (uint32_t)(3 * (j >> 2) + ((j & 3) < 2 ? (j & 3) : 2));
+}
+
+// Deals the disturbance normals of the lane's particles slot by slot.  Call next() for slots
+// 0, 1, ..., P - 1 in order (the calls are unrolled, so the carried normals stay in registers):
+// each block is drawn and transformed when its first particle needs it.
+template <int P>
+struct NoiseDealer {
+    const PhiloxStep& ps;
+    const PhiloxParticle* pb;     // the lane's noise_blocks<P>() per-block Philox parts
+    uint32_t key0, key1;
+    int j;                        // lane in the group
+    float c0, c1, c2;             // normals left over by the previous block of the quad
+
+    __device__ __forceinline__ void block(int bi, float* z) const
+    {
+        uint32_t r0, r1, r2, r3;
+        philox10_tail(ps, pb[bi], key0, key1, r0, r1, r2, r3);
+        bm_pair(r0, r1, z[0], z[1]);
+        bm_pair(r2, r3, z[2], z[3]);
+    }
+
+    __device__ __forceinline__ void next(int p, float& w0, float& w1, float& w2)
+    {
+        if constexpr (P >= 4) {
+            const int i = p & 3, h = p >> 2;
+            float z[4];
+            if (i < 3) block(3 * h + i, z);
+            if (i == 0) {
+                w0 = z[0]; w1 = z[1]; w2 = z[2];
+                c0 = z[3];
+            } else if (i == 1) {
+                w0 = c0; w1 = z[0]; w2 = z[1];
+                c0 = z[2]; c1 = z[3];
+            } else if (i == 2) {
+                w0 = c0; w1 = c1; w2 = z[0];
+                c0 = z[1]; c1 = z[2]; c2 = z[3];
+            } else {
+                w0 = c0; w1 = c1; w2 = c2;
+            }
+        } else if constexpr (P == 2) {
+            // lane half e = j & 1 of its quad holds particles 2e, 2e + 1 and draws blocks e and
+            // e + 1 (A and B): e = 0 takes (A0 A1 A2) (A3 B0 B1), e = 1 takes (A2 A3 B0)
+            // (B1 B2 B3); the pair that only one half needs is selected before its transform
+            if (p == 0) {
+                uint32_t a[4], b[4];
+                philox10_tail(ps, pb[0], key0, key1, a[0], a[1], a[2], a[3]);
+                philox10_tail(ps, pb[1], key0, key1, b[0], b[1], b[2], b[3]);
+                const bool e = (j & 1) != 0;
+                float a2, a3, b0, b1, x0, x1;
+                bm_pair(a[2], a[3], a2, a3);
+                bm_pair(b[0], b[1], b0, b1);
+                bm_pair(e ? b[2] : a[0], e ? b[3] : a[1], x0, x1);
+                w0 = e ? a2 : x0; w1 = e ? a3 : x1; w2 = e ? b0 : a2;
+                c0 = e ? b1 : a3; c1 = e ? x0 : b0; c2 = e ? x1 : b1;
+            } else {
+                w0 = c0; w1 = c1; w2 = c2;
+            }
+        } else {
+            // lane i of its lane quad holds particle i and drew block min(i, 2); lane 1 needs
+            // lane 0's fourth normal, lane 2 lane 1's third and fourth (quad_perm [0, 0, 1, 3])
+            float z[4];
+            block(0, z);
+            constexpr int kPerm = 0xD0;
+            const float pz2 = __int_as_float(
+                __builtin_amdgcn_mov_dpp(__float_as_int(z[2]), kPerm, 0xf, 0xf, true));
+            const float pz3 = __int_as_float(
+                __builtin_amdgcn_mov_dpp(__float_as_int(z[3]), kPerm, 0xf, 0xf, true));
+            const int i = j & 3;
+            w0 = i == 0 ? z[0] : (i == 1 ? pz3 : (i == 2 ? pz2 : z[1]));
+            w1 = i == 0 ? z[1] : (i == 1 ? z[0] : (i == 2 ? pz3 : z[2]));
+            w2 = i == 0 ? z[2] : (i == 1 ? z[1] : (i == 2 ? z[0] : z[3]));
+        }
+    }
+};
+
 // ------------------------------------------------------------------------------------------------
 // single-precision car model
 // ------------------------------------------------------------------------------------------------

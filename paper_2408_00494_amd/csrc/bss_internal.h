@@ -167,6 +167,23 @@ hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int n
                         bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,
                         hipStream_t stream);
+// the solve launch of one particles-per-lane count (each compiled in its own translation unit)
+hipError_t launch_solve_p1(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                           bool shield, bool split, bool resample, bool con, size_t lds,
+                           const double* x0_base, const double* Sigma0_base, int extra_shift,
+                           hipStream_t stream);
+hipError_t launch_solve_p2(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                           bool shield, bool split, bool resample, bool con, size_t lds,
+                           const double* x0_base, const double* Sigma0_base, int extra_shift,
+                           hipStream_t stream);
+hipError_t launch_solve_p4(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                           bool shield, bool split, bool resample, bool con, size_t lds,
+                           const double* x0_base, const double* Sigma0_base, int extra_shift,
+                           hipStream_t stream);
+hipError_t launch_solve_p8(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                           bool shield, bool split, bool resample, bool con, size_t lds,
+                           const double* x0_base, const double* Sigma0_base, int extra_shift,
+                           hipStream_t stream);
 hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
                         int extra_shift, hipStream_t stream);
 // Repair of the updated sequence of one instance after its merge: `rep` is the instance's repair
@@ -190,6 +207,11 @@ hipError_t launch_philox(uint32_t key0, uint32_t key1, const uint32_t* ctr, uint
                          int64_t n, hipStream_t stream);
 hipError_t launch_normals(uint32_t key0, uint32_t key1, const uint32_t* ctr, float* z, int64_t n,
                           hipStream_t stream);
+// disturbance words and normals of a solve through the solve kernel's path (lanes in {8, 16, 32,
+// 64}, ppl in {1, 2, 4, 8}, lanes * ppl >= M)
+hipError_t launch_disturbance(int lanes, int ppl, uint32_t key0, uint32_t key1, uint32_t s,
+                              int K, int M, int T, int crn, float* w, uint32_t* words,
+                              hipStream_t stream);
 hipError_t launch_model_step(const CarF32& car, const float* x, const float* u, float* xn,
                              int64_t n, hipStream_t stream);
 hipError_t launch_sdf(double a, double b, const double* pts, double* out, int64_t n,

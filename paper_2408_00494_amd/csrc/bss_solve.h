@@ -1,0 +1,673 @@
+// bss_solve.h -- the solve kernel of one BSS-MPPI solve (gfx950), compiled once per
+// particles-per-lane count (bss_solve_p{1,2,4,8}.hip) so that the variants build in parallel.
+//
+// L lanes per control sample k (256/L samples per 256-thread block), P particles per lane in
+// registers.  Draws eps_{k,t} (Philox tag 0) lane-parallel over t, optionally shield-repairs
+// u_{k,t} per step, propagates the M particles with the single-precision midpoint rule plus the
+// disturbance (tag 1), reduces the particle mean and position covariance across the L lanes in
+// double precision every step (the belief record of each step goes to a [K][T+1][9] buffer),
+// then scores the belief trajectory L records at a time (one per lane: signed distance, sigma_y,
+// barrier h, running cost, control cost, C_safe), and folds the block's samples into a
+// log-sum-exp partial (weights relative to the block's own minimum cost).  Scoring after the
+// particle loop keeps its double-precision temporaries out of the loop's register budget.
+#pragma once
+
+#include "bss_wave.h"
+
+namespace bss {
+
+namespace {
+
+// ----------------------------------------------------------------------------------------------
+// solve: rollout + scoring + block partial of the K-reduction
+// ----------------------------------------------------------------------------------------------
+// Up to four particles per lane the loop fits 128 registers, which keeps four waves per SIMD;
+// eight particles fit the budget of three, the shield's double-precision repair that of two.
+// One solve block with L lanes per sample (L is a compile-time constant so that the group
+// reductions are straight-line DPP sequences).
+// Disturbance normals of step t for the P particles of one lane, written to slot t & 1 of the
+// ring [2][P][3][256] (lane-contiguous, so the stores and the loads are conflict-free).
+template <int P>
+__device__ __forceinline__ void produce_noise(float* ring, int t, int q, int j,
+                                              const PhiloxParticle* pb, uint32_t c3w, uint32_t lk,
+                                              uint32_t key0, uint32_t key1)
+{
+    const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
+    float* dst = ring + (t & 1) * (P * 3 * 256) + q;
+    NoiseDealer<P> deal{ps, pb, key0, key1, j, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        float w0, w1, w2;
+        deal.next(p, w0, w1, w2);
+        dst[(p * 3 + 0) * 256] = w0;
+        dst[(p * 3 + 1) * 256] = w1;
+        dst[(p * 3 + 2) * 256] = w2;
+    }
+}
+
+// Gaussian re-sampling of Alg. 2 as printed: the particles of step t are redrawn as
+// xbar_t + L_t xi with xbar_t and the unbiased full 6x6 covariance of the current set of the
+// sample (FP64 group sums of the components shifted by particle 0: 6 sums and 21 products) and
+// L_t its semi-definite factor; xi are six standard normals from tags 4 and 5 with counter
+// (t, m, k).  Positions and heading stay compensated pairs relative to the estimate.
+//
+// Sigma points (mode 2, M = 12): the same moments with equal weights 1/12, plus the disturbance
+// covariance diag(0, 0, 0, sigma_w^2) scaled by qbar (the previous points' mean of
+// (1 + kappa |vx|)^2), and the deterministic points mean +- sqrt(6) L e_i instead of the draw.
+template <int P, int L>
+__device__ __forceinline__ void resample_particles(int t, int j, int k, int M, uint32_t s,
+                                                   uint32_t key0, uint32_t key1, int mode,
+                                                   double qbar, const float* sw, float* Xs,
+                                                   float* Xc, float* Ys, float* Yc, float* Ps,
+                                                   float* Pc, float* vx, float* vy, float* vr)
+{
+    double ref[6];
+    ref[0] = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
+    ref[1] = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
+    ref[2] = (double)group_first(Ps[0], L) - (double)group_first(Pc[0], L);
+    ref[3] = (double)group_first(vx[0], L);
+    ref[4] = (double)group_first(vy[0], L);
+    ref[5] = (double)group_first(vr[0], L);
+    double sd[6], sq[6][6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        sd[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) sq[a][b] = 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (particle_of<P, L>(j, p) < M) {
+            double dv[6];
+            dv[0] = ((double)Xs[p] - (double)Xc[p]) - ref[0];
+            dv[1] = ((double)Ys[p] - (double)Yc[p]) - ref[1];
+            dv[2] = ((double)Ps[p] - (double)Pc[p]) - ref[2];
+            dv[3] = (double)vx[p] - ref[3];
+            dv[4] = (double)vy[p] - ref[4];
+            dv[5] = (double)vr[p] - ref[5];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                sd[a] += dv[a];
+#pragma unroll
+                for (int b = 0; b <= a; ++b) sq[a][b] = fma(dv[a], dv[b], sq[a][b]);
+            }
+        }
+    }
+    const double invM = 1.0 / (double)M;
+    const double invM1 = mode == 2 ? invM : (M > 1 ? 1.0 / (double)(M - 1) : 0.0);
+    double mean[6], cov[6][6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sd[a] = group_sum(sd[a], L);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        mean[a] = ref[a] + sd[a] * invM;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const double c = (group_sum(sq[a][b], L) - sd[a] * (sd[b] * invM)) * invM1;
+            cov[a][b] = c;
+            cov[b][a] = c;
+        }
+    }
+    if (mode == 2) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cov[3 + a][3 + a] += (double)sw[a] * (double)sw[a] * qbar;
+    }
+    double Lf[6][6];
+    chol_psd6(cov, Lf);
+    // the draws' counters (t, m, k, tag 4 or 5) share their first two rounds as the disturbance's
+    // do: per step two parts common to the sample, per particle one
+    const uint64_t pk = (uint64_t)kPhiloxM1 * (uint32_t)k;
+    const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
+    PhiloxStep psr[2];
+    if (mode != 2) {
+        psr[0] = philox_step((uint32_t)t, rng_word3(kTagResample0, s), lk, key0, key1);
+        psr[1] = philox_step((uint32_t)t, rng_word3(kTagResample1, s), lk, key0, key1);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t m = (uint32_t)particle_of<P, L>(j, p);
+        double xi[6];
+        if (mode == 2) {
+            // selects instead of a runtime index keep xi in registers
+            const double r = m < 6u ? 2.449489742783178 : -2.449489742783178;
+            const uint32_t e = m % 6u;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) xi[a] = (m < 12u && e == (uint32_t)a) ? r : 0.0;
+        } else {
+            const PhiloxParticle pm = philox_particle(m, hk, key0, key1);
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                uint32_t c0, c1, c2, c3;
+                philox10_tail(psr[blk], pm, key0, key1, c0, c1, c2, c3);
+                float z0, z1;
+                bm_pair(c0, c1, z0, z1);
+                xi[3 * blk + 0] = z0;
+                xi[3 * blk + 1] = z1;
+                xi[3 * blk + 2] = bm_cos(c2, c3);
+            }
+        }
+        double dev[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double acc = mean[a];
+#pragma unroll
+            for (int b = 0; b <= a; ++b) acc = fma(Lf[a][b], xi[b], acc);
+            dev[a] = acc;
+        }
+        Xs[p] = (float)dev[0];
+        Xc[p] = (float)((double)Xs[p] - dev[0]);
+        Ys[p] = (float)dev[1];
+        Yc[p] = (float)((double)Ys[p] - dev[1]);
+        Ps[p] = (float)dev[2];
+        Pc[p] = (float)((double)Ps[p] - dev[2]);
+        vx[p] = (float)dev[3];
+        vy[p] = (float)dev[4];
+        vr[p] = (float)dev[5];
+    }
+}
+
+// One solve block with L lanes per sample (L is a compile-time constant so that the group
+// reductions are straight-line DPP sequences).
+//
+// SPLIT (512 threads): threads 256..511 generate the disturbance normals of step t + 1 while
+// threads 0..255 integrate step t, through a two-slot LDS ring and one barrier per step.  This
+// puts two waves on every SIMD when a launch has too few samples to fill the chip otherwise (a
+// lone wave issues at about half the SIMD's rate); the arithmetic and its order are unchanged, so
+// the results are bitwise the same as without the split.
+template <int P, bool SHIELD, int L, bool SPLIT, bool RESAMPLE, bool CON>
+__device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDesc bd,
+                                            const double* __restrict__ x0_base,
+                                            const double* __restrict__ Sigma0_base,
+                                            int extra_shift)
+{
+    static_assert(!(SPLIT && SHIELD), "the shielded loop is not split");
+    static_assert(!(SPLIT && RESAMPLE), "the re-sampling loop is not split");
+    static_assert(!CON || (SHIELD && RESAMPLE && !SPLIT) || (!SHIELD && !RESAMPLE),
+                  "half-space constraints: the plain, split and generic variants only");
+    constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
+    constexpr int groups = 256 >> log2L;
+    const int T = d.T, M = d.M;
+    const int vshift = d.vshift + extra_shift;
+    const double* __restrict__ v = d.v[d.cur];
+    extern __shared__ double smem[];
+    double* S_sh = smem;                                     // [groups]
+    double* w_sh = S_sh + groups;                            // [groups]
+    float2* u_sh = reinterpret_cast<float2*>(w_sh + groups);  // [groups][T]
+    float* ring = reinterpret_cast<float*>(u_sh + groups * T);  // SPLIT: [2][P][3][256]
+    const int q = SPLIT ? (int)(threadIdx.x & 255u) : (int)threadIdx.x;
+    const bool producer = SPLIT && threadIdx.x >= 256u;
+    const int g = q >> log2L;
+    const int j = q & (L - 1);
+    const int k = bd.k0 + g;
+    const bool active = k < d.K;
+    float2* us = u_sh + g * T;
+    double* mom_k = d.mom + (size_t)(active ? k : 0) * (T + 1) * 9;
+    const uint32_t s = d.solve_index;
+    const uint32_t key0 = d.key0, key1 = d.key1;
+    const double* x0p = x0_base + 6 * d.x0_index;
+    const double* S0p = Sigma0_base ? Sigma0_base + 36 * d.x0_index : nullptr;
+    // half-space constraints on the whole state (compiled into the CON variants only): their
+    // variances a_i^T Sigma a_i per record
+    const int ncon = CON ? d.sc.n_con : 0;
+    double* cvar_k = ncon > 0 ? d.cvar + (size_t)(active ? k : 0) * (T + 1) * ncon : nullptr;
+
+    // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
+    if (active && (!SPLIT || producer)) {
+        const float sig0 = d.sig_eps0, sig1 = d.sig_eps1;
+        const float smax = d.steer_max, amax = d.accel_max;
+        for (int t = j; t < T; t += L) {
+            uint32_t c0 = (uint32_t)t, c1 = 0u, c2 = (uint32_t)k, c3 = rng_word3(kTagEps, s);
+            philox10(c0, c1, c2, c3, key0, key1);
+            float z0, z1;
+            bm_pair(c0, c1, z0, z1);
+            const int r = vrow(t, vshift, T);
+            const float v0 = (float)v[2 * r], v1 = (float)v[2 * r + 1];
+            const float u0 = fminf(fmaxf(fmaf(sig0, z0, v0), -smax), smax);
+            const float u1 = fminf(fmaxf(fmaf(sig1, z1, v1), -amax), amax);
+            us[t] = make_float2(u0, u1);
+            if (!SHIELD && d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = us[t];
+        }
+    }
+    // disturbance stream of this lane's particles: the first two Philox rounds are partly shared;
+    // with common random numbers every sample draws the stream of sample word 0
+    const uint32_t c3w = rng_word3(kTagW, s);
+    const uint64_t pk = (uint64_t)kPhiloxM1 * (d.crn ? 0u : (uint32_t)k);
+    const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
+    constexpr int NB = noise_blocks<P>();
+    if (SPLIT && producer && active) {
+        PhiloxParticle pb0[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            pb0[i] = philox_particle(noise_block_word<P, L>(j, i), hk, key0, key1);
+        produce_noise<P>(ring, 0, q, j, pb0, c3w, lk, key0, key1);
+    }
+    __syncthreads();
+
+    if (SPLIT || active) {
+        const bool consumer = !producer && active;
+        double x0[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x0[i] = x0p[i];
+        const bool spread = S0p != nullptr;
+
+        // state relative to the estimate: position and heading as compensated (sum, correction)
+        float Xs[P], Xc[P], Ys[P], Yc[P], Ps[P], Pc[P], vx[P], vy[P], vr[P];
+        if (consumer) {
+            double L0[36];
+            if (spread) chol6(S0p, L0);
+            // sigma points at t = 0: mean +- sqrt(6) L e_i of the given estimate
+            const bool sigma = RESAMPLE && d.belief == 2;
+            double Lp[6][6];
+            if (sigma) {
+                double A[6][6];
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) A[a][b] = spread ? S0p[a * 6 + b] : 0.0;
+                chol_psd6(A, Lp);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int m = particle_of<P, L>(j, p);
+                double dev[6] = {0, 0, 0, 0, 0, 0};
+                if (sigma) {
+                    const double r = m < 6 ? 2.449489742783178 : -2.449489742783178;
+                    const int e = m % 6;
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) acc = (m < 12 && e == b) ? r * Lp[a][b] : acc;
+                        dev[a] = acc;
+                    }
+                } else if (spread) {
+                    double xi[6];
+#pragma unroll
+                    for (int blk = 0; blk < 2; ++blk) {
+                        uint32_t c0 = (uint32_t)blk, c1 = (uint32_t)m, c2 = (uint32_t)k,
+                                 c3 = rng_word3(kTagInit, s);
+                        philox10(c0, c1, c2, c3, key0, key1);
+                        float z0, z1;
+                        bm_pair(c0, c1, z0, z1);
+                        xi[blk * 3 + 0] = z0;
+                        xi[blk * 3 + 1] = z1;
+                        xi[blk * 3 + 2] = bm_cos(c2, c3);
+                    }
+                    for (int i = 0; i < 6; ++i) {
+                        double acc = 0.0;
+                        for (int q = 0; q <= i; ++q) acc += L0[i * 6 + q] * xi[q];
+                        dev[i] = acc;
+                    }
+                }
+                Xs[p] = (float)dev[0];
+                Xc[p] = (float)((double)Xs[p] - dev[0]);
+                Ys[p] = (float)dev[1];
+                Yc[p] = (float)((double)Ys[p] - dev[1]);
+                Ps[p] = (float)dev[2];
+                Pc[p] = (float)((double)Ps[p] - dev[2]);
+                vx[p] = (float)(x0[3] + dev[3]);
+                vy[p] = (float)(x0[4] + dev[4]);
+                vr[p] = (float)(x0[5] + dev[5]);
+            }
+        }
+        const double rev0d = x0[2] * 0.15915494309189535;
+        const float rev0 = (float)(rev0d - rint(rev0d));
+        const CarF32 car = d.car;
+        const float sw0 = d.sig_w0, sw1 = d.sig_w1, sw2 = d.sig_w2;
+        const float ksp = d.sig_w_speed;
+
+        // belief at t = 0 is the given estimate (record 0)
+        double bel[9];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) bel[i] = x0[i];
+        bel[6] = spread ? S0p[0] : 0.0;
+        bel[7] = spread ? S0p[1] : 0.0;
+        bel[8] = spread ? S0p[7] : 0.0;
+        // a_i^T Sigma a_i of each half-space constraint (eq. 11 with eta_i = a_i); at t = 0 from
+        // the given covariance
+        double bcv[kMaxCon];
+#pragma unroll
+        for (int c = 0; c < kMaxCon; ++c) {
+            double q = 0.0;
+            if (c < ncon && spread) {
+                const double* a = d.sc.con_a + 6 * c;
+                for (int r = 0; r < 6; ++r) {
+                    double row = 0.0;
+                    for (int e = 0; e < 6; ++e) row = fma(S0p[r * 6 + e], a[e], row);
+                    q = fma(a[r], row, q);
+                }
+            }
+            bcv[c] = q;
+        }
+        if (consumer && j == 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) mom_k[i] = bel[i];
+#pragma unroll
+            for (int c = 0; c < kMaxCon; ++c)
+                if (c < ncon) cvar_k[c] = bcv[c];
+        }
+        PhiloxParticle pb[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            pb[i] = philox_particle(noise_block_word<P, L>(j, i), hk, key0, key1);
+        const double invM = 1.0 / (double)M;
+        const double invM1 =
+            (RESAMPLE && d.belief == 2) ? invM : (M > 1 ? 1.0 / (double)(M - 1) : 0.0);
+        const float swv[3] = {sw0, sw1, sw2};
+        double qbar = 1.0;      // sigma points: previous points' mean of (1 + kappa |vx|)^2
+
+        // In split mode every thread runs every iteration and meets exactly one barrier per step,
+        // outside all divergent branches (waves may hold both active and inactive samples).
+        for (int t = 0; t < T; ++t) {
+            if (SPLIT && producer) {
+                if (active && t + 1 < T)
+                    produce_noise<P>(ring, t + 1, q, j, pb, c3w, lk, key0, key1);
+            } else if (!SPLIT || consumer) {
+                float2 uu = us[t];
+                if (SHIELD) {
+                    const ScoreF64& sc = d.sc;
+                    if (sc.shield_iters > 0) {
+                        double scon[kMaxCon];
+                        if (ncon > 0) con_sigmas(sc, bcv, scon);
+                        const double* sc_con = ncon > 0 ? scon : nullptr;
+                        const BeliefEval be = eval_belief(sc, bel, sc_con);
+                        const double fd = sc.shield_fd;
+                        const int role = j < 5 ? j : 0;
+                        const double o0 = role == 1 ? fd : (role == 2 ? -fd : 0.0);
+                        const double o1 = role == 3 ? fd : (role == 4 ? -fd : 0.0);
+                        double us0 = uu.x, us1 = uu.y;
+                        for (int it = 0; it < sc.shield_iters; ++it) {
+                            // lanes 0-4 of the group evaluate r at u and at the four
+                            // difference points
+                            const double rv = repair_residual(sc, bel, be, be.h, us0 + o0,
+                                                              us1 + o1, sc_con);
+                            const double r0 = __shfl(rv, 0, L);
+                            const double rp0 = __shfl(rv, 1, L), rm0 = __shfl(rv, 2, L);
+                            const double rp1 = __shfl(rv, 3, L), rm1 = __shfl(rv, 4, L);
+                            if (!(r0 > 0.0)) break;
+                            const double g0 = (rp0 - rm0) / (2.0 * fd);
+                            const double g1 = (rp1 - rm1) / (2.0 * fd);
+                            const double den = g0 * g0 + g1 * g1 + sc.shield_gmin * sc.shield_gmin;
+                            us0 = clampd(us0 - r0 * g0 / den, -sc.steer_max, sc.steer_max);
+                            us1 = clampd(us1 - r0 * g1 / den, -sc.accel_max, sc.accel_max);
+                        }
+                        uu = make_float2((float)us0, (float)us1);
+                    }
+                    if (j == 0) {
+                        us[t] = uu;
+                        if (d.u) reinterpret_cast<float2*>(d.u)[(size_t)k * T + t] = uu;
+                    }
+                }
+                if (RESAMPLE && d.belief != 0 && t > 0)
+                    resample_particles<P, L>(t, j, k, M, s, key0, key1, d.belief, qbar, swv, Xs,
+                                             Xc, Ys, Yc, Ps, Pc, vx, vy, vr);
+                if (RESAMPLE && d.belief == 2) {
+                    double qs = 0.0;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if (particle_of<P, L>(j, p) < M) {
+                            const double f = 1.0 + (double)ksp * fabs((double)vx[p]);
+                            qs = fma(f, f, qs);
+                        }
+                    }
+                    qbar = group_sum(qs, L) * invM;
+                }
+                const StepF32 st = make_step(car, uu.x, uu.y);
+                PhiloxStep ps{};
+                if (!SPLIT) ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
+                NoiseDealer<P> deal{ps, pb, key0, key1, j, 0.0f, 0.0f, 0.0f};
+                // FP64 moment sums of the lane's particles; positions shifted by particle 0 of
+                // the sample (lane 0 of the group), taken after its update in the first chunk
+                double sX = 0, sY = 0, sP = 0, svx = 0, svy = 0, svr = 0, sXX = 0, sXY = 0,
+                       sYY = 0;
+                double refX = 0.0, refY = 0.0;
+                // sums of squares of the constraint projections y = a_i^T (x - xref), xref the
+                // estimate with particle 0's position (the sums of y follow from the moment sums)
+                double c2[kMaxCon];
+#pragma unroll
+                for (int c = 0; c < kMaxCon; ++c) c2[c] = 0.0;
+                // With up to four particles per lane the step runs in stages over all of them
+                // (disturbance normals, first field evaluation, midpoint, second evaluation,
+                // update), each stage one straight-line block with no per-particle branch, so
+                // that the compiler interleaves the particles' independent dependency chains.
+                // With eight, the staged form does not fit the registers of three waves per
+                // SIMD; those particles are stepped one after the other (several waves per SIMD
+                // hide the latency instead), except in the repair's variant, whose two waves per
+                // SIMD leave room for stages over four particles at a time.
+                constexpr int Q = P <= 4 ? P : (SHIELD && !RESAMPLE && !CON ? 4 : 1);
+#pragma unroll
+                for (int p0 = 0; p0 < P; p0 += Q) {
+                    float w0[Q], w1[Q], w2[Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        const int p = p0 + i;
+                        if (RESAMPLE && d.belief == 2) {
+                            w0[i] = w1[i] = w2[i] = 0.0f;   // sigma points: Q enters instead
+                        } else if (SPLIT) {
+                            const float* src = ring + (t & 1) * (P * 3 * 256) + q;
+                            w0[i] = src[(p * 3 + 0) * 256];
+                            w1[i] = src[(p * 3 + 1) * 256];
+                            w2[i] = src[(p * 3 + 2) * 256];
+                        } else {
+                            deal.next(p, w0[i], w1[i], w2[i]);
+                        }
+                    }
+                    if (ksp != 0.0f) {
+                        // state-dependent disturbance: std sigma_w (1 + kappa |vx|) at the
+                        // step's starting state
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) {
+                            const float fw = fmaf(ksp, fabsf(vx[p0 + i]), 1.0f);
+                            w0[i] *= fw;
+                            w1[i] *= fw;
+                            w2[i] *= fw;
+                        }
+                    }
+                    float rev[Q], dX[Q], dY[Q], dvx[Q], dvy[Q], dr[Q];
+                    float vxm[Q], vym[Q], vrm[Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) rev[i] = fmaf(Ps[p0 + i], kInv2Pi, rev0);
+                    car_field_f32_n<Q>(car, st, rev, vx + p0, vy + p0, vr + p0, dX, dY, dvx, dvy,
+                                       dr);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        const int p = p0 + i;
+                        rev[i] = fmaf(fmaf(car.half_dt, vr[p], Ps[p]), kInv2Pi, rev0);
+                        vxm[i] = fmaf(car.half_dt, dvx[i], vx[p]);
+                        vym[i] = fmaf(car.half_dt, dvy[i], vy[p]);
+                        vrm[i] = fmaf(car.half_dt, dr[i], vr[p]);
+                    }
+                    car_field_f32_n<Q>(car, st, rev, vxm, vym, vrm, dX, dY, dvx, dvy, dr);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        const int p = p0 + i;
+                        kahan_add(Xs[p], Xc[p], car.dt * dX[i]);
+                        kahan_add(Ys[p], Yc[p], car.dt * dY[i]);
+                        kahan_add(Ps[p], Pc[p], car.dt * vrm[i]);
+                        vx[p] = fmaf(sw0, w0[i], fmaf(car.dt, dvx[i], vx[p]));
+                        vy[p] = fmaf(sw1, w1[i], fmaf(car.dt, dvy[i], vy[p]));
+                        vr[p] = fmaf(sw2, w2[i], fmaf(car.dt, dr[i], vr[p]));
+                    }
+                    if (p0 == 0) {
+                        refX = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
+                        refY = (double)group_first(Ys[0], L) - (double)group_first(Yc[0], L);
+                    }
+                    // accumulate the chunk (particles beyond M contribute nothing)
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        const int p = p0 + i;
+                        if (particle_of<P, L>(j, p) < M) {
+                            const double X = ((double)Xs[p] - (double)Xc[p]) - refX;
+                            const double Y = ((double)Ys[p] - (double)Yc[p]) - refY;
+                            sX += X;
+                            sY += Y;
+                            sP += (double)Ps[p] - (double)Pc[p];
+                            svx += (double)vx[p];
+                            svy += (double)vy[p];
+                            svr += (double)vr[p];
+                            sXX = fma(X, X, sXX);
+                            sXY = fma(X, Y, sXY);
+                            sYY = fma(Y, Y, sYY);
+#pragma unroll
+                            for (int c = 0; c < kMaxCon; ++c) {
+                                if (c < ncon) {
+                                    const double* a = d.sc.con_a + 6 * c;
+                                    const double y = fma(
+                                        a[0], X,
+                                        fma(a[1], Y,
+                                            fma(a[2], (double)Ps[p] - (double)Pc[p],
+                                                fma(a[3], (double)vx[p] - x0[3],
+                                                    fma(a[4], (double)vy[p] - x0[4],
+                                                        a[5] * ((double)vr[p] - x0[5]))))));
+                                    c2[c] = fma(y, y, c2[c]);
+                                }
+                            }
+                        }
+                    }
+                }
+                // moments: FP64 sums over the L lanes (DPP inside a row, swaps across rows)
+                sX = group_sum(sX, L);
+                sY = group_sum(sY, L);
+                sP = group_sum(sP, L);
+                svx = group_sum(svx, L);
+                svy = group_sum(svy, L);
+                svr = group_sum(svr, L);
+                sXX = group_sum(sXX, L);
+                sXY = group_sum(sXY, L);
+                sYY = group_sum(sYY, L);
+                const double mX = sX * invM, mY = sY * invM;
+                bel[0] = x0[0] + (refX + mX);
+                bel[1] = x0[1] + (refY + mY);
+                bel[2] = x0[2] + sP * invM;
+                bel[3] = svx * invM;
+                bel[4] = svy * invM;
+                bel[5] = svr * invM;
+                bel[6] = (sXX - sX * mX) * invM1;
+                bel[7] = (sXY - sX * mY) * invM1;
+                bel[8] = (sYY - sY * mY) * invM1;
+#pragma unroll
+                for (int c = 0; c < kMaxCon; ++c) {
+                    if (c < ncon) {
+                        // sum of the projections from the moment sums, then the unbiased variance
+                        const double* a = d.sc.con_a + 6 * c;
+                        const double s1 =
+                            fma(a[0], sX,
+                                fma(a[1], sY,
+                                    fma(a[2], sP,
+                                        fma(a[3], fma(-(double)M, x0[3], svx),
+                                            fma(a[4], fma(-(double)M, x0[4], svy),
+                                                a[5] * fma(-(double)M, x0[5], svr))))));
+                        const double s2 = group_sum(c2[c], L);
+                        double var = (s2 - s1 * (s1 * invM)) * invM1;
+                        if (d.belief == 2) {
+                            // sigma points: plus a_i^T Q a_i of the disturbance covariance,
+                            // scaled like Q by the points' mean of (1 + kappa |vx|)^2
+                            const double q0 = a[3] * (double)sw0, q1 = a[4] * (double)sw1,
+                                         q2 = a[5] * (double)sw2;
+                            var = fma(qbar, fma(q0, q0, fma(q1, q1, q2 * q2)), var);
+                        }
+                        bcv[c] = var;
+                    }
+                }
+
+                // record t+1, written by lane (t+1) % L of the group (spreads the stores)
+                if (j == ((t + 1) & (L - 1))) {
+                    double* rec = mom_k + (size_t)(t + 1) * 9;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+#pragma unroll
+                    for (int c = 0; c < kMaxCon; ++c)
+                        if (c < ncon) cvar_k[(size_t)(t + 1) * ncon + c] = bcv[c];
+                }
+            }
+            if (SPLIT) __syncthreads();
+        }
+    }
+    // ---- phase 3: score the belief trajectory, L records at a time (one per lane) ----
+    __threadfence_block();
+    __syncthreads();
+    double S_part = 0.0;
+    if (active && !producer) {
+        double h_carry = 0.0;
+        for (int base = 0; base <= T; base += L) {
+            const int count = min(L, T + 1 - base);
+            const int rec = base + min(j, count - 1);
+            S_part += score_chunk(d.sc, mom_k + (size_t)rec * 9, base + j, count, j, L, T, us, v,
+                                  vshift, h_carry,
+                                  ncon > 0 ? cvar_k + (size_t)rec * ncon : nullptr);
+        }
+    }
+    const double S_k = group_sum(S_part, L);
+    if (j == 0 && !producer) {
+        S_sh[g] = active ? S_k : INFINITY;
+        if (active) d.S[k] = S_k;
+    }
+    __syncthreads();
+    const int n = min(groups, d.K - bd.k0);
+    block_partial(T, n, S_sh, w_sh, u_sh, v, vshift, d.sc.lambda,
+                  d.partial + (size_t)(bd.k0 >> (8 - log2L)) * (2 * T + 4));
+}
+
+// Solve grid: every block looks up its instance and first sample; the lane count is uniform over
+// a block, so the dispatch below is a block-uniform branch.
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false>
+__global__ __launch_bounds__(SPLIT ? 512 : 256)
+__attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE || CON) ? 2
+                                   : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
+    const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
+    const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
+{
+    const BlockDesc bd = blocks[blockIdx.x];
+    const InstanceDesc& d = insts[bd.inst];
+    switch (d.lanes) {
+    case 8:
+        solve_block<P, SHIELD, 8, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    case 16:
+        solve_block<P, SHIELD, 16, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    case 32:
+        solve_block<P, SHIELD, 32, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    default:
+        solve_block<P, SHIELD, 64, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
+        break;
+    }
+}
+template <int P>
+hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                          bool shield, bool split, bool resample, bool con, size_t lds,
+                          const double* x0_base, const double* Sigma0_base, int extra_shift,
+                          hipStream_t stream)
+{
+    const dim3 g(nblocks), b256(256), b512(512);
+    if (con && (shield || resample))
+        hipLaunchKernelGGL((solve_kernel<P, true, false, true, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (con && split)
+        hipLaunchKernelGGL((solve_kernel<P, false, true, false, true>), g, b512, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (con)
+        hipLaunchKernelGGL((solve_kernel<P, false, false, false, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (shield && resample)
+        hipLaunchKernelGGL((solve_kernel<P, true, false, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (shield)
+        hipLaunchKernelGGL((solve_kernel<P, true, false, false>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (resample)
+        hipLaunchKernelGGL((solve_kernel<P, false, false, true>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else if (split)
+        hipLaunchKernelGGL((solve_kernel<P, false, true, false>), g, b512, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    else
+        hipLaunchKernelGGL((solve_kernel<P, false, false, false>), g, b256, lds, stream, inst,
+                           blocks, x0_base, Sigma0_base, extra_shift);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+}  // namespace bss

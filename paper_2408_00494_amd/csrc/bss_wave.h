@@ -1,0 +1,254 @@
+// bss_wave.h -- wave-level building blocks shared by the solve and merge kernels (gfx950):
+// compensated sums, 6x6 factorisations, DPP / swap cross-lane reductions over a lane group, the
+// belief scoring of a chunk of records and the block-level log-sum-exp partial.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bss_device.h"
+#include "bss_internal.h"
+
+namespace bss {
+
+namespace {
+
+constexpr float kInv2Pi = 0.15915494309189535f;
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float d)
+{
+    const float y = d - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Cholesky factor of the state-estimate covariance, per lane (6x6, semi-definite tolerated).
+// Semi-definite factor for the Gaussian re-sampling draw: as chol6, but a pivot
+// d <= 1e-10 A_jj + 1e-24 counts as zero (variances at the rounding level of an exactly degenerate
+// particle set are not amplified).  Fully unrolled so that A and L stay in registers.
+__device__ __forceinline__ void chol_psd6(const double (&A)[6][6], double (&L)[6][6])
+{
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) L[i][j] = 0.0;
+        double d = A[j][j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
+        if (d > 1e-10 * A[j][j] + 1e-24) {
+            const double ljj = sqrt(d);
+            L[j][j] = ljj;
+#pragma unroll
+            for (int i = j + 1; i < 6; ++i) {
+                double acc = A[i][j];
+#pragma unroll
+                for (int q = 0; q < j; ++q) acc -= L[i][q] * L[j][q];
+                L[i][j] = acc / ljj;
+            }
+        }
+    }
+}
+
+__device__ inline void chol6(const double* A, double* L)
+{
+    for (int i = 0; i < 36; ++i) L[i] = 0.0;
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j * 6 + j];
+        for (int q = 0; q < j; ++q) d -= L[j * 6 + q] * L[j * 6 + q];
+        if (d <= 0.0) continue;
+        const double ljj = sqrt(d);
+        L[j * 6 + j] = ljj;
+        for (int i = j + 1; i < 6; ++i) {
+            double acc = A[i * 6 + j];
+            for (int q = 0; q < j; ++q) acc -= L[i * 6 + q] * L[j * 6 + q];
+            L[i * 6 + j] = acc / ljj;
+        }
+    }
+}
+
+// Cross-lane moves inside a row of 16 lanes (DPP): no LDS traffic, one VALU move per dword.  Every
+// control used here reads a valid lane of the same row, so no "old" value is needed (bound_ctrl
+// set): the destination register is not initialised first.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppHalfRowMirror = 0x141; // lane i <- lane 7-i within each 8
+constexpr int kDppRowMirror = 0x140;     // lane i <- lane 15-i within each 16
+constexpr int kDppRowBcast0 = 0x150;     // every lane of a row <- lane 0 of the row
+constexpr int kDppRowBcast8 = 0x158;     // every lane of a row <- lane 8 of the row
+constexpr int kDppQuadBcast0 = 0x00;     // quad_perm [0,0,0,0]
+constexpr int kDppQuadBcast0And2 = 0xA0; // quad_perm [0,0,2,2]
+
+// Cross-row exchanges with the gfx950 swap instructions (plain VALU ops, no LDS round trip).
+// With both operands equal to x, v_permlane16_swap leaves in its first result, in every lane of
+// a row pair (0,1) or (2,3), the even row's value of x and in its second result the odd row's;
+// v_permlane32_swap does the same for the lower and upper halves of the wave.
+__device__ __forceinline__ void pair_rows16(float x, float& even, float& odd)
+{
+    const uint32_t u = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    even = __uint_as_float(r[0]);
+    odd = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void pair_halves32(float x, float& lower, float& upper)
+{
+    const uint32_t u = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    lower = __uint_as_float(r[0]);
+    upper = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ double xor16_sum(double x)
+{
+    const uint32_t lo = (uint32_t)__double2loint(x), hi = (uint32_t)__double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+__device__ __forceinline__ double xor32_sum(double x)
+{
+    const uint32_t lo = (uint32_t)__double2loint(x), hi = (uint32_t)__double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+// Sum over the L lanes of a group (L = 1, 2, 4, ..., 64, groups aligned in the wave, L uniform
+// over the block), result in every lane of the group and bitwise identical across them (each
+// stage adds the same two partial sums in either order).  Within a row of 16 the partners come
+// from DPP; across rows from the swap instructions.
+__device__ __forceinline__ double group_sum(double x, int L)
+{
+    if (L > 1) x += dpp_f64<kDppQuadSwap1>(x);
+    if (L > 2) x += dpp_f64<kDppQuadSwap2>(x);
+    if (L > 4) x += dpp_f64<kDppHalfRowMirror>(x);
+    if (L > 8) x += dpp_f64<kDppRowMirror>(x);
+    if (L > 16) x = xor16_sum(x);
+    if (L > 32) x = xor32_sum(x);
+    return x;
+}
+
+// Value of lane 0 of the group in every lane of the group.
+__device__ __forceinline__ float group_first(float x, int L)
+{
+    if (L == 1) return x;
+    if (L == 2) return dpp_f32<kDppQuadBcast0And2>(x);
+    if (L == 4) return dpp_f32<kDppQuadBcast0>(x);
+    if (L == 8) {
+        const float a = dpp_f32<kDppRowBcast0>(x), b = dpp_f32<kDppRowBcast8>(x);
+        return (threadIdx.x & 8) ? b : a;
+    }
+    float y = dpp_f32<kDppRowBcast0>(x);
+    if (L == 16) return y;
+    float even, odd;
+    pair_rows16(y, even, odd);
+    if (L == 32) return even;
+    float lower, upper;
+    pair_halves32(even, lower, upper);
+    return lower;
+}
+
+__device__ __forceinline__ int vrow(int t, int vshift, int T)
+{
+    const int r = t + vshift;
+    return r < T ? r : T - 1;
+}
+
+// Score one chunk of belief records, one record per lane of a W-lane group: running cost (times
+// phi_scale on the terminal record), control cost on records < T, and C_safe on the transition
+// into the record (record 0 has none).  `h_carry` holds h of the record before the chunk and is
+// advanced to the chunk's last record.  Returns this lane's contribution.
+// crec: the record's half-space constraint variances, or nullptr where the launch carries none.
+__device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int rec_idx, int count,
+                                     int lane, int W, int T, const float2* u_row, const double* v,
+                                     int vshift, double& h_carry, const double* crec = nullptr)
+{
+    const bool valid = lane < count;
+    double part = 0.0;
+    double h = 0.0;
+    if (valid) {
+        double scon[kMaxCon];
+        if (crec) con_sigmas(sc, crec, scon);
+        const BeliefEval be = eval_belief(sc, rec, crec ? scon : nullptr);
+        double q = stage_cost(sc, rec, be);
+        if (rec_idx == T) {
+            q *= sc.phi_scale;
+        } else {
+            const float2 ut = u_row[rec_idx];
+            const int r = vrow(rec_idx, vshift, T);
+            q += sc.gamma_u * (v[2 * r] * sc.inv_var0 * (double)ut.x +
+                               v[2 * r + 1] * sc.inv_var1 * (double)ut.y);
+        }
+        h = be.h;
+        part = q;
+    }
+    const double h_left = __shfl(h, lane > 0 ? lane - 1 : 0, W);
+    const double h_prev = lane == 0 ? h_carry : h_left;
+    if (valid && rec_idx >= 1) part += sc.C_cbf * fmax(-h + (1.0 - sc.gamma) * h_prev, 0.0);
+    h_carry = __shfl(h, count - 1, W);
+    return part;
+}
+
+// Fold n samples (costs S_sh[0..n), controls u_sh[g][T]) into one log-sum-exp partial.
+// Must be called by all 256 threads of the block after the inputs are visible in LDS.
+__device__ inline void block_partial(int T, int n, const double* S_sh, double* w_sh,
+                                     const float2* u_sh, const double* v, int vshift,
+                                     double lambda, double* out)
+{
+    const int tid = threadIdx.x;
+    double mb = INFINITY;
+    for (int g = 0; g < n; ++g) {
+        const double s = S_sh[g];
+        if (isfinite(s)) mb = fmin(mb, s);
+    }
+    if (tid < n) {
+        const double s = S_sh[tid];
+        w_sh[tid] = (isfinite(s) && isfinite(mb)) ? exp(-(s - mb) / lambda) : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * T; i += (int)blockDim.x) {
+        const int t = i >> 1;
+        const int r = vrow(t, vshift, T);
+        const double vi = v[2 * r + (i & 1)];
+        double acc = 0.0;
+        for (int g = 0; g < n; ++g) {
+            const float2 ut = u_sh[g * T + t];
+            const double ui = (i & 1) ? (double)ut.y : (double)ut.x;
+            acc += w_sh[g] * (ui - vi);
+        }
+        out[i] = acc;
+    }
+    if (tid == 0) {
+        double Z = 0.0, W2 = 0.0, nf = 0.0;
+        for (int g = 0; g < n; ++g) {
+            Z += w_sh[g];
+            W2 += w_sh[g] * w_sh[g];
+            nf += isfinite(S_sh[g]) ? 1.0 : 0.0;
+        }
+        out[2 * T] = Z;
+        out[2 * T + 1] = W2;
+        out[2 * T + 2] = nf;
+        out[2 * T + 3] = mb;
+    }
+}
+
+}  // namespace
+
+}  // namespace bss

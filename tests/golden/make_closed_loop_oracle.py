@@ -4,7 +4,7 @@ combination, with the plant and episode rules of tests/closed_loop.py, and the p
 (e_y, crash flag, barrier flag, vx) they come from.  Calls only the oracle and the input
 generators.
 
-    python tests/golden/make_closed_loop_oracle.py [steps] [nthreads]
+    python tests/golden/make_closed_loop_oracle.py [steps] [nthreads] [output path]
 """
 import json
 import os
@@ -21,7 +21,7 @@ import closed_loop as CL  # noqa: E402
 def main():
     steps = int(sys.argv[1]) if len(sys.argv) > 1 else 250
     nthreads = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
-    out_path = os.path.join(HERE, "closed_loop_oracle.json")
+    out_path = sys.argv[3] if len(sys.argv) > 3 else os.path.join(HERE, "closed_loop_oracle.json")
     res = {"steps_per_combo": steps, "controller": "oracle", "combos": []}
     for i, (d, g) in enumerate(CL.COMBOS):
         prob = CL.combo_problem(i)

@@ -78,6 +78,40 @@ def test_philox_bit_exact_on_solve_counters():
         assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("K,M,T,lanes,ppl,crn", [
+    (5, 13, 4, 16, 1, False),    # one particle per lane: lane quads share a particle quad
+    (3, 30, 3, 16, 2, False),    # two per lane, ragged last quad
+    (4, 64, 3, 16, 4, False),    # the paper-scale shape
+    (3, 37, 2, 16, 4, False),    # ragged M with whole quads per lane
+    (3, 128, 2, 16, 8, False),   # the shielded shape (two quads per lane)
+    (2, 300, 2, 64, 8, False),   # 64 lanes, ragged
+    (3, 16, 3, 8, 2, True),      # common random numbers (sample word 0 for every sample)
+    (2, 20, 2, 32, 1, False),
+])
+def test_solve_noise_path_matches_oracle(K, M, T, lanes, ppl, crn):
+    """The solve kernel's disturbance path (shared first rounds, per-block tails, quad dealing,
+    lane placement) against the oracle: every Philox word bit-exact, every dealt normal within
+    the single-precision Box-Muller bound."""
+    seed, s = 0x1234ABCD9876, 19
+    w, words = bss.dev_disturbance(seed, s, K, M, T, lanes, ppl, crn)
+    w = w.cpu().numpy().astype(np.float64)
+    words = words.cpu().numpy().view(np.uint32)
+    nblk = 3 * ((M + 3) // 4)
+    t, b, k = np.meshgrid(np.arange(T), np.arange(nblk), np.arange(K), indexing="ij")
+    kw = np.zeros_like(k) if crn else k
+    ctr = np.stack([t.ravel(), b.ravel(), kw.ravel(),
+                    np.full(t.size, (1 << 28) | s)], axis=1).astype(np.uint32)
+    want = oracle.philox_many(ctr, seed).reshape(T, nblk, K, 4).transpose(2, 0, 1, 3)
+    assert np.array_equal(words, want)
+    err = 0.0
+    for kk in range(K):
+        for tt in range(T):
+            for m in range(M):
+                ref = oracle.disturbance_normals(seed, s, 0 if crn else kk, tt, m)
+                err = max(err, float(np.max(np.abs(w[kk, tt, m] - ref))))
+    assert err <= 2e-6, err
+
+
 def test_philox_known_answers_on_device():
     rows = [[0, 0, 0, 0, 0, 0], [0xFFFFFFFF] * 6,
             [0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344, 0xa4093822, 0x299f31d0]]
