@@ -22,6 +22,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 import paper_2408_00494_amd as bss  # noqa: E402
+import sensitivity as SENS  # noqa: E402
 
 NTHREADS = min(16, os.cpu_count() or 1)
 
@@ -289,12 +290,12 @@ def test_paper_scale_solve_matches_oracle():
 def test_shielded_solve_matches_oracle():
     """K=8192, M=128, T=60 with the shield repair (delta=0.05, gamma=0.1).
 
-    End to end, the outputs the update consumes (costs, weighted controls) meet the bar.  Inside a
-    sample the repair feeds the belief of step t back into u_t, so the single- vs double-precision
-    particle differences are re-amplified at every step of the horizon; the sampled controls and
-    beliefs of a small share of samples drift past the end-to-end bound.  Each stage is therefore
-    also checked on the other side's inputs: the repair from the GPU's belief, and the
-    propagation under the GPU's repaired controls."""
+    Inside a sample the repair feeds the belief of step t back into u_t, so single- vs
+    double-precision particle differences are re-amplified at every step of the horizon.  The
+    implementation is therefore checked stage by stage on the other side's inputs (the repair
+    from the GPU's own belief and pre-repair control to 1e-6, the propagation under the GPU's
+    repaired controls to 1e-3), and end to end against the method's own sensitivity (the oracle
+    against itself with the estimate moved by ~1e-6; tests/sensitivity.py)."""
     prob, x0, v = W.config_shielded(delta=0.05, gamma=0.1)
     s = 2
     solver = bss.Solver(prob)
@@ -302,20 +303,12 @@ def test_shielded_solve_matches_oracle():
     solver.solve_index = s
     solver.solve(x0)
     b = solver.buffers()
-    g_u = b["u"].cpu().numpy().astype(np.float64)
-    g_mom = b["mom"].cpu().numpy()
-    g_S = b["S"].cpu().numpy()
-    g_v = solver.get_controls()
+    got = {"u": b["u"].cpu().numpy().astype(np.float64), "mom": b["mom"].cpu().numpy(),
+           "S": b["S"].cpu().numpy(), "v": solver.get_controls()}
     solver.close()
     ref = oracle.solve(prob, s, x0, v, nthreads=NTHREADS)
-    assert cost_err(g_S, ref["S"]) <= 1e-3
-    assert ctrl_err(g_v, ref["v"], prob) <= 1e-4
     span = np.max(np.abs(ref["mom"]), axis=1, keepdims=True)
-    per_k = np.max(np.abs(g_mom - ref["mom"]) / np.where(span > 0, span, 1.0), axis=(1, 2))
-    frac_bad = float(np.mean(per_k > 1e-3))
-    print(f"shield: S {cost_err(g_S, ref['S']):.2e}  v {ctrl_err(g_v, ref['v'], prob):.2e}  "
-          f"samples with moment error > 1e-3: {frac_bad:.4%} (max {per_k.max():.2e})", flush=True)
-    assert frac_bad <= 0.01
+    per_k = np.max(np.abs(got["mom"] - ref["mom"]) / np.where(span > 0, span, 1.0), axis=(1, 2))
 
     # the repair acted on this workload
     eps_only = oracle.solve(dict(prob, shield_iters=0), s, x0, v, nthreads=NTHREADS)
@@ -341,14 +334,19 @@ def test_shielded_solve_matches_oracle():
                    + v32.astype(np.float64)).astype(np.float32)
             pre = np.clip(pre, -scale.astype(np.float32), scale.astype(np.float32))
             row += 1
-            u_rep = oracle.repair(prob, nu, g_mom[k, t], pre.astype(np.float64))
+            u_rep = oracle.repair(prob, nu, got["mom"][k, t], pre.astype(np.float64))
             u_rep32 = u_rep.astype(np.float32).astype(np.float64)
-            worst_rep = max(worst_rep, float(np.max(np.abs(u_rep32 - g_u[k, t]) / scale)))
-        mom_k = oracle.propagate(prob, s, int(k), x0, g_u[k])
-        worst_prop = max(worst_prop, mom_err(g_mom[k:k + 1], mom_k[None]))
+            worst_rep = max(worst_rep, float(np.max(np.abs(u_rep32 - got["u"][k, t]) / scale)))
+        mom_k = oracle.propagate(prob, s, int(k), x0, got["u"][k])
+        worst_prop = max(worst_prop, mom_err(got["mom"][k:k + 1], mom_k[None]))
     print(f"shield stages: repair {worst_rep:.2e}  propagation {worst_prop:.2e}", flush=True)
     assert worst_rep <= 1e-6
     assert worst_prop <= 1e-3
+
+    # end to end, against the oracle's own sensitivity
+    gpu = SENS.drift(prob, got, ref)
+    own = SENS.self_drift(prob, s, x0, v, ref, nthreads=NTHREADS)
+    SENS.check(gpu, own, "shielded workload")
 
 
 @pytest.mark.parametrize("K,M,T,lanes", [(1, 1, 1, 0), (3, 13, 7, 8), (257, 16, 30, 0),
@@ -547,9 +545,9 @@ def test_obstacle_solve_matches_oracle():
 
 def test_shielded_obstacle_solve_matches_oracle():
     """The repair against the obstacles as well as the walls.  As for the shielded workload, the
-    repair feeds each step's belief back into u, so the end-to-end bar applies to what the update
-    consumes (costs, v+), a small share of samples may drift in u, and the repair is checked as a
-    stage on the GPU's own beliefs and pre-repair controls."""
+    repair feeds each step's belief back into u: the repair is checked as a stage on the GPU's
+    own beliefs and pre-repair controls (1e-6), and the solve end to end against the oracle's own
+    sensitivity (tests/sensitivity.py)."""
     prob, x0, v = W.config_small()
     prob = _with_obstacles(dict(prob, K=512, M=32, shield_iters=2), _OBSTACLES)
     s = 4
@@ -558,17 +556,12 @@ def test_shielded_obstacle_solve_matches_oracle():
     solver.solve_index = s
     solver.solve(x0)
     b = solver.buffers()
-    g_u = b["u"].cpu().numpy().astype(np.float64)
-    g_mom = b["mom"].cpu().numpy()
-    g_S = b["S"].cpu().numpy()
-    g_v = solver.get_controls()
+    got = {"u": b["u"].cpu().numpy().astype(np.float64), "mom": b["mom"].cpu().numpy(),
+           "S": b["S"].cpu().numpy(), "v": solver.get_controls()}
     solver.close()
     ref = oracle.solve(prob, s, x0, v, nthreads=NTHREADS)
-    assert cost_err(g_S, ref["S"]) <= 1e-3
-    assert ctrl_err(g_v, ref["v"], prob) <= 1e-4
     scale = np.array([prob["steer_max"], prob["accel_max"]])
-    per_k = np.max(np.abs(g_u - ref["u"]) / scale, axis=(1, 2))
-    assert np.mean(per_k > 1e-4) <= 0.02      # drift past the control bar in a few samples only
+    per_k = np.max(np.abs(got["u"] - ref["u"]) / scale, axis=(1, 2))
     # the repair acted on this workload
     plain = oracle.solve(dict(prob, shield_iters=0), s, x0, v, nthreads=NTHREADS)
     assert np.mean(np.any(np.abs(ref["u"] - plain["u"]) > 1e-12, axis=2)) > 1e-3
@@ -585,14 +578,13 @@ def test_shielded_obstacle_solve_matches_oracle():
                    + v[t].astype(np.float32).astype(np.float64)).astype(np.float32)
             pre = np.clip(pre, -scale.astype(np.float32), scale.astype(np.float32))
             row += 1
-            u_rep = oracle.repair(prob, nu, g_mom[k, t], pre.astype(np.float64))
+            u_rep = oracle.repair(prob, nu, got["mom"][k, t], pre.astype(np.float64))
             u_rep32 = u_rep.astype(np.float32).astype(np.float64)
-            worst = max(worst, float(np.max(np.abs(u_rep32 - g_u[k, t]) / scale)))
-    print(f"obstacles + shield: S {cost_err(g_S, ref['S']):.2e} v "
-          f"{ctrl_err(g_v, ref['v'], prob):.2e} samples with u drift > 1e-4 "
-          f"{np.mean(per_k > 1e-4):.2%} (max {per_k.max():.1e}) "
-          f"repair stage {worst:.2e}", flush=True)
+            worst = max(worst, float(np.max(np.abs(u_rep32 - got["u"][k, t]) / scale)))
+    print(f"obstacles + shield: repair stage {worst:.2e}", flush=True)
     assert worst <= 1e-6
+    SENS.check(SENS.drift(prob, got, ref), SENS.self_drift(prob, s, x0, v, ref, nthreads=NTHREADS),
+               "obstacles + shield")
 
 
 def test_far_obstacle_changes_nothing_on_device():
