@@ -4,8 +4,9 @@ A step is one receding-horizon control period of the paper-scale workload: one f
 (rollout + scoring + log-sum-exp update, K=4096 samples x M=64 particles x T=50 steps) from a
 device-resident state estimate, followed by the warm-start shift.  The value is rollout-steps per
 second (K*M*T per solve) over the timed steps.  Also reported:
-  * roofline of the rollout kernel (the dominant kernel) against the VALU issue rate, with its
-    average launch time measured by HIP events on the solve stream;
+  * roofline of the rollout kernel (the dominant kernel): its FP32 operations per launch (175.5
+    per rollout-step, counted from the kernel's arithmetic) over its average launch time
+    measured by HIP events on the solve stream, against the FP32 vector peak of 157.3 TFLOP/s;
   * the FP64 CPU oracle timed on the host on the same workload (cpu_baseline);
   * plain synchronous solve latency (p50/p99) from host inputs.
 
@@ -23,28 +24,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Minimal VALU issue slots one rollout-step (one particle advanced one step) needs, counted from
-# the operations of the method: a 32-bit float or integer operation is 1 slot, a double-precision
-# operation 2, a transcendental (log, sqrt, sin, cos, rcp) or a 32x32->64-bit multiply 4 (they
-# issue at a quarter of the full rate).  Breakdown: Philox4x32-10 100, uniforms 8, Box-Muller 33,
-# two vector-field evaluations 116, midpoint combination and noise 13, double-precision moment
-# accumulation 34.
-SLOTS_PER_ROLLOUT_STEP = 304
-# MI355X: 256 CUs x 128 lane-slots per clock (4 SIMDs x 32 lanes, the rate behind the published
-# 157.3 TFLOP/s FP32 vector peak with FMA = 2 FLOP) x 2.4 GHz = 78.6e12 lane-slots/s
-VALU_PEAK_SLOTS = 256 * 128 * 2.4e9
-# FP32 FLOPs of the particle dynamics per rollout-step (FMA = 2), and MI355X's FP32 vector peak
-FP32_FLOP_PER_ROLLOUT_STEP = 206
+# FP32 work of one rollout-step (one particle advanced one step), counted from the operations the
+# kernel executes for the method (FMA = 2 FLOP, add / sub / mul = 1, a transcendental rcp / log /
+# sqrt / sin / cos = 1; min / max / med3 / rint and integer work excluded):
+#   disturbance normals, per particle (a quad's three Philox blocks give six Box-Muller pairs,
+#     each 2 sub + 3 mul + log, sqrt, sin, cos): 7.5 + 6 transcendental
+#   two vector-field evaluations, each: slip-angle ratios 6, two arctangent polynomials 36,
+#     slip angle 1, tire forces 2, heading reduction 1, global velocities 6, accelerations 11,
+#     + rcp, sin, cos: 2 x (63 + 3)
+#   midpoint combination and update: headings 6, midpoint 6, the three position sums 6 (the
+#     compensation terms of the kernel's compensated sums are not counted), velocities with the
+#     disturbance 12: 30
+# = 163.5 FP32 FLOP + 12 transcendental = 175.5 FP32 operations per rollout-step (the counters
+# read 174.9: 64 x (ADD + MUL + 2 FMA + TRANS) per rollout-step).
+FP32_FLOP_PER_ROLLOUT_STEP = 175.5
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 32 lanes x 2 (packed dual-issue) x 2 FLOP (FMA) x
+# 2.4 GHz = 157.3e12 FLOP/s; without packed FP32 (which this build disables) half of it.
 FP32_PEAK = 157.3e12
+FP32_PEAK_NONPACKED = FP32_PEAK / 2
 
-# HBM bytes per launch of the solve kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a 1 GiB device copy
-# (FETCH_SIZE x2.0, WRITE_SIZE x1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "3c66542b17308c36", "lanes": 16, "ppl": 4, "split": True,
-                    "fetch_bytes": 7615.6 * 1024 * 2.0, "write_bytes": 15035.0 * 1024 * 1.0}
-KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_kernels.hip",
+KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
+                  "paper_2408_00494_amd/csrc/bss_wave.h",
                   "paper_2408_00494_amd/csrc/bss_device.h",
                   "paper_2408_00494_amd/csrc/bss_internal.h"]
+
+# Counter measurements of the solve kernel on this workload (rocprofv3 --pmc, average per
+# dispatch), valid only for the kernel sources (hash) and the launch shape they were taken on:
+#   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
+#     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
+#   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
+MEASURED = {"sources_sha256_16": None, "lanes": 16, "ppl": 4, "split": True,
+            "fetch_bytes": None, "write_bytes": None, "valu_insts": None,
+            "fp32_flop": None}
+
+
+def sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured(lanes, ppl, split):
+    """Counter measurements of the solve kernel, or None if the kernel or the launch shape
+    changed since they were taken."""
+    if MEASURED["sources_sha256_16"] != sources_hash() or \
+            (lanes, ppl, split) != (MEASURED["lanes"], MEASURED["ppl"], MEASURED["split"]):
+        return None
+    return MEASURED
 
 
 def ALG_BYTES_PER_SOLVE(K, M, T, lanes):
@@ -53,21 +82,6 @@ def ALG_BYTES_PER_SOLVE(K, M, T, lanes):
     groups = 256 // lanes
     blocks = (K + groups - 1) // groups
     return 2 * K * (T + 1) * 9 * 8 + K * 8 + blocks * (2 * T + 4) * 8 + T * 2 * 8
-
-
-def measured_traffic(lanes, ppl, split):
-    """Counter-measured HBM bytes per solve-kernel launch, or None if the kernel or the launch
-    shape changed since."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != MEASURED_TRAFFIC["sources_sha256_16"] or \
-            (lanes, ppl, split) != (MEASURED_TRAFFIC["lanes"], MEASURED_TRAFFIC["ppl"],
-                                    MEASURED_TRAFFIC["split"]):
-        return None
-    return MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]
 
 
 def progress(msg):
@@ -383,8 +397,8 @@ def main():
 
     value = rs_per_solve * args.steps / elapsed
     kernel_ms = kernel_ms_total / max(n_meas, 1)
-    slots = SLOTS_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3)
-    traffic = measured_traffic(info["lanes"], info["ppl"], info["split"])
+    fp32 = FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3)
+    meas = measured(info["lanes"], info["ppl"], info["split"])
 
     # plain synchronous solves from host inputs (latency of one control period)
     lat = []
@@ -412,12 +426,17 @@ def main():
                                "ellipse track",
                    "K": K, "M": M, "T": T, "lanes": info["lanes"], "ppl": info["ppl"],
                    "noise_split": info["split"]},
-        "roofline": {"bound": "alu", "achieved": slots / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": slots / VALU_PEAK_SLOTS, "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": fp32 / 1e12, "peak": FP32_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fp32 / FP32_PEAK,
+                     "traffic": (meas["fetch_bytes"] + meas["write_bytes"]) if meas else None,
                      "kernel": "solve_kernel", "kernel_ms": kernel_ms,
+                     "fp32_flop_per_rollout_step": FP32_FLOP_PER_ROLLOUT_STEP,
+                     "frac_of_nonpacked_peak": fp32 / FP32_PEAK_NONPACKED,
                      "algorithmic_bytes": ALG_BYTES_PER_SOLVE(K, M, T, info["lanes"]),
-                     "fp32_tflops": FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3) / 1e12,
-                     "fp32_frac_of_157": FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3) / FP32_PEAK},
+                     "valu_lane_insts_per_rollout_step":
+                         meas["valu_insts"] * 64 / rs_per_solve if meas else None,
+                     "counter_fp32_flop_per_rollout_step":
+                         meas["fp32_flop"] / rs_per_solve if meas else None},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mode": "plain synchronous solve from host inputs"},
     }

@@ -163,6 +163,14 @@ InstanceDesc make_desc(const bss_params& p)
     return d;
 }
 
+bool samples_shielded(const bss_params& p) { return p.shield_iters > 0 && p.local_repair != 2; }
+bool launch_shield(const bss_params& p) { return samples_shielded(p); }
+bool launch_resample(const bss_params& p) { return p.belief != 0; }
+bool shape_for_shield(const bss_params& p)
+{
+    return samples_shielded(p) && p.belief == 0 && p.n_con == 0;
+}
+
 void append_blocks(std::vector<BlockDesc>& out, int inst, int K, int lanes)
 {
     const int groups = 256 / lanes;
@@ -231,9 +239,6 @@ constexpr size_t kStateBytes = offsetof(InstanceDesc, shift_after) - offsetof(In
 
 size_t max_blocks(int K) { return (size_t)solve_blocks(K, 64); }
 
-// the sampled controls are repaired (the per-sample shield) unless only the update is repaired
-bool samples_shielded(const bss_params& p) { return p.shield_iters > 0 && p.local_repair != 2; }
-
 // sizes, params and launch shape of a context's descriptor (state fields zero, buffers unset);
 // its repair iterations are those of the sampled controls (none when only the update is repaired)
 void fill_desc(bss_ctx* c)
@@ -249,19 +254,6 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
     std::vector<BlockDesc> out;
     append_blocks(out, inst, K, lanes);
     return out;
-}
-
-// Kernel variant flags of an instance (half-space constraints add the CON flag to the plain or
-// split variant, or, with the repair or the re-sampling, to the generic one).
-bool launch_shield(const bss_params& p) { return samples_shielded(p); }
-bool launch_resample(const bss_params& p) { return p.belief != 0; }
-
-// the automatic shape's eight particles per lane for the repair: the plain shielded variant only
-// (the generic one, which the constraints or the re-sampling select, runs out of registers at
-// eight)
-bool shape_for_shield(const bss_params& p)
-{
-    return samples_shielded(p) && p.belief == 0 && p.n_con == 0;
 }
 
 hipError_t upload_shape(bss_ctx* c)

@@ -30,6 +30,17 @@ size_t align256(size_t x);
 // state fields and buffer pointers are left zero for the caller to fill.
 InstanceDesc make_desc(const bss_params& p);
 
+// The sampled controls are repaired (the per-sample shield) unless only the update is repaired.
+bool samples_shielded(const bss_params& p);
+// Kernel variant flags of an instance (half-space constraints add the CON flag to the plain or
+// split variant, or, with the repair or the re-sampling, to the generic one).
+bool launch_shield(const bss_params& p);
+bool launch_resample(const bss_params& p);
+// The automatic shape's eight particles per lane for the repair: the plain shielded variant only
+// (the generic one, which the constraints or the re-sampling select, runs out of registers at
+// eight).
+bool shape_for_shield(const bss_params& p);
+
 // Solve blocks of one instance: (inst, k0) for k0 = 0, 256/L, 2*256/L, ... < K.
 void append_blocks(std::vector<BlockDesc>& out, int inst, int K, int lanes);
 
