@@ -393,6 +393,33 @@ bss_status bss_server_replay(bss_server* s, int64_t n, const double* t_arrival,
 /* Wait for the work in flight and free the server (NULL is accepted). */
 void bss_server_destroy(bss_server* s);
 
+/* ---- one solve that allocates nothing --------------------------------------------------- */
+
+/* Bytes of the library's static per-GPU scratch array: 48 MiB, held on each GPU the library runs
+ * on until the process ends. */
+#define BSS_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  One solve of parameter set p from the device-resident
+ * state estimate x0_dev [6] (and Sigma0_dev [36] or NULL) and mean sequence v_in_dev [T][2] at
+ * solve index solve_index: the same kernels and launch shape as bss_solve_async on a context of
+ * p whose mean sequence is v_in, with no pending shift, at that solve index, so v_out_dev [T][2]
+ * receives that context's v+ and stats_dev [8] its stats (layout of bss_buffers) bit for bit.
+ * All pointers are device pointers owned by the caller; v_in_dev and v_out_dev must differ; v_in
+ * is only read.  Asynchronous on `stream`: three kernels, no copy, no allocation, no host
+ * synchronisation.  Every scratch buffer of the solve (descriptor, grids, belief records,
+ * constraint variances, costs, block partials) lives in the library's static array of
+ * BSS_NOALLOC_SCRATCH_BYTES on the current GPU (bss_noalloc_scratch_bytes gives a problem's
+ * need); calls that overlap on one GPU share it and race, so enqueue them on one stream or
+ * order them.  Errors: BSS_E_INVAL for invalid parameters, NULL pointers, v_in_dev == v_out_dev,
+ * local_repair != 0, or a problem whose scratch exceeds the array (the message gives both
+ * sizes; checked before any device call); BSS_E_DEVICE for a failed launch. */
+bss_status bss_solve_noalloc(const bss_params* p, uint32_t solve_index, const double* x0_dev,
+                             const double* Sigma0_dev, const double* v_in_dev, double* v_out_dev,
+                             double* stats_dev, void* stream);
+/* Scratch bytes bss_solve_noalloc needs for p (0 for invalid parameters). */
+size_t bss_noalloc_scratch_bytes(const bss_params* p);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* bss_last_error(void);
 

@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import BssError, check, params_from_problem
 
-__all__ = ["Solver", "Batch", "Server", "BssError", "backoff", "validate", "dev_philox", "dev_normals", "dev_disturbance",
+__all__ = ["Solver", "Batch", "Server", "BssError", "backoff", "validate", "dev_philox", "dev_normals", "dev_disturbance", "solve_noalloc", "noalloc_scratch_bytes",
            "dev_model_step", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
 
 
@@ -353,6 +353,21 @@ def dev_normals(seed: int, ctr):
     z = torch.empty((ctr.shape[0], 4), dtype=torch.float32, device=ctr.device)
     check(_lib.lib().bss_dev_normals(int(seed), _ptr(ctr), _ptr(z), ctr.shape[0], _stream_ptr()))
     return z
+
+
+def solve_noalloc(problem: dict, s: int, x0, v_in, v_out, stats, Sigma0=None, stream=None):
+    """One solve through bss_solve_noalloc (no device allocation: the library's static scratch):
+    device tensors x0 [6], v_in [T][2], v_out [T][2], stats [8] (float64), Sigma0 [36] or None;
+    enqueued on `stream` (default: torch's current stream)."""
+    p = params_from_problem(problem)
+    check(_lib.lib().bss_solve_noalloc(C.byref(p), int(s), _ptr(x0), _ptr(Sigma0), _ptr(v_in),
+                                       _ptr(v_out), _ptr(stats), _stream_ptr(stream)))
+
+
+def noalloc_scratch_bytes(problem: dict) -> int:
+    """Scratch bytes bss_solve_noalloc needs for the problem (0 if it is invalid)."""
+    p = params_from_problem(problem)
+    return int(_lib.lib().bss_noalloc_scratch_bytes(C.byref(p)))
 
 
 def dev_disturbance(seed: int, s: int, K: int, M: int, T: int, lanes: int, ppl: int,

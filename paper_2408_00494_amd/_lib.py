@@ -85,6 +85,7 @@ EXPORTS = [
     "bss_server_config_default", "bss_server_create", "bss_server_submit", "bss_server_pump",
     "bss_server_poll", "bss_server_drain", "bss_server_get_controls", "bss_server_set_controls",
     "bss_server_vehicle_state", "bss_server_replay", "bss_server_destroy",
+    "bss_solve_noalloc", "bss_noalloc_scratch_bytes",
 ]
 
 
@@ -130,6 +131,8 @@ def _declare(lib):
         "bss_dev_philox": (i32, [u64, vp, vp, i64, vp]),
         "bss_dev_normals": (i32, [u64, vp, vp, i64, vp]),
         "bss_dev_disturbance": (i32, [u64, u32, i32, i32, i32, i32, i32, i32, vp, vp, vp]),
+        "bss_solve_noalloc": (i32, [P, u32, vp, vp, vp, vp, vp, vp]),
+        "bss_noalloc_scratch_bytes": (C.c_size_t, [P]),
         "bss_dev_model_step": (i32, [P, vp, vp, vp, i64, vp]),
         "bss_dev_sdf": (i32, [d, d, vp, vp, i64, vp]),
         "bss_dev_score": (i32, [P, vp, vp, vp, vp, vp]),

@@ -190,3 +190,22 @@ def test_server_and_batch_argument_checks():
     assert lib.bss_batch_create(None, 0, 0, 0, C.byref(out)) == _lib.BSS_E_INVAL
     assert lib.bss_batch_solve(None) == _lib.BSS_E_INVAL
     assert lib.bss_set_shape(None, 16, 4, -1) == _lib.BSS_E_INVAL
+
+
+def test_noalloc_rejects_oversized_problems_before_any_device_call():
+    """The solve that allocates nothing checks its scratch need against the static array before
+    touching a device (so this runs without a GPU; the pointers are never dereferenced)."""
+    lib = _lib.lib()
+    prob, _, _ = W.config_shielded()
+    big = _lib.params_from_problem(dict(prob, T=200))
+    need = lib.bss_noalloc_scratch_bytes(C.byref(big))
+    assert need > (48 << 20)
+    fake = C.c_void_p(256)
+    st = lib.bss_solve_noalloc(C.byref(big), 0, fake, None, fake, C.c_void_p(512), fake, None)
+    assert st == 1                                            # BSS_E_INVAL
+    msg = lib.bss_last_error().decode()
+    assert "scratch" in msg and str(48 << 20) in msg, msg
+    small = _lib.params_from_problem(W.config_small()[0])
+    assert 0 < lib.bss_noalloc_scratch_bytes(C.byref(small)) < (48 << 20)
+    assert lib.bss_solve_noalloc(C.byref(small), 0, fake, None, fake, fake, fake, None) == 1
+    assert "distinct" in lib.bss_last_error().decode()
