@@ -43,6 +43,12 @@ class OrcParams(C.Structure):
         ("model", C.c_int32),
         ("lin_A", C.c_double * 36), ("lin_B", C.c_double * 12),
         ("n_con", C.c_int32), ("con_a", C.c_double * 24), ("con_b", C.c_double * 4),
+        ("vehicle", C.c_int32),
+        ("Rw", C.c_double), ("Iw", C.c_double), ("T_max", C.c_double),
+        ("pac_B", C.c_double), ("pac_C", C.c_double), ("pac_D", C.c_double),
+        ("pac_E", C.c_double),
+        ("track_len", C.c_double), ("kappa_amp", C.c_double),
+        ("n_sub", C.c_int32),
     ]
 
 
@@ -136,6 +142,30 @@ def _load():
     lib.orc_step_shift.restype = None
     lib.orc_chol_psd6.argtypes = [_f64p, _f64p]
     lib.orc_chol_psd6.restype = None
+    # the 8-state vehicle
+    lib.orc8_magic.argtypes = [P, C.c_double]
+    lib.orc8_magic.restype = C.c_double
+    lib.orc8_tire.argtypes = [P, C.c_double, C.c_double, C.c_double, _f64p]
+    lib.orc8_tire.restype = None
+    lib.orc8_kappa.argtypes = [P, C.c_double]
+    lib.orc8_kappa.restype = C.c_double
+    lib.orc8_deriv.argtypes = [P, _f64p, _f64p, _f64p]
+    lib.orc8_deriv.restype = None
+    lib.orc8_step.argtypes = [P, _f64p, _f64p, _f64p]
+    lib.orc8_step.restype = None
+    lib.orc8_moments.argtypes = [_f64p, C.c_int32, _f64p]
+    lib.orc8_moments.restype = None
+    lib.orc8_barrier.argtypes = [P, C.c_double, _f64p]
+    lib.orc8_barrier.restype = C.c_double
+    lib.orc8_stage_cost.argtypes = [P, _f64p]
+    lib.orc8_stage_cost.restype = C.c_double
+    lib.orc8_repair.argtypes = [P, C.c_double, _f64p, _f64p]
+    lib.orc8_repair.restype = None
+    lib.orc8_score.argtypes = [P, C.c_double, _f64p, _f64p, _f64p]
+    lib.orc8_score.restype = C.c_double
+    lib.orc8_solve.argtypes = [P, C.c_uint32, _f64p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               _f64p, C.c_int32]
+    lib.orc8_solve.restype = C.c_int32
     return lib
 
 
@@ -378,3 +408,89 @@ def chol_psd6(A):
     L = np.zeros(36)
     lib().orc_chol_psd6(np.ascontiguousarray(A, dtype=np.float64).ravel(), L)
     return L.reshape(6, 6)
+
+
+# ---- the paper's 8-state vehicle (vehicle = 1): x = [vX, vY, r, wF, wR, epsi, eY, s] ----------
+NREC8 = 9
+
+
+def magic8(cfg, z):
+    return lib().orc8_magic(C.byref(make_params(cfg)), float(z))
+
+
+def tire8(cfg, Fz, slip, alpha):
+    F = np.zeros(2)
+    lib().orc8_tire(C.byref(make_params(cfg)), float(Fz), float(slip), float(alpha), F)
+    return F
+
+
+def kappa8(cfg, s):
+    return lib().orc8_kappa(C.byref(make_params(cfg)), float(s))
+
+
+def deriv8(cfg, x, u):
+    dx = np.zeros(8)
+    lib().orc8_deriv(C.byref(make_params(cfg)), np.ascontiguousarray(x, dtype=np.float64),
+                     np.ascontiguousarray(u, dtype=np.float64), dx)
+    return dx
+
+
+def model_step8(cfg, x, u):
+    xn = np.zeros(8)
+    lib().orc8_step(C.byref(make_params(cfg)), np.ascontiguousarray(x, dtype=np.float64),
+                    np.ascontiguousarray(u, dtype=np.float64), xn)
+    return xn
+
+
+def moments8(particles):
+    part = np.ascontiguousarray(particles, dtype=np.float64)
+    rec = np.zeros(NREC8)
+    lib().orc8_moments(part.ravel(), part.shape[0], rec)
+    return rec
+
+
+def barrier8(cfg, nu, rec):
+    return lib().orc8_barrier(C.byref(make_params(cfg)), float(nu),
+                              np.ascontiguousarray(rec, dtype=np.float64))
+
+
+def stage_cost8(cfg, rec):
+    return lib().orc8_stage_cost(C.byref(make_params(cfg)),
+                                 np.ascontiguousarray(rec, dtype=np.float64))
+
+
+def repair8(cfg, nu, rec_t, u):
+    uu = np.array(u, dtype=np.float64)
+    lib().orc8_repair(C.byref(make_params(cfg)), float(nu),
+                      np.ascontiguousarray(rec_t, dtype=np.float64), uu)
+    return uu
+
+
+def score8(cfg, nu, rec, u, v):
+    return lib().orc8_score(C.byref(make_params(cfg)), float(nu),
+                            np.ascontiguousarray(rec, dtype=np.float64).ravel(),
+                            np.ascontiguousarray(u, dtype=np.float64).ravel(),
+                            np.ascontiguousarray(v, dtype=np.float64).ravel())
+
+
+def solve8(cfg, s, x0, v, want_traces=True, nthreads=None):
+    """One solve of the 8-state problem from the estimate x0 [8] (known exactly) and warm start
+    v [T][2]: returns dict(v=v+, u [K][T][2], mom [K][T+1][9], S [K], stats [4], status)."""
+    p = make_params(cfg)
+    K, T = cfg["K"], cfg["T"]
+    vv = np.array(v, dtype=np.float64).reshape(T, 2).copy()
+    stats = np.zeros(4)
+    out = {}
+    if want_traces:
+        u = np.zeros((K, T, 2))
+        mom = np.zeros((K, T + 1, NREC8))
+        S = np.zeros(K)
+        ptrs = [_ptr(u), _ptr(mom), _ptr(S)]
+    else:
+        ptrs = [None, None, None]
+    rc = lib().orc8_solve(C.byref(p), int(s), np.ascontiguousarray(x0, dtype=np.float64), vv,
+                          *ptrs, stats, int(nthreads or os.cpu_count() or 1))
+    out.update(v=vv, stats=stats, status=int(rc))
+    if want_traces:
+        out.update(u=u, mom=mom, S=S)
+    return out

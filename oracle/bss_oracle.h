@@ -69,6 +69,16 @@ typedef struct orc_params {
     int32_t n_con;        /* half-space state constraints (0..4) */
     double con_a[24];     /* constraint i: a_i = con_a[6i..6i+5] */
     double con_b[4];      /* constraint i: bound b_i */
+    /* vehicle: 0 = the 6-state car above; 1 = the paper's 8-state single-track vehicle with wheel
+     * speeds in the road-aligned frame (bss_oracle8.c), x = [vX, vY, r, wF, wR, epsi, eY, s],
+     * u = [steer, throttle], reusing m, Iz, lf, lr, mu, g, v_min, dt, the control box
+     * (accel_max bounds the throttle), the noise, the weights and half_width */
+    int32_t vehicle;
+    double Rw, Iw, T_max;              /* wheel radius [m], drive-line inertia per axle [kg m^2],
+                                          rear drive torque at full throttle [N m] */
+    double pac_B, pac_C, pac_D, pac_E; /* magic-formula coefficients (pure slip) */
+    double track_len, kappa_amp;       /* centerline curvature (2 pi / L)(1 + a sin(4 pi s / L)) */
+    int32_t n_sub;                     /* explicit-midpoint substeps per control period */
 } orc_params;
 
 #define ORC_MAX_CON 4
@@ -142,6 +152,24 @@ void orc_local_repair(const orc_params* p, uint32_t s, const double x0[6], const
                       const double* v_plus, double* v_safe, double* mom_out);
 
 void orc_step_shift(int32_t T, double* v);
+
+/* ---- the 8-state vehicle (vehicle = 1; bss_oracle8.c) ---------------------------------------
+ * Records hold 9 doubles: the means of the 8 states, then the unbiased variance of eY. */
+#define ORC8_NX 8
+#define ORC8_NREC 9
+double orc8_magic(const orc_params* p, double z);
+void   orc8_tire(const orc_params* p, double Fz, double slip, double alpha, double F[2]);
+double orc8_kappa(const orc_params* p, double s);
+void   orc8_deriv(const orc_params* p, const double x[8], const double u[2], double dx[8]);
+void   orc8_step(const orc_params* p, const double x[8], const double u[2], double xn[8]);
+void   orc8_moments(const double* particles, int32_t M, double rec[9]);
+double orc8_barrier(const orc_params* p, double nu, const double rec[9]);
+double orc8_stage_cost(const orc_params* p, const double rec[9]);
+void   orc8_repair(const orc_params* p, double nu, const double rec_t[9], double u[2]);
+double orc8_score(const orc_params* p, double nu, const double* rec, const double* u,
+                  const double* v);
+int32_t orc8_solve(const orc_params* p, uint32_t s, const double x0[8], double* v, double* u_out,
+                   double* rec_out, double* S_out, double stats[4], int32_t nthreads);
 
 #ifdef __cplusplus
 }

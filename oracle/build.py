@@ -7,9 +7,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    """Compile bss_oracle.c with gcc (no fast-math: the oracle must follow IEEE double)."""
+    """Compile bss_oracle.c and bss_oracle8.c with gcc (no fast-math: the oracle must follow IEEE double)."""
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-Wall", "-Wextra", "-fPIC", "-shared",
-           "-o", LIB + ".tmp", os.path.join(HERE, "bss_oracle.c"), "-lm", "-lpthread"]
+           "-o", LIB + ".tmp", os.path.join(HERE, "bss_oracle.c"),
+           os.path.join(HERE, "bss_oracle8.c"), "-lm", "-lpthread"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -46,6 +46,12 @@ _DEFAULTS = dict(
     # half-space constraints on the whole state (up to 4): a_i^T x <= b_i with
     # a_i = con_a[6i..6i+5] over (X, Y, psi, vx, vy, r) and b_i = con_b[i]
     n_con=0, con_a=[0.0] * 24, con_b=[0.0] * 4,
+    # vehicle: 0 = the 6-state car above, 1 = the paper's 8-state single-track vehicle with wheel
+    # speeds in the road-aligned frame (config_vehicle8 sets its values): wheel radius, drive-line
+    # inertia per axle, rear drive torque at full throttle, magic-formula coefficients, track
+    # length and curvature amplitude, midpoint substeps per control period
+    vehicle=0, Rw=0.095, Iw=0.3, T_max=8.0, pac_B=10.0, pac_C=1.9, pac_D=1.0, pac_E=0.97,
+    track_len=120.0, kappa_amp=0.8, n_sub=4,
 )
 
 
@@ -205,3 +211,45 @@ def serving_trace(fleet, duration_s: float = 60.0, rate_hz: float = 20.0, seed: 
         sarc = (s0[veh[i]] + speed * t[i]) % cum[-1]
         x0[i] = pose_on_centerline(p["ell_a"], p["ell_b"], float(np.interp(sarc, cum, th)), speed)
     return {"t": t, "vehicle": veh, "K": K, "M": M, "delta": delta, "x0": x0}
+
+
+# ------------------------------------------------------------------------------------------------
+# the paper's 8-state vehicle (vehicle = 1)
+# ------------------------------------------------------------------------------------------------
+def vehicle8_problem(**overrides) -> dict:
+    """The 8-state single-track vehicle with wheel speeds, x = [vX, vY, r, wF, wR, epsi, eY, s],
+    u = [steer, throttle].  The paper gives the AutoRally's size (1 m long, 22 kg) but none of
+    its inertia, tire, wheel or track data, so the values are stated choices: a 22 kg car with
+    lf = 0.34 m, lr = 0.23 m, Iz = 1.1 kg m^2, wheel radius 0.095 m, drive-line inertia 0.3 kg m^2
+    per axle, 8 N m of rear drive torque at full throttle (throttle in [-1, 1]), the generic
+    dry-road magic-formula coefficients B = 10, C = 1.9, D = 1, E = 0.97 for both slip
+    directions with mu = 0.9, slip denominators floored at 2 m/s, four midpoint substeps per
+    0.05 s period, and a closed synthetic track of length 120 m with curvature
+    (2 pi / 120)(1 + 0.8 sin(4 pi s / 120)) (radii 10.6 m to 95 m); the paper's goal speed
+    (6 m/s), lateral-deviation weight (0.1) and half-width (2 m)."""
+    base = dict(vehicle=1, m=22.0, Iz=1.1, lf=0.34, lr=0.23, mu=0.9, g=9.81, v_min=2.0, dt=0.05,
+                Rw=0.095, Iw=0.3, T_max=8.0, pac_B=10.0, pac_C=1.9, pac_D=1.0, pac_E=0.97,
+                track_len=120.0, kappa_amp=0.8, n_sub=4,
+                steer_max=0.4, accel_max=1.0, sigma_eps=[0.1, 0.3], sigma_w=[0.05, 0.05, 0.05],
+                v_goal=6.0, q_vx=1.0, q_vy=0.0, q_r=0.0, q_ey=0.1, q_epsi=1.0,
+                half_width=2.0, delta=0.05, gamma=0.2)
+    base.update(overrides)
+    return default_problem(**base)
+
+
+def vehicle8_start(prob: dict, rng: np.random.Generator, vX: float = 5.0) -> np.ndarray:
+    """Start on the centerline (eY = epsi = 0) at a path coordinate uniform along the track,
+    rolling (wheel speeds vX / Rw) at vX."""
+    s0 = rng.uniform(0.0, prob["track_len"])
+    w = vX / prob["Rw"]
+    return np.array([vX, 0.0, 0.0, w, w, 0.0, 0.0, s0])
+
+
+def config_vehicle8(seed: int = 6):
+    """The paper's largest BSS-MPPI setting of its Table 1 (1000 control samples x 20 particles,
+    horizon 20) on the 8-state vehicle: K=1000, M=20, T=20, seeded start along the track."""
+    prob = vehicle8_problem(K=1000, M=20, T=20, seed=seed)
+    rng = np.random.default_rng(seed)
+    x0 = vehicle8_start(prob, rng)
+    v = np.zeros((prob["T"], 2))
+    return prob, x0, v
