@@ -94,7 +94,25 @@ typedef enum bss_status {
  *   a_i^T x^n, the same unbiased estimate as the covariance; with sigma points plus a_i^T Q a_i of
  *   the disturbance).  Such instances run in rollout variants with the constraints compiled in
  *   (batches and the server run them for all their members when one is constrained); the staged
- *   bss_dev_score and bss_dev_repair reject n_con > 0.
+ *   bss_dev_score and bss_dev_repair reject n_con > 0. * Vehicle (the Simulation Study's model): vehicle = 0 is the 6-state car above; vehicle = 1 is
+ *   the paper's 8-state single-track vehicle with wheel speeds in the road-aligned frame,
+ *   x = [vX, vY, r, wF, wR, epsi, eY, s] (body velocities, yaw rate, front and rear wheel speeds,
+ *   heading error and lateral deviation from the centerline, path coordinate), u = [steer,
+ *   throttle in +-accel_max]: wheel-frame slips (Rw w - v_x) / max(v_x, v_min) and slip angles
+ *   -atan(v_y / max(v_x, v_min)), magic-formula pure-slip forces mu Fz D sin(C atan(Bz -
+ *   E(Bz - atan Bz))) (pac_B..pac_E, static axle loads), combined by the friction ellipse
+ *   Fy = Fy0 sqrt(1 - (Fx0 / (mu D Fz))^2); m vX' = m r vY + Fxf cos d - Fyf sin d + Fxr,
+ *   m vY' = -m r vX + Fxf sin d + Fyf cos d + Fyr, Iz r' = lf (Fxf sin d + Fyf cos d) - lr Fyr,
+ *   Iw wF' = -Rw Fxf, Iw wR' = throttle T_max - Rw Fxr; s' = (vX cos epsi - vY sin epsi) /
+ *   (1 - kappa eY), eY' = vX sin epsi + vY cos epsi, epsi' = r - kappa s' with the centerline
+ *   curvature kappa(s) = (2 pi / track_len)(1 + kappa_amp sin(4 pi s / track_len)); n_sub
+ *   explicit-midpoint substeps per period dt; the disturbance acts on (vX, vY, r).  The belief is
+ *   the mean of the 8 states and the variance of eY (sigma_y), the barrier eq. 33 and the
+ *   running cost (x - x_g)^T Q (x - x_g) + C_obs [|eY| >= w_T] with x_g = (v_goal, 0, ...) and
+ *   Q = diag(q_vx, q_vy, q_r, 0, 0, q_epsi, q_ey, 0) (eq. 27).  The state estimate has 8 entries
+ *   and is known exactly (Sigma0 must be NULL); the shield repair, obstacles, half-space
+ *   constraints, belief != 0, sigma_w_speed, the repair of the update, batches and the server
+ *   are not available for it (BSS_E_INVAL).
  */
 typedef struct bss_params {
     double m, Iz, lf, lr, Cf, Cr, mu, g, v_min, dt;
@@ -119,6 +137,11 @@ typedef struct bss_params {
     int32_t n_con;
     double con_a[24];
     double con_b[4];
+    int32_t vehicle;
+    double Rw, Iw, T_max;
+    double pac_B, pac_C, pac_D, pac_E;
+    double track_len, kappa_amp;
+    int32_t n_sub;
 } bss_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc returns a
@@ -194,18 +217,20 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
 /* Change the stream of a context (subsequent calls enqueue there). */
 bss_status bss_set_stream(bss_ctx* c, void* stream);
 
-/* One solve from host inputs, synchronous: x0[6] the state estimate, Sigma0 a 6x6 row-major
- * covariance or NULL (known state), u0_out[2] receives the command v+_0, info may be NULL.
+/* One solve from host inputs, synchronous: x0[6] the state estimate (x0[8] for vehicle = 1),
+ * Sigma0 a 6x6 row-major covariance or NULL (known state), u0_out[2] receives the command v+_0,
+ * info may be NULL.
  * Updates the mean control sequence in place (Alg. 1: v <- v_safe) and advances the solve index.
  * Errors: BSS_E_INVAL (non-finite x0 or Sigma0, NULL pointers), BSS_E_NUMERIC (every cost was
  * non-finite; v unchanged), BSS_E_DEVICE. */
 bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, double u0_out[2],
                      bss_info* info);
 
-/* One solve from device-resident inputs, asynchronous on the context's stream: x0_dev [6] and
- * Sigma0_dev [36] (or NULL) are device pointers that must stay valid until the work completes.
- * Results land in the context's buffers (bss_get_buffers); the status word stats[4] is 5 when
- * every cost was non-finite (then v is unchanged).  Errors: BSS_E_INVAL, BSS_E_DEVICE. */
+/* One solve from device-resident inputs, asynchronous on the context's stream: x0_dev [6] ([8]
+ * for vehicle = 1) and Sigma0_dev [36] (or NULL) are device pointers that must stay valid until
+ * the work completes.  Results land in the context's buffers (bss_get_buffers); the status word
+ * stats[4] is 5 when every cost was non-finite (then v is unchanged).  Errors: BSS_E_INVAL,
+ * BSS_E_DEVICE. */
 bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma0_dev);
 
 /* Receding-horizon warm start: v_t <- v_{t+1} for t < T-1; v_{T-1} keeps its value.  The shift is
@@ -401,8 +426,8 @@ void bss_server_destroy(bss_server* s);
 
 /* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc.  One solve of parameter set p from the device-resident
- * state estimate x0_dev [6] (and Sigma0_dev [36] or NULL) and mean sequence v_in_dev [T][2] at
- * solve index solve_index: the same kernels and launch shape as bss_solve_async on a context of
+ * state estimate x0_dev [6] ([8] for vehicle = 1; Sigma0_dev [36] or NULL) and mean sequence
+ * v_in_dev [T][2] at solve index solve_index: the same kernels and launch shape as bss_solve_async on a context of
  * p whose mean sequence is v_in, with no pending shift, at that solve index, so v_out_dev [T][2]
  * receives that context's v+ and stats_dev [8] its stats (layout of bss_buffers) bit for bit.
  * All pointers are device pointers owned by the caller; v_in_dev and v_out_dev must differ; v_in
@@ -448,6 +473,11 @@ bss_status bss_dev_disturbance(uint64_t seed, uint32_t solve_index, int32_t K, i
 /* One noise-free single-precision RK2 step of the car: x[n][6], u[n][2] -> xn[n][6]. */
 bss_status bss_dev_model_step(const bss_params* p, const float* x, const float* u, float* xn,
                               int64_t n, void* stream);
+/* One noise-free single-precision control period of the 8-state vehicle (vehicle = 1; its n_sub
+ * midpoint substeps, the Simulation Study's single-track model with wheel speeds): x[n][8]
+ * (absolute path coordinate), u[n][2] -> xn[n][8].  BSS_E_INVAL for vehicle != 1. */
+bss_status bss_dev_model_step8(const bss_params* p, const float* x, const float* u, float* xn,
+                               int64_t n, void* stream);
 /* Signed distance to the centerline ellipse and its outward normal, double precision:
  * pts[n][2] -> out[n][3] = (e_y, n_x, n_y). */
 bss_status bss_dev_sdf(double a, double b, const double* pts, double* out, int64_t n,

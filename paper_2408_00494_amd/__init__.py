@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import BssError, check, params_from_problem
 
 __all__ = ["Solver", "Batch", "Server", "BssError", "backoff", "validate", "dev_philox", "dev_normals", "dev_disturbance", "solve_noalloc", "noalloc_scratch_bytes",
-           "dev_model_step", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
+           "dev_model_step", "dev_model_step8", "dev_sdf", "dev_score", "dev_update", "dev_repair"]
 
 
 def _torch():
@@ -390,6 +390,17 @@ def dev_model_step(problem: dict, x, u):
     xn = torch.empty_like(x)
     check(_lib.lib().bss_dev_model_step(C.byref(p), _ptr(x), _ptr(u), _ptr(xn), x.shape[0],
                                         _stream_ptr()))
+    return xn
+
+
+def dev_model_step8(problem: dict, x, u):
+    """One noise-free single-precision period of the 8-state vehicle: x [n, 8], u [n, 2]
+    (float32 device tensors) -> xn [n, 8]."""
+    torch = _torch()
+    p = params_from_problem(problem)
+    xn = torch.empty_like(x)
+    check(_lib.lib().bss_dev_model_step8(C.byref(p), _ptr(x), _ptr(u), _ptr(xn), x.shape[0],
+                                         _stream_ptr()))
     return xn
 
 

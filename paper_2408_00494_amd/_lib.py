@@ -50,6 +50,12 @@ class BssParams(C.Structure):
         ("n_con", C.c_int32),
         ("con_a", C.c_double * 24),
         ("con_b", C.c_double * 4),
+        ("vehicle", C.c_int32),
+        ("Rw", C.c_double), ("Iw", C.c_double), ("T_max", C.c_double),
+        ("pac_B", C.c_double), ("pac_C", C.c_double), ("pac_D", C.c_double),
+        ("pac_E", C.c_double),
+        ("track_len", C.c_double), ("kappa_amp", C.c_double),
+        ("n_sub", C.c_int32),
     ]
 
 
@@ -78,7 +84,7 @@ EXPORTS = [
     "bss_get_controls",
     "bss_set_controls", "bss_set_solve_index", "bss_get_solve_index", "bss_get_info",
     "bss_timing_enable", "bss_timing_read", "bss_set_lanes", "bss_destroy", "bss_last_error",
-    "bss_dev_philox", "bss_dev_normals", "bss_dev_disturbance", "bss_dev_model_step", "bss_dev_sdf", "bss_dev_score",
+    "bss_dev_philox", "bss_dev_normals", "bss_dev_disturbance", "bss_dev_model_step", "bss_dev_model_step8", "bss_dev_sdf", "bss_dev_score",
     "bss_dev_update_workspace", "bss_dev_update", "bss_dev_repair", "bss_set_shape",
     "bss_batch_create", "bss_batch_states", "bss_batch_set_states", "bss_batch_copy_states", "bss_batch_solve",
     "bss_batch_capture", "bss_batch_tune", "bss_batch_info", "bss_batch_destroy",
@@ -134,6 +140,7 @@ def _declare(lib):
         "bss_solve_noalloc": (i32, [P, u32, vp, vp, vp, vp, vp, vp]),
         "bss_noalloc_scratch_bytes": (C.c_size_t, [P]),
         "bss_dev_model_step": (i32, [P, vp, vp, vp, i64, vp]),
+        "bss_dev_model_step8": (i32, [P, vp, vp, vp, i64, vp]),
         "bss_dev_sdf": (i32, [d, d, vp, vp, i64, vp]),
         "bss_dev_score": (i32, [P, vp, vp, vp, vp, vp]),
         "bss_dev_update_workspace": (C.c_size_t, [i32, i32]),

@@ -138,6 +138,38 @@ CarF32 make_car(const bss_params& p)
     return c;
 }
 
+Car8F32 make_car8(const bss_params& p)
+{
+    Car8F32 c;
+    const int n = p.n_sub > 0 ? p.n_sub : 1;
+    const double L = p.lf + p.lr;
+    const double Fzf = p.m * p.g * p.lr / L, Fzr = p.m * p.g * p.lf / L;
+    c.h = (float)(p.dt / n);
+    c.half_h = (float)(0.5 * p.dt / n);
+    c.n_sub = n;
+    c.lf = (float)p.lf;
+    c.lr = (float)p.lr;
+    c.inv_m = (float)(1.0 / p.m);
+    c.inv_Iz = (float)(1.0 / p.Iz);
+    c.Rw = (float)p.Rw;
+    c.Rw_Iw = (float)(p.Rw / p.Iw);
+    c.Tmax_Iw = (float)(p.T_max / p.Iw);
+    c.muFzf = (float)(p.mu * Fzf);
+    c.muFzr = (float)(p.mu * Fzr);
+    const double ff = p.mu * p.pac_D * Fzf, fr = p.mu * p.pac_D * Fzr;
+    c.inv_fmaxf = ff > 0.0 ? (float)(1.0 / ff) : 0.0f;
+    c.inv_fmaxr = fr > 0.0 ? (float)(1.0 / fr) : 0.0f;
+    c.B = (float)p.pac_B;
+    c.C = (float)p.pac_C;
+    c.D = (float)p.pac_D;
+    c.E = (float)p.pac_E;
+    c.v_min = (float)p.v_min;
+    c.kappa0 = (float)(2.0 * M_PI / p.track_len);
+    c.kappa_amp = (float)p.kappa_amp;
+    c.s_rev = (float)(2.0 / p.track_len);
+    return c;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 InstanceDesc make_desc(const bss_params& p)
@@ -158,7 +190,9 @@ InstanceDesc make_desc(const bss_params& p)
     d.belief = p.belief;
     d.crn = p.crn;
     d.sig_w_speed = (float)p.sigma_w_speed;
+    d.vehicle = p.vehicle;
     d.car = make_car(p);
+    d.car8 = make_car8(p);
     d.sc = make_score(p);
     return d;
 }
@@ -260,7 +294,8 @@ hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
-    c->shape.split = c->shape.split && !launch_shield(c->p) && !launch_resample(c->p);
+    c->shape.split = c->shape.split && !launch_shield(c->p) && !launch_resample(c->p) &&
+                     c->p.vehicle == 0;
     c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
     // static leading fields only: the device state is left as it is
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
@@ -336,6 +371,18 @@ void bss_params_default(bss_params* p)
     p->n_con = 0;
     for (int i = 0; i < 6 * kMaxCon; ++i) p->con_a[i] = 0.0;
     for (int i = 0; i < kMaxCon; ++i) p->con_b[i] = 0.0;
+    // the 8-state vehicle's values (used with vehicle = 1 only)
+    p->vehicle = 0;
+    p->Rw = 0.095;
+    p->Iw = 0.3;
+    p->T_max = 8.0;
+    p->pac_B = 10.0;
+    p->pac_C = 1.9;
+    p->pac_D = 1.0;
+    p->pac_E = 0.97;
+    p->track_len = 120.0;
+    p->kappa_amp = 0.8;
+    p->n_sub = 4;
     p->lambda = 1.0;
     p->gamma_u = 1.0;
     p->v_goal = 6.0;
@@ -423,6 +470,27 @@ bss_status bss_validate(const bss_params* p)
         return fail(BSS_E_INVAL, "the repair of the update (local_repair) needs shield_iters >= 1");
     if (p->shield_iters > 0 && (!finite_pos(p->shield_fd) || !finite_nonneg(p->shield_gmin)))
         return fail(BSS_E_INVAL, "shield_fd must be > 0 and shield_gmin >= 0");
+    if (p->vehicle != 0 && p->vehicle != 1) return fail(BSS_E_INVAL, "vehicle must be 0 or 1");
+    if (p->vehicle == 1) {
+        if (!finite_pos(p->Rw) || !finite_pos(p->Iw) || !finite_nonneg(p->T_max))
+            return fail(BSS_E_INVAL, "vehicle 1: Rw, Iw must be > 0 and T_max >= 0");
+        if (!finite_pos(p->pac_B) || !finite_pos(p->pac_C) || !finite_pos(p->pac_D) ||
+            !std::isfinite(p->pac_E))
+            return fail(BSS_E_INVAL, "vehicle 1: magic-formula B, C, D must be > 0, E finite");
+        if (!(p->track_len > 0.0) || !(std::fabs(p->kappa_amp) < 1.0))
+            return fail(BSS_E_INVAL, "vehicle 1: track_len must be > 0 and |kappa_amp| < 1");
+        const double kmax = 2.0 * M_PI / p->track_len * (1.0 + std::fabs(p->kappa_amp));
+        if (!(2.0 * kmax * p->half_width < 1.0))
+            return fail(BSS_E_INVAL, "vehicle 1: the road frame needs 2 w_T max|kappa| < 1 "
+                                     "(got %g)", 2.0 * kmax * p->half_width);
+        if (p->n_sub < 1 || p->n_sub > 64)
+            return fail(BSS_E_INVAL, "vehicle 1: n_sub must be 1..64");
+        if (p->shield_iters != 0 || p->n_obs != 0 || p->n_con != 0 || p->belief != 0 ||
+            p->sigma_w_speed != 0.0 || p->local_repair != 0)
+            return fail(BSS_E_INVAL, "vehicle 1 supports neither the repair, obstacles, "
+                                     "half-space constraints, belief != 0, sigma_w_speed nor "
+                                     "local_repair");
+    }
     if (p->lanes != 0 && p->lanes != 8 && p->lanes != 16 && p->lanes != 32 && p->lanes != 64)
         return fail(BSS_E_INVAL, "lanes must be 0, 8, 16, 32 or 64");
     if (p->lanes != 0 && (p->M + p->lanes - 1) / p->lanes > 8)
@@ -635,9 +703,17 @@ static bss_status enqueue_solve(bss_ctx* c, const double* x0_dev, const double* 
         e = hipEventRecord(c->ev[c->ev_used], c->stream);
         if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     }
-    e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl, launch_shield(c->p),
-                     c->shape.split, launch_resample(c->p), c->p.n_con > 0, c->lds, x0_dev,
-                     Sigma0_dev, c->pending_shift, c->stream);
+    if (c->p.vehicle == 1) {
+        if (Sigma0_dev)
+            return fail(BSS_E_INVAL, "vehicle 1 takes a known estimate (Sigma0 must be NULL)");
+        e = launch_solve8(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl, c->lds, x0_dev,
+                          c->pending_shift, c->stream);
+    } else {
+        e = launch_solve(c->d_desc, c->d_blocks, c->desc.nblocks, c->shape.ppl,
+                         launch_shield(c->p), c->shape.split, launch_resample(c->p),
+                         c->p.n_con > 0, c->lds, x0_dev, Sigma0_dev, c->pending_shift,
+                         c->stream);
+    }
     if (e != hipSuccess) return device_fail(e, "solve launch");
     if (c->timing) {
         e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
@@ -688,8 +764,11 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
     bss_status st = check_free(c);
     if (st != BSS_OK) return st;
     if (!x0 || !u0_out) return fail(BSS_E_INVAL, "x0 and u0_out must not be NULL");
-    for (int i = 0; i < 6; ++i)
+    const int nx = c->p.vehicle == 1 ? 8 : 6;
+    for (int i = 0; i < nx; ++i)
         if (!std::isfinite(x0[i])) return fail(BSS_E_INVAL, "x0[%d] is not finite", i);
+    if (Sigma0 && c->p.vehicle == 1)
+        return fail(BSS_E_INVAL, "vehicle 1 takes a known estimate (Sigma0 must be NULL)");
     if (Sigma0) {
         for (int i = 0; i < 36; ++i)
             if (!std::isfinite(Sigma0[i])) return fail(BSS_E_INVAL, "Sigma0[%d] not finite", i);
@@ -697,10 +776,10 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
             if (Sigma0[i * 6 + i] < 0.0) return fail(BSS_E_INVAL, "Sigma0 has a negative variance");
     }
     // stage through pinned memory so the copies are truly asynchronous
-    std::memcpy(c->host + 16, x0, 6 * sizeof(double));
+    std::memcpy(c->host + 16, x0, nx * sizeof(double));
     if (Sigma0) std::memcpy(c->host + 24, Sigma0, 36 * sizeof(double));
-    hipError_t e = hipMemcpyAsync(c->x0, c->host + 16, 6 * sizeof(double), hipMemcpyHostToDevice,
-                                  c->stream);
+    hipError_t e = hipMemcpyAsync(c->x0, c->host + 16, nx * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && Sigma0)
         e = hipMemcpyAsync(c->Sigma0, c->host + 24, 36 * sizeof(double), hipMemcpyHostToDevice,
                            c->stream);
@@ -992,6 +1071,9 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return fail(BSS_E_INVAL, "context %d is NULL", i);
         if (ctxs[i]->batch) return fail(BSS_E_STATE, "context %d already belongs to a batch", i);
+        if (ctxs[i]->p.vehicle != 0)
+            return fail(BSS_E_INVAL, "context %d uses the 8-state vehicle, which batches do not "
+                                     "run", i);
         if (ctxs[i]->p.local_repair != 0)
             return fail(BSS_E_INVAL, "context %d repairs its update (local_repair), which runs per "
                         "context, not in batches", i);
@@ -1298,6 +1380,18 @@ bss_status bss_dev_model_step(const bss_params* p, const float* x, const float* 
     if (n < 0 || (n > 0 && (!x || !u || !xn))) return fail(BSS_E_INVAL, "bad arguments");
     hipError_t e = launch_model_step(make_car(*p), x, u, xn, n, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "model_step launch");
+    return BSS_OK;
+}
+
+bss_status bss_dev_model_step8(const bss_params* p, const float* x, const float* u, float* xn,
+                               int64_t n, void* stream)
+{
+    bss_status st = bss_validate(p);
+    if (st != BSS_OK) return st;
+    if (p->vehicle != 1) return fail(BSS_E_INVAL, "bss_dev_model_step8 needs vehicle = 1");
+    if (n < 0 || (n > 0 && (!x || !u || !xn))) return fail(BSS_E_INVAL, "bad arguments");
+    hipError_t e = launch_model_step8(make_car8(*p), x, u, xn, n, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "model_step8 launch");
     return BSS_OK;
 }
 

@@ -24,6 +24,7 @@ double backoff_of(const bss_params& p);
 
 ScoreF64 make_score(const bss_params& p);
 CarF32 make_car(const bss_params& p);
+Car8F32 make_car8(const bss_params& p);
 size_t align256(size_t x);
 
 // Descriptor of a parameter set: sizes, Philox key, model and score constants.  Launch shape,

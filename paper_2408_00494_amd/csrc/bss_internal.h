@@ -33,6 +33,21 @@ struct CarF32 {
     float v_min;
 };
 
+// Constants of the 8-state single-track vehicle with wheel speeds (vehicle = 1) in the form the
+// single-precision integrator uses (built on the host).
+struct Car8F32 {
+    float h, half_h;           // substep dt / n_sub and half of it
+    int32_t n_sub;             // midpoint substeps per control period
+    float lf, lr, inv_m, inv_Iz;
+    float Rw, Rw_Iw, Tmax_Iw;  // wheel radius, Rw / Iw, T_max / Iw
+    float muFzf, muFzr;        // mu times the static load of each axle
+    float inv_fmaxf, inv_fmaxr;  // 1 / (mu D Fz) per axle (friction-ellipse semi-axis)
+    float B, C, D, E;          // magic-formula coefficients
+    float v_min;               // floor of the slip denominators
+    float kappa0, kappa_amp;   // curvature (2 pi / L)(1 + a sin(...))
+    float s_rev;               // 2 / L: revolutions of sin(4 pi s / L) per metre
+};
+
 // The centerline ellipse in the form the signed distance uses (built on the host): semi-axes
 // ordered e0 >= e1 for the nearest-point solve, and the reciprocals it multiplies by.
 struct EllipseF64 {
@@ -106,7 +121,9 @@ struct InstanceDesc {
     float sig_eps0, sig_eps1;
     float sig_w0, sig_w1, sig_w2;
     float sig_w_speed;             // disturbance std factor 1 + sig_w_speed |vx|
+    int32_t vehicle;               // 0 the 6-state car, 1 the 8-state vehicle (car8, own kernel)
     CarF32 car;
+    Car8F32 car8;
     ScoreF64 sc;
     // buffers
     double* v[2];                  // ping-pong pair of mean sequences [T][2]
@@ -207,6 +224,14 @@ hipError_t launch_philox(uint32_t key0, uint32_t key1, const uint32_t* ctr, uint
                          int64_t n, hipStream_t stream);
 hipError_t launch_normals(uint32_t key0, uint32_t key1, const uint32_t* ctr, float* z, int64_t n,
                           hipStream_t stream);
+// Solve grid of 8-state instances (vehicle = 1; persistent particles, no repair); x0_base holds
+// 8 doubles per instance at x0_index.
+hipError_t launch_solve8(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
+                         size_t lds, const double* x0_base, int extra_shift, hipStream_t stream);
+// one noise-free single-precision period of the 8-state vehicle: x[n][8], u[n][2] -> xn[n][8]
+hipError_t launch_model_step8(const Car8F32& car, const float* x, const float* u, float* xn,
+                              int64_t n, hipStream_t stream);
+
 // disturbance words and normals of a solve through the solve kernel's path (lanes in {8, 16, 32,
 // 64}, ppl in {1, 2, 4, 8}, lanes * ppl >= M)
 hipError_t launch_disturbance(int lanes, int ppl, uint32_t key0, uint32_t key1, uint32_t s,

@@ -113,6 +113,8 @@ extern "C" bss_status bss_solve_noalloc(const bss_params* p, uint32_t solve_inde
         return fail(BSS_E_INVAL, "bss_solve_noalloc: x0, v_in, v_out and stats must not be NULL");
     if (v_in_dev == v_out_dev)
         return fail(BSS_E_INVAL, "bss_solve_noalloc: v_in and v_out must be distinct buffers");
+    if (p->vehicle == 1 && Sigma0_dev)
+        return fail(BSS_E_INVAL, "bss_solve_noalloc: vehicle 1 takes a known estimate");
     const LaunchShape sh = choose_shape(p->K, p->M, p->T, p->lanes, 0, -1, shape_for_shield(*p));
     const int nblocks = solve_blocks(p->K, sh.lanes);
     const ScratchLayout L = layout_of(*p, nblocks);
@@ -150,14 +152,17 @@ extern "C" bss_status bss_solve_noalloc(const bss_params* p, uint32_t solve_inde
     MergeDesc* d_cols = (MergeDesc*)(b + L.cols);
 
     const hipStream_t s = (hipStream_t)stream;
-    const bool split = sh.split && !launch_shield(*p) && !launch_resample(*p);
+    const bool split = sh.split && !launch_shield(*p) && !launch_resample(*p) &&
+                       p->vehicle == 0;
     const size_t lds = solve_lds_bytes(sh.lanes, p->T, sh.ppl, split);
     hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, s, d, d_desc, d_blocks, nblocks,
                        256 / sh.lanes, d_cols, 2 * p->T);
     e = hipGetLastError();
     if (e != hipSuccess) return device_fail(e, "bss_solve_noalloc: set-up launch");
-    e = launch_solve(d_desc, d_blocks, nblocks, sh.ppl, launch_shield(*p), split,
-                     launch_resample(*p), p->n_con > 0, lds, x0_dev, Sigma0_dev, 0, s);
+    e = p->vehicle == 1
+            ? launch_solve8(d_desc, d_blocks, nblocks, sh.ppl, lds, x0_dev, 0, s)
+            : launch_solve(d_desc, d_blocks, nblocks, sh.ppl, launch_shield(*p), split,
+                           launch_resample(*p), p->n_con > 0, lds, x0_dev, Sigma0_dev, 0, s);
     if (e != hipSuccess) return device_fail(e, "bss_solve_noalloc: solve launch");
     e = launch_merge(d_desc, d_cols, 2 * p->T, 0, s);
     if (e != hipSuccess) return device_fail(e, "bss_solve_noalloc: merge launch");

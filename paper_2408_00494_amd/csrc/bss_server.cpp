@@ -331,6 +331,9 @@ bss_status bss_server_create(const bss_server_config* cfg, const bss_params* veh
         if (q.local_repair != 0)
             return fail(BSS_E_INVAL, "vehicle %d: the repair of the update (local_repair) runs per "
                         "context, not in the server's batched launches", i);
+        if (q.vehicle != 0)
+            return fail(BSS_E_INVAL, "vehicle %d: the 8-state vehicle model (vehicle = 1) runs "
+                        "per context, not in the server's batched launches", i);
         max_con = std::max(max_con, (int)q.n_con);
     }
     // one request of K_max per stream must fit, with the variances of the most constrained vehicle
@@ -410,6 +413,9 @@ bss_status bss_server_submit(bss_server* s, int32_t vehicle, int32_t K, int32_t 
         return fail(BSS_E_INVAL, "vehicle %d out of range", vehicle);
     if (K < 1 || K > s->cfg.K_max) return fail(BSS_E_INVAL, "K=%d outside [1, K_max]", K);
     if (M < 1 || M > s->cfg.M_max) return fail(BSS_E_INVAL, "M=%d outside [1, M_max]", M);
+    if (s->veh[vehicle].p.belief == 2 && M != 12)
+        return fail(BSS_E_INVAL, "vehicle %d uses the sigma-point belief, which has M = 12 "
+                    "points (got M=%d)", vehicle, M);
     if (!(delta > 0.0 && delta < 0.5)) return fail(BSS_E_INVAL, "delta must be in (0, 0.5)");
     for (int i = 0; i < 6; ++i)
         if (!std::isfinite(x0[i])) return fail(BSS_E_INVAL, "x0[%d] is not finite", i);

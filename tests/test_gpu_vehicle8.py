@@ -1,0 +1,139 @@
+"""GPU-vs-oracle parity of the paper's 8-state vehicle (vehicle = 1: single-track model with wheel
+speeds, magic-formula tires and the friction ellipse, in the road-aligned frame).  Bars as for the
+6-state car: sampled controls within 1e-5 of full scale, belief records within 1e-3 of their
+trajectory scale, costs within 1e-3 relative, v+ within 1e-4 of full scale."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_00494_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_2408_00494_amd as bss  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def _errs(prob, got, ref):
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    span = np.max(np.abs(ref["mom"]), axis=1, keepdims=True)
+    return {"u": float(np.max(np.abs(got["u"] - ref["u"]) / scale)),
+            "mom": float(np.max(np.abs(got["mom"] - ref["mom"]) / np.where(span > 0, span, 1.0))),
+            "S": float(np.max(np.abs(got["S"] - ref["S"]) / np.abs(ref["S"]))),
+            "v": float(np.max(np.abs(got["v"] - ref["v"]) / scale))}
+
+
+def _run(prob, x0, v, s, lanes=0):
+    solver = bss.Solver(prob, lanes=lanes)
+    solver.set_controls(v)
+    solver.solve_index = s
+    u0, info = solver.solve(x0)
+    b = solver.buffers()
+    got = {"u": b["u"].cpu().numpy().astype(np.float64), "mom": b["mom"].cpu().numpy(),
+           "S": b["S"].cpu().numpy(), "v": solver.get_controls(), "u0": u0, "info": info}
+    solver.close()
+    return got
+
+
+def _compare(prob, x0, v, s=0, lanes=0):
+    got = _run(prob, x0, v, s, lanes)
+    ref = oracle.solve8(prob, s, x0, v, nthreads=NTHREADS)
+    e = _errs(prob, got, ref)
+    print(f"vehicle 8: K={prob['K']} M={prob['M']} T={prob['T']} shape "
+          f"{got['info']['lanes']}x{got['info']['ppl']} errs {e}", flush=True)
+    assert e["u"] <= 1e-5
+    assert e["mom"] <= 1e-3
+    assert e["S"] <= 1e-3
+    assert e["v"] <= 1e-4
+    assert np.array_equal(got["u0"], got["v"][0])
+    return got, ref
+
+
+def _warm(T):
+    t = np.arange(T)
+    return np.column_stack([0.05 * np.sin(0.3 * t), 0.3 + 0.2 * np.cos(0.2 * t)])
+
+
+def test_model_step8_matches_oracle():
+    """One noise-free period of the single-precision integrator against the oracle's double
+    precision from the same (single-precision) inputs."""
+    prob = W.vehicle8_problem()
+    rng = np.random.default_rng(11)
+    n = 4096
+    vX = rng.uniform(2.0, 8.0, n)
+    w = vX / prob["Rw"]
+    x = np.column_stack([vX, rng.normal(0, 0.3, n), rng.normal(0, 0.5, n),
+                         w * (1 + rng.normal(0, 0.03, n)), w * (1 + rng.normal(0, 0.03, n)),
+                         rng.normal(0, 0.15, n), rng.uniform(-1.8, 1.8, n),
+                         rng.uniform(0, prob["track_len"], n)])
+    u = np.column_stack([rng.uniform(-0.4, 0.4, n), rng.uniform(-1, 1, n)])
+    x32, u32 = x.astype(np.float32), u.astype(np.float32)
+    dev = lambda a: torch.as_tensor(a, device="cuda")  # noqa: E731
+    got = bss.dev_model_step8(prob, dev(x32), dev(u32)).cpu().numpy().astype(np.float64)
+    want = np.array([oracle.model_step8(prob, x32[i].astype(np.float64),
+                                        u32[i].astype(np.float64)) for i in range(n)])
+    step = np.abs(want - x32.astype(np.float64))
+    scale = np.array([8, 1, 1, 90, 90, 0.5, 2, 120])
+    rel = np.abs(got - want) / (scale * 1e-6 + 1e-4 * step)
+    print(f"model_step8: worst {float(np.max(rel)):.2f} of the bar "
+          f"(max abs error per state {np.max(np.abs(got - want), axis=0)})", flush=True)
+    assert np.all(rel <= 1.0)
+
+
+@pytest.mark.parametrize("K,M,T,lanes", [(256, 20, 20, 0), (200, 13, 15, 8), (64, 37, 12, 16),
+                                         (128, 8, 20, 32), (1, 5, 10, 0), (96, 64, 16, 16)])
+def test_vehicle8_solve_matches_oracle(K, M, T, lanes):
+    prob = W.vehicle8_problem(K=K, M=M, T=T, seed=21)
+    x0 = W.vehicle8_start(prob, np.random.default_rng(K + M))
+    _compare(prob, x0, _warm(T), s=3, lanes=lanes)
+
+
+def test_vehicle8_common_random_numbers_match_oracle():
+    prob = W.vehicle8_problem(K=128, M=16, T=20, seed=22, crn=1)
+    x0 = W.vehicle8_start(prob, np.random.default_rng(5))
+    _compare(prob, x0, _warm(20), s=1)
+
+
+def test_paper_size_vehicle8_solve_matches_oracle():
+    """The paper's largest BSS-MPPI setting of Table 1 (1000 samples x 20 particles, horizon 20)
+    on the 8-state vehicle, every sample compared."""
+    prob, x0, v = W.config_vehicle8()
+    got, ref = _compare(prob, x0, v, s=0)
+    assert got["info"]["ess"] > 2.0
+
+
+def test_vehicle8_receding_horizon_sequence_matches_oracle():
+    """Five control periods: solve, apply v+_0 to the oracle's noise-free model, shift."""
+    prob = W.vehicle8_problem(K=256, M=20, T=20, seed=23)
+    x = W.vehicle8_start(prob, np.random.default_rng(7))
+    solver = bss.Solver(prob)
+    v_ref = np.zeros((20, 2))
+    scale = np.array([prob["steer_max"], prob["accel_max"]])
+    for s in range(5):
+        u0, _ = solver.solve(x)
+        ref = oracle.solve8(prob, s, x, v_ref, want_traces=False, nthreads=NTHREADS)
+        v_gpu = solver.get_controls()
+        assert float(np.max(np.abs(v_gpu - ref["v"]) / scale)) <= 1e-4
+        v_ref = oracle.step_shift(v_gpu)
+        solver.step_shift()
+        x = oracle.model_step8(prob, x, u0)
+    solver.close()
+
+
+def test_vehicle8_rejections():
+    prob = W.vehicle8_problem(K=64, M=8, T=10)
+    x0 = W.vehicle8_start(prob, np.random.default_rng(1))
+    solver = bss.Solver(prob)
+    with pytest.raises(RuntimeError, match="known estimate"):
+        solver.solve(x0, Sigma0=np.eye(6) * 1e-3)
+    with pytest.raises(RuntimeError, match="8-state"):
+        bss.Batch([solver])
+    solver.close()
+    with pytest.raises(RuntimeError, match="vehicle 1"):
+        bss.Solver(dict(prob, shield_iters=2))
