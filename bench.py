@@ -102,6 +102,7 @@ def parse():
     ap.add_argument("--no-resampling", action="store_true")
     ap.add_argument("--no-constraints", action="store_true")
     ap.add_argument("--no-shielded", action="store_true")
+    ap.add_argument("--no-vehicle8", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving trace replayed with batching (0 skips serving)")
     ap.add_argument("--plain-seconds", type=float, default=15.0,
@@ -201,6 +202,22 @@ def _bench_variant(bss, torch, prob, x0, steps, warmup):
     s.close()
     return {"value": rs * steps / el, "unit": "rollout-steps/s", "ms_per_step": el * 1e3 / steps,
             "kernel_ms": kms / max(n, 1), "lanes": info["lanes"], "ppl": info["ppl"]}
+
+
+def bench_vehicle8(bss, W, torch, steps=20, warmup=3):
+    """The paper's 8-state vehicle (single-track model with wheel speeds, magic-formula tires and
+    the friction ellipse, four midpoint substeps per period): the paper's largest BSS-MPPI setting
+    of its Table 1 (1000 samples x 20 particles, horizon 20), and a larger one that fills the
+    chip (8192 x 64, horizon 20)."""
+    out = {}
+    for key, sizes in (("table1_size", dict(K=1000, M=20, T=20)),
+                       ("large", dict(K=8192, M=64, T=20))):
+        prob, x0, _ = W.config_vehicle8()
+        prob = dict(prob, **sizes)
+        out[key] = dict(_bench_variant(bss, torch, prob, x0, steps, warmup),
+                        workload=f"8-state vehicle, K={sizes['K']}, M={sizes['M']}, "
+                                 f"T={sizes['T']}")
+    return out
 
 
 def bench_shielded(bss, W, torch, steps=20, warmup=3):
@@ -447,6 +464,11 @@ def main():
     if not args.no_constraints:
         out["constraints"] = bench_constraints(bss, W, torch)
         progress(f"half-space constraints: {out['constraints']['value']:.3e} rollout-steps/s")
+    if not args.no_vehicle8:
+        out["vehicle8"] = bench_vehicle8(bss, W, torch)
+        progress(f"8-state vehicle: {out['vehicle8']['table1_size']['ms_per_step']:.3f} ms per "
+                 f"step at the paper's Table 1 size, {out['vehicle8']['large']['value']:.3e} "
+                 "rollout-steps/s large")
     if not args.no_shielded:
         out["shielded"] = bench_shielded(bss, W, torch)
         progress(f"shielded: {out['shielded']['shielded']['value']:.3e} rollout-steps/s, with "
