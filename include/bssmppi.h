@@ -162,8 +162,9 @@ typedef struct bss_allocator {
  *                               Sigma_XX, Sigma_XY, Sigma_YY; record 0 is the given estimate
  *   S      [K]          double  trajectory costs of the last solve
  *   stats  [8]          double  S_min, Z = sum_k w_k, ESS = Z^2/sum w^2, #finite costs,
- *                               status (0 ok, 5 numeric), v+_0 (steer, accel), unused
- *   x0     [6]          double  staging slot for the state estimate
+ *                               status (0 ok, 5 numeric), v+_0 (steer, accel), number of
+ *                               DCBF violations (as bss_info.dcbf_violations)
+ *   x0     [6]          double  staging slot for the state estimate ([8] for vehicle = 1)
  *   Sigma0 [36]         double  staging slot for the state-estimate covariance
  *   con_var [K][T+1][n_con] double  a_i^T Sigma a_i of the half-space constraints per record
  *                               (NULL when n_con = 0); record 0 holds a_i^T Sigma0 a_i     */
@@ -184,12 +185,19 @@ typedef struct bss_buffers {
 /* Optional per-solve copy to device memory (bss_set_outputs); the solve itself does not need it. */
 #define BSS_OUT_CONTROLS 1   /* sampled controls u [K][T][2] */
 
-/* Result summary of a solve (host). */
+/* Result summary of a solve (host): S_min = min_k S_k and Z = sum_k exp(-(S_k - S_min)/lambda)
+ * (eq. 7), ess = Z^2 / sum_k w_k^2, n_finite = samples with a finite cost;
+ * dcbf_violations = the solve's (sample, step) transitions whose belief violated the linear
+ * class-kappa condition h_{t+1} >= (1 - gamma) h_t (eq. 24, the ones C_safe penalises);
+ * kernel_ms = the rollout kernel's time of the last solve (HIP events) while timing is enabled
+ * (bss_timing_enable), else -1. */
 typedef struct bss_info {
     double S_min, Z, ess;
     int32_t n_finite;
     int32_t lanes, ppl;       /* launch shape used: lanes per sample, particles per lane */
     int32_t split;            /* 1 when the disturbance normals came from separate waves */
+    int32_t dcbf_violations;
+    float kernel_ms;
 } bss_info;
 
 typedef struct bss_ctx bss_ctx;

@@ -337,7 +337,8 @@ BssAllocator_release = _lib.BssAllocator._fields_[1][1]
 
 def _info_dict(info):
     return {"S_min": info.S_min, "Z": info.Z, "ess": info.ess, "n_finite": info.n_finite,
-            "lanes": info.lanes, "ppl": info.ppl, "split": bool(info.split)}
+            "lanes": info.lanes, "ppl": info.ppl, "split": bool(info.split),
+            "dcbf_violations": info.dcbf_violations, "kernel_ms": info.kernel_ms}
 
 
 # ---- stand-alone kernels (device tensors in/out, current stream) --------------------------------

@@ -74,7 +74,7 @@ class BssBuffers(C.Structure):
 class BssInfo(C.Structure):
     _fields_ = [("S_min", C.c_double), ("Z", C.c_double), ("ess", C.c_double),
                 ("n_finite", C.c_int32), ("lanes", C.c_int32), ("ppl", C.c_int32),
-                ("split", C.c_int32)]
+                ("split", C.c_int32), ("dcbf_violations", C.c_int32), ("kernel_ms", C.c_float)]
 
 
 # every exported symbol of include/bssmppi.h

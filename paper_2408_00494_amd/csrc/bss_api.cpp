@@ -541,20 +541,20 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     const size_t sz_cvar = align256(K * (T + 1) * (size_t)p->n_con * sizeof(double));
     const size_t sz_S = align256(K * sizeof(double));
     const size_t sz_stats = align256(8 * sizeof(double));
-    const size_t sz_part = align256(G * (2 * T + 4) * sizeof(double));
+    const size_t sz_part = align256(G * partial_stride(T) * sizeof(double));
     const size_t sz_x0 = 256;
     const size_t sz_sig = align256(36 * sizeof(double));
     const size_t sz_desc = align256(sizeof(InstanceDesc));
     const size_t sz_blk = align256(G * sizeof(BlockDesc));
     const size_t sz_col = align256(2 * T * sizeof(MergeDesc));
     // repair of the update: descriptor, grid, controls [T][2] f32, beliefs [T+1][9], constraint
-    // variances [T+1][n_con], cost, partial [2T+4], stats [8]
+    // variances [T+1][n_con], cost, partial [2T+5], stats [8]
     const size_t sz_rep = p->local_repair == 0
                               ? 0
                               : sz_desc + 256 + align256(T * 2 * sizeof(float)) +
                                     align256((T + 1) * 9 * sizeof(double)) +
                                     align256((T + 1) * (size_t)p->n_con * sizeof(double)) + 256 +
-                                    align256((2 * T + 4) * sizeof(double)) + sz_stats;
+                                    align256(partial_stride(T) * sizeof(double)) + sz_stats;
     const size_t total = 2 * sz_v + sz_u + sz_mom + sz_cvar + sz_S + sz_stats + sz_part + sz_x0 +
                          sz_sig + sz_desc + sz_blk + sz_col + sz_rep;
 
@@ -631,7 +631,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         r.S = (double*)b;
         b += 256;
         r.partial = (double*)b;
-        b += align256((2 * T + 4) * sizeof(double));
+        b += align256(partial_stride(T) * sizeof(double));
         r.stats = (double*)b;
         // a single sample is latency-bound: as many lanes as the particles can use (up to the
         // wave), so that each lane steps few particles, whatever the shape of the sampled solve
@@ -747,6 +747,14 @@ static void fill_info(const bss_ctx* c, const double* stats, bss_info* info)
     info->Z = stats[1];
     info->ess = stats[2];
     info->n_finite = (int32_t)stats[3];
+    info->dcbf_violations = (int32_t)stats[7];
+    // the rollout kernel's time of the last solve (the stream is synchronised by the callers)
+    info->kernel_ms = -1.0f;
+    if (c->timing && !c->batch && c->ev_used >= 2) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[c->ev_used - 2], c->ev[c->ev_used - 1]) == hipSuccess)
+            info->kernel_ms = ms;
+    }
     if (c->batch) {
         info->lanes = c->batch->lanes[c->batch_index];
         info->ppl = c->batch->ppl;
@@ -1423,7 +1431,7 @@ size_t bss_dev_update_workspace(int32_t K, int32_t T)
 {
     if (K < 1 || T < 1) return 0;
     return align256((size_t)T * 2 * sizeof(double)) +
-           (size_t)partial_blocks(K) * (2 * (size_t)T + 4) * sizeof(double);
+           (size_t)partial_blocks(K) * (size_t)partial_stride(T) * sizeof(double);
 }
 
 bss_status bss_dev_update(const bss_params* p, const double* S, const float* u, double* v,

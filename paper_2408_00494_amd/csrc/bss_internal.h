@@ -132,8 +132,9 @@ struct InstanceDesc {
     double* cvar;                  // [K][T+1][n_con] a_i^T Sigma a_i, or nullptr without
                                    // half-space constraints
     double* S;                     // [K] trajectory costs
-    double* partial;               // [nblocks][2T + 4] per-block log-sum-exp partials
-    double* stats;                 // [8]: S_min, Z, ESS, #finite, status, v+_0 (2), unused
+    double* partial;               // [nblocks][2T + 5] per-block log-sum-exp partials
+    double* stats;                 // [8]: S_min, Z, ESS, #finite, status, v+_0 (2),
+                                   //      DCBF violations
 };
 
 struct BlockDesc {
@@ -148,7 +149,11 @@ struct MergeDesc {
 
 // Per-block partial of the K-reduction (weights relative to the block's own minimum cost m_b):
 //   [0, 2T)  N_i = sum_k w_k (u_{k,i} - v_i),   [2T] Z_b = sum w_k,   [2T+1] sum w_k^2,
-//   [2T+2]   number of finite costs,            [2T+3] m_b (+inf if none is finite).
+//   [2T+2]   number of finite costs,            [2T+3] m_b (+inf if none is finite),
+//   [2T+4]   number of the block's (sample, step) transitions whose belief violated the DCBF
+//            condition h_{t+1} >= (1 - gamma) h_t.
+constexpr int kPartialTail = 5;
+__host__ __device__ inline int partial_stride(int T) { return 2 * T + kPartialTail; }
 
 // samples per block of the partial kernel used for stand-alone K-reductions
 constexpr int kPartialSlice = 16;

@@ -56,14 +56,15 @@ __device__ __forceinline__ double wave_reduce(double x, Op op)
 // exp(-(m_b - m)/lambda), fixed-order reductions of Z, sum w^2, #finite and the entry's numerator
 // (lane l takes blocks l, l + 64, ...); results in every lane.
 __device__ inline void merge_entry(const double* partial, int G, int T, int col, double lambda,
-                                   double& m, double& Z, double& W2, double& nf, double& N)
+                                   double& m, double& Z, double& W2, double& nf, double& N,
+                                   double& V)
 {
     const int lane = (int)(threadIdx.x & 63u);
-    const int stride = 2 * T + 4;
+    const int stride = partial_stride(T);
     // up to four blocks per lane are loaded in one pass (all loads in flight together); larger
     // grids fall back to a second pass over the remaining blocks
     constexpr int kHeld = 4;
-    double hm[kHeld], hz[kHeld], hw[kHeld], hn[kHeld], hc[kHeld];
+    double hm[kHeld], hz[kHeld], hw[kHeld], hn[kHeld], hc[kHeld], hv[kHeld];
 #pragma unroll
     for (int i = 0; i < kHeld; ++i) {
         const int b = lane + 64 * i;
@@ -73,6 +74,7 @@ __device__ inline void merge_entry(const double* partial, int G, int T, int col,
         hw[i] = b < G ? pb[2 * T + 1] : 0.0;
         hn[i] = b < G ? pb[2 * T + 2] : 0.0;
         hc[i] = b < G ? pb[col] : 0.0;
+        hv[i] = b < G ? pb[2 * T + 4] : 0.0;
     }
     m = INFINITY;
 #pragma unroll
@@ -84,6 +86,7 @@ __device__ inline void merge_entry(const double* partial, int G, int T, int col,
     W2 = 0.0;
     nf = 0.0;
     N = 0.0;
+    V = 0.0;
 #pragma unroll
     for (int i = 0; i < kHeld; ++i) {
         const double sc = isfinite(hm[i]) ? exp(-(hm[i] - m) / lambda) : 0.0;
@@ -91,6 +94,7 @@ __device__ inline void merge_entry(const double* partial, int G, int T, int col,
         W2 += sc * sc * hw[i];
         nf += hn[i];
         N += sc * hc[i];
+        V += hv[i];
     }
     for (int b = lane + 64 * kHeld; b < G; b += 64) {
         const double* pb = partial + (size_t)b * stride;
@@ -100,15 +104,17 @@ __device__ inline void merge_entry(const double* partial, int G, int T, int col,
         W2 += sc * sc * pb[2 * T + 1];
         nf += pb[2 * T + 2];
         N += sc * pb[col];
+        V += pb[2 * T + 4];
     }
     Z = wave_reduce(Z, AddOp());
     W2 = wave_reduce(W2, AddOp());
     nf = wave_reduce(nf, AddOp());
     N = wave_reduce(N, AddOp());
+    V = wave_reduce(V, AddOp());
 }
 
 __device__ inline void write_stats(double* stats, int col, double vo, bool ok, double m, double Z,
-                                   double W2, double nf)
+                                   double W2, double nf, double V)
 {
     if (col < 2) stats[5 + col] = vo;
     if (col == 0) {
@@ -117,7 +123,7 @@ __device__ inline void write_stats(double* stats, int col, double vo, bool ok, d
         stats[2] = ok ? Z * Z / W2 : 0.0;
         stats[3] = nf;
         stats[4] = ok ? 0.0 : 5.0;
-        stats[7] = 0.0;
+        stats[7] = V;
     }
 }
 
@@ -138,13 +144,13 @@ __global__ __launch_bounds__(256) void merge_kernel(InstanceDesc* insts, const M
     // the entry's current mean value is loaded before the reduction so the load overlaps it
     const int r = vrow(col >> 1, d.vshift + extra_shift, T);
     const double vi = d.v[cur][2 * r + (col & 1)];
-    double m, Z, W2, nf, N;
-    merge_entry(d.partial, d.nblocks, T, col, d.sc.lambda, m, Z, W2, nf, N);
+    double m, Z, W2, nf, N, V;
+    merge_entry(d.partial, d.nblocks, T, col, d.sc.lambda, m, Z, W2, nf, N, V);
     if ((threadIdx.x & 63u) == 0) {
         const bool ok = nf > 0.0 && Z > 0.0;
         const double vo = ok ? vi + N / Z : vi;
         d.v[1 - cur][col] = vo;
-        write_stats(d.stats, col, vo, ok, m, Z, W2, nf);
+        write_stats(d.stats, col, vo, ok, m, Z, W2, nf, V);
         const uint32_t prev = atomicAdd(&d.done, 1u);
         if (prev == (uint32_t)(2 * T - 1)) {
             // every entry of this instance is written: publish the new state
@@ -192,13 +198,13 @@ __global__ __launch_bounds__(256) void merge_plain_kernel(int T, int G, double l
 {
     const int col = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
     if (col >= 2 * T) return;
-    double m, Z, W2, nf, N;
-    merge_entry(partial, G, T, col, lambda, m, Z, W2, nf, N);
+    double m, Z, W2, nf, N, V;
+    merge_entry(partial, G, T, col, lambda, m, Z, W2, nf, N, V);
     if ((threadIdx.x & 63u) == 0) {
         const bool ok = nf > 0.0 && Z > 0.0;
         const double vo = ok ? v_in[col] + N / Z : v_in[col];
         v_out[col] = vo;
-        write_stats(stats, col, vo, ok, m, Z, W2, nf);
+        write_stats(stats, col, vo, ok, m, Z, W2, nf, V);
     }
 }
 
@@ -240,7 +246,8 @@ __global__ __launch_bounds__(256) void partial_kernel(int K, int T, double lambd
     const float2* uu = reinterpret_cast<const float2*>(u) + (size_t)k0 * T;
     for (int i = threadIdx.x; i < n * T; i += 256) u_sh[i] = uu[i];
     __syncthreads();
-    block_partial(T, n, S_sh, w_sh, u_sh, v, 0, lambda, partial + (size_t)blockIdx.x * (2 * T + 4));
+    block_partial(T, n, S_sh, w_sh, u_sh, v, 0, lambda, 0.0,
+                  partial + (size_t)blockIdx.x * partial_stride(T));
 }
 
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out,

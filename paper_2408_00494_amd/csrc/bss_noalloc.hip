@@ -82,7 +82,7 @@ ScratchLayout layout_of(const bss_params& p, int nblocks)
     L.S = o;
     o += align256(K * sizeof(double));
     L.partial = o;
-    o += align256((size_t)nblocks * (2 * T + 4) * sizeof(double));
+    o += align256((size_t)nblocks * partial_stride(T) * sizeof(double));
     L.total = o;
     return L;
 }

@@ -74,7 +74,7 @@ size_t scratch_bytes(int K, int T, int lanes)
     const size_t blocks = (size_t)solve_blocks(K, lanes);
     return align256((size_t)K * (T + 1) * 9 * sizeof(double)) +
            align256((size_t)K * sizeof(double)) +
-           align256(blocks * (2 * (size_t)T + 4) * sizeof(double));
+           align256(blocks * (size_t)partial_stride(T) * sizeof(double));
 }
 
 }  // namespace

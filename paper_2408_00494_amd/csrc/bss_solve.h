@@ -586,7 +586,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     // ---- phase 3: score the belief trajectory, L records at a time (one per lane) ----
     __threadfence_block();
     __syncthreads();
-    double S_part = 0.0;
+    double S_part = 0.0, V_part = 0.0;
     if (active && !producer) {
         double h_carry = 0.0;
         for (int base = 0; base <= T; base += L) {
@@ -594,18 +594,23 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
             const int rec = base + min(j, count - 1);
             S_part += score_chunk(d.sc, mom_k + (size_t)rec * 9, base + j, count, j, L, T, us, v,
                                   vshift, h_carry,
-                                  ncon > 0 ? cvar_k + (size_t)rec * ncon : nullptr);
+                                  ncon > 0 ? cvar_k + (size_t)rec * ncon : nullptr, &V_part);
         }
     }
     const double S_k = group_sum(S_part, L);
+    const double V_k = group_sum(V_part, L);
+    __shared__ double viol_sh[32];           // DCBF violations per group (at most 32 groups)
     if (j == 0 && !producer) {
         S_sh[g] = active ? S_k : INFINITY;
+        viol_sh[g] = active ? V_k : 0.0;
         if (active) d.S[k] = S_k;
     }
     __syncthreads();
     const int n = min(groups, d.K - bd.k0);
-    block_partial(T, n, S_sh, w_sh, u_sh, v, vshift, d.sc.lambda,
-                  d.partial + (size_t)(bd.k0 >> (8 - log2L)) * (2 * T + 4));
+    double nviol = 0.0;
+    for (int i = 0; i < n; ++i) nviol += viol_sh[i];
+    block_partial(T, n, S_sh, w_sh, u_sh, v, vshift, d.sc.lambda, nviol,
+                  d.partial + (size_t)(bd.k0 >> (8 - log2L)) * partial_stride(T));
 }
 
 // Solve grid: every block looks up its instance and first sample; the lane count is uniform over

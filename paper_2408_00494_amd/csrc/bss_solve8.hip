@@ -128,7 +128,7 @@ __device__ __forceinline__ double barrier8(const ScoreF64& sc, const double* rec
 // Score one chunk of 8-state records, one per lane of a W-lane group (as score_chunk).
 __device__ inline double score_chunk8(const ScoreF64& sc, const double* rec, int rec_idx,
                                       int count, int lane, int W, int T, const float2* u_row,
-                                      const double* v, int vshift, double& h_carry)
+                                      const double* v, int vshift, double& h_carry, double& viol)
 {
     const bool valid = lane < count;
     double part = 0.0, h = 0.0;
@@ -150,7 +150,11 @@ __device__ inline double score_chunk8(const ScoreF64& sc, const double* rec, int
     }
     const double h_left = __shfl(h, lane > 0 ? lane - 1 : 0, W);
     const double h_prev = lane == 0 ? h_carry : h_left;
-    if (valid && rec_idx >= 1) part += sc.C_cbf * fmax(-h + (1.0 - sc.gamma) * h_prev, 0.0);
+    if (valid && rec_idx >= 1) {
+        const double excess = -h + (1.0 - sc.gamma) * h_prev;
+        part += sc.C_cbf * fmax(excess, 0.0);
+        if (excess > 0.0) viol += 1.0;
+    }
     h_carry = __shfl(h, count - 1, W);
     return part;
 }
@@ -280,25 +284,30 @@ __device__ __forceinline__ void solve8_block(const InstanceDesc& d, const BlockD
     // score the belief trajectory, L records at a time
     __threadfence_block();
     __syncthreads();
-    double S_part = 0.0;
+    double S_part = 0.0, V_part = 0.0;
     if (active) {
         double h_carry = 0.0;
         for (int base = 0; base <= T; base += L) {
             const int count = min(L, T + 1 - base);
             const int rec = base + min(j, count - 1);
             S_part += score_chunk8(d.sc, mom_k + (size_t)rec * 9, base + j, count, j, L, T, us,
-                                   v, vshift, h_carry);
+                                   v, vshift, h_carry, V_part);
         }
     }
     const double S_k = group_sum(S_part, L);
+    const double V_k = group_sum(V_part, L);
+    __shared__ double viol_sh[32];           // DCBF violations per group (at most 32 groups)
     if (j == 0) {
         S_sh[g] = active ? S_k : INFINITY;
+        viol_sh[g] = active ? V_k : 0.0;
         if (active) d.S[k] = S_k;
     }
     __syncthreads();
     const int n = min(groups, d.K - bd.k0);
-    block_partial(T, n, S_sh, w_sh, u_sh, v, vshift, d.sc.lambda,
-                  d.partial + (size_t)(bd.k0 >> (8 - log2L)) * (2 * T + 4));
+    double nviol = 0.0;
+    for (int i = 0; i < n; ++i) nviol += viol_sh[i];
+    block_partial(T, n, S_sh, w_sh, u_sh, v, vshift, d.sc.lambda, nviol,
+                  d.partial + (size_t)(bd.k0 >> (8 - log2L)) * partial_stride(T));
 }
 
 template <int P>

@@ -176,9 +176,12 @@ __device__ __forceinline__ int vrow(int t, int vshift, int T)
 // into the record (record 0 has none).  `h_carry` holds h of the record before the chunk and is
 // advanced to the chunk's last record.  Returns this lane's contribution.
 // crec: the record's half-space constraint variances, or nullptr where the launch carries none.
+// viol (may be null) counts the transitions into this lane's record that violate the DCBF
+// condition h_t >= (1 - gamma) h_{t-1} (the ones C_safe penalises).
 __device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int rec_idx, int count,
                                      int lane, int W, int T, const float2* u_row, const double* v,
-                                     int vshift, double& h_carry, const double* crec = nullptr)
+                                     int vshift, double& h_carry, const double* crec = nullptr,
+                                     double* viol = nullptr)
 {
     const bool valid = lane < count;
     double part = 0.0;
@@ -201,16 +204,21 @@ __device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int 
     }
     const double h_left = __shfl(h, lane > 0 ? lane - 1 : 0, W);
     const double h_prev = lane == 0 ? h_carry : h_left;
-    if (valid && rec_idx >= 1) part += sc.C_cbf * fmax(-h + (1.0 - sc.gamma) * h_prev, 0.0);
+    if (valid && rec_idx >= 1) {
+        const double excess = -h + (1.0 - sc.gamma) * h_prev;
+        part += sc.C_cbf * fmax(excess, 0.0);
+        if (viol && excess > 0.0) *viol += 1.0;
+    }
     h_carry = __shfl(h, count - 1, W);
     return part;
 }
 
-// Fold n samples (costs S_sh[0..n), controls u_sh[g][T]) into one log-sum-exp partial.
+// Fold n samples (costs S_sh[0..n), controls u_sh[g][T]) into one log-sum-exp partial; nviol is
+// the block's count of DCBF violations.
 // Must be called by all 256 threads of the block after the inputs are visible in LDS.
 __device__ inline void block_partial(int T, int n, const double* S_sh, double* w_sh,
                                      const float2* u_sh, const double* v, int vshift,
-                                     double lambda, double* out)
+                                     double lambda, double nviol, double* out)
 {
     const int tid = threadIdx.x;
     double mb = INFINITY;
@@ -246,6 +254,7 @@ __device__ inline void block_partial(int T, int n, const double* S_sh, double* w
         out[2 * T + 1] = W2;
         out[2 * T + 2] = nf;
         out[2 * T + 3] = mb;
+        out[2 * T + 4] = nviol;
     }
 }
 

@@ -209,3 +209,34 @@ def test_noalloc_rejects_oversized_problems_before_any_device_call():
     assert 0 < lib.bss_noalloc_scratch_bytes(C.byref(small)) < (48 << 20)
     assert lib.bss_solve_noalloc(C.byref(small), 0, fake, None, fake, fake, fake, None) == 1
     assert "distinct" in lib.bss_last_error().decode()
+
+
+def test_create_reports_nomem_when_the_allocator_fails():
+    """An allocator that returns NULL makes bss_create fail with BSS_E_NOMEM before any device
+    call, leave *out NULL and release the host state (repeated failures do not grow the
+    process)."""
+    import resource
+    lib = _lib.lib()
+    calls = []
+
+    def alloc(nbytes, _user):
+        calls.append(int(nbytes))
+        return None
+
+    def release(ptr, _user):
+        calls.append(-1)
+
+    a_cb = _lib.BssAllocator._fields_[0][1](alloc)
+    r_cb = _lib.BssAllocator._fields_[1][1](release)
+    allocator = _lib.BssAllocator(a_cb, r_cb, None)
+    p = _lib.params_from_problem(W.config_small()[0])
+    ctx = C.c_void_p(1234)
+    assert lib.bss_create(C.byref(p), C.byref(allocator), None, C.byref(ctx)) == 2
+    assert ctx.value is None
+    assert "allocator returned NULL" in lib.bss_last_error().decode()
+    assert calls and calls[0] > 0 and -1 not in calls
+    rss0 = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss
+    for _ in range(20000):
+        assert lib.bss_create(C.byref(p), C.byref(allocator), None, C.byref(ctx)) == 2
+    rss1 = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss
+    assert rss1 - rss0 < 16 * 1024          # KiB: a leaked context per call would be ~MBs

@@ -673,3 +673,37 @@ def test_local_repair_with_initial_spread_matches_oracle(belief):
     e_stage = ctrl_err(v_safe, ref_safe, prob)
     print(f"local repair, Sigma0, belief {belief}: stage {e_stage:.2e}", flush=True)
     assert e_stage <= 1e-4
+
+
+def _violations(prob, mom, nu):
+    """DCBF violations of belief records [K][T+1][9]: transitions with
+    -h_t + (1 - gamma) h_{t-1} > 0 (eq. 24), h from the oracle's barrier."""
+    K, T1 = mom.shape[0], mom.shape[1]
+    h = np.array([[oracle.barrier(prob, nu, mom[k, t]) for t in range(T1)] for k in range(K)])
+    return int(np.sum(-h[:, 1:] + (1.0 - prob["gamma"]) * h[:, :-1] > 0.0))
+
+
+def test_info_counts_dcbf_violations_and_times_the_kernel():
+    """bss_info.dcbf_violations equals the count the oracle's barrier gives on the GPU's own belief
+    records (the same decision in double precision), and on the oracle's own records to within
+    the samples whose decision sits at the rounding level; kernel_ms is the timed launch."""
+    prob, x0, v = W.config_small()
+    prob = dict(prob, gamma=0.05, sigma_w=[0.4, 0.4, 0.2])
+    s = 5
+    solver = bss.Solver(prob)
+    solver.set_controls(v)
+    solver.solve_index = s
+    solver.timing(True)
+    _, info = solver.solve(x0)
+    mom = solver.buffers()["mom"].cpu().numpy()
+    solver.close()
+    nu = oracle.backoff(prob["delta"])
+    staged = _violations(prob, mom, nu)
+    ref = oracle.solve(prob, s, x0, v, nthreads=NTHREADS)
+    end = _violations(prob, ref["mom"], nu)
+    print(f"DCBF violations: GPU {info['dcbf_violations']}, oracle on the GPU's records {staged}, "
+          f"oracle {end}; kernel {info['kernel_ms']:.4f} ms", flush=True)
+    assert info["dcbf_violations"] > 0
+    assert info["dcbf_violations"] == staged
+    assert abs(end - staged) <= max(2, staged // 1000)
+    assert 0.0 < info["kernel_ms"] < 1000.0
