@@ -81,7 +81,7 @@ def ALG_BYTES_PER_SOLVE(K, M, T, lanes):
     phase (K (T+1) 9 doubles each way), costs, block partials, and the mean sequence read."""
     groups = 256 // lanes
     blocks = (K + groups - 1) // groups
-    return 2 * K * (T + 1) * 9 * 8 + K * 8 + blocks * (2 * T + 4) * 8 + T * 2 * 8
+    return 2 * K * (T + 1) * 9 * 8 + K * 8 + blocks * (2 * T + 5) * 8 + T * 2 * 8
 
 
 def progress(msg):
@@ -274,6 +274,22 @@ def bench_batched(bss, W, torch, rounds=20, warmup=3):
     batch = bss.Batch(solvers, ppl=0, shift_after=True)
     ppl = batch.tune()
     layout = batch.layout()
+    # the tuned layout's two solve grids side by side, eager launches: the persistent
+    # work-queue grid and one workgroup per block-table entry
+    grid_ms = {}
+    for persistent in (True, False):
+        batch.set_grid(persistent)
+        batch.set_states(x0s)
+        for _ in range(warmup):
+            batch.solve()
+        ev0.record(stream)
+        for _ in range(rounds):
+            batch.solve()
+        ev1.record(stream)
+        ev1.synchronize()
+        grid_ms["persistent" if persistent else "one_workgroup_per_block"] = \
+            ev0.elapsed_time(ev1) / rounds
+    batch.set_grid(layout["persistent"])
     batch.set_states(x0s)
     batch.capture()
     for _ in range(warmup):
@@ -315,7 +331,10 @@ def bench_batched(bss, W, torch, rounds=20, warmup=3):
             "rollout_steps_per_round": rs,
             "batched": {"value": rs / wall_b, "unit": "rollout-steps/s", "ms_per_round":
                         wall_b * 1e3, "gpu_ms_per_round": gpu_b * 1e3, "ppl": ppl,
-                        "solve_blocks": layout["nblocks"], "launch": "captured HIP graph"},
+                        "solve_blocks": layout["nblocks"], "noise_split": layout["split"],
+                        "persistent_grid": layout["persistent"],
+                        "launch": "captured HIP graph",
+                        "eager_gpu_ms_per_round_by_grid": grid_ms},
             "plain": {"value": rs / wall_p, "unit": "rollout-steps/s", "ms_per_round":
                       wall_p * 1e3, "gpu_ms_per_round": gpu_p * 1e3,
                       "launch": "two launches per instance, one stream"},

@@ -329,13 +329,26 @@ bss_status bss_batch_solve(bss_batch* b);
  * batch's stream must be a created stream (BSS_E_STATE on the null stream). */
 bss_status bss_batch_capture(bss_batch* b);
 
-/* Time each particles-per-lane candidate, with and without the noise split, on the batch (trial
- * solves whose state changes are undone) and keep the fastest layout; *ppl_out (may be NULL)
- * receives its particles per lane.  Call before bss_batch_capture. */
+/* Autotuner of the batch's launch: times every particles-per-lane candidate, with and without
+ * the noise split, each as a plain grid (one block per table entry) and as a persistent grid (as
+ * many blocks as are resident on the device, taking the block table's entries -- longest horizon
+ * first -- from a work-queue counter), on the batch itself (trial solves whose state changes,
+ * mean sequences and stats are undone; the members' cost and belief buffers hold a trial solve
+ * until the next one), and keeps the fastest layout.  The choice is cached for the process per
+ * batch signature (device, and each member's K, M, T and variant flags in order): a later batch
+ * of the same signature takes it without trial solves.  *ppl_out (may be NULL) receives the
+ * particles per lane.  Call before bss_batch_capture. */
 bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out);
 
-/* Number of solve blocks, particles per lane and noise split (0/1) of the batch's current layout
- * (any may be NULL). */
+/* Solve grid of the batch's rollout launch (the propagation of Alg. 2 for every member): 0 =
+ * one block per entry of the block table, 1 = persistent (as many blocks as are resident on the
+ * device, each taking the next entry, longest horizon first, from a work-queue counter that a
+ * kernel launched first resets).  Results are the same bit for bit.  Call before
+ * bss_batch_capture (BSS_E_STATE after).  bss_batch_tune chooses it by measurement. */
+bss_status bss_batch_set_grid(bss_batch* b, int32_t persistent);
+
+/* Number of solve blocks, particles per lane and grid flags of the batch's current layout (any
+ * may be NULL): *split bit 0 = noise split, bit 1 = persistent grid. */
 bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl, int32_t* split);
 
 /* Synchronise the batch's stream, hand each member its state back and free the batch (NULL is

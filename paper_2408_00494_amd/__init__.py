@@ -228,10 +228,15 @@ class Batch:
         check(_lib.lib().bss_batch_tune(self._b, C.byref(p)))
         return p.value
 
+    def set_grid(self, persistent: bool):
+        """Plain (False) or persistent work-queue (True) solve grid; before capture."""
+        check(_lib.lib().bss_batch_set_grid(self._b, 1 if persistent else 0))
+
     def layout(self):
         nb, p, sp = C.c_int32(), C.c_int32(), C.c_int32()
         check(_lib.lib().bss_batch_info(self._b, C.byref(nb), C.byref(p), C.byref(sp)))
-        return {"nblocks": nb.value, "ppl": p.value, "split": bool(sp.value)}
+        return {"nblocks": nb.value, "ppl": p.value, "split": bool(sp.value & 1),
+                "persistent": bool(sp.value & 2)}
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:

@@ -7,6 +7,8 @@
 #include <cstring>
 #include <algorithm>
 #include <cstddef>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -254,7 +256,9 @@ struct bss_batch {
     BlockDesc* d_blocks;
     MergeDesc* d_cols;
     double* d_x0;             // [n][6]
+    uint32_t* d_queue;        // work-queue counter of the persistent grid
     int nblocks, ncols, ppl, shift_after;
+    bool persistent;          // solve grid: resident blocks taking the block table from a queue
     bool split;               // 512-thread blocks with noise-producing waves
     bool resample;            // some member redraws its particles every step
     bool con;                 // some member has half-space constraints
@@ -1049,7 +1053,8 @@ static hipError_t batch_enqueue(bss_batch* b)
 {
     hipError_t e = launch_solve(b->d_desc, b->d_blocks, b->nblocks, b->ppl, b->shield,
                                 b->split, b->resample, b->con, b->lds,
-                                b->d_x0, nullptr, 0, b->stream);
+                                b->d_x0, nullptr, 0, b->stream,
+                                b->persistent ? b->d_queue : nullptr);
     if (e == hipSuccess) e = launch_merge(b->d_desc, b->d_cols, b->ncols, 0, b->stream);
     return e;
 }
@@ -1114,7 +1119,7 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     const size_t sz_desc = align256((size_t)n * sizeof(InstanceDesc));
     const size_t total = 2 * sz_desc + align256(nb * sizeof(BlockDesc)) +
                          align256(nc * sizeof(MergeDesc)) +
-                         align256((size_t)n * 6 * sizeof(double));
+                         align256((size_t)n * 6 * sizeof(double)) + 256;
     hipError_t e = hipMalloc(&b->block, total);
     if (e != hipSuccess) {
         b->block = nullptr;
@@ -1131,6 +1136,9 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     b->d_cols = (MergeDesc*)p;
     p += align256(nc * sizeof(MergeDesc));
     b->d_x0 = (double*)p;
+    p += align256((size_t)n * 6 * sizeof(double));
+    b->d_queue = (uint32_t*)p;
+    b->persistent = false;
 
     // the batch takes over each context's descriptor (device state included); pending host
     // shifts are folded into the device state
@@ -1231,34 +1239,73 @@ bss_status bss_batch_capture(bss_batch* b)
     return BSS_OK;
 }
 
+// Autotuning results per batch signature (the members' K, M, T and variant flags, in order) and
+// device, for the life of the process.
+struct TuneChoice {
+    int ppl, split;
+    bool persistent;
+    float ms;
+};
+
+static std::mutex g_tune_mutex;
+static std::map<std::string, TuneChoice> g_tune_cache;
+
+static std::string tune_key(const bss_batch* b)
+{
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::string key = "dev" + std::to_string(dev);
+    for (const bss_ctx* c : b->ctxs) {
+        const bss_params& p = c->p;
+        key += "|" + std::to_string(p.K) + "," + std::to_string(p.M) + "," + std::to_string(p.T) +
+               "," + std::to_string(launch_shield(p)) + std::to_string(launch_resample(p)) +
+               std::to_string(p.n_con > 0);
+    }
+    return key;
+}
+
 bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
 {
     if (!b) return fail(BSS_E_INVAL, "batch is NULL");
     if (b->captured) return fail(BSS_E_STATE, "tune before capturing the batch");
+    const std::string key = tune_key(b);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            b->persistent = it->second.persistent;
+            hipError_t e = batch_layout(b, it->second.ppl, it->second.split);
+            if (e != hipSuccess) return device_fail(e, "applying the cached batch layout");
+            if (ppl_out) *ppl_out = it->second.ppl;
+            return BSS_OK;
+        }
+    }
     int M_max = 0;
     for (bss_ctx* c : b->ctxs) M_max = std::max(M_max, c->p.M);
-    // the trial solves advance each member's state and overwrite both of its mean-sequence
-    // buffers: save the descriptors and the buffers, restore them afterwards
+    // the trial solves advance each member's state, overwrite both of its mean-sequence buffers
+    // and its stats: save the descriptors, the buffers and the stats, restore them afterwards
     size_t vbytes = 0;
-    for (bss_ctx* c : b->ctxs) vbytes += 2 * (size_t)c->p.T * 2 * sizeof(double);
+    for (bss_ctx* c : b->ctxs) vbytes += (2 * (size_t)c->p.T * 2 + 8) * sizeof(double);
     double* vsave = nullptr;
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hipMalloc(&vsave, vbytes);
     if (e != hipSuccess) return device_fail(e, "allocating the tuning backup");
-    auto copy_v = [&](bool save) {
+    auto copy_state = [&](bool save) {
         hipError_t r = hipSuccess;
         char* q = (char*)vsave;
         for (bss_ctx* c : b->ctxs) {
             const size_t nb = (size_t)c->p.T * 2 * sizeof(double);
-            for (int h = 0; h < 2 && r == hipSuccess; ++h) {
-                r = save ? hipMemcpy(q, c->desc.v[h], nb, hipMemcpyDeviceToDevice)
-                         : hipMemcpy(c->desc.v[h], q, nb, hipMemcpyDeviceToDevice);
-                q += nb;
+            double* bufs[3] = {c->desc.v[0], c->desc.v[1], c->desc.stats};
+            const size_t sizes[3] = {nb, nb, 8 * sizeof(double)};
+            for (int h = 0; h < 3 && r == hipSuccess; ++h) {
+                r = save ? hipMemcpy(q, bufs[h], sizes[h], hipMemcpyDeviceToDevice)
+                         : hipMemcpy(bufs[h], q, sizes[h], hipMemcpyDeviceToDevice);
+                q += sizes[h];
             }
         }
         return r;
     };
-    e = copy_v(true);
+    e = copy_state(true);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_backup, b->d_desc, (size_t)b->n * sizeof(InstanceDesc),
                       hipMemcpyDeviceToDevice);
@@ -1271,27 +1318,26 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
         (void)hipFree(vsave);
         return fail(BSS_E_DEVICE, "hipEventCreate");
     }
-    int best = b->ppl, best_split = b->split ? 1 : 0;
-    float best_ms = 1e30f;
+    // candidates: particles per lane x noise split x plain or persistent grid
+    TuneChoice best{b->ppl, b->split ? 1 : 0, false, 1e30f};
     const int cands[] = {1, 2, 4, 8};
     for (int cand : cands) {
         if ((M_max + cand - 1) / cand > 64) continue;
         for (int sp = 0; sp <= ((b->shield || b->resample) ? 0 : 1) && e == hipSuccess; ++sp) {
-            e = batch_layout(b, cand, sp);
-            if (e != hipSuccess) break;
-            if ((sp == 1) != b->split) continue;   // the split ring does not fit this batch
-            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
-            if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
-            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
-            if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(ev1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-            if (e != hipSuccess) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = cand;
-                best_split = sp;
+            for (int pers = 0; pers <= 1 && e == hipSuccess; ++pers) {
+                b->persistent = pers == 1;
+                e = batch_layout(b, cand, sp);
+                if (e != hipSuccess) break;
+                if ((sp == 1) != b->split) break;   // the split ring does not fit this batch
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+                if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
+                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+                if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+                if (e != hipSuccess) break;
+                if (ms < best.ms) best = TuneChoice{cand, sp, pers == 1, ms};
             }
         }
         if (e != hipSuccess) break;
@@ -1303,11 +1349,27 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
     if (e == hipSuccess)
         e = hipMemcpy(b->d_desc, b->d_backup, (size_t)b->n * sizeof(InstanceDesc),
                       hipMemcpyDeviceToDevice);
-    if (e == hipSuccess) e = copy_v(false);
+    if (e == hipSuccess) e = copy_state(false);
     (void)hipFree(vsave);
-    if (e == hipSuccess) e = batch_layout(b, best, best_split);
+    b->persistent = best.persistent;
+    if (e == hipSuccess) e = batch_layout(b, best.ppl, best.split);
     if (e != hipSuccess) return device_fail(e, "autotuning the batch");
-    if (ppl_out) *ppl_out = best;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        g_tune_cache[key] = best;
+    }
+    if (ppl_out) *ppl_out = best.ppl;
+    return BSS_OK;
+}
+
+bss_status bss_batch_set_grid(bss_batch* b, int32_t persistent)
+{
+    if (!b) return fail(BSS_E_INVAL, "batch is NULL");
+    if (persistent != 0 && persistent != 1) return fail(BSS_E_INVAL, "persistent must be 0 or 1");
+    if (b->captured) return fail(BSS_E_STATE, "set the grid before capturing the batch");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return device_fail(e, "synchronising");
+    b->persistent = persistent == 1;
     return BSS_OK;
 }
 
@@ -1316,7 +1378,7 @@ bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl, int32_t*
     if (!b) return fail(BSS_E_INVAL, "batch is NULL");
     if (nblocks) *nblocks = b->nblocks;
     if (ppl) *ppl = b->ppl;
-    if (split) *split = b->split ? 1 : 0;
+    if (split) *split = (b->split ? 1 : 0) | (b->persistent ? 2 : 0);
     return BSS_OK;
 }
 

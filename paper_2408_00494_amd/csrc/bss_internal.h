@@ -185,27 +185,30 @@ int solve_blocks(int K, int lanes);
 // repairs its samples), split (separate noise waves), resample (some instance redraws its
 // particles), con (some instance has half-space constraints: the variant with them compiled in;
 // with shield or resample that is the generic one, both of those switched at run time).
+// queue (may be null): a zero-initialised counter in device memory for a persistent grid (as
+// many blocks as are resident on the device take the block table's entries in order; the
+// counter is reset by a kernel launched first, so the pair can be captured in a graph).
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
                         bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,
-                        hipStream_t stream);
+                        hipStream_t stream, uint32_t* queue = nullptr);
 // the solve launch of one particles-per-lane count (each compiled in its own translation unit)
 hipError_t launch_solve_p1(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                            bool shield, bool split, bool resample, bool con, size_t lds,
                            const double* x0_base, const double* Sigma0_base, int extra_shift,
-                           hipStream_t stream);
+                           uint32_t* queue, hipStream_t stream);
 hipError_t launch_solve_p2(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                            bool shield, bool split, bool resample, bool con, size_t lds,
                            const double* x0_base, const double* Sigma0_base, int extra_shift,
-                           hipStream_t stream);
+                           uint32_t* queue, hipStream_t stream);
 hipError_t launch_solve_p4(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                            bool shield, bool split, bool resample, bool con, size_t lds,
                            const double* x0_base, const double* Sigma0_base, int extra_shift,
-                           hipStream_t stream);
+                           uint32_t* queue, hipStream_t stream);
 hipError_t launch_solve_p8(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                            bool shield, bool split, bool resample, bool con, size_t lds,
                            const double* x0_base, const double* Sigma0_base, int extra_shift,
-                           hipStream_t stream);
+                           uint32_t* queue, hipStream_t stream);
 hipError_t launch_merge(const InstanceDesc* inst, const MergeDesc* cols, int ncols,
                         int extra_shift, hipStream_t stream);
 // Repair of the updated sequence of one instance after its merge: `rep` is the instance's repair

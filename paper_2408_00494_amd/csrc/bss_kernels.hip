@@ -495,23 +495,23 @@ int solve_blocks(int K, int lanes)
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
                         bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,
-                        hipStream_t stream)
+                        hipStream_t stream, uint32_t* queue)
 {
     if (nblocks <= 0) return hipSuccess;
     split = split && !shield && !resample;
     switch (ppl) {
     case 1:
         return launch_solve_p1(inst, blocks, nblocks, shield, split, resample, con,
-                                    lds, x0_base, Sigma0_base, extra_shift, stream);
+                                    lds, x0_base, Sigma0_base, extra_shift, queue, stream);
     case 2:
         return launch_solve_p2(inst, blocks, nblocks, shield, split, resample, con,
-                                    lds, x0_base, Sigma0_base, extra_shift, stream);
+                                    lds, x0_base, Sigma0_base, extra_shift, queue, stream);
     case 4:
         return launch_solve_p4(inst, blocks, nblocks, shield, split, resample, con,
-                                    lds, x0_base, Sigma0_base, extra_shift, stream);
+                                    lds, x0_base, Sigma0_base, extra_shift, queue, stream);
     case 8:
         return launch_solve_p8(inst, blocks, nblocks, shield, split, resample, con,
-                                    lds, x0_base, Sigma0_base, extra_shift, stream);
+                                    lds, x0_base, Sigma0_base, extra_shift, queue, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -615,14 +615,13 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 
 // Solve grid: every block looks up its instance and first sample; the lane count is uniform over
 // a block, so the dispatch below is a block-uniform branch.
-template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false>
-__global__ __launch_bounds__(SPLIT ? 512 : 256)
-__attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE || CON) ? 2
-                                   : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
-    const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
-    const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON>
+__device__ __forceinline__ void solve_any_block(const InstanceDesc* __restrict__ insts,
+                                                const BlockDesc bd,
+                                                const double* __restrict__ x0_base,
+                                                const double* __restrict__ Sigma0_base,
+                                                int extra_shift)
 {
-    const BlockDesc bd = blocks[blockIdx.x];
     const InstanceDesc& d = insts[bd.inst];
     switch (d.lanes) {
     case 8:
@@ -639,38 +638,110 @@ __attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE || CON) ? 2
         break;
     }
 }
+
+// Solve grid: every block looks up its instance and first sample; the lane count is uniform over
+// a block, so the dispatch is a block-uniform branch.  With a work queue (queue non-null, zeroed
+// before the launch) the grid is persistent: each resident block takes the next entry of the
+// block table from the queue's counter until the table is exhausted, so a batch's blocks (ordered
+// longest horizon first) are dealt to whichever block finishes first.
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false>
+__global__ __launch_bounds__(SPLIT ? 512 : 256)
+__attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE || CON) ? 2
+                                   : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
+    const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
+    const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift,
+    uint32_t* queue, int nblocks)
+{
+    if (!queue) {
+        solve_any_block<P, SHIELD, SPLIT, RESAMPLE, CON>(insts, blocks[blockIdx.x], x0_base,
+                                                         Sigma0_base, extra_shift);
+        return;
+    }
+    __shared__ int next_block;
+    for (;;) {
+        if (threadIdx.x == 0) next_block = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int b = next_block;
+        if (b >= nblocks) break;   // block-uniform
+        solve_any_block<P, SHIELD, SPLIT, RESAMPLE, CON>(insts, blocks[b], x0_base, Sigma0_base,
+                                                         extra_shift);
+        __syncthreads();           // the next entry reuses the block's LDS and next_block
+    }
+}
+
+__global__ void queue_reset_kernel(uint32_t* queue)
+{
+    if (threadIdx.x == 0) *queue = 0u;
+}
+
+// Resident blocks of one solve-kernel variant on the whole device (the persistent grid).
+template <class Kernel>
+int resident_grid(Kernel k, int threads, size_t lds)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON>
+hipError_t launch_variant(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                          size_t lds, const double* x0_base, const double* Sigma0_base,
+                          int extra_shift, uint32_t* queue, hipStream_t stream)
+{
+    const int threads = SPLIT ? 512 : 256;
+    auto kern = solve_kernel<P, SHIELD, SPLIT, RESAMPLE, CON>;
+    int grid = nblocks;
+    if (queue) {
+        const int resident = resident_grid(kern, threads, lds);
+        if (resident <= 0) return hipErrorInvalidValue;
+        grid = resident < nblocks ? resident : nblocks;
+        hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, stream, queue);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, stream, inst, blocks, x0_base,
+                       Sigma0_base, extra_shift, queue, nblocks);
+    return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                           bool shield, bool split, bool resample, bool con, size_t lds,
                           const double* x0_base, const double* Sigma0_base, int extra_shift,
-                          hipStream_t stream)
+                          uint32_t* queue, hipStream_t stream)
 {
-    const dim3 g(nblocks), b256(256), b512(512);
     if (con && (shield || resample))
-        hipLaunchKernelGGL((solve_kernel<P, true, false, true, true>), g, b256, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else if (con && split)
-        hipLaunchKernelGGL((solve_kernel<P, false, true, false, true>), g, b512, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else if (con)
-        hipLaunchKernelGGL((solve_kernel<P, false, false, false, true>), g, b256, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else if (shield && resample)
-        hipLaunchKernelGGL((solve_kernel<P, true, false, true>), g, b256, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else if (shield)
-        hipLaunchKernelGGL((solve_kernel<P, true, false, false>), g, b256, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else if (resample)
-        hipLaunchKernelGGL((solve_kernel<P, false, false, true>), g, b256, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else if (split)
-        hipLaunchKernelGGL((solve_kernel<P, false, true, false>), g, b512, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    else
-        hipLaunchKernelGGL((solve_kernel<P, false, false, false>), g, b256, lds, stream, inst,
-                           blocks, x0_base, Sigma0_base, extra_shift);
-    return hipGetLastError();
+        return launch_variant<P, true, false, true, true>(inst, blocks, nblocks, lds, x0_base,
+                                                          Sigma0_base, extra_shift, queue, stream);
+    if (con && split)
+        return launch_variant<P, false, true, false, true>(inst, blocks, nblocks, lds, x0_base,
+                                                           Sigma0_base, extra_shift, queue,
+                                                           stream);
+    if (con)
+        return launch_variant<P, false, false, false, true>(inst, blocks, nblocks, lds, x0_base,
+                                                            Sigma0_base, extra_shift, queue,
+                                                            stream);
+    if (shield && resample)
+        return launch_variant<P, true, false, true, false>(inst, blocks, nblocks, lds, x0_base,
+                                                           Sigma0_base, extra_shift, queue,
+                                                           stream);
+    if (shield)
+        return launch_variant<P, true, false, false, false>(inst, blocks, nblocks, lds, x0_base,
+                                                            Sigma0_base, extra_shift, queue,
+                                                            stream);
+    if (resample)
+        return launch_variant<P, false, false, true, false>(inst, blocks, nblocks, lds, x0_base,
+                                                            Sigma0_base, extra_shift, queue,
+                                                            stream);
+    if (split)
+        return launch_variant<P, false, true, false, false>(inst, blocks, nblocks, lds, x0_base,
+                                                            Sigma0_base, extra_shift, queue,
+                                                            stream);
+    return launch_variant<P, false, false, false, false>(inst, blocks, nblocks, lds, x0_base,
+                                                         Sigma0_base, extra_shift, queue, stream);
 }
 
 }  // namespace

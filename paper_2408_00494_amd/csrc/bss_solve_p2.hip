@@ -6,10 +6,10 @@ namespace bss {
 hipError_t launch_solve_p2(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                           bool shield, bool split, bool resample, bool con, size_t lds,
                           const double* x0_base, const double* Sigma0_base, int extra_shift,
-                          hipStream_t stream)
+                          uint32_t* queue, hipStream_t stream)
 {
     return launch_solve_p<2>(inst, blocks, nblocks, shield, split, resample, con, lds, x0_base,
-                             Sigma0_base, extra_shift, stream);
+                             Sigma0_base, extra_shift, queue, stream);
 }
 
 }  // namespace bss

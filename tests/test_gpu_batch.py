@@ -189,3 +189,51 @@ def test_batch_ownership_rules():
         bss.Batch([s1], ppl=3)
     s1.close()
     s2.close()
+
+
+@pytest.mark.parametrize("ppl", [4, 8])
+def test_persistent_grid_equals_plain_grid(ppl):
+    """The persistent work-queue grid (resident blocks taking the block table's entries from a
+    counter) computes every member bit for bit as the plain grid does, eagerly and replayed from
+    a captured graph (the counter is reset by a kernel inside the graph), over several periods;
+    the tuner's choice is cached per batch signature."""
+    members = _mixed(12, seed=13, kmax=4096)
+    vs = _warm_starts(members, seed=17)
+    x0s = np.stack([x0 for _, x0, _ in members])
+    side = torch.cuda.Stream()
+    plain = _solvers(members, vs, stream=side)
+    pers = _solvers(members, vs, stream=side)
+    bp = bss.Batch(plain, ppl=ppl)
+    bq = bss.Batch(pers, ppl=ppl)
+    bq.set_grid(True)
+    assert bq.layout()["persistent"] and not bp.layout()["persistent"]
+    bp.set_states(x0s)
+    bq.set_states(x0s)
+    bq.capture()
+    for rep in range(3):
+        bp.solve()
+        bq.solve()
+        side.synchronize()
+        for i in range(len(members)):
+            assert np.array_equal(plain[i].get_controls(), pers[i].get_controls()), (rep, i)
+            assert np.array_equal(plain[i].buffers()["S"].cpu().numpy(),
+                                  pers[i].buffers()["S"].cpu().numpy()), (rep, i)
+    with pytest.raises(RuntimeError, match="capturing"):
+        bq.set_grid(False)
+    bp.close()
+    bq.close()
+    for s in plain + pers:
+        s.close()
+    # the tuner: the second batch of the same signature takes the cached layout
+    a = _solvers(members, vs)
+    ba = bss.Batch(a, ppl=0)
+    chosen = ba.tune()
+    first = ba.layout()
+    ba.close()
+    b = _solvers(members, vs)
+    bb = bss.Batch(b, ppl=0)
+    assert bb.tune() == chosen
+    assert bb.layout() == first
+    bb.close()
+    for s in a + b:
+        s.close()
