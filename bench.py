@@ -331,6 +331,8 @@ def bench_batched(bss, W, torch, rounds=20, warmup=3):
             "rollout_steps_per_round": rs,
             "batched": {"value": rs / wall_b, "unit": "rollout-steps/s", "ms_per_round":
                         wall_b * 1e3, "gpu_ms_per_round": gpu_b * 1e3, "ppl": ppl,
+                        "ppl_by_M": {str(p["M"]): P for (p, _, _), P in
+                                     zip(members, layout["member_ppl"])},
                         "solve_blocks": layout["nblocks"], "noise_split": layout["split"],
                         "persistent_grid": layout["persistent"],
                         "launch": "captured HIP graph",

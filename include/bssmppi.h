@@ -292,8 +292,8 @@ void bss_destroy(bss_ctx* c);
  *
  * A batch runs one solve of each of n contexts (each with its own K, M, T, costs, seed and warm
  * start, Alg. 1 per context) in two kernel launches: the rollout/scoring grid is the union of the
- * contexts' blocks (ordered longest horizon first) and the merge grid the union of their control
- * entries.  All per-solve state (mean-sequence buffer, pending shift, solve index) advances on the
+ * contexts' blocks (ordered by their work, longest first) and the merge grid the union of their
+ * control entries.  All per-solve state (mean-sequence buffer, pending shift, solve index) advances on the
  * device, so the two launches can be captured once in a HIP graph and replayed.  Each context of a
  * batch computes exactly what it computes alone with the same launch shape.  While a context
  * belongs to a batch, its own solve and state calls return BSS_E_STATE. */
@@ -301,7 +301,8 @@ typedef struct bss_batch bss_batch;
 
 /* Group n contexts (distinct, not in another batch, all on the current device) into a batch whose
  * work is enqueued on the stream of ctxs[0].  ppl: particles per lane used by every member (1, 2,
- * 4 or 8; 0 = automatic; bss_batch_tune measures the candidates).  shift_after = 1 leaves one
+ * 4 or 8; 0 = automatic; bss_batch_tune measures the candidates, bss_batch_set_member_ppl sets
+ * one per member).  shift_after = 1 leaves one
  * warm-start shift pending after each solve (the receding-horizon loop of a controller), 0 none.
  * The batch takes over each context's mean sequence, shift and solve index, and hands them back
  * in bss_batch_destroy.  Errors: BSS_E_INVAL, BSS_E_STATE, BSS_E_NOMEM, BSS_E_DEVICE. */
@@ -329,26 +330,46 @@ bss_status bss_batch_solve(bss_batch* b);
  * batch's stream must be a created stream (BSS_E_STATE on the null stream). */
 bss_status bss_batch_capture(bss_batch* b);
 
-/* Autotuner of the batch's launch: times every particles-per-lane candidate, with and without
- * the noise split, each as a plain grid (one block per table entry) and as a persistent grid (as
- * many blocks as are resident on the device, taking the block table's entries -- longest horizon
- * first -- from a work-queue counter), on the batch itself (trial solves whose state changes,
- * mean sequences and stats are undone; the members' cost and belief buffers hold a trial solve
- * until the next one), and keeps the fastest layout.  The choice is cached for the process per
- * batch signature (device, and each member's K, M, T and variant flags in order): a later batch
- * of the same signature takes it without trial solves.  *ppl_out (may be NULL) receives the
- * particles per lane.  Call before bss_batch_capture. */
+/* Autotuner of the batch's launch.  First one particles-per-lane count P for every member: each
+ * candidate with and without the noise split, each as a one-shot grid (one block per table entry)
+ * and as a persistent grid (as many blocks as are resident on the device, taking the block
+ * table's entries -- most work first -- from a work-queue counter).  Then, for batches whose
+ * members neither repair their samples, redraw their particles nor have half-space constraints,
+ * each member's own P in the same launch: members grouped by M, the groups in order of their
+ * work try every other P on top of the best common one, and a change is kept when the batch gets
+ * faster by more than 1 %.  Every candidate is timed on the batch itself (trial solves whose
+ * state changes, mean sequences and stats are undone; the members' cost and belief buffers hold
+ * a trial solve until the next one), and the fastest layout is kept.  The choice is cached for
+ * the process per batch signature (device, and each member's K, M, T and variant flags in order):
+ * a later batch of the same signature takes it without trial solves.  *ppl_out (may be NULL)
+ * receives the common P, or 0 when the members run their own (bss_batch_member_shape).  Call
+ * before bss_batch_capture. */
 bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out);
 
 /* Solve grid of the batch's rollout launch (the propagation of Alg. 2 for every member): 0 =
  * one block per entry of the block table, 1 = persistent (as many blocks as are resident on the
- * device, each taking the next entry, longest horizon first, from a work-queue counter that a
- * kernel launched first resets).  Results are the same bit for bit.  Call before
- * bss_batch_capture (BSS_E_STATE after).  bss_batch_tune chooses it by measurement. */
+ * device, each taking the next entry, most work first, from a work-queue counter that a kernel
+ * launched first resets).  Results are the same bit for bit.  The persistent grid is built for
+ * batches whose members neither repair their samples, redraw their particles nor have
+ * half-space constraints (BSS_E_INVAL otherwise).  Call before bss_batch_capture (BSS_E_STATE
+ * after).  bss_batch_tune chooses it by measurement. */
 bss_status bss_batch_set_grid(bss_batch* b, int32_t persistent);
 
-/* Number of solve blocks, particles per lane and grid flags of the batch's current layout (any
- * may be NULL): *split bit 0 = noise split, bit 1 = persistent grid. */
+/* Each member's own particles per lane, run in one launch: ppl[n], each 1, 2, 4 or 8 with
+ * ceil(M_i / ppl[i]) <= 64 (BSS_E_INVAL otherwise); the members' lanes per sample follow (the
+ * smallest power of two >= 8 holding M_i).  A member computes exactly what it computes alone with
+ * the same lanes and particles per lane.  For batches whose members neither repair their
+ * samples, redraw their particles nor have half-space constraints (BSS_E_INVAL otherwise).  Call
+ * before bss_batch_capture (BSS_E_STATE after). */
+bss_status bss_batch_set_member_ppl(bss_batch* b, const int32_t* ppl);
+
+/* Lanes per sample and particles per lane of member i (0 <= i < n) in the current layout (either
+ * may be NULL). */
+bss_status bss_batch_member_shape(const bss_batch* b, int32_t i, int32_t* lanes, int32_t* ppl);
+
+/* Number of solve blocks, particles per lane (0 when the members run their own) and grid flags of
+ * the batch's current layout (any may be NULL): *split bit 0 = noise split, bit 1 = persistent
+ * grid. */
 bss_status bss_batch_info(bss_batch* b, int32_t* nblocks, int32_t* ppl, int32_t* split);
 
 /* Synchronise the batch's stream, hand each member its state back and free the batch (NULL is

@@ -232,11 +232,25 @@ class Batch:
         """Plain (False) or persistent work-queue (True) solve grid; before capture."""
         check(_lib.lib().bss_batch_set_grid(self._b, 1 if persistent else 0))
 
+    def set_member_ppl(self, ppl):
+        """Each member's own particles per lane (1, 2, 4 or 8), in one launch; before capture."""
+        if len(ppl) != self.n:
+            raise ValueError(f"need {self.n} values, got {len(ppl)}")
+        arr = (C.c_int32 * self.n)(*[int(p) for p in ppl])
+        check(_lib.lib().bss_batch_set_member_ppl(self._b, arr))
+
+    def member_shape(self, i):
+        """(lanes per sample, particles per lane) of member i in the current layout."""
+        lanes, p = C.c_int32(), C.c_int32()
+        check(_lib.lib().bss_batch_member_shape(self._b, int(i), C.byref(lanes), C.byref(p)))
+        return lanes.value, p.value
+
     def layout(self):
         nb, p, sp = C.c_int32(), C.c_int32(), C.c_int32()
         check(_lib.lib().bss_batch_info(self._b, C.byref(nb), C.byref(p), C.byref(sp)))
         return {"nblocks": nb.value, "ppl": p.value, "split": bool(sp.value & 1),
-                "persistent": bool(sp.value & 2)}
+                "persistent": bool(sp.value & 2),
+                "member_ppl": [self.member_shape(i)[1] for i in range(self.n)]}
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:

@@ -88,7 +88,7 @@ EXPORTS = [
     "bss_dev_update_workspace", "bss_dev_update", "bss_dev_repair", "bss_set_shape",
     "bss_batch_create", "bss_batch_states", "bss_batch_set_states", "bss_batch_copy_states", "bss_batch_solve",
     "bss_batch_capture", "bss_batch_tune", "bss_batch_set_grid", "bss_batch_info",
-    "bss_batch_destroy",
+    "bss_batch_set_member_ppl", "bss_batch_member_shape", "bss_batch_destroy",
     "bss_server_config_default", "bss_server_create", "bss_server_submit", "bss_server_pump",
     "bss_server_poll", "bss_server_drain", "bss_server_get_controls", "bss_server_set_controls",
     "bss_server_vehicle_state", "bss_server_replay", "bss_server_destroy",
@@ -156,6 +156,8 @@ def _declare(lib):
         "bss_batch_capture": (i32, [vp]),
         "bss_batch_tune": (i32, [vp, C.POINTER(i32)]),
         "bss_batch_set_grid": (i32, [vp, i32]),
+        "bss_batch_set_member_ppl": (i32, [vp, C.POINTER(i32)]),
+        "bss_batch_member_shape": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "bss_batch_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "bss_batch_destroy": (None, [vp]),
         "bss_server_config_default": (None, [C.POINTER(BssServerConfig)]),

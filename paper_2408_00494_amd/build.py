@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbssmppi.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("bss_solve_p8.hip", "bss_solve_p4.hip", "bss_solve_p2.hip",
+           for f in ("bss_solve_pm.hip", "bss_solve_p8.hip", "bss_solve_p4.hip", "bss_solve_p2.hip",
                      "bss_solve_p1.hip", "bss_solve8.hip", "bss_kernels.hip", "bss_noalloc.hip",
                      "bss_api.cpp",
                      "bss_server.cpp")]

@@ -257,12 +257,15 @@ struct bss_batch {
     MergeDesc* d_cols;
     double* d_x0;             // [n][6]
     uint32_t* d_queue;        // work-queue counter of the persistent grid
-    int nblocks, ncols, ppl, shift_after;
+    int nblocks, ncols, shift_after;
+    int ppl;                  // particles per lane of every member, 0: each member's own
+    std::vector<int> member_ppl;  // each member's particles per lane when ppl == 0
     bool persistent;          // solve grid: resident blocks taking the block table from a queue
     bool split;               // 512-thread blocks with noise-producing waves
     bool resample;            // some member redraws its particles every step
     bool con;                 // some member has half-space constraints
     std::vector<int> lanes;   // lanes per sample of each member in the current layout
+    std::vector<int> ppls;    // particles per lane of each member in the current layout
     size_t lds;
     bool shield;
     hipGraph_t graph;
@@ -283,6 +286,7 @@ void fill_desc(bss_ctx* c)
 {
     c->desc = make_desc(c->p);
     c->desc.lanes = c->shape.lanes;
+    c->desc.ppl = c->shape.ppl;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
     if (!samples_shielded(c->p)) c->desc.sc.shield_iters = 0;
 }
@@ -297,6 +301,7 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
 hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
+    c->desc.ppl = c->shape.ppl;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
     c->shape.split = c->shape.split && !launch_shield(c->p) && !launch_resample(c->p) &&
                      c->p.vehicle == 0;
@@ -641,6 +646,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         // wave), so that each lane steps few particles, whatever the shape of the sampled solve
         c->rshape = choose_shape(1, p->M, p->T, 0, 1, 0, true);
         r.lanes = c->rshape.lanes;
+        r.ppl = c->rshape.ppl;
         c->rlds = solve_lds_bytes(r.lanes, p->T, c->rshape.ppl, false);
     }
 
@@ -761,7 +767,7 @@ static void fill_info(const bss_ctx* c, const double* stats, bss_info* info)
     }
     if (c->batch) {
         info->lanes = c->batch->lanes[c->batch_index];
-        info->ppl = c->batch->ppl;
+        info->ppl = c->batch->ppls[c->batch_index];
         info->split = c->batch->split ? 1 : 0;
     } else {
         info->lanes = c->shape.lanes;
@@ -1000,36 +1006,39 @@ void bss_destroy(bss_ctx* c)
 // ---- batches ---------------------------------------------------------------------------------
 static hipError_t batch_layout(bss_batch* b, int ppl, int split)
 {
-    // launch shape of every instance for a common particles-per-lane count, the solve grid with
-    // blocks ordered by horizon (longest first; with P fixed a block's work is proportional to T),
-    // and the merge grid
+    // launch shape of every instance for a common particles-per-lane count (ppl > 0) or for each
+    // member's own (ppl == 0, b->member_ppl), the solve grid with blocks ordered by their work
+    // (longest first: every thread of a block steps P particles for T steps), and the merge grid
     std::vector<BlockDesc> blocks;
     std::vector<MergeDesc> cols;
-    std::vector<int> lanes(b->n);
+    std::vector<int> lanes(b->n), ppls(b->n);
     size_t lds = 0;
     for (int i = 0; i < b->n; ++i) {
         const bss_params& p = b->ctxs[i]->p;
-        const LaunchShape sh = choose_shape(p.K, p.M, p.T, 0, ppl, 0);
+        ppls[i] = ppl != 0 ? ppl : b->member_ppl[i];
+        const LaunchShape sh = choose_shape(p.K, p.M, p.T, 0, ppls[i], 0);
         lanes[i] = sh.lanes;
         std::vector<BlockDesc> t = block_table(i, p.K, sh.lanes);
         blocks.insert(blocks.end(), t.begin(), t.end());
         for (int col = 0; col < 2 * p.T; ++col) cols.push_back(MergeDesc{i, col});
     }
     std::stable_sort(blocks.begin(), blocks.end(), [&](const BlockDesc& x, const BlockDesc& y) {
-        return b->ctxs[x.inst]->p.T > b->ctxs[y.inst]->p.T;
+        return (int64_t)b->ctxs[x.inst]->p.T * ppls[x.inst] >
+               (int64_t)b->ctxs[y.inst]->p.T * ppls[y.inst];
     });
     // split blocks (noise generated by a second set of waves) when asked, or automatically when
     // the whole grid has fewer than two waves per SIMD; every member's ring must fit
     bool sp = split > 0 || (split < 0 && (int64_t)blocks.size() * 4 < 2 * 1024);
     sp = sp && !b->shield && !b->resample;
     for (int i = 0; i < b->n && sp; ++i)
-        sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppl, true) <= kMaxLds;
+        sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], true) <= kMaxLds;
     for (int i = 0; i < b->n; ++i)
-        lds = std::max(lds, solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppl, sp));
+        lds = std::max(lds, solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], sp));
     hipError_t e = hipSuccess;
     for (int i = 0; i < b->n && e == hipSuccess; ++i) {
         InstanceDesc head = b->ctxs[i]->desc;
         head.lanes = lanes[i];
+        head.ppl = ppls[i];
         head.nblocks = solve_blocks(b->ctxs[i]->p.K, lanes[i]);
         head.x0_index = i;
         e = hipMemcpy(b->d_desc + i, &head, offsetof(InstanceDesc, cur), hipMemcpyHostToDevice);
@@ -1046,6 +1055,7 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
     b->ppl = ppl;
     b->split = sp;
     b->lanes = lanes;
+    b->ppls = ppls;
     return e;
 }
 
@@ -1165,6 +1175,7 @@ bss_status bss_batch_create(bss_ctx* const* ctxs, int32_t n, int32_t ppl, int32_
     }
     if (e == hipSuccess) e = hipMemset(b->d_x0, 0, (size_t)n * 6 * sizeof(double));
     const int ppl0 = ppl != 0 ? ppl : (M_max > 256 ? 8 : 4);
+    b->member_ppl.assign(n, ppl0);
     if (e == hipSuccess) e = batch_layout(b, ppl0, -1);
     if (e != hipSuccess) {
         batch_free(b);
@@ -1244,6 +1255,7 @@ bss_status bss_batch_capture(bss_batch* b)
 struct TuneChoice {
     int ppl, split;
     bool persistent;
+    std::vector<int> member_ppl;   // each member's P when ppl == 0
     float ms;
 };
 
@@ -1264,6 +1276,33 @@ static std::string tune_key(const bss_batch* b)
     return key;
 }
 
+static bool plain_batch(const bss_batch* b) { return !b->shield && !b->resample && !b->con; }
+
+// Lays the batch out (ppl 0: b->member_ppl) and times three solves after two warm-up solves;
+// *applied is false when the layout could not take the requested noise split.
+static hipError_t time_layout(bss_batch* b, int ppl, int split, bool persistent, hipEvent_t ev0,
+                              hipEvent_t ev1, float* ms, bool* applied)
+{
+    b->persistent = persistent;
+    hipError_t e = batch_layout(b, ppl, split);
+    *applied = e == hipSuccess && (split == 1) == b->split;
+    if (!*applied) return e;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+    if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
+    if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev0, ev1);
+    return e;
+}
+
+static hipError_t apply_choice(bss_batch* b, const TuneChoice& t)
+{
+    b->persistent = t.persistent;
+    if (t.ppl == 0) b->member_ppl = t.member_ppl;
+    return batch_layout(b, t.ppl, t.split);
+}
+
 bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
 {
     if (!b) return fail(BSS_E_INVAL, "batch is NULL");
@@ -1273,8 +1312,7 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
         std::lock_guard<std::mutex> lock(g_tune_mutex);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            b->persistent = it->second.persistent;
-            hipError_t e = batch_layout(b, it->second.ppl, it->second.split);
+            hipError_t e = apply_choice(b, it->second);
             if (e != hipSuccess) return device_fail(e, "applying the cached batch layout");
             if (ppl_out) *ppl_out = it->second.ppl;
             return BSS_OK;
@@ -1318,29 +1356,66 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
         (void)hipFree(vsave);
         return fail(BSS_E_DEVICE, "hipEventCreate");
     }
-    // candidates: particles per lane x noise split x plain or persistent grid
-    TuneChoice best{b->ppl, b->split ? 1 : 0, false, 1e30f};
+    const bool plain = plain_batch(b);
     const int cands[] = {1, 2, 4, 8};
+    // 1. one P for every member: P x noise split x one-shot or persistent grid (the persistent
+    //    grid and the per-member P exist for plain batches only)
+    TuneChoice best{b->ppl, b->split ? 1 : 0, false, b->member_ppl, 1e30f};
     for (int cand : cands) {
         if ((M_max + cand - 1) / cand > 64) continue;
-        for (int sp = 0; sp <= ((b->shield || b->resample) ? 0 : 1) && e == hipSuccess; ++sp) {
-            for (int pers = 0; pers <= 1 && e == hipSuccess; ++pers) {
-                b->persistent = pers == 1;
-                e = batch_layout(b, cand, sp);
-                if (e != hipSuccess) break;
-                if ((sp == 1) != b->split) break;   // the split ring does not fit this batch
-                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_enqueue(b);
-                if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
-                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_enqueue(b);
-                if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        for (int sp = 0; sp <= (plain ? 1 : 0) && e == hipSuccess; ++sp) {
+            bool applied = true;
+            for (int pers = 0; pers <= (plain ? 1 : 0) && e == hipSuccess && applied; ++pers) {
                 float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-                if (e != hipSuccess) break;
-                if (ms < best.ms) best = TuneChoice{cand, sp, pers == 1, ms};
+                e = time_layout(b, cand, sp, pers == 1, ev0, ev1, &ms, &applied);
+                if (e == hipSuccess && applied && ms < best.ms)
+                    best = TuneChoice{cand, sp, pers == 1, {}, ms};
             }
+            if (!applied) break;   // the split ring does not fit this batch
         }
         if (e != hipSuccess) break;
+    }
+    // 2. each member's own P in one launch: members grouped by M (which sets how many of a
+    //    layout's particle slots are used); starting from the best common P, the groups in order
+    //    of their work try every other P, and a change is kept when the whole batch gets faster
+    //    by more than 1 %
+    if (plain && e == hipSuccess && best.ppl != 0) {
+        std::vector<int> mp(b->n, best.ppl);
+        b->member_ppl = mp;
+        float cur = 0.0f;
+        bool applied = false;
+        e = time_layout(b, 0, best.split, best.persistent, ev0, ev1, &cur, &applied);
+        if (e == hipSuccess && applied) {
+            std::map<int, double> work;
+            for (bss_ctx* c : b->ctxs) work[c->p.M] += (double)c->p.K * c->p.M * c->p.T;
+            std::vector<std::pair<double, int>> order;
+            for (const auto& kv : work) order.push_back({kv.second, kv.first});
+            std::sort(order.rbegin(), order.rend());
+            for (const auto& grp : order) {
+                const int M = grp.second;
+                int now = best.ppl;
+                for (int i = 0; i < b->n; ++i)
+                    if (b->ctxs[i]->p.M == M) now = mp[i];
+                for (int cand : cands) {
+                    if (cand == now || (M + cand - 1) / cand > 64) continue;
+                    std::vector<int> trial = mp;
+                    for (int i = 0; i < b->n; ++i)
+                        if (b->ctxs[i]->p.M == M) trial[i] = cand;
+                    b->member_ppl = trial;
+                    float ms = 0.0f;
+                    e = time_layout(b, 0, best.split, best.persistent, ev0, ev1, &ms, &applied);
+                    if (e != hipSuccess) break;
+                    if (applied && ms < 0.99f * cur) {
+                        mp = trial;
+                        cur = ms;
+                        now = cand;
+                    }
+                }
+                if (e != hipSuccess) break;
+            }
+            if (e == hipSuccess && cur < best.ms)
+                best = TuneChoice{0, best.split, best.persistent, mp, cur};
+        }
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
@@ -1351,8 +1426,7 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
                       hipMemcpyDeviceToDevice);
     if (e == hipSuccess) e = copy_state(false);
     (void)hipFree(vsave);
-    b->persistent = best.persistent;
-    if (e == hipSuccess) e = batch_layout(b, best.ppl, best.split);
+    if (e == hipSuccess) e = apply_choice(b, best);
     if (e != hipSuccess) return device_fail(e, "autotuning the batch");
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -1362,11 +1436,50 @@ bss_status bss_batch_tune(bss_batch* b, int32_t* ppl_out)
     return BSS_OK;
 }
 
+bss_status bss_batch_set_member_ppl(bss_batch* b, const int32_t* ppl)
+{
+    if (!b || !ppl) return fail(BSS_E_INVAL, "batch and ppl must not be NULL");
+    if (b->captured) return fail(BSS_E_STATE, "set the particles per lane before capturing");
+    if (!plain_batch(b))
+        return fail(BSS_E_INVAL, "per-member particles per lane: batches whose members neither "
+                                 "repair their samples, redraw their particles nor have "
+                                 "half-space constraints");
+    std::vector<int> mp(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        const int P = ppl[i], M = b->ctxs[i]->p.M;
+        if (P != 1 && P != 2 && P != 4 && P != 8)
+            return fail(BSS_E_INVAL, "member %d: particles per lane must be 1, 2, 4 or 8", i);
+        if ((M + P - 1) / P > 64)
+            return fail(BSS_E_INVAL, "member %d: M=%d needs more than 64 lanes with %d particles "
+                        "per lane", i, M, P);
+        mp[i] = P;
+    }
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return device_fail(e, "synchronising");
+    b->member_ppl = mp;
+    e = batch_layout(b, 0, b->split ? 1 : 0);
+    if (e != hipSuccess) return device_fail(e, "laying out the batch");
+    return BSS_OK;
+}
+
+bss_status bss_batch_member_shape(const bss_batch* b, int32_t i, int32_t* lanes, int32_t* ppl)
+{
+    if (!b) return fail(BSS_E_INVAL, "batch is NULL");
+    if (i < 0 || i >= b->n) return fail(BSS_E_INVAL, "member %d of %d", i, b->n);
+    if (lanes) *lanes = b->lanes[i];
+    if (ppl) *ppl = b->ppls[i];
+    return BSS_OK;
+}
+
 bss_status bss_batch_set_grid(bss_batch* b, int32_t persistent)
 {
     if (!b) return fail(BSS_E_INVAL, "batch is NULL");
     if (persistent != 0 && persistent != 1) return fail(BSS_E_INVAL, "persistent must be 0 or 1");
     if (b->captured) return fail(BSS_E_STATE, "set the grid before capturing the batch");
+    if (persistent == 1 && !plain_batch(b))
+        return fail(BSS_E_INVAL, "the persistent grid runs batches whose members neither repair "
+                                 "their samples, redraw their particles nor have half-space "
+                                 "constraints");
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return device_fail(e, "synchronising");
     b->persistent = persistent == 1;

@@ -102,8 +102,9 @@ struct ScoreF64 {
 
 // One problem instance (device memory).
 struct InstanceDesc {
-    // sizes and launch shape (P, particles per lane, is the kernel's template parameter)
-    int32_t K, M, T, lanes;
+    // sizes and launch shape: lanes per sample and P, particles per lane (the kernel's template
+    // parameter, except in the per-instance variant, which dispatches on this field)
+    int32_t K, M, T, lanes, ppl;
     int32_t nblocks;               // solve blocks of this instance (= number of partials)
     int32_t x0_index;              // state estimate at x0_base + 6 x0_index (launch argument)
     // per-solve state, advanced on the device by the last merge block of the instance
@@ -185,9 +186,12 @@ int solve_blocks(int K, int lanes);
 // repairs its samples), split (separate noise waves), resample (some instance redraws its
 // particles), con (some instance has half-space constraints: the variant with them compiled in;
 // with shield or resample that is the generic one, both of those switched at run time).
+// ppl: particles per lane of every instance, or 0 to take each instance's from its descriptor
+// (plain and split variants only).
 // queue (may be null): a zero-initialised counter in device memory for a persistent grid (as
 // many blocks as are resident on the device take the block table's entries in order; the
-// counter is reset by a kernel launched first, so the pair can be captured in a graph).
+// counter is reset by a kernel launched first, so the pair can be captured in a graph); plain
+// and split variants only.
 hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks, int ppl,
                         bool shield, bool split, bool resample, bool con, size_t lds,
                         const double* x0_base, const double* Sigma0_base, int extra_shift,
@@ -206,6 +210,11 @@ hipError_t launch_solve_p4(const InstanceDesc* inst, const BlockDesc* blocks, in
                            const double* x0_base, const double* Sigma0_base, int extra_shift,
                            uint32_t* queue, hipStream_t stream);
 hipError_t launch_solve_p8(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
+                           bool shield, bool split, bool resample, bool con, size_t lds,
+                           const double* x0_base, const double* Sigma0_base, int extra_shift,
+                           uint32_t* queue, hipStream_t stream);
+// P taken per instance from InstanceDesc::ppl (plain and split variants only)
+hipError_t launch_solve_pm(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                            bool shield, bool split, bool resample, bool con, size_t lds,
                            const double* x0_base, const double* Sigma0_base, int extra_shift,
                            uint32_t* queue, hipStream_t stream);

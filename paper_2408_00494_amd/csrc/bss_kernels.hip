@@ -500,6 +500,9 @@ hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int n
     if (nblocks <= 0) return hipSuccess;
     split = split && !shield && !resample;
     switch (ppl) {
+    case 0:
+        return launch_solve_pm(inst, blocks, nblocks, shield, split, resample, con,
+                               lds, x0_base, Sigma0_base, extra_shift, queue, stream);
     case 1:
         return launch_solve_p1(inst, blocks, nblocks, shield, split, resample, con,
                                     lds, x0_base, Sigma0_base, extra_shift, queue, stream);

@@ -130,6 +130,7 @@ extern "C" bss_status bss_solve_noalloc(const bss_params* p, uint32_t solve_inde
 
     InstanceDesc d = make_desc(*p);
     d.lanes = sh.lanes;
+    d.ppl = sh.ppl;
     d.nblocks = nblocks;
     if (!samples_shielded(*p)) d.sc.shield_iters = 0;
     d.x0_index = 0;

@@ -189,6 +189,7 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         d.K = r.K;
         d.M = r.M;
         d.lanes = sh.lanes;
+        d.ppl = s->ppl;
         d.nblocks = nb;
         d.x0_index = i;
         d.cur = v.cur;

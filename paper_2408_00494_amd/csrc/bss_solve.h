@@ -613,16 +613,14 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                   d.partial + (size_t)(bd.k0 >> (8 - log2L)) * partial_stride(T));
 }
 
-// Solve grid: every block looks up its instance and first sample; the lane count is uniform over
-// a block, so the dispatch below is a block-uniform branch.
+// One block of instance d with its lane count L taken from the descriptor (uniform over a block,
+// so the dispatch is a block-uniform branch).
 template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON>
-__device__ __forceinline__ void solve_any_block(const InstanceDesc* __restrict__ insts,
-                                                const BlockDesc bd,
-                                                const double* __restrict__ x0_base,
-                                                const double* __restrict__ Sigma0_base,
-                                                int extra_shift)
+__device__ __forceinline__ void solve_lanes_block(const InstanceDesc& d, const BlockDesc bd,
+                                                  const double* __restrict__ x0_base,
+                                                  const double* __restrict__ Sigma0_base,
+                                                  int extra_shift)
 {
-    const InstanceDesc& d = insts[bd.inst];
     switch (d.lanes) {
     case 8:
         solve_block<P, SHIELD, 8, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base, extra_shift);
@@ -639,33 +637,82 @@ __device__ __forceinline__ void solve_any_block(const InstanceDesc* __restrict__
     }
 }
 
+// One block of the solve grid: the block looks up its instance and first sample.  P = 0 takes
+// the particles per lane from the instance as well (a batch whose members run different P in one
+// launch); the kernel's registers are then those of its largest P.
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON>
+__device__ __forceinline__ void solve_any_block(const InstanceDesc* __restrict__ insts,
+                                                const BlockDesc bd,
+                                                const double* __restrict__ x0_base,
+                                                const double* __restrict__ Sigma0_base,
+                                                int extra_shift)
+{
+    const InstanceDesc& d = insts[bd.inst];
+    if constexpr (P == 0) {
+        switch (d.ppl) {
+        case 1:
+            solve_lanes_block<1, SHIELD, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base,
+                                                               extra_shift);
+            break;
+        case 2:
+            solve_lanes_block<2, SHIELD, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base,
+                                                               extra_shift);
+            break;
+        case 4:
+            solve_lanes_block<4, SHIELD, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base,
+                                                               extra_shift);
+            break;
+        default:
+            solve_lanes_block<8, SHIELD, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base,
+                                                               extra_shift);
+            break;
+        }
+    } else {
+        solve_lanes_block<P, SHIELD, SPLIT, RESAMPLE, CON>(d, bd, x0_base, Sigma0_base,
+                                                           extra_shift);
+    }
+}
+
+// The block body as a call of its own, for the persistent loop: inlined into the loop, the body
+// takes more registers than the one-shot kernel and spills; out of line it keeps its own
+// allocation, at the price of saving and restoring the callee-saved registers once per entry.
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON>
+__device__ __attribute__((noinline)) void solve_any_block_call(
+    const InstanceDesc* __restrict__ insts, const BlockDesc bd,
+    const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift)
+{
+    solve_any_block<P, SHIELD, SPLIT, RESAMPLE, CON>(insts, bd, x0_base, Sigma0_base,
+                                                     extra_shift);
+}
+
 // Solve grid: every block looks up its instance and first sample; the lane count is uniform over
-// a block, so the dispatch is a block-uniform branch.  With a work queue (queue non-null, zeroed
-// before the launch) the grid is persistent: each resident block takes the next entry of the
-// block table from the queue's counter until the table is exhausted, so a batch's blocks (ordered
-// longest horizon first) are dealt to whichever block finishes first.
-template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false>
+// a block, so the dispatch is a block-uniform branch.  PERSIST: the grid is persistent, each
+// resident block takes the next entry of the block table from a work-queue counter (zeroed before
+// the launch) until the table is exhausted, so a batch's blocks (ordered longest first) are dealt
+// to whichever block finishes first.  It is a kernel of its own, so that the one-shot kernel
+// keeps the inlined body.
+template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON = false, bool PERSIST = false>
 __global__ __launch_bounds__(SPLIT ? 512 : 256)
 __attribute__((amdgpu_waves_per_eu((SHIELD || RESAMPLE || CON) ? 2
-                                   : (P <= 4 ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
+                                   : ((P >= 1 && P <= 4) ? (SPLIT ? 2 : 4) : 3)))) void solve_kernel(
     const InstanceDesc* __restrict__ insts, const BlockDesc* __restrict__ blocks,
     const double* __restrict__ x0_base, const double* __restrict__ Sigma0_base, int extra_shift,
     uint32_t* queue, int nblocks)
 {
-    if (!queue) {
+    if constexpr (!PERSIST) {
         solve_any_block<P, SHIELD, SPLIT, RESAMPLE, CON>(insts, blocks[blockIdx.x], x0_base,
                                                          Sigma0_base, extra_shift);
-        return;
-    }
-    __shared__ int next_block;
-    for (;;) {
-        if (threadIdx.x == 0) next_block = (int)atomicAdd(queue, 1u);
-        __syncthreads();
-        const int b = next_block;
-        if (b >= nblocks) break;   // block-uniform
-        solve_any_block<P, SHIELD, SPLIT, RESAMPLE, CON>(insts, blocks[b], x0_base, Sigma0_base,
-                                                         extra_shift);
-        __syncthreads();           // the next entry reuses the block's LDS and next_block
+    } else {
+        __shared__ int next_block;
+        for (;;) {
+            if (threadIdx.x == 0) next_block = (int)atomicAdd(queue, 1u);
+            __syncthreads();
+            const int b = next_block;
+            if (b >= nblocks) break;   // block-uniform
+            solve_any_block_call<P, SHIELD, SPLIT, RESAMPLE, CON>(insts, blocks[b], x0_base,
+                                                                  Sigma0_base, extra_shift);
+            __syncthreads();           // the next entry reuses the block's LDS and next_block
+        }
     }
 }
 
@@ -686,24 +733,32 @@ int resident_grid(Kernel k, int threads, size_t lds)
     return per_cu * cus;
 }
 
+// The persistent grid (queue non-null) is built for the plain and split variants only.
 template <int P, bool SHIELD, bool SPLIT, bool RESAMPLE, bool CON>
 hipError_t launch_variant(const InstanceDesc* inst, const BlockDesc* blocks, int nblocks,
                           size_t lds, const double* x0_base, const double* Sigma0_base,
                           int extra_shift, uint32_t* queue, hipStream_t stream)
 {
     const int threads = SPLIT ? 512 : 256;
-    auto kern = solve_kernel<P, SHIELD, SPLIT, RESAMPLE, CON>;
-    int grid = nblocks;
-    if (queue) {
-        const int resident = resident_grid(kern, threads, lds);
-        if (resident <= 0) return hipErrorInvalidValue;
-        grid = resident < nblocks ? resident : nblocks;
-        hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, stream, queue);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    if constexpr (!SHIELD && !RESAMPLE && !CON) {
+        if (queue) {
+            auto kern = solve_kernel<P, SHIELD, SPLIT, RESAMPLE, CON, true>;
+            const int resident = resident_grid(kern, threads, lds);
+            if (resident <= 0) return hipErrorInvalidValue;
+            const int grid = resident < nblocks ? resident : nblocks;
+            hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, stream, queue);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, stream, inst, blocks,
+                               x0_base, Sigma0_base, extra_shift, queue, nblocks);
+            return hipGetLastError();
+        }
+    } else {
+        if (queue) return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, stream, inst, blocks, x0_base,
-                       Sigma0_base, extra_shift, queue, nblocks);
+    hipLaunchKernelGGL((solve_kernel<P, SHIELD, SPLIT, RESAMPLE, CON, false>), dim3(nblocks),
+                       dim3(threads), lds, stream, inst, blocks, x0_base, Sigma0_base,
+                       extra_shift, nullptr, nblocks);
     return hipGetLastError();
 }
 

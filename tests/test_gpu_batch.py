@@ -125,11 +125,14 @@ def test_device_state_copy_and_tuning_keep_results():
     b = _solvers(members, vs)
     ba = bss.Batch(a, ppl=0)
     chosen = ba.tune()
-    assert chosen in (1, 2, 4, 8)
-    assert ba.layout()["ppl"] == chosen
+    assert chosen in (0, 1, 2, 4, 8)
+    lay = ba.layout()
+    assert lay["ppl"] == chosen
     ba.copy_states_from(torch.as_tensor(x0s, device="cuda"))
     ba.solve()
-    bb = bss.Batch(b, ppl=chosen)
+    bb = bss.Batch(b, ppl=chosen if chosen else 4)
+    if chosen == 0:                        # each member runs its own particles per lane
+        bb.set_member_ppl(lay["member_ppl"])
     bb.set_states(x0s)
     bb.solve()
     torch.cuda.synchronize()
@@ -236,4 +239,78 @@ def test_persistent_grid_equals_plain_grid(ppl):
     assert bb.layout() == first
     bb.close()
     for s in a + b:
+        s.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_member_ppl_equals_solve_alone(persistent):
+    """Each member with its own particles per lane in one launch computes bit for bit what it
+    computes alone with the same lanes and particles per lane."""
+    members = _mixed(8, seed=6, kmax=2048)
+    vs = _warm_starts(members, seed=13)
+    x0s = np.stack([x0 for _, x0, _ in members])
+    cycle = [1, 2, 4, 8]
+    ppl = []
+    for i, (p, _, _) in enumerate(members):
+        P = cycle[i % 4]
+        while (p["M"] + P - 1) // P > 64:
+            P *= 2
+        ppl.append(P)
+    periods = 3
+    alone = []
+    for (p, x0, _), v, P in zip(members, vs, ppl):
+        s = bss.Solver(p)
+        s.set_controls(v)
+        s.set_shape(ppl=P)
+        for _ in range(periods):
+            s.solve(x0)
+            s.step_shift()
+        alone.append((s.get_controls(), s.buffers()["S"].cpu().numpy(), s.info()["lanes"]))
+        s.close()
+    side = torch.cuda.Stream()
+    solvers = _solvers(members, vs, stream=side)
+    batch = bss.Batch(solvers, ppl=4, shift_after=True)
+    batch.set_member_ppl(ppl)
+    batch.set_grid(persistent)
+    lay = batch.layout()
+    assert lay["ppl"] == 0 and lay["member_ppl"] == ppl and lay["persistent"] == persistent
+    batch.set_states(x0s)
+    batch.capture()
+    with pytest.raises(RuntimeError, match="capturing"):
+        batch.set_member_ppl(ppl)
+    for _ in range(periods):
+        batch.solve()
+    side.synchronize()
+    for i, s in enumerate(solvers):
+        v_ref, S_ref, lanes_ref = alone[i]
+        assert batch.member_shape(i) == (lanes_ref, ppl[i]), f"member {i}"
+        assert s.info()["ppl"] == ppl[i]
+        assert np.array_equal(s.get_controls(), v_ref), f"member {i} (P={ppl[i]})"
+        assert np.array_equal(s.buffers()["S"].cpu().numpy(), S_ref), f"member {i} (P={ppl[i]})"
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_member_ppl_and_persistent_grid_rejections():
+    members = _mixed(3, seed=8, kmax=512)
+    vs = _warm_starts(members, seed=2)
+    solvers = _solvers(members, vs)
+    batch = bss.Batch(solvers, ppl=4)
+    with pytest.raises(RuntimeError, match="1, 2, 4 or 8"):
+        batch.set_member_ppl([4, 3, 4])
+    with pytest.raises(ValueError):
+        batch.set_member_ppl([4, 4])
+    batch.close()
+    # a batch with a shielded member runs one P for all and the one-shot grid only
+    base, x0b, _ = W.config_small()
+    sh = bss.Solver(dict(base, K=64, M=16, T=10, shield_iters=2, seed=5))
+    b2 = bss.Batch([solvers[0], sh], ppl=4)
+    with pytest.raises(RuntimeError, match="repair their samples"):
+        b2.set_member_ppl([4, 4])
+    with pytest.raises(RuntimeError, match="repair their"):
+        b2.set_grid(True)
+    b2.close()
+    sh.close()
+    for s in solvers:
         s.close()
