@@ -7,8 +7,9 @@ combination: 1000 receding-horizon steps of the GPU controller on the FP64 plant
   that sensitive, stay within twice the oracle's own drift when its estimate moves by ~1e-6
   (tests/sensitivity.py).
 * Rates: the oracle controller's statistics and per-step series
-  (tests/golden/closed_loop_oracle.json) cover the first 250 steps; the GPU run's same window
-  (same start, same plant noise) is compared with them.  Single- and double-precision closed
+  (tests/golden/closed_loop_oracle.json) cover the first 250 or 1000 steps of each combination
+  (each entry records its own); the GPU run's same window (same start, same plant noise) is
+  compared with them.  Single- and double-precision closed
   loops drift apart (the dynamics amplify rounding), so the two runs are two realisations of the
   same closed loop, and consecutive steps are strongly correlated: the standard error of each
   difference comes from batch means (10 batches of 25 steps) of both series,
