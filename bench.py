@@ -38,8 +38,8 @@ if ROOT not in sys.path:
 # = 163.5 FP32 FLOP + 12 transcendental = 175.5 FP32 operations per rollout-step (the counters
 # read 174.9: 64 x (ADD + MUL + 2 FMA + TRANS) per rollout-step).
 FP32_FLOP_PER_ROLLOUT_STEP = 175.5
-# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 32 lanes x 2 (packed dual-issue) x 2 FLOP (FMA) x
-# 2.4 GHz = 157.3e12 FLOP/s; without packed FP32 (which this build disables) half of it.
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed FP32, two values per lane) x
+# 2 FLOP (FMA) x 2.4 GHz = 157.3e12 FLOP/s; without packed FP32 (which this build disables) half.
 FP32_PEAK = 157.3e12
 FP32_PEAK_NONPACKED = FP32_PEAK / 2
 
@@ -53,9 +53,11 @@ KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
 #   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
 #     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
 #   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
-MEASURED = {"sources_sha256_16": None, "lanes": 16, "ppl": 4, "split": True,
-            "fetch_bytes": None, "write_bytes": None, "valu_insts": None,
-            "fp32_flop": None}
+MEASURED = {"sources_sha256_16": "6361cf98532a9a0f", "lanes": 16, "ppl": 4, "split": True,
+            # FETCH_SIZE 7620.5 KiB x (1048576 / 524305), WRITE_SIZE 15043.3 KiB x 1.0
+            "fetch_bytes": 15606278, "write_bytes": 15404339,
+            # SQ_INSTS_VALU; 64 x (ADD + MUL + 2 FMA + TRANS) of the FP32 counters
+            "valu_insts": 49045877, "fp32_flop": 2290876416}
 
 
 def sources_hash():
