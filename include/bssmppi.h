@@ -215,9 +215,11 @@ bss_status bss_validate(const bss_params* p);
 /* Back-off coefficient nu for the parameter set (host computation, Remark 1). */
 bss_status bss_backoff(const bss_params* p, double* nu_out);
 
-/* Create a context on the current HIP device.  `alloc` may be NULL (hipMalloc is used); `stream`
+/* Create a context on the current HIP device (the device is chosen by the caller with hipSetDevice
+ * before the call; the context stays on it).  `alloc` may be NULL (hipMalloc is used); `stream`
  * is a hipStream_t (NULL = the null stream) on which every later call of this context enqueues
- * its work.  The mean control sequence starts at zero and the solve index at 0.
+ * its work.  The mean control sequence starts at zero (Alg. 1's initial v) and the solve index
+ * at 0.
  * Errors: BSS_E_INVAL (parameters, out == NULL), BSS_E_NOMEM, BSS_E_DEVICE. */
 bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* stream,
                       bss_ctx** out);
@@ -241,9 +243,10 @@ bss_status bss_solve(bss_ctx* c, const double x0[6], const double* Sigma0, doubl
  * BSS_E_DEVICE. */
 bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma0_dev);
 
-/* Receding-horizon warm start: v_t <- v_{t+1} for t < T-1; v_{T-1} keeps its value.  The shift is
- * recorded in the context and applied when the next solve reads v (no kernel is launched);
- * bss_get_controls returns the shifted sequence. */
+/* Receding-horizon warm start (Alg. 1: the updated sequence seeds the next control period; after
+ * its first control has been applied the sequence moves one step): v_t <- v_{t+1} for t < T-1;
+ * v_{T-1} keeps its value.  The shift is recorded in the context and applied when the next solve
+ * reads v (no kernel is launched); bss_get_controls returns the shifted sequence. */
 bss_status bss_step_shift(bss_ctx* c);
 
 /* Select the optional per-solve copy of the sampled controls (BSS_OUT_CONTROLS, on after
@@ -284,8 +287,9 @@ bss_status bss_set_lanes(bss_ctx* c, int32_t lanes);
  * split).  Errors: BSS_E_INVAL (values, or M > 64 P), BSS_E_STATE (context in a batch). */
 bss_status bss_set_shape(bss_ctx* c, int32_t lanes, int32_t ppl, int32_t split);
 
-/* Destroy a context and free its buffers (NULL is accepted; a context that belongs to a batch is
- * left alone: destroy the batch first). */
+/* Destroy a context and free its buffers (resource management; no passage of the paper).  NULL is
+ * accepted; a context that belongs to a batch is left alone: destroy the batch first.  Work
+ * enqueued on the context's stream is waited for before its buffers are released. */
 void bss_destroy(bss_ctx* c);
 
 /* ---- batches: many controllers, one solve launch and one merge launch ---------------------------
