@@ -53,9 +53,9 @@ KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
 #   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
 #     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
 #   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
-MEASURED = {"sources_sha256_16": "6361cf98532a9a0f", "lanes": 16, "ppl": 4, "split": True,
-            # FETCH_SIZE 7620.5 KiB x (1048576 / 524305), WRITE_SIZE 15043.3 KiB x 1.0
-            "fetch_bytes": 15606278, "write_bytes": 15404339,
+MEASURED = {"sources_sha256_16": "37776ac52870e84c", "lanes": 16, "ppl": 4, "split": True,
+            # FETCH_SIZE 7628.5 KiB x (1048576 / 524305), WRITE_SIZE 15043.3 KiB x 1.0
+            "fetch_bytes": 15622717, "write_bytes": 15404378,
             # SQ_INSTS_VALU; 64 x (ADD + MUL + 2 FMA + TRANS) of the FP32 counters
             "valu_insts": 49045877, "fp32_flop": 2290876416}
 

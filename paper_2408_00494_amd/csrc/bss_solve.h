@@ -45,6 +45,19 @@ __device__ __forceinline__ void produce_noise(float* ring, int t, int q, int j,
     }
 }
 
+// LDS of the re-sampling sums, one array for every lane count of a kernel (the largest need is 8
+// lanes': group_sums_lds of 14 values).
+constexpr int kResampleLdsDoubles = group_sums_lds_doubles<14, 8>();
+static_assert(group_sums_lds_doubles<14, 16>() <= kResampleLdsDoubles &&
+                  group_sums_lds_doubles<14, 32>() <= kResampleLdsDoubles,
+              "re-sampling LDS");
+
+__device__ __forceinline__ double* resample_lds()
+{
+    __shared__ double buf[kResampleLdsDoubles];
+    return buf;
+}
+
 // Gaussian re-sampling of Alg. 2 as printed: the particles of step t are redrawn as
 // xbar_t + L_t xi with xbar_t and the unbiased full 6x6 covariance of the current set of the
 // sample (FP64 group sums of the components shifted by particle 0: 6 sums and 21 products) and
@@ -95,15 +108,50 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
     }
     const double invM = 1.0 / (double)M;
     const double invM1 = mode == 2 ? invM : (M > 1 ? 1.0 / (double)(M - 1) : 0.0);
-    double mean[6], cov[6][6];
+    // the 27 sums over the group's lanes: through LDS (two passes of 14 and 13 values) for up to
+    // 32 lanes, where DPP would take three moves and an add per sum and stage; across a whole
+    // wave by DPP and the swap instructions
+    if constexpr (L <= 32) {
+        double* lds = resample_lds();
+        double lo[14], hi[13];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) sd[a] = group_sum(sd[a], L);
+        for (int a = 0; a < 6; ++a) lo[a] = sd[a];
+        int n = 6;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                if (n < 14) lo[n] = sq[a][b];
+                else hi[n - 14] = sq[a][b];
+                ++n;
+            }
+        group_sums_lds<14, L, 14>(lo, lds);
+        group_sums_lds<13, L, 14>(hi, lds);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) sd[a] = lo[a];
+        n = 6;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                sq[a][b] = n < 14 ? lo[n] : hi[n - 14];
+                ++n;
+            }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) sd[a] = group_sum(sd[a], L);
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) sq[a][b] = group_sum(sq[a][b], L);
+    }
+    double mean[6], cov[6][6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
         mean[a] = ref[a] + sd[a] * invM;
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
-            const double c = (group_sum(sq[a][b], L) - sd[a] * (sd[b] * invM)) * invM1;
+            const double c = (sq[a][b] - sd[a] * (sd[b] * invM)) * invM1;
             cov[a][b] = c;
             cov[b][a] = c;
         }

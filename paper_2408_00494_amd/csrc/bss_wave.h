@@ -39,13 +39,14 @@ __device__ __forceinline__ void chol_psd6(const double (&A)[6][6], double (&L)[6
         for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
         if (d > 1e-10 * A[j][j] + 1e-24) {
             const double ljj = sqrt(d);
+            const double inv = 1.0 / ljj;   // one division per column (FP64 division is long)
             L[j][j] = ljj;
 #pragma unroll
             for (int i = j + 1; i < 6; ++i) {
                 double acc = A[i][j];
 #pragma unroll
                 for (int q = 0; q < j; ++q) acc -= L[i][q] * L[j][q];
-                L[i][j] = acc / ljj;
+                L[i][j] = acc * inv;
             }
         }
     }
@@ -143,6 +144,58 @@ __device__ __forceinline__ double group_sum(double x, int L)
     if (L > 16) x = xor16_sum(x);
     if (L > 32) x = xor32_sum(x);
     return x;
+}
+
+// Orders this wave's LDS accesses around a wave-local exchange: the lanes of a wave run in lockstep
+// and their LDS operations complete in program order, so only the compiler must keep the order.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Doubles of LDS that group_sums_lds<., L, N> needs per 256-thread block: each wave holds 64 / L
+// groups, each N rows of L + 1 doubles.
+template <int N, int L>
+constexpr int group_sums_lds_doubles() { return 4 * (64 / L) * N * (L + 1); }
+
+// Sums over the L lanes of each group of N doubles per lane (L = 8, 16 or 32), through the wave's
+// own region of `scratch`: one row of L + 1 doubles per value and group (the L lanes' entries, then
+// the total).  Lane i of a group adds up rows i, i + L, ... in lane order and stores the totals;
+// every lane then reads all N totals, so they are bitwise identical across the group.  The rows'
+// odd stride keeps the lanes' accesses on distinct banks.  Every lane of the group takes part.
+// The regions are laid out for NCAP >= N values whatever N is, so that calls with different N
+// keep every wave inside its own region (waves run apart: one may start its next call while
+// another still reads the totals of this one).
+template <int N, int L, int NCAP = N>
+__device__ __forceinline__ void group_sums_lds(double (&x)[N], double* scratch)
+{
+    static_assert(L == 8 || L == 16 || L == 32, "group_sums_lds: 8, 16 or 32 lanes");
+    static_assert(N <= NCAP, "group_sums_lds: N <= NCAP");
+    constexpr int ROW = L + 1;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int i = lane & (L - 1);
+    double* base = scratch + (size_t)(threadIdx.x >> 6) * (64 / L) * NCAP * ROW +
+                   (size_t)(lane / L) * NCAP * ROW;
+#pragma unroll
+    for (int k = 0; k < N; ++k) base[k * ROW + i] = x[k];
+    wave_lds_sync();
+#pragma unroll
+    for (int k0 = 0; k0 < N; k0 += L) {
+        const int k = k0 + i;
+        if (k < N) {
+            const double* row = base + k * ROW;
+            double acc = row[0];
+#pragma unroll
+            for (int q = 1; q < L; ++q) acc += row[q];
+            base[k * ROW + L] = acc;
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < N; ++k) x[k] = base[k * ROW + L];
+    wave_lds_sync();   // the next call writes the same region
 }
 
 // Value of lane 0 of the group in every lane of the group.

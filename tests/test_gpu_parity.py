@@ -381,6 +381,22 @@ def test_noise_split_is_bitwise_identical(K, M, T, ppl):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("K,M,T,shape", [(1000, 20, 20, (32, 1)), (512, 64, 30, (64, 1)),
+                                         (2048, 32, 25, (32, 1)), (4096, 64, 20, (16, 4)),
+                                         (256, 16, 30, (16, 1))])
+def test_default_shape_of_small_launches_matches_oracle(K, M, T, shape):
+    """The automatic launch shape spreads the particles of a launch with fewer sample lanes than
+    one wave per SIMD over more lanes (fewer per lane); every shape meets the oracle bars."""
+    prob, x0, _ = W.config_small()
+    prob = dict(prob, K=K, M=M, T=T, seed=K + M)
+    t = np.arange(T)
+    v = np.column_stack([0.05 * np.sin(0.3 * t), 0.5 * np.cos(0.2 * t)])
+    solver = bss.Solver(prob)
+    assert (solver.info()["lanes"], solver.info()["ppl"]) == shape
+    solver.close()
+    _compare_solve(prob, x0, v, s=2)
+
+
 def test_cantelli_backoff_solve_matches_oracle():
     """Distribution-free back-off nu = sqrt((1 - delta)/delta) (Remark 1) instead of the Gaussian
     quantile: larger nu, so the barrier binds earlier."""

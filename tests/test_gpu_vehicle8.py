@@ -106,6 +106,8 @@ def test_paper_size_vehicle8_solve_matches_oracle():
     prob, x0, v = W.config_vehicle8()
     got, ref = _compare(prob, x0, v, s=0)
     assert got["info"]["ess"] > 2.0
+    # a launch this small (1000 samples) spreads its 20 particles one per lane over 32 lanes
+    assert (got["info"]["lanes"], got["info"]["ppl"]) == (32, 1)
 
 
 def test_vehicle8_receding_horizon_sequence_matches_oracle():
