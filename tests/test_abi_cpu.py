@@ -101,7 +101,8 @@ def test_validation_accepts_workloads():
 
 
 @pytest.mark.parametrize("kw,frag", [
-    (dict(K=0), "K="), (dict(M=0), "M="), (dict(M=513), "M="), (dict(T=0), "T="),
+    (dict(K=0), "K="), (dict(K=(1 << 20) + 1), "K="), (dict(M=0), "M="), (dict(M=513), "M="),
+    (dict(T=0), "T="),
     (dict(T=257), "T="), (dict(delta=0.0), "delta"), (dict(delta=0.5), "delta"),
     (dict(gamma=0.0), "gamma"), (dict(gamma=1.5), "gamma"), (dict(**{"lambda": 0.0}), "lambda"),
     (dict(dt=-1.0), "dt"), (dict(sigma_w=[0.1, -1.0, 0.0]), "sigma_w"),

@@ -37,7 +37,12 @@ def ctrl_err(v_gpu, v_ref, prob):
 
 
 def mom_err(m_gpu, m_ref):
+    """|d| / max_t |ref| per record entry and sample.  The off-diagonal position covariance S_XY
+    is bounded by sqrt(S_XX S_YY), so it is measured against at least the geometric mean of the
+    spans of S_XX and S_YY: over a million samples some have position spreads that are nearly
+    uncorrelated by chance, and their S_XY span sits at the rounding level of the block."""
     span = np.max(np.abs(m_ref), axis=1, keepdims=True)
+    span[..., 7] = np.maximum(span[..., 7], np.sqrt(span[..., 6] * span[..., 8]))
     span = np.where(span > 0, span, 1.0)
     return float(np.max(np.abs(m_gpu - m_ref) / span))
 
@@ -350,8 +355,11 @@ def test_shielded_solve_matches_oracle():
 
 
 @pytest.mark.parametrize("K,M,T,lanes", [(1, 1, 1, 0), (3, 13, 7, 8), (257, 16, 30, 0),
-                                         (5, 512, 4, 64), (2, 37, 256, 16), (70, 2, 3, 32)])
+                                         (5, 512, 4, 64), (2, 37, 256, 16), (70, 2, 3, 32),
+                                         (1 << 20, 16, 3, 0), (9, 512, 256, 0)])
 def test_edge_sizes_match_oracle(K, M, T, lanes):
+    """Ragged and extreme sizes, among them the maxima K = 2^20, M = 512 (64 lanes x 8) and
+    T = 256 together with M = 512."""
     prob, x0, _ = W.config_small()
     prob = dict(prob, K=K, M=M, T=T)
     v = np.column_stack([0.05 * np.sin(np.arange(T)), 0.5 * np.cos(np.arange(T))])
