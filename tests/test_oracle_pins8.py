@@ -240,3 +240,25 @@ def test_paper_size_solve8_runs_and_is_deterministic():
     assert a["status"] == 0 and np.all(np.isfinite(a["S"]))
     assert np.array_equal(a["v"], b["v"]) and np.array_equal(a["S"], b["S"])
     assert a["stats"][2] > 2.0                           # the weights are not degenerate
+
+
+# ---- integration -----------------------------------------------------------------------------
+def test_substeps_converge_at_second_order_to_an_independent_ode_solution():
+    """The period step is n_sub explicit-midpoint substeps of the vector field.  Against SciPy's
+    adaptive Runge-Kutta solution of the same field (tolerances 1e-13), the error of one period
+    falls by about four per doubling of n_sub (second order: a first-order slip, e.g. the
+    endpoint slope in place of the midpoint's, would give two), and a fine subdivision agrees
+    with the independent solution."""
+    from scipy.integrate import solve_ivp
+    prob = _prob()   # the 0.05 s period
+    x0 = np.array([5.0, 0.3, 0.5, 55.0, 60.0, 0.1, 0.5, 10.0])
+    u = np.array([0.15, 0.4])
+    sol = solve_ivp(lambda t, x: oracle.deriv8(prob, x, u), (0.0, prob["dt"]), x0,
+                    method="DOP853", rtol=1e-13, atol=1e-13)
+    ref = sol.y[:, -1]
+    errs = [float(np.max(np.abs(oracle.model_step8(dict(prob, n_sub=n), x0, u) - ref)))
+            for n in (4, 8, 16, 32)]
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.3 < r < 4.7 for r in ratios), (errs, ratios)
+    fine = oracle.model_step8(dict(prob, n_sub=1024), x0, u)
+    assert np.max(np.abs(fine - ref)) < 1e-6
