@@ -53,11 +53,12 @@ KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
 #   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
 #     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
 #   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
-MEASURED = {"sources_sha256_16": "37776ac52870e84c", "lanes": 16, "ppl": 4, "split": True,
-            # FETCH_SIZE 7628.5 KiB x (1048576 / 524305), WRITE_SIZE 15043.3 KiB x 1.0
-            "fetch_bytes": 15622717, "write_bytes": 15404378,
+MEASURED = {"sources_sha256_16": "fb833bee1d816836", "lanes": 16, "ppl": 4, "split": True,
+            "records_on_chip": True,
+            # FETCH_SIZE 270.75 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
+            "fetch_bytes": 554478, "write_bytes": 253952,
             # SQ_INSTS_VALU; 64 x (ADD + MUL + 2 FMA + TRANS) of the FP32 counters
-            "valu_insts": 49045877, "fp32_flop": 2290876416}
+            "valu_insts": 48868129, "fp32_flop": 2290876416}
 
 
 def sources_hash():
@@ -69,21 +70,24 @@ def sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured(lanes, ppl, split):
-    """Counter measurements of the solve kernel, or None if the kernel or the launch shape
-    changed since they were taken."""
+def measured(lanes, ppl, split, on_chip):
+    """Counter measurements of the solve kernel, or None if the kernel, the launch shape or where
+    the belief records live changed since they were taken."""
     if MEASURED["sources_sha256_16"] != sources_hash() or \
-            (lanes, ppl, split) != (MEASURED["lanes"], MEASURED["ppl"], MEASURED["split"]):
+            (lanes, ppl, split, on_chip) != (MEASURED["lanes"], MEASURED["ppl"], MEASURED["split"],
+                                             MEASURED["records_on_chip"]):
         return None
     return MEASURED
 
 
-def ALG_BYTES_PER_SOLVE(K, M, T, lanes):
-    """Bytes the solve kernel must move: belief records written and read back by the scoring
-    phase (K (T+1) 9 doubles each way), costs, block partials, and the mean sequence read."""
+def ALG_BYTES_PER_SOLVE(K, M, T, lanes, records_in_hbm):
+    """Bytes the solve kernel must move: costs, block partials, the mean sequence read, and, when
+    the belief records go through HBM rather than staying on chip, the records written and read
+    back by the scoring phase (K (T+1) 9 doubles each way)."""
     groups = 256 // lanes
     blocks = (K + groups - 1) // groups
-    return 2 * K * (T + 1) * 9 * 8 + K * 8 + blocks * (2 * T + 5) * 8 + T * 2 * 8
+    rec = 2 * K * (T + 1) * 9 * 8 if records_in_hbm else 0
+    return rec + K * 8 + blocks * (2 * T + 5) * 8 + T * 2 * 8
 
 
 def progress(msg):
@@ -413,7 +417,9 @@ def main():
     solver = bss.Solver(prob, lanes=args.lanes)
     if args.ppl or args.split != -1:
         solver.set_shape(lanes=args.lanes, ppl=args.ppl, split=args.split)
-    solver.set_outputs(controls=False)   # the solve does not need the copy
+    # a controller needs neither the sampled controls nor the belief records: the records stay on
+    # chip where they fit
+    solver.set_outputs(controls=False, beliefs=False)
     x0_dev = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
 
     for _ in range(args.warmup):
@@ -438,7 +444,7 @@ def main():
     value = rs_per_solve * args.steps / elapsed
     kernel_ms = kernel_ms_total / max(n_meas, 1)
     fp32 = FP32_FLOP_PER_ROLLOUT_STEP * rs_per_solve / (kernel_ms * 1e-3)
-    meas = measured(info["lanes"], info["ppl"], info["split"])
+    meas = measured(info["lanes"], info["ppl"], info["split"], info["records_on_chip"])
 
     # plain synchronous solves from host inputs (latency of one control period)
     lat = []
@@ -465,14 +471,15 @@ def main():
                                "T=50 steps, disturbance std x2, seeded start on the 30x20 m "
                                "ellipse track",
                    "K": K, "M": M, "T": T, "lanes": info["lanes"], "ppl": info["ppl"],
-                   "noise_split": info["split"]},
+                   "noise_split": info["split"], "records_on_chip": info["records_on_chip"]},
         "roofline": {"bound": "alu", "achieved": fp32 / 1e12, "peak": FP32_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": fp32 / FP32_PEAK,
                      "traffic": (meas["fetch_bytes"] + meas["write_bytes"]) if meas else None,
                      "kernel": "solve_kernel", "kernel_ms": kernel_ms,
                      "fp32_flop_per_rollout_step": FP32_FLOP_PER_ROLLOUT_STEP,
                      "frac_of_nonpacked_peak": fp32 / FP32_PEAK_NONPACKED,
-                     "algorithmic_bytes": ALG_BYTES_PER_SOLVE(K, M, T, info["lanes"]),
+                     "algorithmic_bytes": ALG_BYTES_PER_SOLVE(K, M, T, info["lanes"],
+                                                              not info["records_on_chip"]),
                      "valu_lane_insts_per_rollout_step":
                          meas["valu_insts"] * 64 / rs_per_solve if meas else None,
                      "counter_fp32_flop_per_rollout_step":

@@ -160,6 +160,8 @@ typedef struct bss_allocator {
  *                               only when BSS_OUT_CONTROLS is set)
  *   mom    [K][T+1][9]  double  belief per sample and step: mean X, Y, psi, vx, vy, r, then
  *                               Sigma_XX, Sigma_XY, Sigma_YY; record 0 is the given estimate
+ *                               (written when BSS_OUT_BELIEFS is set or the records do not fit
+ *                               on chip)
  *   S      [K]          double  trajectory costs of the last solve
  *   stats  [8]          double  S_min, Z = sum_k w_k, ESS = Z^2/sum w^2, #finite costs,
  *                               status (0 ok, 5 numeric), v+_0 (steer, accel), number of
@@ -182,15 +184,20 @@ typedef struct bss_buffers {
                           sample and record, or NULL when n_con = 0 */
 } bss_buffers;
 
-/* Optional per-solve copy to device memory (bss_set_outputs); the solve itself does not need it. */
+/* Optional per-solve outputs in device memory (bss_set_outputs); the update does not need them. */
 #define BSS_OUT_CONTROLS 1   /* sampled controls u [K][T][2] */
+#define BSS_OUT_BELIEFS 2    /* belief records mom [K][T+1][9] and con_var [K][T+1][n_con]; without
+                                it a single context's solve keeps them in on-chip memory when they
+                                fit beside the resident blocks (then mom and con_var are not
+                                written), and in its device buffers otherwise */
 
 /* Result summary of a solve (host): S_min = min_k S_k and Z = sum_k exp(-(S_k - S_min)/lambda)
  * (eq. 7), ess = Z^2 / sum_k w_k^2, n_finite = samples with a finite cost;
  * dcbf_violations = the solve's (sample, step) transitions whose belief violated the linear
  * class-kappa condition h_{t+1} >= (1 - gamma) h_t (eq. 24, the ones C_safe penalises);
  * kernel_ms = the rollout kernel's time of the last solve (HIP events) while timing is enabled
- * (bss_timing_enable), else -1. */
+ * (bss_timing_enable), else -1; records_on_chip = 1 when the context's solves keep the belief
+ * records in on-chip memory (BSS_OUT_BELIEFS off and room for them). */
 typedef struct bss_info {
     double S_min, Z, ess;
     int32_t n_finite;
@@ -198,6 +205,7 @@ typedef struct bss_info {
     int32_t split;            /* 1 when the disturbance normals came from separate waves */
     int32_t dcbf_violations;
     float kernel_ms;
+    int32_t records_on_chip;
 } bss_info;
 
 typedef struct bss_ctx bss_ctx;
@@ -249,8 +257,9 @@ bss_status bss_solve_async(bss_ctx* c, const double* x0_dev, const double* Sigma
  * reads v (no kernel is launched); bss_get_controls returns the shifted sequence. */
 bss_status bss_step_shift(bss_ctx* c);
 
-/* Select the optional per-solve copy of the sampled controls (BSS_OUT_CONTROLS, on after
- * bss_create; 0 turns it off). */
+/* Select the optional per-solve outputs (BSS_OUT_CONTROLS | BSS_OUT_BELIEFS, both on after
+ * bss_create).  The solve's costs, update, command and stats are the same bit for bit either way.
+ * Errors: BSS_E_INVAL (unknown flags), BSS_E_STATE (context in a batch), BSS_E_DEVICE. */
 bss_status bss_set_outputs(bss_ctx* c, int32_t flags);
 
 /* Device buffers of the context (see bss_buffers). */

@@ -147,9 +147,12 @@ class Solver:
         noise split (-1 automatic, 0 off, 1 on)."""
         check(_lib.lib().bss_set_shape(self._ctx, int(lanes), int(ppl), int(split)))
 
-    def set_outputs(self, controls: bool = True):
-        """Turn the optional per-solve copy of the sampled controls on or off."""
-        check(_lib.lib().bss_set_outputs(self._ctx, _lib.BSS_OUT_CONTROLS if controls else 0))
+    def set_outputs(self, controls: bool = True, beliefs: bool = True):
+        """Turn the optional per-solve outputs on or off: the copy of the sampled controls, and
+        the belief records (without them the records may stay on chip; results are the same)."""
+        flags = ((_lib.BSS_OUT_CONTROLS if controls else 0) |
+                 (_lib.BSS_OUT_BELIEFS if beliefs else 0))
+        check(_lib.lib().bss_set_outputs(self._ctx, flags))
 
     def buffers(self):
         """Torch views of the context's device buffers: v (current mean sequence, before any
@@ -357,7 +360,8 @@ BssAllocator_release = _lib.BssAllocator._fields_[1][1]
 def _info_dict(info):
     return {"S_min": info.S_min, "Z": info.Z, "ess": info.ess, "n_finite": info.n_finite,
             "lanes": info.lanes, "ppl": info.ppl, "split": bool(info.split),
-            "dcbf_violations": info.dcbf_violations, "kernel_ms": info.kernel_ms}
+            "dcbf_violations": info.dcbf_violations, "kernel_ms": info.kernel_ms,
+            "records_on_chip": bool(info.records_on_chip)}
 
 
 # ---- stand-alone kernels (device tensors in/out, current stream) --------------------------------

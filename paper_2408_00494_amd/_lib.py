@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libbssmppi.so")
 
 BSS_OK, BSS_E_INVAL, BSS_E_NOMEM, BSS_E_DEVICE, BSS_E_STATE, BSS_E_NUMERIC = range(6)
 BSS_OUT_CONTROLS = 1
+BSS_OUT_BELIEFS = 2
 STATUS_NAMES = {0: "BSS_OK", 1: "BSS_E_INVAL", 2: "BSS_E_NOMEM", 3: "BSS_E_DEVICE",
                 4: "BSS_E_STATE", 5: "BSS_E_NUMERIC"}
 
@@ -74,7 +75,8 @@ class BssBuffers(C.Structure):
 class BssInfo(C.Structure):
     _fields_ = [("S_min", C.c_double), ("Z", C.c_double), ("ess", C.c_double),
                 ("n_finite", C.c_int32), ("lanes", C.c_int32), ("ppl", C.c_int32),
-                ("split", C.c_int32), ("dcbf_violations", C.c_int32), ("kernel_ms", C.c_float)]
+                ("split", C.c_int32), ("dcbf_violations", C.c_int32), ("kernel_ms", C.c_float),
+                ("records_on_chip", C.c_int32)]
 
 
 # every exported symbol of include/bssmppi.h

@@ -298,6 +298,24 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
     return out;
 }
 
+// Belief records on chip (rec_lds) when no output asks for them and their LDS costs no residency:
+// the blocks the grid needs per CU must still fit next to each other (40 KB are left for the
+// kernels' static LDS, at most 33 KB in the re-sampling variants).
+bool records_on_chip(const bss_ctx* c, size_t base_lds)
+{
+    if ((c->outputs & BSS_OUT_BELIEFS) || c->p.vehicle != 0) return false;
+    const size_t per_block =
+        base_lds + record_lds_bytes(c->shape.lanes, c->p.T, c->p.n_con) + 40 * 1024;
+    if (per_block > kMaxLdsPerBlock) return false;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return false;
+    const int64_t per_cu_needed = (solve_blocks(c->p.K, c->shape.lanes) + cus - 1) / cus;
+    return (int64_t)(kMaxLdsPerBlock / per_block) >= per_cu_needed;
+}
+
 hipError_t upload_shape(bss_ctx* c)
 {
     c->desc.lanes = c->shape.lanes;
@@ -306,6 +324,8 @@ hipError_t upload_shape(bss_ctx* c)
     c->shape.split = c->shape.split && !launch_shield(c->p) && !launch_resample(c->p) &&
                      c->p.vehicle == 0;
     c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
+    c->desc.rec_lds = records_on_chip(c, c->lds) ? 1 : 0;
+    if (c->desc.rec_lds) c->lds += record_lds_bytes(c->shape.lanes, c->p.T, c->p.n_con);
     // static leading fields only: the device state is left as it is
     hipError_t e = hipMemcpy(c->d_desc, &c->desc, offsetof(InstanceDesc, cur),
                              hipMemcpyHostToDevice);
@@ -537,7 +557,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
     c->timing = false;
     c->ev_used = 0;
     c->pending_shift = 0;
-    c->outputs = BSS_OUT_CONTROLS;
+    c->outputs = BSS_OUT_CONTROLS | BSS_OUT_BELIEFS;
     c->batch = nullptr;
     c->batch_index = 0;
     c->host = nullptr;
@@ -647,6 +667,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         c->rshape = choose_shape(1, p->M, p->T, 0, 1, 0, true);
         r.lanes = c->rshape.lanes;
         r.ppl = c->rshape.ppl;
+        r.rec_lds = 0;
         c->rlds = solve_lds_bytes(r.lanes, p->T, c->rshape.ppl, false);
     }
 
@@ -765,6 +786,7 @@ static void fill_info(const bss_ctx* c, const double* stats, bss_info* info)
         if (hipEventElapsedTime(&ms, c->ev[c->ev_used - 2], c->ev[c->ev_used - 1]) == hipSuccess)
             info->kernel_ms = ms;
     }
+    info->records_on_chip = c->batch ? 0 : c->desc.rec_lds;
     if (c->batch) {
         info->lanes = c->batch->lanes[c->batch_index];
         info->ppl = c->batch->ppls[c->batch_index];
@@ -827,7 +849,7 @@ bss_status bss_set_outputs(bss_ctx* c, int32_t flags)
 {
     bss_status st = check_free(c);
     if (st != BSS_OK) return st;
-    if (flags & ~BSS_OUT_CONTROLS) return fail(BSS_E_INVAL, "unknown flags");
+    if (flags & ~(BSS_OUT_CONTROLS | BSS_OUT_BELIEFS)) return fail(BSS_E_INVAL, "unknown flags");
     c->outputs = flags;
     float* u = (flags & BSS_OUT_CONTROLS) ? (float*)((char*)c->desc.v[1] +
                                                      align256((size_t)c->p.T * 2 * sizeof(double)))
@@ -837,6 +859,7 @@ bss_status bss_set_outputs(bss_ctx* c, int32_t flags)
     if (e == hipSuccess)
         e = hipMemcpy((char*)c->d_desc + offsetof(InstanceDesc, u), &u, sizeof(u),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = upload_shape(c);   // where the records live, and the LDS
     if (e != hipSuccess) return device_fail(e, "setting outputs");
     return BSS_OK;
 }
@@ -1039,6 +1062,7 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
         InstanceDesc head = b->ctxs[i]->desc;
         head.lanes = lanes[i];
         head.ppl = ppls[i];
+        head.rec_lds = 0;   // a batch keeps every member's records in HBM
         head.nblocks = solve_blocks(b->ctxs[i]->p.K, lanes[i]);
         head.x0_index = i;
         e = hipMemcpy(b->d_desc + i, &head, offsetof(InstanceDesc, cur), hipMemcpyHostToDevice);

@@ -107,6 +107,9 @@ struct InstanceDesc {
     int32_t K, M, T, lanes, ppl;
     int32_t nblocks;               // solve blocks of this instance (= number of partials)
     int32_t x0_index;              // state estimate at x0_base + 6 x0_index (launch argument)
+    int32_t rec_lds;               // 1: belief records (and constraint variances) kept in the
+                                   // block's LDS after the controls (or the noise ring) instead
+                                   // of mom / cvar; the launch's LDS includes them
     // per-solve state, advanced on the device by the last merge block of the instance
     int32_t cur;                   // v[cur] holds the mean sequence
     int32_t vshift;                // pending warm-start shifts: read v[min(t + vshift, T - 1)]
@@ -172,6 +175,11 @@ constexpr size_t kMaxLds = 65536;
 
 // dynamic LDS of one solve block with L lanes per sample (P = the kernel's particles per lane)
 size_t solve_lds_bytes(int lanes, int T, int ppl, bool split);
+// LDS of the belief records of one block kept on chip (rec_lds): (256 / lanes) samples x (T + 1)
+// records x (9 + n_con) doubles.
+size_t record_lds_bytes(int lanes, int T, int n_con);
+// LDS one workgroup can allocate on gfx950.
+constexpr size_t kMaxLdsPerBlock = 163840;
 // requested_split: -1 automatic (split when the launch has fewer than two waves per SIMD), 0 off,
 // 1 on (when the ring fits); shield: the sampled controls are repaired (the automatic shape then
 // puts eight particles in a lane)

@@ -440,6 +440,11 @@ size_t solve_lds_bytes(int lanes, int T, int ppl, bool split)
            (split ? (size_t)2 * ppl * 3 * 256 * sizeof(float) : 0);
 }
 
+size_t record_lds_bytes(int lanes, int T, int n_con)
+{
+    return (size_t)(256 / lanes) * (T + 1) * (9 + n_con) * sizeof(double);
+}
+
 bool split_pays(int nblocks, int lanes, int T, int ppl)
 {
     // fewer than two waves per SIMD (256 CUs x 4 SIMDs, four waves per block), and room for the

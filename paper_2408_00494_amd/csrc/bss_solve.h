@@ -242,6 +242,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     double* w_sh = S_sh + groups;                            // [groups]
     float2* u_sh = reinterpret_cast<float2*>(w_sh + groups);  // [groups][T]
     float* ring = reinterpret_cast<float*>(u_sh + groups * T);  // SPLIT: [2][P][3][256]
+    // on-chip belief records (rec_lds): [groups][T+1][9], then [groups][T+1][n_con]
+    double* rec_sh = reinterpret_cast<double*>(ring + (SPLIT ? 2 * P * 3 * 256 : 0));
     const int q = SPLIT ? (int)(threadIdx.x & 255u) : (int)threadIdx.x;
     const bool producer = SPLIT && threadIdx.x >= 256u;
     const int g = q >> log2L;
@@ -249,7 +251,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     const int k = bd.k0 + g;
     const bool active = k < d.K;
     float2* us = u_sh + g * T;
-    double* mom_k = d.mom + (size_t)(active ? k : 0) * (T + 1) * 9;
+    // the records of this sample: in HBM (mom, an output) or in the block's LDS (generic pointers
+    // either way; the scoring phase reads them back from the same block)
+    double* mom_k = d.rec_lds ? rec_sh + (size_t)g * (T + 1) * 9
+                              : d.mom + (size_t)(active ? k : 0) * (T + 1) * 9;
     const uint32_t s = d.solve_index;
     const uint32_t key0 = d.key0, key1 = d.key1;
     const double* x0p = x0_base + 6 * d.x0_index;
@@ -257,7 +262,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     // half-space constraints on the whole state (compiled into the CON variants only): their
     // variances a_i^T Sigma a_i per record
     const int ncon = CON ? d.sc.n_con : 0;
-    double* cvar_k = ncon > 0 ? d.cvar + (size_t)(active ? k : 0) * (T + 1) * ncon : nullptr;
+    double* cvar_k =
+        ncon == 0 ? nullptr
+        : d.rec_lds ? rec_sh + (size_t)groups * (T + 1) * 9 + (size_t)g * (T + 1) * ncon
+                    : d.cvar + (size_t)(active ? k : 0) * (T + 1) * ncon;
 
     // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
     if (active && (!SPLIT || producer)) {

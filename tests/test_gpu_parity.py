@@ -731,3 +731,57 @@ def test_info_counts_dcbf_violations_and_times_the_kernel():
     assert info["dcbf_violations"] == staged
     assert abs(end - staged) <= max(2, staged // 1000)
     assert 0.0 < info["kernel_ms"] < 1000.0
+
+
+# ======================= belief records kept on chip (BSS_OUT_BELIEFS off) =======================
+def _config_variant(name):
+    prob, x0, _ = W.config_paper_scale()
+    if name == "plain_split":
+        return dict(prob, K=1024), x0, True
+    if name == "paper_scale":
+        return prob, x0, True
+    if name == "many_blocks":      # needs four blocks per CU: the records stay in HBM
+        return dict(prob, K=16384, T=30), x0, False
+    if name == "shielded":
+        p, x, _ = W.config_shielded()
+        return dict(p, K=512), x, True
+    if name == "resampled":
+        return dict(prob, K=512, belief=1), x0, True
+    if name == "sigma_points":
+        return dict(prob, K=512, M=12, belief=2), x0, True
+    if name == "constrained":
+        p, x, _ = W.config_constrained()
+        return dict(p, K=1024), x, True
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["plain_split", "paper_scale", "many_blocks", "shielded",
+                                  "resampled", "sigma_points", "constrained"])
+def test_records_on_chip_give_identical_results(name):
+    """Without the belief-record output a context's solve keeps the records in the block's LDS
+    when they fit beside the resident blocks; costs, updates and stats are the same bit for bit
+    over three receding-horizon periods."""
+    prob, x0, on_chip = _config_variant(name)
+    T = prob["T"]
+    t = np.arange(T)
+    v = np.column_stack([0.05 * np.sin(0.3 * t), 0.3 * np.cos(0.2 * t)])
+    out = []
+    for beliefs in (True, False):
+        s = bss.Solver(prob)
+        s.set_outputs(controls=False, beliefs=beliefs)
+        s.set_controls(v)
+        res = []
+        for _ in range(3):
+            u0, info = s.solve(x0)
+            b = s.buffers()
+            res.append((u0, s.get_controls(), b["S"].cpu().numpy(), b["stats"].cpu().numpy(),
+                        info["dcbf_violations"]))
+            s.step_shift()
+        out.append((res, s.info()["records_on_chip"]))
+        s.close()
+    (ref, chip_ref), (got, chip_got) = out
+    assert not chip_ref
+    assert chip_got == on_chip
+    for (a, b) in zip(ref, got):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
