@@ -314,3 +314,40 @@ def test_member_ppl_and_persistent_grid_rejections():
     sh.close()
     for s in solvers:
         s.close()
+
+
+def test_many_small_members_equal_their_solves_alone():
+    """A batch of 384 small controllers (K 1..96, M 1..48, T 1..24, seeded), replayed from a
+    graph: every member equals its solve alone bit for bit."""
+    rng = np.random.default_rng(17)
+    base, x0b, _ = W.config_small()
+    members = []
+    for i in range(384):
+        K, M, T = int(rng.integers(1, 97)), int(rng.integers(1, 49)), int(rng.integers(1, 25))
+        members.append((dict(base, K=K, M=M, T=T, seed=1000 + i), x0b, np.zeros((T, 2))))
+    vs = _warm_starts(members, seed=23)
+    x0s = np.stack([x0 for _, x0, _ in members])
+    side = torch.cuda.Stream()
+    solvers = _solvers(members, vs, stream=side)
+    batch = bss.Batch(solvers, ppl=2, shift_after=True)
+    batch.set_states(x0s)
+    batch.capture()
+    for _ in range(2):
+        batch.solve()
+    side.synchronize()
+    got = [(s.get_controls(), s.buffers()["S"].cpu().numpy()) for s in solvers]
+    shapes = [batch.member_shape(i) for i in range(len(members))]
+    batch.close()
+    for s in solvers:
+        s.close()
+    for i in rng.choice(len(members), 48, replace=False):
+        (p, x0, _), v = members[i], vs[i]
+        s = bss.Solver(p)
+        s.set_controls(v)
+        s.set_shape(lanes=shapes[i][0], ppl=shapes[i][1])
+        for _ in range(2):
+            s.solve(x0)
+            s.step_shift()
+        assert np.array_equal(s.get_controls(), got[i][0]), f"member {i}"
+        assert np.array_equal(s.buffers()["S"].cpu().numpy(), got[i][1]), f"member {i}"
+        s.close()
