@@ -58,7 +58,14 @@ MEASURED = {"sources_sha256_16": "fb833bee1d816836", "lanes": 16, "ppl": 4, "spl
             # FETCH_SIZE 270.75 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
             "fetch_bytes": 554478, "write_bytes": 253952,
             # SQ_INSTS_VALU; 64 x (ADD + MUL + 2 FMA + TRANS) of the FP32 counters
-            "valu_insts": 48868129, "fp32_flop": 2290876416}
+            "valu_insts": 48868129, "fp32_flop": 2290876416,
+            # wave instructions by kind (SQ_INSTS_VALU_*): FP32 arithmetic (ADD, MUL, FMA),
+            # FP32 transcendentals, FP64 (ADD, MUL, FMA, TRANS), integer (INT32, INT64),
+            # conversions; the rest (moves, DPP, selects, bit operations) has no counter
+            "valu_by_kind": {"fp32_arith": 3080192 + 5136384 + 12705792,
+                             "fp32_trans": 2166784,
+                             "fp64": 4603312 + 788589 + 1506073 + 62138,
+                             "int": 530916 + 2553856, "cvt": 2132224}}
 
 
 def sources_hash():
@@ -483,7 +490,12 @@ def main():
                      "valu_lane_insts_per_rollout_step":
                          meas["valu_insts"] * 64 / rs_per_solve if meas else None,
                      "counter_fp32_flop_per_rollout_step":
-                         meas["fp32_flop"] / rs_per_solve if meas else None},
+                         meas["fp32_flop"] / rs_per_solve if meas else None,
+                     # shares of the VALU lane instructions (counters), the transcendental and
+                     # integer shares among them
+                     "valu_shares": ({kind: n / meas["valu_insts"]
+                                      for kind, n in meas["valu_by_kind"].items()}
+                                     if meas else None)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mode": "plain synchronous solve from host inputs"},
     }
