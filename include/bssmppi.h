@@ -290,7 +290,9 @@ bss_status bss_set_lanes(bss_ctx* c, int32_t lanes);
  * a nonzero ppl takes precedence over lanes) and the noise split (-1 automatic, 0 off, 1 on): with
  * the split, each block of 512 threads has a second set of waves that generates the disturbance
  * normals one step ahead, which doubles the waves per SIMD of a launch too small to fill the chip
- * (automatic: when the launch has fewer than two waves per SIMD; never for the shielded loop).
+ * (automatic: when the launch has fewer than two waves per SIMD; never for the shielded loop
+ * nor for constraints together with re-sampling; with re-sampling the noise waves also draw the
+ * re-sampling normals).
  * The M particles of a sample are spread over L lanes with P = ceil(M / L) per lane.  Results
  * depend on the shape only through the summation order of the per-step moments (not on the
  * split).  Errors: BSS_E_INVAL (values, or M > 64 P), BSS_E_STATE (context in a batch). */

@@ -321,9 +321,15 @@ hipError_t upload_shape(bss_ctx* c)
     c->desc.lanes = c->shape.lanes;
     c->desc.ppl = c->shape.ppl;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
-    c->shape.split = c->shape.split && !launch_shield(c->p) && !launch_resample(c->p) &&
-                     c->p.vehicle == 0;
-    c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split);
+    // the noise split: not with the repair of the samples nor the generic constraint variant; with
+    // the re-sampling draw the noise waves also draw its normals, in a ring three times as large
+    // (40 KB are left for the kernel's static LDS, 33 KB in the re-sampling variants)
+    const bool rs = launch_resample(c->p);
+    c->shape.split = c->shape.split && !launch_shield(c->p) && c->p.vehicle == 0 &&
+                     !(rs && c->p.n_con > 0) &&
+                     (!rs || solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, true, true) +
+                                     40 * 1024 <= kMaxLdsPerBlock);
+    c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split, rs);
     c->desc.rec_lds = records_on_chip(c, c->lds) ? 1 : 0;
     if (c->desc.rec_lds) c->lds += record_lds_bytes(c->shape.lanes, c->p.T, c->p.n_con);
     // static leading fields only: the device state is left as it is

@@ -174,7 +174,9 @@ constexpr int kMaxT = 256;
 constexpr size_t kMaxLds = 65536;
 
 // dynamic LDS of one solve block with L lanes per sample (P = the kernel's particles per lane)
-size_t solve_lds_bytes(int lanes, int T, int ppl, bool split);
+// Dynamic LDS of a solve block: costs and weights, the controls, and with the noise split the ring
+// of normals (three per particle and slot, nine with the re-sampling draw's).
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample = false);
 // LDS of the belief records of one block kept on chip (rec_lds): (256 / lanes) samples x (T + 1)
 // records x (9 + n_con) doubles.
 size_t record_lds_bytes(int lanes, int T, int n_con);

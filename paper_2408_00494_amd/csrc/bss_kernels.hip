@@ -433,11 +433,11 @@ static int ppl_for(int M, int lanes)
     return p;
 }
 
-size_t solve_lds_bytes(int lanes, int T, int ppl, bool split)
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample)
 {
     const int groups = 256 / lanes;
     return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2) +
-           (split ? (size_t)2 * ppl * 3 * 256 * sizeof(float) : 0);
+           (split ? (size_t)2 * ppl * (resample ? 9 : 3) * 256 * sizeof(float) : 0);
 }
 
 size_t record_lds_bytes(int lanes, int T, int n_con)
@@ -508,7 +508,7 @@ hipError_t launch_solve(const InstanceDesc* inst, const BlockDesc* blocks, int n
                         hipStream_t stream, uint32_t* queue)
 {
     if (nblocks <= 0) return hipSuccess;
-    split = split && !shield && !resample;
+    split = split && !shield && !(resample && con);
     switch (ppl) {
     case 0:
         return launch_solve_pm(inst, blocks, nblocks, shield, split, resample, con,

@@ -26,22 +26,50 @@ namespace {
 // One solve block with L lanes per sample (L is a compile-time constant so that the group
 // reductions are straight-line DPP sequences).
 // Disturbance normals of step t for the P particles of one lane, written to slot t & 1 of the
-// ring [2][P][3][256] (lane-contiguous, so the stores and the loads are conflict-free).
-template <int P>
+// ring [2][P][RW][256] (lane-contiguous, so the stores and the loads are conflict-free); with
+// RW = 9 (the re-sampling loop) also the six standard normals of each particle's re-sampling draw
+// at step t > 0 (counters (t, m, k, tag 4 or 5): the draw of resample_particles).
+template <int P, int L, int RW>
 __device__ __forceinline__ void produce_noise(float* ring, int t, int q, int j,
                                               const PhiloxParticle* pb, uint32_t c3w, uint32_t lk,
-                                              uint32_t key0, uint32_t key1)
+                                              uint32_t key0, uint32_t key1, bool draws = false,
+                                              uint32_t s = 0u, int k = 0)
 {
     const PhiloxStep ps = philox_step((uint32_t)t, c3w, lk, key0, key1);
-    float* dst = ring + (t & 1) * (P * 3 * 256) + q;
+    float* dst = ring + (t & 1) * (P * RW * 256) + q;
     NoiseDealer<P> deal{ps, pb, key0, key1, j, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         float w0, w1, w2;
         deal.next(p, w0, w1, w2);
-        dst[(p * 3 + 0) * 256] = w0;
-        dst[(p * 3 + 1) * 256] = w1;
-        dst[(p * 3 + 2) * 256] = w2;
+        dst[(p * RW + 0) * 256] = w0;
+        dst[(p * RW + 1) * 256] = w1;
+        dst[(p * RW + 2) * 256] = w2;
+    }
+    if constexpr (RW == 9) {
+        if (draws && t > 0) {
+            const uint64_t pkr = (uint64_t)kPhiloxM1 * (uint32_t)k;
+            const uint32_t hkr = (uint32_t)(pkr >> 32), lkr = (uint32_t)pkr;
+            const PhiloxStep psr0 =
+                philox_step((uint32_t)t, rng_word3(kTagResample0, s), lkr, key0, key1);
+            const PhiloxStep psr1 =
+                philox_step((uint32_t)t, rng_word3(kTagResample1, s), lkr, key0, key1);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const uint32_t m = (uint32_t)particle_of<P, L>(j, p);
+                const PhiloxParticle pm = philox_particle(m, hkr, key0, key1);
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    uint32_t c0, c1, c2, c3;
+                    philox10_tail(blk == 0 ? psr0 : psr1, pm, key0, key1, c0, c1, c2, c3);
+                    float z0, z1;
+                    bm_pair(c0, c1, z0, z1);
+                    dst[(p * RW + 3 + 3 * blk + 0) * 256] = z0;
+                    dst[(p * RW + 3 + 3 * blk + 1) * 256] = z1;
+                    dst[(p * RW + 3 + 3 * blk + 2) * 256] = bm_cos(c2, c3);
+                }
+            }
+        }
     }
 }
 
@@ -67,12 +95,16 @@ __device__ __forceinline__ double* resample_lds()
 // Sigma points (mode 2, M = 12): the same moments with equal weights 1/12, plus the disturbance
 // covariance diag(0, 0, 0, sigma_w^2) scaled by qbar (the previous points' mean of
 // (1 + kappa |vx|)^2), and the deterministic points mean +- sqrt(6) L e_i instead of the draw.
+// xi_src (split loop): the draws' normals of this lane's particles at step t in the noise ring
+// (normal a of particle p at xi_src[(9 p + 3 + a) 256]), produced by the noise waves; nullptr:
+// drawn here.
 template <int P, int L>
 __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, uint32_t s,
                                                    uint32_t key0, uint32_t key1, int mode,
                                                    double qbar, const float* sw, float* Xs,
                                                    float* Xc, float* Ys, float* Yc, float* Ps,
-                                                   float* Pc, float* vx, float* vy, float* vr)
+                                                   float* Pc, float* vx, float* vy, float* vr,
+                                                   const float* xi_src = nullptr)
 {
     double ref[6];
     ref[0] = (double)group_first(Xs[0], L) - (double)group_first(Xc[0], L);
@@ -167,7 +199,7 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
     const uint64_t pk = (uint64_t)kPhiloxM1 * (uint32_t)k;
     const uint32_t hk = (uint32_t)(pk >> 32), lk = (uint32_t)pk;
     PhiloxStep psr[2];
-    if (mode != 2) {
+    if (mode != 2 && !xi_src) {
         psr[0] = philox_step((uint32_t)t, rng_word3(kTagResample0, s), lk, key0, key1);
         psr[1] = philox_step((uint32_t)t, rng_word3(kTagResample1, s), lk, key0, key1);
     }
@@ -181,6 +213,9 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
             const uint32_t e = m % 6u;
 #pragma unroll
             for (int a = 0; a < 6; ++a) xi[a] = (m < 12u && e == (uint32_t)a) ? r : 0.0;
+        } else if (xi_src) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) xi[a] = xi_src[(p * 9 + 3 + a) * 256];
         } else {
             const PhiloxParticle pm = philox_particle(m, hk, key0, key1);
 #pragma unroll
@@ -229,7 +264,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                                             int extra_shift)
 {
     static_assert(!(SPLIT && SHIELD), "the shielded loop is not split");
-    static_assert(!(SPLIT && RESAMPLE), "the re-sampling loop is not split");
+    static_assert(!(SPLIT && RESAMPLE && CON), "the generic loop is not split");
     static_assert(!CON || (SHIELD && RESAMPLE && !SPLIT) || (!SHIELD && !RESAMPLE),
                   "half-space constraints: the plain, split and generic variants only");
     constexpr int log2L = L == 8 ? 3 : (L == 16 ? 4 : (L == 32 ? 5 : 6));
@@ -241,9 +276,12 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     double* S_sh = smem;                                     // [groups]
     double* w_sh = S_sh + groups;                            // [groups]
     float2* u_sh = reinterpret_cast<float2*>(w_sh + groups);  // [groups][T]
-    float* ring = reinterpret_cast<float*>(u_sh + groups * T);  // SPLIT: [2][P][3][256]
+    // SPLIT: [2][P][RW][256], RW = 3 disturbance normals per particle, 9 with the re-sampling
+    // draw's six
+    constexpr int RW = RESAMPLE ? 9 : 3;
+    float* ring = reinterpret_cast<float*>(u_sh + groups * T);
     // on-chip belief records (rec_lds): [groups][T+1][9], then [groups][T+1][n_con]
-    double* rec_sh = reinterpret_cast<double*>(ring + (SPLIT ? 2 * P * 3 * 256 : 0));
+    double* rec_sh = reinterpret_cast<double*>(ring + (SPLIT ? 2 * P * RW * 256 : 0));
     const int q = SPLIT ? (int)(threadIdx.x & 255u) : (int)threadIdx.x;
     const bool producer = SPLIT && threadIdx.x >= 256u;
     const int g = q >> log2L;
@@ -295,7 +333,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 #pragma unroll
         for (int i = 0; i < NB; ++i)
             pb0[i] = philox_particle(noise_block_word<P, L>(j, i), hk, key0, key1);
-        produce_noise<P>(ring, 0, q, j, pb0, c3w, lk, key0, key1);
+        produce_noise<P, L, RW>(ring, 0, q, j, pb0, c3w, lk, key0, key1);
     }
     __syncthreads();
 
@@ -417,7 +455,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         for (int t = 0; t < T; ++t) {
             if (SPLIT && producer) {
                 if (active && t + 1 < T)
-                    produce_noise<P>(ring, t + 1, q, j, pb, c3w, lk, key0, key1);
+                    produce_noise<P, L, RW>(ring, t + 1, q, j, pb, c3w, lk, key0, key1,
+                                            RESAMPLE && d.belief == 1, s, k);
             } else if (!SPLIT || consumer) {
                 float2 uu = us[t];
                 if (SHIELD) {
@@ -455,8 +494,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                     }
                 }
                 if (RESAMPLE && d.belief != 0 && t > 0)
-                    resample_particles<P, L>(t, j, k, M, s, key0, key1, d.belief, qbar, swv, Xs,
-                                             Xc, Ys, Yc, Ps, Pc, vx, vy, vr);
+                    resample_particles<P, L>(
+                        t, j, k, M, s, key0, key1, d.belief, qbar, swv, Xs, Xc, Ys, Yc, Ps, Pc,
+                        vx, vy, vr,
+                        SPLIT ? ring + (t & 1) * (P * RW * 256) + q : nullptr);
                 if (RESAMPLE && d.belief == 2) {
                     double qs = 0.0;
 #pragma unroll
@@ -500,10 +541,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         if (RESAMPLE && d.belief == 2) {
                             w0[i] = w1[i] = w2[i] = 0.0f;   // sigma points: Q enters instead
                         } else if (SPLIT) {
-                            const float* src = ring + (t & 1) * (P * 3 * 256) + q;
-                            w0[i] = src[(p * 3 + 0) * 256];
-                            w1[i] = src[(p * 3 + 1) * 256];
-                            w2[i] = src[(p * 3 + 2) * 256];
+                            const float* src = ring + (t & 1) * (P * RW * 256) + q;
+                            w0[i] = src[(p * RW + 0) * 256];
+                            w1[i] = src[(p * RW + 1) * 256];
+                            w2[i] = src[(p * RW + 2) * 256];
                         } else {
                             deal.next(p, w0[i], w1[i], w2[i]);
                         }
@@ -843,6 +884,10 @@ hipError_t launch_solve_p(const InstanceDesc* inst, const BlockDesc* blocks, int
         return launch_variant<P, true, false, false, false>(inst, blocks, nblocks, lds, x0_base,
                                                             Sigma0_base, extra_shift, queue,
                                                             stream);
+    if (resample && split)
+        return launch_variant<P, false, true, true, false>(inst, blocks, nblocks, lds, x0_base,
+                                                           Sigma0_base, extra_shift, queue,
+                                                           stream);
     if (resample)
         return launch_variant<P, false, false, true, false>(inst, blocks, nblocks, lds, x0_base,
                                                             Sigma0_base, extra_shift, queue,

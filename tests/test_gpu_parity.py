@@ -389,6 +389,33 @@ def test_noise_split_is_bitwise_identical(K, M, T, ppl):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("belief,K,M,T,ppl", [(1, 4096, 64, 50, 4), (1, 333, 37, 23, 2),
+                                              (1, 70, 5, 9, 1), (2, 512, 12, 30, 1),
+                                              (1, 200, 30, 12, 2)])
+def test_resampling_noise_split_is_bitwise_identical(belief, K, M, T, ppl):
+    """With the noise split the noise waves also draw the re-sampling normals (belief 1) ahead of
+    the integrating waves; no result bit changes (sigma points: the integrating waves use no
+    normals)."""
+    prob, x0, _ = W.config_paper_scale()
+    prob = dict(prob, K=K, M=M, T=T, belief=belief)
+    v = np.column_stack([0.05 * np.sin(np.arange(T)), 0.5 * np.cos(np.arange(T))])
+    out = []
+    for split in (0, 1):
+        s = bss.Solver(prob)
+        s.set_shape(ppl=ppl, split=split)
+        assert s.info()["split"] == bool(split)
+        s.set_controls(v)
+        s.solve_index = 7
+        s.solve(x0)
+        s.solve(x0)
+        b = s.buffers()
+        out.append((s.get_controls(), b["mom"].cpu().numpy(), b["S"].cpu().numpy(),
+                    b["u"].cpu().numpy()))
+        s.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("K,M,T,shape", [(1000, 20, 20, (32, 1)), (512, 64, 30, (64, 1)),
                                          (2048, 32, 25, (32, 1)), (4096, 64, 20, (16, 4)),
                                          (256, 16, 30, (16, 1))])
