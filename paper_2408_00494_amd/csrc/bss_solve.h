@@ -343,6 +343,19 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 #pragma unroll
         for (int i = 0; i < 6; ++i) x0[i] = x0p[i];
         const bool spread = S0p != nullptr;
+        // half-space directions in registers, with a_i^T of the estimate's velocities folded into
+        // one constant: a_i^T (x - xref) = a_i^T (X, Y, psi, vx, vy, r) - cb_i (the plain and
+        // split constraint variants; the generic one has no registers to spare)
+        constexpr bool HOIST = CON && !SHIELD && !RESAMPLE;
+        double ca[HOIST ? kMaxCon : 1][6], cb[HOIST ? kMaxCon : 1];
+        if constexpr (HOIST) {
+#pragma unroll
+            for (int c = 0; c < kMaxCon; ++c) {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) ca[c][e] = c < ncon ? d.sc.con_a[6 * c + e] : 0.0;
+                cb[c] = fma(ca[c][3], x0[3], fma(ca[c][4], x0[4], ca[c][5] * x0[5]));
+            }
+        }
 
         // state relative to the estimate: position and heading as compensated (sum, correction)
         float Xs[P], Xc[P], Ys[P], Yc[P], Ps[P], Pc[P], vx[P], vy[P], vr[P];
@@ -605,18 +618,36 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                             sXX = fma(X, X, sXX);
                             sXY = fma(X, Y, sXY);
                             sYY = fma(Y, Y, sYY);
+                            if constexpr (HOIST) {
+                                const double Pd = (double)Ps[p] - (double)Pc[p];
 #pragma unroll
-                            for (int c = 0; c < kMaxCon; ++c) {
-                                if (c < ncon) {
-                                    const double* a = d.sc.con_a + 6 * c;
-                                    const double y = fma(
-                                        a[0], X,
-                                        fma(a[1], Y,
-                                            fma(a[2], (double)Ps[p] - (double)Pc[p],
-                                                fma(a[3], (double)vx[p] - x0[3],
-                                                    fma(a[4], (double)vy[p] - x0[4],
-                                                        a[5] * ((double)vr[p] - x0[5]))))));
-                                    c2[c] = fma(y, y, c2[c]);
+                                for (int c = 0; c < kMaxCon; ++c) {
+                                    if (c < ncon) {
+                                        const double y = fma(
+                                            ca[c][0], X,
+                                            fma(ca[c][1], Y,
+                                                fma(ca[c][2], Pd,
+                                                    fma(ca[c][3], (double)vx[p],
+                                                        fma(ca[c][4], (double)vy[p],
+                                                            fma(ca[c][5], (double)vr[p],
+                                                                -cb[c]))))));
+                                        c2[c] = fma(y, y, c2[c]);
+                                    }
+                                }
+                            } else {
+#pragma unroll
+                                for (int c = 0; c < kMaxCon; ++c) {
+                                    if (c < ncon) {
+                                        const double* a = d.sc.con_a + 6 * c;
+                                        const double y = fma(
+                                            a[0], X,
+                                            fma(a[1], Y,
+                                                fma(a[2], (double)Ps[p] - (double)Pc[p],
+                                                    fma(a[3], (double)vx[p] - x0[3],
+                                                        fma(a[4], (double)vy[p] - x0[4],
+                                                            a[5] * ((double)vr[p] - x0[5]))))));
+                                        c2[c] = fma(y, y, c2[c]);
+                                    }
                                 }
                             }
                         }
