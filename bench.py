@@ -53,10 +53,10 @@ KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
 #   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
 #     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
 #   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
-MEASURED = {"sources_sha256_16": "fb833bee1d816836", "lanes": 16, "ppl": 4, "split": True,
+MEASURED = {"sources_sha256_16": "01145378277a3e88", "lanes": 16, "ppl": 4, "split": True,
             "records_on_chip": True,
-            # FETCH_SIZE 270.75 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
-            "fetch_bytes": 554478, "write_bytes": 253952,
+            # FETCH_SIZE 249.5 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
+            "fetch_bytes": 510960, "write_bytes": 253952,
             # SQ_INSTS_VALU; 64 x (ADD + MUL + 2 FMA + TRANS) of the FP32 counters
             "valu_insts": 48868129, "fp32_flop": 2290876416,
             # wave instructions by kind (SQ_INSTS_VALU_*): FP32 arithmetic (ADD, MUL, FMA),
