@@ -298,14 +298,21 @@ std::vector<BlockDesc> block_table(int inst, int K, int lanes)
     return out;
 }
 
+// Static LDS beside a solve block's dynamic LDS: the variants with the re-sampling compiled in
+// hold its 32 KB of sums (the generic constraint variant too), every variant a few block slots.
+static size_t static_lds_margin(const bss_params& p)
+{
+    const bool rs_compiled = launch_resample(p) || (p.n_con > 0 && launch_shield(p));
+    return (rs_compiled ? kResampleStaticLds : 0) + kStaticLdsSlots;
+}
+
 // Belief records on chip (rec_lds) when no output asks for them and their LDS costs no residency:
-// the blocks the grid needs per CU must still fit next to each other (40 KB are left for the
-// kernels' static LDS, at most 33 KB in the re-sampling variants).
+// the blocks the grid needs per CU must still fit next to each other.
 bool records_on_chip(const bss_ctx* c, size_t base_lds)
 {
     if ((c->outputs & BSS_OUT_BELIEFS) || c->p.vehicle != 0) return false;
-    const size_t per_block =
-        base_lds + record_lds_bytes(c->shape.lanes, c->p.T, c->p.n_con) + 40 * 1024;
+    const size_t per_block = base_lds + record_lds_bytes(c->shape.lanes, c->p.T, c->p.n_con) +
+                             static_lds_margin(c->p);
     if (per_block > kMaxLdsPerBlock) return false;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -322,14 +329,17 @@ hipError_t upload_shape(bss_ctx* c)
     c->desc.ppl = c->shape.ppl;
     c->desc.nblocks = solve_blocks(c->p.K, c->shape.lanes);
     // the noise split: not with the repair of the samples nor the generic constraint variant; with
-    // the re-sampling draw the noise waves also draw its normals, in a ring three times as large
-    // (40 KB are left for the kernel's static LDS, 33 KB in the re-sampling variants)
+    // the re-sampling draw the noise waves also draw its normals, in a ring three times as large,
+    // which must fit beside the kernel's static LDS
     const bool rs = launch_resample(c->p);
     c->shape.split = c->shape.split && !launch_shield(c->p) && c->p.vehicle == 0 &&
                      !(rs && c->p.n_con > 0) &&
                      (!rs || solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, true, true) +
-                                     40 * 1024 <= kMaxLdsPerBlock);
-    c->lds = solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split, rs);
+                                     static_lds_margin(c->p) <= kMaxLdsPerBlock);
+    c->lds = c->p.vehicle == 1
+                 ? solve8_lds_bytes(c->shape.lanes, c->p.T)
+                 : solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split, rs,
+                                   c->p.n_con > 0);
     c->desc.rec_lds = records_on_chip(c, c->lds) ? 1 : 0;
     if (c->desc.rec_lds) c->lds += record_lds_bytes(c->shape.lanes, c->p.T, c->p.n_con);
     // static leading fields only: the device state is left as it is
@@ -674,7 +684,7 @@ bss_status bss_create(const bss_params* p, const bss_allocator* alloc, void* str
         r.lanes = c->rshape.lanes;
         r.ppl = c->rshape.ppl;
         r.rec_lds = 0;
-        c->rlds = solve_lds_bytes(r.lanes, p->T, c->rshape.ppl, false);
+        c->rlds = solve_lds_bytes(r.lanes, p->T, c->rshape.ppl, false, false, p->n_con > 0);
     }
 
     hipError_t e = hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault);
@@ -1060,9 +1070,11 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
     bool sp = split > 0 || (split < 0 && (int64_t)blocks.size() * 4 < 2 * 1024);
     sp = sp && !b->shield && !b->resample;
     for (int i = 0; i < b->n && sp; ++i)
-        sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], true) <= kMaxLds;
+        sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], true, false, b->con) <=
+             kMaxLdsSplit;
     for (int i = 0; i < b->n; ++i)
-        lds = std::max(lds, solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], sp));
+        lds = std::max(lds, solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], sp,
+                                            b->resample, b->con));
     hipError_t e = hipSuccess;
     for (int i = 0; i < b->n && e == hipSuccess; ++i) {
         InstanceDesc head = b->ctxs[i]->desc;

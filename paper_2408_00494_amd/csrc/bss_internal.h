@@ -171,17 +171,36 @@ struct LaunchShape {
 };
 
 constexpr int kMaxT = 256;
+// LDS budget of a solve block without the noise split (several blocks share a CU) and with it
+// (512-thread blocks, at most two per CU when the split pays)
 constexpr size_t kMaxLds = 65536;
+constexpr size_t kMaxLdsSplit = 81920;
 
-// dynamic LDS of one solve block with L lanes per sample (P = the kernel's particles per lane)
-// Dynamic LDS of a solve block: costs and weights, the controls, and with the noise split the ring
-// of normals (three per particle and slot, nine with the re-sampling draw's).
-size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample = false);
+// Moment exchange of the solve kernel: each lane stores its partial moment sums in its group's
+// rows (the L lanes' entries, then the group total: an odd stride of L + 1 doubles), and the rows
+// are totalled in LDS.  Rows: the nine moment sums, and in the constraint variants the constraints'
+// sums of squares of the projections; then the group's reference position (two doubles).
+constexpr int moment_rows(bool con) { return con ? 9 + kMaxCon : 9; }
+constexpr int moment_region_doubles(int lanes, bool con) { return moment_rows(con) * (lanes + 1) + 2; }
+
+// Dynamic LDS of a solve block (6-state car): costs and weights, the controls, with the noise
+// split the ring of normals (three per particle and slot, nine with the re-sampling draw's), then
+// the moment exchange (two slots with the split: the noise waves total step t's sums while the
+// others integrate step t + 1).  con: a constraint variant is launched.
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample = false,
+                       bool con = false);
+// Dynamic LDS of a block of the 8-state vehicle's kernel: costs and weights, and the controls.
+size_t solve8_lds_bytes(int lanes, int T);
 // LDS of the belief records of one block kept on chip (rec_lds): (256 / lanes) samples x (T + 1)
 // records x (9 + n_con) doubles.
 size_t record_lds_bytes(int lanes, int T, int n_con);
 // LDS one workgroup can allocate on gfx950.
 constexpr size_t kMaxLdsPerBlock = 163840;
+// Static LDS of the solve kernels: the re-sampling sums (the variants with the re-sampling compiled
+// in: group sums of 14 values over 8 lanes, one row of 9 doubles per value and group, 32 groups)
+// and at most 2 KB of block-level slots in every variant.
+constexpr size_t kResampleStaticLds = (size_t)4 * 8 * 14 * 9 * sizeof(double);
+constexpr size_t kStaticLdsSlots = 2048;
 // requested_split: -1 automatic (split when the launch has fewer than two waves per SIMD), 0 off,
 // 1 on (when the ring fits); shield: the sampled controls are repaired (the automatic shape then
 // puts eight particles in a lane)

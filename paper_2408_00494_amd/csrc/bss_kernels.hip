@@ -433,11 +433,18 @@ static int ppl_for(int M, int lanes)
     return p;
 }
 
-size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample)
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample, bool con)
 {
     const int groups = 256 / lanes;
     return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2) +
-           (split ? (size_t)2 * ppl * (resample ? 9 : 3) * 256 * sizeof(float) : 0);
+           (split ? (size_t)2 * ppl * (resample ? 9 : 3) * 256 * sizeof(float) : 0) +
+           (size_t)(split ? 2 : 1) * groups * moment_region_doubles(lanes, con) * sizeof(double);
+}
+
+size_t solve8_lds_bytes(int lanes, int T)
+{
+    const int groups = 256 / lanes;
+    return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2);
 }
 
 size_t record_lds_bytes(int lanes, int T, int n_con)
@@ -449,7 +456,7 @@ bool split_pays(int nblocks, int lanes, int T, int ppl)
 {
     // fewer than two waves per SIMD (256 CUs x 4 SIMDs, four waves per block), and room for the
     // noise ring
-    return (int64_t)nblocks * 4 < 2 * 1024 && solve_lds_bytes(lanes, T, ppl, true) <= kMaxLds;
+    return (int64_t)nblocks * 4 < 2 * 1024 && solve_lds_bytes(lanes, T, ppl, true) <= kMaxLdsSplit;
 }
 
 LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl,
@@ -489,7 +496,7 @@ LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested
         s.lanes <<= 1;
         s.ppl = ppl_for(M, s.lanes);
     }
-    const bool fits = solve_lds_bytes(s.lanes, T, s.ppl, true) <= kMaxLds;
+    const bool fits = solve_lds_bytes(s.lanes, T, s.ppl, true) <= kMaxLdsSplit;
     s.split = requested_split > 0 ? fits
               : requested_split == 0 ? false
                                      : split_pays(solve_blocks(K, s.lanes), s.lanes, T, s.ppl);

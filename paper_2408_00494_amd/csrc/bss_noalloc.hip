@@ -155,7 +155,9 @@ extern "C" bss_status bss_solve_noalloc(const bss_params* p, uint32_t solve_inde
     const hipStream_t s = (hipStream_t)stream;
     const bool split = sh.split && !launch_shield(*p) && !launch_resample(*p) &&
                        p->vehicle == 0;
-    const size_t lds = solve_lds_bytes(sh.lanes, p->T, sh.ppl, split);
+    const size_t lds = p->vehicle == 1 ? solve8_lds_bytes(sh.lanes, p->T)
+                                       : solve_lds_bytes(sh.lanes, p->T, sh.ppl, split,
+                                                         launch_resample(*p), p->n_con > 0);
     hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, s, d, d_desc, d_blocks, nblocks,
                        256 / sh.lanes, d_cols, 2 * p->T);
     e = hipGetLastError();

@@ -211,8 +211,6 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         d.cvar = v.p.n_con > 0 ? (double*)(sl.arena + used + base_bytes) : nullptr;
         d.stats = sl.d_stats + 8 * i;
         used += need;
-        lds = std::max(lds, solve_lds_bytes(sh.lanes, T, s->ppl, false));
-        ring_fits = ring_fits && solve_lds_bytes(sh.lanes, T, s->ppl, true) <= kMaxLds;
         shield = shield || v.p.shield_iters > 0;
         resample = resample || v.p.belief != 0;
         con = con || v.p.n_con > 0;
@@ -225,12 +223,19 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
         taken.push_back(qi);
     }
     if (descs.empty()) return BSS_OK;
+    // the launch's variant holds the constraint rows of the moment exchange when any member has
+    // constraints
+    for (const InstanceDesc& d : descs) {
+        lds = std::max(lds, solve_lds_bytes(d.lanes, T, s->ppl, false, false, con));
+        ring_fits = ring_fits &&
+                    solve_lds_bytes(d.lanes, T, s->ppl, true, false, con) <= kMaxLdsSplit;
+    }
     // a batch too small to put two waves on every SIMD generates its noise in separate waves
     const bool split = !shield && !resample && ring_fits && (int64_t)blocks.size() * 4 < 2 * 1024;
     if (split) {
         size_t l2 = 0;
         for (const InstanceDesc& d : descs)
-            l2 = std::max(l2, solve_lds_bytes(d.lanes, T, s->ppl, true));
+            l2 = std::max(l2, solve_lds_bytes(d.lanes, T, s->ppl, true, false, con));
         lds = l2;
     }
 

@@ -73,9 +73,106 @@ __device__ __forceinline__ void produce_noise(float* ring, int t, int q, int j,
     }
 }
 
+// ---- moment exchange: per-lane partial moment sums totalled in LDS ----
+// Pairwise sum of row[0..L): adjacent pairs, then pairs of pairs, and so on (one fixed order, so
+// every variant that totals the same entries gets the same bits).
+template <int L>
+__device__ __forceinline__ double tree_sum(const double* row)
+{
+    if constexpr (L > 16) {
+        return tree_sum<L / 2>(row) + tree_sum<L / 2>(row + L / 2);
+    } else {
+        double a[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) a[i] = row[i];
+#pragma unroll
+        for (int w = 1; w < L; w <<= 1)
+#pragma unroll
+            for (int i = 0; i < L; i += 2 * w) a[i] += a[i + w];
+        return a[0];
+    }
+}
+
+// Entry r of a belief record (mean X, Y, psi, vx, vy, r; covariance XX, XY, YY) from the group
+// totals: tot = row r's total, s0 / s1 = the totals of the shifted positions (rows 0 and 1),
+// ref = the reference position's coordinate (rows 0 and 1, else 0), x0r = the estimate's entry
+// (rows 0 to 2, else 0).
+__device__ __forceinline__ double belief_entry(int r, double tot, double s0, double s1, double ref,
+                                               double x0r, double invM, double invM1)
+{
+    // no contraction: every variant rounds these operations the same way
+#pragma clang fp contract(off)
+    if (r < 3) return x0r + (ref + tot * invM);
+    if (r < 6) return tot * invM;
+    const double a = r == 8 ? s1 : s0;
+    const double b = (r == 6 ? s0 : s1) * invM;
+    return fma(-a, b, tot) * invM1;
+}
+
+// Totals of rows [0, nr) of a group's region (lane i of the group totals rows i, i + L, ...),
+// stored after each row's L entries.  The entries must be visible to the calling wave.
+template <int L>
+__device__ __forceinline__ void total_rows(double* reg, int j, int nr)
+{
+#pragma unroll
+    for (int r0 = 0; r0 < moment_rows(true); r0 += L) {
+        const int r = r0 + j;
+        if (r < nr) reg[r * (L + 1) + L] = tree_sum<L>(reg + r * (L + 1));
+    }
+    wave_lds_sync();
+}
+
+// Writes the nine entries of a belief record from a totalled region, entry r by lane r of the
+// group (and r + 8 by lane r when L = 8).
+template <int L>
+__device__ __forceinline__ void record_from_totals(const double* reg, int j, double refX,
+                                                   double refY, const double (&x0)[6],
+                                                   double invM, double invM1, double* rec)
+{
+    constexpr int ROW = L + 1;
+    const double s0 = reg[L], s1 = reg[ROW + L];
+#pragma unroll
+    for (int r0 = 0; r0 < 9; r0 += L) {
+        const int r = r0 + j;
+        if (r < 9) {
+            const double ref = r == 0 ? refX : (r == 1 ? refY : 0.0);
+            const double x0r = r == 0 ? x0[0] : (r == 1 ? x0[1] : (r == 2 ? x0[2] : 0.0));
+            rec[r] = belief_entry(r, reg[r * ROW + L], s0, s1, ref, x0r, invM, invM1);
+        }
+    }
+}
+
+// Unbiased variance of a half-space constraint's projection a^T x over the particles (eq. 11 with
+// eta_i = a_i) from a totalled region: the sum of the projections follows from the moment totals
+// (rows 0 to 5, positions shifted by the reference, velocities about the estimate's), s2 is the
+// total of the squared projections.  Sigma points add a^T Q a of the disturbance covariance,
+// scaled like Q by the points' mean of (1 + kappa |vx|)^2.
+__device__ __forceinline__ double con_variance(const double* a, const double* reg, int L,
+                                               double s2, const double (&x0)[6], int M,
+                                               double invM, double invM1, bool sigma, double qbar,
+                                               float sw0, float sw1, float sw2)
+{
+#pragma clang fp contract(off)
+    const int ROW = L + 1;
+    const double s1 =
+        fma(a[0], reg[L],
+            fma(a[1], reg[ROW + L],
+                fma(a[2], reg[2 * ROW + L],
+                    fma(a[3], fma(-(double)M, x0[3], reg[3 * ROW + L]),
+                        fma(a[4], fma(-(double)M, x0[4], reg[4 * ROW + L]),
+                            a[5] * fma(-(double)M, x0[5], reg[5 * ROW + L]))))));
+    double var = (s2 - s1 * (s1 * invM)) * invM1;
+    if (sigma) {
+        const double q0 = a[3] * (double)sw0, q1 = a[4] * (double)sw1, q2 = a[5] * (double)sw2;
+        var = fma(qbar, fma(q0, q0, fma(q1, q1, q2 * q2)), var);
+    }
+    return var;
+}
+
 // LDS of the re-sampling sums, one array for every lane count of a kernel (the largest need is 8
 // lanes': group_sums_lds of 14 values).
 constexpr int kResampleLdsDoubles = group_sums_lds_doubles<14, 8>();
+static_assert(kResampleLdsDoubles * sizeof(double) == kResampleStaticLds, "re-sampling LDS size");
 static_assert(group_sums_lds_doubles<14, 16>() <= kResampleLdsDoubles &&
                   group_sums_lds_doubles<14, 32>() <= kResampleLdsDoubles,
               "re-sampling LDS");
@@ -280,8 +377,13 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
     // draw's six
     constexpr int RW = RESAMPLE ? 9 : 3;
     float* ring = reinterpret_cast<float*>(u_sh + groups * T);
+    // moment exchange: [slots][groups][GR] doubles, two slots with the split (step t's sums are
+    // totalled by the noise waves while step t + 1 is integrated), one without
+    constexpr int NR = moment_rows(CON);
+    constexpr int GR = moment_region_doubles(L, CON);
+    double* mscr = reinterpret_cast<double*>(ring + (SPLIT ? 2 * P * RW * 256 : 0));
     // on-chip belief records (rec_lds): [groups][T+1][9], then [groups][T+1][n_con]
-    double* rec_sh = reinterpret_cast<double*>(ring + (SPLIT ? 2 * P * RW * 256 : 0));
+    double* rec_sh = mscr + (SPLIT ? 2 : 1) * groups * GR;
     const int q = SPLIT ? (int)(threadIdx.x & 255u) : (int)threadIdx.x;
     const bool producer = SPLIT && threadIdx.x >= 256u;
     const int g = q >> log2L;
@@ -463,6 +565,54 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         const float swv[3] = {sw0, sw1, sw2};
         double qbar = 1.0;      // sigma points: previous points' mean of (1 + kappa |vx|)^2
 
+        // Record rt from a group region holding the lanes' partial sums of step rt - 1 (and, for
+        // the variants that repair or carry constraints, the belief and the constraint variances
+        // of record rt in every lane of the group).  Run by the integrating waves right after
+        // their sums, or with the split by the noise waves during the next step.
+        auto finish_moments = [&](double* reg, int rt, double rX, double rY) {
+            constexpr int ROW = L + 1;
+            total_rows<L>(reg, j, 9 + ncon);
+            if constexpr (!SHIELD) {
+                // the belief feeds only the records: entry r by lane r, constraint c's variance
+                // by lane 9 + c (lane 1 + c of the second pass when L = 8)
+                record_from_totals<L>(reg, j, rX, rY, x0, invM, invM1, mom_k + (size_t)rt * 9);
+                if constexpr (CON) {
+#pragma unroll
+                    for (int r0 = 0; r0 < NR; r0 += L) {
+                        const int c = r0 + j - 9;
+                        if (c >= 0 && c < ncon)
+                            cvar_k[(size_t)rt * ncon + c] =
+                                con_variance(d.sc.con_a + 6 * c, reg, L, reg[(9 + c) * ROW + L],
+                                             x0, M, invM, invM1, d.belief == 2, qbar, sw0, sw1,
+                                             sw2);
+                    }
+                }
+            } else {
+                // the repair of the next step needs the belief in every lane
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    bel[i] = belief_entry(i, reg[i * ROW + L], reg[L], reg[ROW + L],
+                                          i == 0 ? rX : (i == 1 ? rY : 0.0), i < 3 ? x0[i] : 0.0,
+                                          invM, invM1);
+#pragma unroll
+                for (int c = 0; c < kMaxCon; ++c)
+                    if (c < ncon)
+                        bcv[c] = con_variance(d.sc.con_a + 6 * c, reg, L,
+                                              reg[(9 + c < NR ? 9 + c : 0) * ROW + L], x0, M,
+                                              invM, invM1, d.belief == 2, qbar, sw0, sw1, sw2);
+                // record rt, written by lane rt % L of the group (spreads the stores)
+                if (j == (rt & (L - 1))) {
+                    double* rec = mom_k + (size_t)rt * 9;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+#pragma unroll
+                    for (int c = 0; c < kMaxCon; ++c)
+                        if (c < ncon) cvar_k[(size_t)rt * ncon + c] = bcv[c];
+                }
+            }
+            wave_lds_sync();   // the region is written again by the next step
+        };
+
         // In split mode every thread runs every iteration and meets exactly one barrier per step,
         // outside all divergent branches (waves may hold both active and inactive samples).
         for (int t = 0; t < T; ++t) {
@@ -470,6 +620,10 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 if (active && t + 1 < T)
                     produce_noise<P, L, RW>(ring, t + 1, q, j, pb, c3w, lk, key0, key1,
                                             RESAMPLE && d.belief == 1, s, k);
+                if (active && t > 0) {
+                    double* reg = mscr + (size_t)(((t - 1) & 1) * groups + g) * GR;
+                    finish_moments(reg, t, reg[NR * (L + 1)], reg[NR * (L + 1) + 1]);
+                }
             } else if (!SPLIT || consumer) {
                 float2 uu = us[t];
                 if (SHIELD) {
@@ -653,62 +807,40 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                         }
                     }
                 }
-                // moments: FP64 sums over the L lanes (DPP inside a row, swaps across rows)
-                sX = group_sum(sX, L);
-                sY = group_sum(sY, L);
-                sP = group_sum(sP, L);
-                svx = group_sum(svx, L);
-                svy = group_sum(svy, L);
-                svr = group_sum(svr, L);
-                sXX = group_sum(sXX, L);
-                sXY = group_sum(sXY, L);
-                sYY = group_sum(sYY, L);
-                const double mX = sX * invM, mY = sY * invM;
-                bel[0] = x0[0] + (refX + mX);
-                bel[1] = x0[1] + (refY + mY);
-                bel[2] = x0[2] + sP * invM;
-                bel[3] = svx * invM;
-                bel[4] = svy * invM;
-                bel[5] = svr * invM;
-                bel[6] = (sXX - sX * mX) * invM1;
-                bel[7] = (sXY - sX * mY) * invM1;
-                bel[8] = (sYY - sY * mY) * invM1;
-#pragma unroll
-                for (int c = 0; c < kMaxCon; ++c) {
-                    if (c < ncon) {
-                        // sum of the projections from the moment sums, then the unbiased variance
-                        const double* a = d.sc.con_a + 6 * c;
-                        const double s1 =
-                            fma(a[0], sX,
-                                fma(a[1], sY,
-                                    fma(a[2], sP,
-                                        fma(a[3], fma(-(double)M, x0[3], svx),
-                                            fma(a[4], fma(-(double)M, x0[4], svy),
-                                                a[5] * fma(-(double)M, x0[5], svr))))));
-                        const double s2 = group_sum(c2[c], L);
-                        double var = (s2 - s1 * (s1 * invM)) * invM1;
-                        if (d.belief == 2) {
-                            // sigma points: plus a_i^T Q a_i of the disturbance covariance,
-                            // scaled like Q by the points' mean of (1 + kappa |vx|)^2
-                            const double q0 = a[3] * (double)sw0, q1 = a[4] * (double)sw1,
-                                         q2 = a[5] * (double)sw2;
-                            var = fma(qbar, fma(q0, q0, fma(q1, q1, q2 * q2)), var);
-                        }
-                        bcv[c] = var;
-                    }
-                }
-
-                // record t+1, written by lane (t+1) % L of the group (spreads the stores)
-                if (j == ((t + 1) & (L - 1))) {
-                    double* rec = mom_k + (size_t)(t + 1) * 9;
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) rec[i] = bel[i];
+                // moment exchange: the lane's partial sums into its group's rows
+                {
+                    constexpr int ROW = L + 1;
+                    double* reg = mscr + (size_t)((SPLIT ? (t & 1) * groups : 0) + g) * GR;
+                    reg[0 * ROW + j] = sX;
+                    reg[1 * ROW + j] = sY;
+                    reg[2 * ROW + j] = sP;
+                    reg[3 * ROW + j] = svx;
+                    reg[4 * ROW + j] = svy;
+                    reg[5 * ROW + j] = svr;
+                    reg[6 * ROW + j] = sXX;
+                    reg[7 * ROW + j] = sXY;
+                    reg[8 * ROW + j] = sYY;
 #pragma unroll
                     for (int c = 0; c < kMaxCon; ++c)
-                        if (c < ncon) cvar_k[(size_t)(t + 1) * ncon + c] = bcv[c];
+                        if (CON && c < ncon) reg[(9 + c < NR ? 9 + c : 0) * ROW + j] = c2[c];
+                    if constexpr (SPLIT) {
+                        // totalled by the noise waves during the next step
+                        if (j == 0) {
+                            reg[NR * ROW] = refX;
+                            reg[NR * ROW + 1] = refY;
+                        }
+                    } else {
+                        wave_lds_sync();
+                        finish_moments(reg, t + 1, refX, refY);
+                    }
                 }
             }
             if (SPLIT) __syncthreads();
+        }
+        // the noise waves total the last step's sums
+        if (SPLIT && producer && active && T > 0) {
+            double* reg = mscr + (size_t)(((T - 1) & 1) * groups + g) * GR;
+            finish_moments(reg, T, reg[NR * (L + 1)], reg[NR * (L + 1) + 1]);
         }
     }
     // ---- phase 3: score the belief trajectory, L records at a time (one per lane) ----
