@@ -169,6 +169,18 @@ __device__ __forceinline__ double con_variance(const double* a, const double* re
     return var;
 }
 
+// Split loop: whether the noise waves total step t's moment sums (the integrating waves total the
+// other steps' themselves, in the wave).  Chosen by measurement so that neither kind of wave waits
+// long at the step barrier: every other step, and every step in the re-sampling variant (whose
+// integrating waves also re-sample).
+template <bool SPLIT, bool RESAMPLE>
+__device__ __forceinline__ bool hand_over(int t)
+{
+    if constexpr (!SPLIT) return false;
+    else if constexpr (RESAMPLE) return true;
+    else return (t & 1) != 0;
+}
+
 // LDS of the re-sampling sums, one array for every lane count of a kernel (the largest need is 8
 // lanes': group_sums_lds of 14 values).
 constexpr int kResampleLdsDoubles = group_sums_lds_doubles<14, 8>();
@@ -620,7 +632,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
                 if (active && t + 1 < T)
                     produce_noise<P, L, RW>(ring, t + 1, q, j, pb, c3w, lk, key0, key1,
                                             RESAMPLE && d.belief == 1, s, k);
-                if (active && t > 0) {
+                if (active && t > 0 && hand_over<SPLIT, RESAMPLE>(t - 1)) {
                     double* reg = mscr + (size_t)(((t - 1) & 1) * groups + g) * GR;
                     finish_moments(reg, t, reg[NR * (L + 1)], reg[NR * (L + 1) + 1]);
                 }
@@ -823,7 +835,7 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
 #pragma unroll
                     for (int c = 0; c < kMaxCon; ++c)
                         if (CON && c < ncon) reg[(9 + c < NR ? 9 + c : 0) * ROW + j] = c2[c];
-                    if constexpr (SPLIT) {
+                    if (hand_over<SPLIT, RESAMPLE>(t)) {
                         // totalled by the noise waves during the next step
                         if (j == 0) {
                             reg[NR * ROW] = refX;
@@ -837,8 +849,8 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
             }
             if (SPLIT) __syncthreads();
         }
-        // the noise waves total the last step's sums
-        if (SPLIT && producer && active && T > 0) {
+        // the noise waves total the last step's sums when it was handed over
+        if (SPLIT && producer && active && T > 0 && hand_over<SPLIT, RESAMPLE>(T - 1)) {
             double* reg = mscr + (size_t)(((T - 1) & 1) * groups + g) * GR;
             finish_moments(reg, T, reg[NR * (L + 1)], reg[NR * (L + 1) + 1]);
         }
