@@ -334,8 +334,8 @@ hipError_t upload_shape(bss_ctx* c)
     const bool rs = launch_resample(c->p);
     c->shape.split = c->shape.split && !launch_shield(c->p) && c->p.vehicle == 0 &&
                      !(rs && c->p.n_con > 0) &&
-                     (!rs || solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, true, true) +
-                                     static_lds_margin(c->p) <= kMaxLdsPerBlock);
+                     split_fits(c->shape.lanes, c->p.T, c->shape.ppl, rs, c->p.n_con > 0,
+                                static_lds_margin(c->p));
     c->lds = c->p.vehicle == 1
                  ? solve8_lds_bytes(c->shape.lanes, c->p.T)
                  : solve_lds_bytes(c->shape.lanes, c->p.T, c->shape.ppl, c->shape.split, rs,
@@ -1070,8 +1070,8 @@ static hipError_t batch_layout(bss_batch* b, int ppl, int split)
     bool sp = split > 0 || (split < 0 && (int64_t)blocks.size() * 4 < 2 * 1024);
     sp = sp && !b->shield && !b->resample;
     for (int i = 0; i < b->n && sp; ++i)
-        sp = solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], true, false, b->con) <=
-             kMaxLdsSplit;
+        sp = solve_base_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], true) <= kMaxLds &&
+             split_fits(lanes[i], b->ctxs[i]->p.T, ppls[i], false, b->con, kStaticLdsSlots);
     for (int i = 0; i < b->n; ++i)
         lds = std::max(lds, solve_lds_bytes(lanes[i], b->ctxs[i]->p.T, ppls[i], sp,
                                             b->resample, b->con));

@@ -171,10 +171,9 @@ struct LaunchShape {
 };
 
 constexpr int kMaxT = 256;
-// LDS budget of a solve block without the noise split (several blocks share a CU) and with it
-// (512-thread blocks, at most two per CU when the split pays)
+// LDS budget of a solve block's controls and noise ring (the shape choice keeps several blocks on a
+// CU within it)
 constexpr size_t kMaxLds = 65536;
-constexpr size_t kMaxLdsSplit = 81920;
 
 // Moment exchange of the solve kernel: each lane stores its partial moment sums in its group's
 // rows (the L lanes' entries, then the group total: an odd stride of L + 1 doubles), and the rows
@@ -189,6 +188,10 @@ constexpr int moment_region_doubles(int lanes, bool con) { return moment_rows(co
 // others integrate step t + 1).  con: a constraint variant is launched.
 size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample = false,
                        bool con = false);
+// The part the launch shape is chosen by (within kMaxLds): costs, weights, controls and the ring.
+size_t solve_base_lds_bytes(int lanes, int T, int ppl, bool split, bool resample = false);
+// Whether a split block of this shape fits the LDS of a workgroup beside the static LDS.
+bool split_fits(int lanes, int T, int ppl, bool resample, bool con, size_t static_lds);
 // Dynamic LDS of a block of the 8-state vehicle's kernel: costs and weights, and the controls.
 size_t solve8_lds_bytes(int lanes, int T);
 // LDS of the belief records of one block kept on chip (rec_lds): (256 / lanes) samples x (T + 1)

@@ -433,12 +433,23 @@ static int ppl_for(int M, int lanes)
     return p;
 }
 
-size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample, bool con)
+size_t solve_base_lds_bytes(int lanes, int T, int ppl, bool split, bool resample)
 {
     const int groups = 256 / lanes;
     return (size_t)2 * groups * sizeof(double) + (size_t)groups * T * sizeof(float2) +
-           (split ? (size_t)2 * ppl * (resample ? 9 : 3) * 256 * sizeof(float) : 0) +
+           (split ? (size_t)2 * ppl * (resample ? 9 : 3) * 256 * sizeof(float) : 0);
+}
+
+size_t solve_lds_bytes(int lanes, int T, int ppl, bool split, bool resample, bool con)
+{
+    const int groups = 256 / lanes;
+    return solve_base_lds_bytes(lanes, T, ppl, split, resample) +
            (size_t)(split ? 2 : 1) * groups * moment_region_doubles(lanes, con) * sizeof(double);
+}
+
+bool split_fits(int lanes, int T, int ppl, bool resample, bool con, size_t static_lds)
+{
+    return solve_lds_bytes(lanes, T, ppl, true, resample, con) + static_lds <= kMaxLdsPerBlock;
 }
 
 size_t solve8_lds_bytes(int lanes, int T)
@@ -456,7 +467,7 @@ bool split_pays(int nblocks, int lanes, int T, int ppl)
 {
     // fewer than two waves per SIMD (256 CUs x 4 SIMDs, four waves per block), and room for the
     // noise ring
-    return (int64_t)nblocks * 4 < 2 * 1024 && solve_lds_bytes(lanes, T, ppl, true) <= kMaxLdsSplit;
+    return (int64_t)nblocks * 4 < 2 * 1024 && solve_base_lds_bytes(lanes, T, ppl, true) <= kMaxLds;
 }
 
 LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested_ppl,
@@ -492,11 +503,12 @@ LaunchShape choose_shape(int K, int M, int T, int requested_lanes, int requested
         s.lanes = lanes;
     }
     s.ppl = ppl_for(M, s.lanes);
-    while ((s.ppl > 8 || solve_lds_bytes(s.lanes, T, s.ppl, false) > kMaxLds) && s.lanes < 64) {
+    while ((s.ppl > 8 || solve_base_lds_bytes(s.lanes, T, s.ppl, false) > kMaxLds) &&
+           s.lanes < 64) {
         s.lanes <<= 1;
         s.ppl = ppl_for(M, s.lanes);
     }
-    const bool fits = solve_lds_bytes(s.lanes, T, s.ppl, true) <= kMaxLdsSplit;
+    const bool fits = solve_base_lds_bytes(s.lanes, T, s.ppl, true) <= kMaxLds;
     s.split = requested_split > 0 ? fits
               : requested_split == 0 ? false
                                      : split_pays(solve_blocks(K, s.lanes), s.lanes, T, s.ppl);

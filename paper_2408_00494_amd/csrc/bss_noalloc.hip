@@ -154,7 +154,8 @@ extern "C" bss_status bss_solve_noalloc(const bss_params* p, uint32_t solve_inde
 
     const hipStream_t s = (hipStream_t)stream;
     const bool split = sh.split && !launch_shield(*p) && !launch_resample(*p) &&
-                       p->vehicle == 0;
+                       p->vehicle == 0 &&
+                       split_fits(sh.lanes, p->T, sh.ppl, false, p->n_con > 0, kStaticLdsSlots);
     const size_t lds = p->vehicle == 1 ? solve8_lds_bytes(sh.lanes, p->T)
                                        : solve_lds_bytes(sh.lanes, p->T, sh.ppl, split,
                                                          launch_resample(*p), p->n_con > 0);

@@ -227,8 +227,8 @@ bss_status launch_batch(bss_server* s, Slot& sl, int* launched)
     // constraints
     for (const InstanceDesc& d : descs) {
         lds = std::max(lds, solve_lds_bytes(d.lanes, T, s->ppl, false, false, con));
-        ring_fits = ring_fits &&
-                    solve_lds_bytes(d.lanes, T, s->ppl, true, false, con) <= kMaxLdsSplit;
+        ring_fits = ring_fits && solve_base_lds_bytes(d.lanes, T, s->ppl, true) <= kMaxLds &&
+                    split_fits(d.lanes, T, s->ppl, false, con, kStaticLdsSlots);
     }
     // a batch too small to put two waves on every SIMD generates its noise in separate waves
     const bool split = !shield && !resample && ring_fits && (int64_t)blocks.size() * 4 < 2 * 1024;

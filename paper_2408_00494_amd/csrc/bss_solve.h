@@ -419,8 +419,9 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
         : d.rec_lds ? rec_sh + (size_t)groups * (T + 1) * 9 + (size_t)g * (T + 1) * ncon
                     : d.cvar + (size_t)(active ? k : 0) * (T + 1) * ncon;
 
-    // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t ----
-    if (active && (!SPLIT || producer)) {
+    // ---- phase 1: control samples u_{k,t} = clip(v_t + eps_{k,t}), lane-parallel over t (with
+    // the split by the integrating waves, while the noise waves draw step 0's normals) ----
+    if (active && !producer) {
         const float sig0 = d.sig_eps0, sig1 = d.sig_eps1;
         const float smax = d.steer_max, amax = d.accel_max;
         for (int t = j; t < T; t += L) {
@@ -855,18 +856,54 @@ __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDe
             finish_moments(reg, T, reg[NR * (L + 1)], reg[NR * (L + 1) + 1]);
         }
     }
-    // ---- phase 3: score the belief trajectory, L records at a time (one per lane) ----
+    // ---- phase 3: score the belief trajectory ----
+    // In windows of W records per sample (a multiple of L, as many as the ring and the exchange,
+    // free now, hold): every thread of the block evaluates records of the window, cost q and
+    // barrier value h into LDS; then lane j of each group adds up its records j, j + L, ... of the
+    // window with C_safe on the transitions into them.  The same form in every variant (the same
+    // arithmetic wherever a record is scored).
     __threadfence_block();
     __syncthreads();
     double S_part = 0.0, V_part = 0.0;
-    if (active && !producer) {
-        double h_carry = 0.0;
-        for (int base = 0; base <= T; base += L) {
-            const int count = min(L, T + 1 - base);
-            const int rec = base + min(j, count - 1);
-            S_part += score_chunk(d.sc, mom_k + (size_t)rec * 9, base + j, count, j, L, T, us, v,
-                                  vshift, h_carry,
-                                  ncon > 0 ? cvar_k + (size_t)rec * ncon : nullptr, &V_part);
+    {
+        constexpr int NT = SPLIT ? 512 : 256;
+        double* qh = reinterpret_cast<double*>(ring);   // [groups][W][q, h]
+        const int free_doubles = (SPLIT ? P * RW * 256 : 0) + (SPLIT ? 2 : 1) * groups * GR;
+        const int W = free_doubles / (2 * groups) / L * L;
+        const int nact = min(groups, d.K - bd.k0);
+        double h_before = 0.0;   // h of the record before the window (record 0 has no transition)
+        for (int w0 = 0; w0 <= T; w0 += W) {
+            const int wn = min(W, T + 1 - w0);
+            for (int r = (int)threadIdx.x; r < nact * wn; r += NT) {
+                const int gg = r / wn, tt = w0 + (r - gg * wn);
+                const size_t kr = (size_t)(bd.k0 + gg) * (T + 1) + tt;
+                const size_t lr = (size_t)gg * (T + 1) + tt;
+                const double* recp = d.rec_lds ? rec_sh + lr * 9 : d.mom + kr * 9;
+                const double* crec = ncon == 0 ? nullptr
+                                     : d.rec_lds ? rec_sh + (size_t)groups * (T + 1) * 9 + lr * ncon
+                                                 : d.cvar + kr * ncon;
+                double h;
+                const double q = record_cost(d.sc, recp, tt, T, u_sh + gg * T, v, vshift, crec, h);
+                qh[2 * (gg * W + (tt - w0))] = q;
+                qh[2 * (gg * W + (tt - w0)) + 1] = h;
+            }
+            __syncthreads();
+            if (active && !producer) {
+                const double* qg = qh + (size_t)g * W * 2;
+                for (int base = 0; base < wn; base += L) {
+                    const int i = base + j;
+                    double part = 0.0;
+                    if (i < wn) {
+                        part = qg[2 * i];
+                        if (w0 + i >= 1)
+                            part += transition_cost(d.sc, qg[2 * i + 1],
+                                                    i > 0 ? qg[2 * i - 1] : h_before, &V_part);
+                    }
+                    S_part += part;
+                }
+                h_before = qg[2 * (wn - 1) + 1];
+            }
+            __syncthreads();   // the next window overwrites the records' (q, h)
         }
     }
     const double S_k = group_sum(S_part, L);

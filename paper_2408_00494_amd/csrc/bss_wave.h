@@ -224,13 +224,42 @@ __device__ __forceinline__ int vrow(int t, int vshift, int T)
     return r < T ? r : T - 1;
 }
 
-// Score one chunk of belief records, one record per lane of a W-lane group: running cost (times
-// phi_scale on the terminal record), control cost on records < T, and C_safe on the transition
-// into the record (record 0 has none).  `h_carry` holds h of the record before the chunk and is
-// advanced to the chunk's last record.  Returns this lane's contribution.
+// Cost of one belief record: the running cost (eqs. 27-28; times phi_scale on the terminal
+// record) plus, on records < T, the control cost (eq. 8); h = the record's barrier value (eq. 33).
 // crec: the record's half-space constraint variances, or nullptr where the launch carries none.
-// viol (may be null) counts the transitions into this lane's record that violate the DCBF
-// condition h_t >= (1 - gamma) h_{t-1} (the ones C_safe penalises).
+__device__ __forceinline__ double record_cost(const ScoreF64& sc, const double* rec, int rec_idx,
+                                             int T, const float2* u_row, const double* v,
+                                             int vshift, const double* crec, double& h)
+{
+    double scon[kMaxCon];
+    if (crec) con_sigmas(sc, crec, scon);
+    const BeliefEval be = eval_belief(sc, rec, crec ? scon : nullptr);
+    double q = stage_cost(sc, rec, be);
+    if (rec_idx == T) {
+        q *= sc.phi_scale;
+    } else {
+        const float2 ut = u_row[rec_idx];
+        const int r = vrow(rec_idx, vshift, T);
+        q += sc.gamma_u * (v[2 * r] * sc.inv_var0 * (double)ut.x +
+                           v[2 * r + 1] * sc.inv_var1 * (double)ut.y);
+    }
+    h = be.h;
+    return q;
+}
+
+// C_safe of the transition into a record (eqs. 24-25): C_cbf times the excess of the DCBF
+// condition h_t >= (1 - gamma) h_{t-1}; viol (may be null) counts the violating transitions.
+__device__ __forceinline__ double transition_cost(const ScoreF64& sc, double h, double h_prev,
+                                                 double* viol)
+{
+    const double excess = -h + (1.0 - sc.gamma) * h_prev;
+    if (viol && excess > 0.0) *viol += 1.0;
+    return sc.C_cbf * fmax(excess, 0.0);
+}
+
+// Score one chunk of belief records, one record per lane of a W-lane group: the record's cost and
+// C_safe on the transition into it (record 0 has none).  `h_carry` holds h of the record before
+// the chunk and is advanced to the chunk's last record.  Returns this lane's contribution.
 __device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int rec_idx, int count,
                                      int lane, int W, int T, const float2* u_row, const double* v,
                                      int vshift, double& h_carry, const double* crec = nullptr,
@@ -239,29 +268,10 @@ __device__ inline double score_chunk(const ScoreF64& sc, const double* rec, int 
     const bool valid = lane < count;
     double part = 0.0;
     double h = 0.0;
-    if (valid) {
-        double scon[kMaxCon];
-        if (crec) con_sigmas(sc, crec, scon);
-        const BeliefEval be = eval_belief(sc, rec, crec ? scon : nullptr);
-        double q = stage_cost(sc, rec, be);
-        if (rec_idx == T) {
-            q *= sc.phi_scale;
-        } else {
-            const float2 ut = u_row[rec_idx];
-            const int r = vrow(rec_idx, vshift, T);
-            q += sc.gamma_u * (v[2 * r] * sc.inv_var0 * (double)ut.x +
-                               v[2 * r + 1] * sc.inv_var1 * (double)ut.y);
-        }
-        h = be.h;
-        part = q;
-    }
+    if (valid) part = record_cost(sc, rec, rec_idx, T, u_row, v, vshift, crec, h);
     const double h_left = __shfl(h, lane > 0 ? lane - 1 : 0, W);
     const double h_prev = lane == 0 ? h_carry : h_left;
-    if (valid && rec_idx >= 1) {
-        const double excess = -h + (1.0 - sc.gamma) * h_prev;
-        part += sc.C_cbf * fmax(excess, 0.0);
-        if (viol && excess > 0.0) *viol += 1.0;
-    }
+    if (valid && rec_idx >= 1) part += transition_cost(sc, h, h_prev, viol);
     h_carry = __shfl(h, count - 1, W);
     return part;
 }
