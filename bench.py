@@ -53,19 +53,19 @@ KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
 #   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
 #     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
 #   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
-MEASURED = {"sources_sha256_16": "01145378277a3e88", "lanes": 16, "ppl": 4, "split": True,
+MEASURED = {"sources_sha256_16": "40b2b8454c020ce1", "lanes": 16, "ppl": 4, "split": True,
             "records_on_chip": True,
-            # FETCH_SIZE 249.5 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
-            "fetch_bytes": 510960, "write_bytes": 253952,
+            # FETCH_SIZE 287.0 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
+            "fetch_bytes": 587757, "write_bytes": 253952,
             # SQ_INSTS_VALU; 64 x (ADD + MUL + 2 FMA + TRANS) of the FP32 counters
-            "valu_insts": 48868129, "fp32_flop": 2290876416,
+            "valu_insts": 45369848, "fp32_flop": 2291138560,
             # wave instructions by kind (SQ_INSTS_VALU_*): FP32 arithmetic (ADD, MUL, FMA),
             # FP32 transcendentals, FP64 (ADD, MUL, FMA, TRANS), integer (INT32, INT64),
             # conversions; the rest (moves, DPP, selects, bit operations) has no counter
-            "valu_by_kind": {"fp32_arith": 3080192 + 5136384 + 12705792,
-                             "fp32_trans": 2166784,
-                             "fp64": 4603312 + 788589 + 1506073 + 62138,
-                             "int": 530916 + 2553856, "cvt": 2132224}}
+            "valu_by_kind": {"fp32_arith": 3080192 + 5138432 + 12705792,
+                             "fp32_trans": 2168832,
+                             "fp64": 3495405 + 518777 + 1155630 + 51901,
+                             "int": 1399779 + 2559744, "cvt": 2134016}}
 
 
 def sources_hash():
