@@ -53,7 +53,7 @@ KERNEL_SOURCES = ["paper_2408_00494_amd/csrc/bss_solve.h",
 #   HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the same counters read for a 1 GiB
 #     device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
 #   VALU: wave instructions issued (SQ_INSTS_VALU) and the FP32 instruction counts.
-MEASURED = {"sources_sha256_16": "40b2b8454c020ce1", "lanes": 16, "ppl": 4, "split": True,
+MEASURED = {"sources_sha256_16": "a3ddd71f55917378", "lanes": 16, "ppl": 4, "split": True,
             "records_on_chip": True,
             # FETCH_SIZE 287.0 KiB x (1048576 / 524305), WRITE_SIZE 248.0 KiB x 1.0
             "fetch_bytes": 587757, "write_bytes": 253952,

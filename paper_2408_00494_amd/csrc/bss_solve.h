@@ -23,8 +23,7 @@ namespace {
 // ----------------------------------------------------------------------------------------------
 // Up to four particles per lane the loop fits 128 registers, which keeps four waves per SIMD;
 // eight particles fit the budget of three, the shield's double-precision repair that of two.
-// One solve block with L lanes per sample (L is a compile-time constant so that the group
-// reductions are straight-line DPP sequences).
+
 // Disturbance normals of step t for the P particles of one lane, written to slot t & 1 of the
 // ring [2][P][RW][256] (lane-contiguous, so the stores and the loads are conflict-free); with
 // RW = 9 (the re-sampling loop) also the six standard normals of each particle's re-sampling draw
@@ -358,14 +357,15 @@ __device__ __forceinline__ void resample_particles(int t, int j, int k, int M, u
     }
 }
 
-// One solve block with L lanes per sample (L is a compile-time constant so that the group
-// reductions are straight-line DPP sequences).
+// One solve block with L lanes per sample (L is a compile-time constant so that the loops over a
+// group's lanes and the sample sums are straight-line code).
 //
 // SPLIT (512 threads): threads 256..511 generate the disturbance normals of step t + 1 while
-// threads 0..255 integrate step t, through a two-slot LDS ring and one barrier per step.  This
-// puts two waves on every SIMD when a launch has too few samples to fill the chip otherwise (a
-// lone wave issues at about half the SIMD's rate); the arithmetic and its order are unchanged, so
-// the results are bitwise the same as without the split.
+// threads 0..255 integrate step t, through a two-slot LDS ring and one barrier per step; they
+// also total the moment sums of the steps handed over to them (hand_over) and evaluate records in
+// the scoring phase.  This puts two waves on every SIMD when a launch has too few samples to fill
+// the chip otherwise (a lone wave issues at about half the SIMD's rate); the arithmetic and its
+// order are unchanged, so the results are bitwise the same as without the split.
 template <int P, bool SHIELD, int L, bool SPLIT, bool RESAMPLE, bool CON>
 __device__ __forceinline__ void solve_block(const InstanceDesc& d, const BlockDesc bd,
                                             const double* __restrict__ x0_base,
